@@ -1,0 +1,206 @@
+/*
+ * ttie.h -- C ABI of libttie.so, the MI355X (gfx950) hot path of the triangle-triangle
+ * intersection energy (TTIE) of "Differentiable 3D Triangle-Triangle Intersection Energy".
+ *
+ * For every candidate pair of triangles (T_a = tris[i], T_b = tris[j]) the library runs
+ * Moeller's reduction (Sec. 1, Fig. 1; appendix `intersects`) to the intervals I_a, I_b on
+ * the intersection line of the two planes, forms the Minkowski interval
+ * I_c = [t_c^0, t_c^1] = [t_a^0 - t_b^1, t_a^1 - t_b^0] (Eq. 1), decides the open-interval
+ * criterion 0 in (t_c^0, t_c^1) exactly, and on intersecting pairs evaluates the energy
+ * T = (t_c^0 t_c^1)^2 (Eq. 2), its 18-dof gradient (Eq. 3) and the inexact Hessian of Eq. 4
+ * made positive semi-definite from the eigenanalysis of Sec. 1.1.  The per-pair pieces are
+ * assembled into a global energy, a dense gradient and a 3x3-block CSR (BSR) Hessian.
+ *
+ * Conventions shared by every call
+ *  - All array arguments are DEVICE pointers (memory of the current HIP device) unless the
+ *    parameter name ends in `_host`.  The caller owns every buffer; the library never
+ *    allocates device memory: its scratch space is one caller-provided workspace
+ *    (ttie_workspace_size / ttie_set_workspace).
+ *  - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls enqueue work
+ *    on it and return without waiting, except where a call says it synchronizes.
+ *  - Positions x: n_verts x 3 float64, row-major (x0,y0,z0,x1,...).  Triangles: n_tris x 3
+ *    int32 vertex indices.  Pairs: n_pairs x 2 int32 triangle indices (i, j), i != j; the
+ *    degrees of freedom of a pair are ordered (u0,u1,u2,v0,v1,v2) with u = tris[i] (T_a)
+ *    and v = tris[j] (T_b).
+ *  - Every call returns a ttie_status and never aborts or throws.  Errors detected on the
+ *    host return immediately; errors found by kernels (an index out of range, a non-finite
+ *    or out-of-domain coordinate, an overflowed capacity) are latched in a device status
+ *    word read by ttie_get_status.  ttie_last_error() describes the last host-side error
+ *    of the calling thread.
+ *  - Coordinates must be finite and each either 0 or of magnitude in [2^-200, 2^200]: on
+ *    that domain the exact orientation predicates below are exact and never overflow.
+ *
+ * Readings of the paper fixed by this library (the paper is silent on them)
+ *  - plane sides and the intersection flag are exact (sign of orientation determinants,
+ *    semi-static FP64 filter, exact fixed-point fallback); pairs sharing a vertex index are
+ *    "adjacent" and carry no energy (Sec. 1 excludes topologically adjacent pairs);
+ *  - T is gated by the flag: T = (t_c^0 t_c^1)^2 on intersecting pairs, 0 otherwise;
+ *  - I_c follows Eq. 1 by default; TTIE_INTERVAL_APPENDIX_HALF halves both ends as the
+ *    appendix does (T scales by exactly 1/16);
+ *  - the Eq. 4 Hessian is J^T M J with J = [dt_c^0; dt_c^1] (2 x 18) and a 2x2 core M chosen
+ *    by the PSD mode (see ttie_options).
+ */
+#ifndef TTIE_H
+#define TTIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ttie_status {
+  TTIE_OK = 0,
+  TTIE_ERR_INVALID_ARGUMENT = 1,   /* null pointer, negative size, bad enum, i == j */
+  TTIE_ERR_INDEX_OUT_OF_RANGE = 2, /* a pair or triangle index outside its array */
+  TTIE_ERR_NONFINITE_INPUT = 3,    /* NaN or Inf coordinate */
+  TTIE_ERR_CAPACITY = 4,           /* an output or the workspace is too small */
+  TTIE_ERR_HIP = 5,                /* a HIP runtime call failed */
+  TTIE_ERR_NO_DEVICE = 6,          /* no usable GPU */
+  TTIE_ERR_UNSUPPORTED = 7         /* coordinate outside the exact-predicate domain */
+} ttie_status;
+
+/* precision policy */
+enum { TTIE_FP64 = 0, TTIE_MIXED = 1 };
+/* 2x2 core of the per-pair Hessian J^T M J (s = t_c^0 t_c^1, a = dt_c^0, b = dt_c^1):
+ *  PER_PART      parts 1 and 2 of Eq. 4 (PSD, Sec. 1.1) plus the non-negative eigencomponent
+ *                of part 3: M = [[2 t1^2 + 2|s||b|/|a|, 2 s/|s|*|s|], [.., 2 t0^2 + 2|s||a|/|b|]]
+ *  NEAREST       Eq. 4 with its negative eigenvalues clamped to 0 (nearest PSD matrix)
+ *  PAPER_LITERAL parts 1 and 2, plus part 3 only when its trace 8 s a.b is positive
+ *                (not PSD in general)
+ *  RAW_EQ4       Eq. 4 unchanged (indefinite on every intersecting pair) */
+enum { TTIE_PSD_PER_PART = 0, TTIE_PSD_NEAREST = 1, TTIE_PSD_PAPER_LITERAL = 2, TTIE_PSD_RAW_EQ4 = 3 };
+enum { TTIE_INTERVAL_EQ1 = 0, TTIE_INTERVAL_APPENDIX_HALF = 1 };
+enum { TTIE_BROAD_BRUTE = 0, TTIE_BROAD_LBVH = 1 };
+enum { TTIE_HVP_EXACT = 0, TTIE_HVP_PSD = 1 };
+/* per-pair flag codes written by ttie_eval */
+enum { TTIE_PAIR_NONE = 0, TTIE_PAIR_HIT = 1, TTIE_PAIR_ADJACENT = 2, TTIE_PAIR_DEGENERATE_FRAME = 3 };
+
+typedef struct ttie_ctx ttie_ctx;
+
+typedef struct ttie_mesh {
+  const double* x;      /* n_verts x 3 float64 */
+  int64_t n_verts;
+  const int32_t* tris;  /* n_tris x 3 int32 */
+  int64_t n_tris;
+} ttie_mesh;
+
+typedef struct ttie_options {
+  int32_t precision; /* TTIE_FP64: everything in float64.  TTIE_MIXED: plane sides,
+                        endpoints, intervals, flag and T in float64; derivatives, gradient
+                        and Hessian in float32 on pair-local coordinates */
+  int32_t psd_mode;  /* TTIE_PSD_* */
+  int32_t interval;  /* TTIE_INTERVAL_* */
+  int32_t reserved;  /* must be 0 */
+} ttie_options;
+
+/* Upper bounds that size the workspace.  max_pairs bounds the candidate list of
+ * ttie_broadphase and of ttie_eval; max_hits bounds the intersecting pairs per evaluation;
+ * max_blocks bounds the non-zero 3x3 blocks of the assembled Hessian. */
+typedef struct ttie_limits {
+  int64_t max_verts, max_tris, max_pairs, max_hits, max_blocks;
+} ttie_limits;
+
+/* ---- library and context ------------------------------------------------------------ */
+const char* ttie_version(void);
+/* Host-side description of the last error returned on this thread ("" if none). */
+const char* ttie_last_error(void);
+
+/* Creates a context bound to HIP device `device`.  TTIE_ERR_NO_DEVICE when no GPU is
+ * visible (safe to call on a machine without one).  *out receives the context. */
+ttie_status ttie_create(int device, ttie_ctx** out);
+ttie_status ttie_destroy(ttie_ctx* ctx);
+
+/* Bytes of device workspace needed for the given limits on the context's device. */
+ttie_status ttie_workspace_size(ttie_ctx* ctx, const ttie_limits* limits, size_t* bytes_host);
+/* Hands the context a caller-owned device buffer of `bytes` (>= ttie_workspace_size) and
+ * the limits it was sized for; clears the buffer's persistent counters on `stream`.  The
+ * buffer must stay alive and unused by the caller until the next ttie_set_workspace or
+ * ttie_destroy. */
+ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* dptr, size_t bytes, void* stream);
+
+/* Device status word latched by kernels since the last call to this function.  Waits for
+ * `stream` to finish, returns the latched status in *status_host and clears it. */
+ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_host);
+
+/* ---- broad phase (candidate pairs) ---------------------------------------------------
+ * Writes the canonical candidate set {(i, j) : i < j, no shared vertex index} of the mesh
+ * -- for TTIE_BROAD_LBVH restricted to pairs whose closed float64 bounding boxes overlap
+ * on all three axes (Sec. 1.2 uses spatial hashing for this step; this is an LBVH over
+ * 30-bit Morton codes) -- into pairs (capacity x 2 int32) in an unspecified order, and the
+ * number of candidates into *n_pairs (device int64).  When the count exceeds `capacity`
+ * only the first `capacity` pairs are written, *n_pairs still receives the full count and
+ * TTIE_ERR_CAPACITY is latched.  capacity must not exceed limits.max_pairs. */
+ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, int32_t* pairs, int64_t capacity,
+                            int64_t* n_pairs, void* stream);
+
+/* ---- evaluation -----------------------------------------------------------------------
+ * Evaluates the candidate pairs and assembles the energy, gradient and Hessian.
+ *  pairs      pair_capacity x 2 int32 candidate list; the number of pairs evaluated is
+ *             n = min(*n_pairs, pair_capacity), *n_pairs being a device int64 (so the output of
+ *             ttie_broadphase can be passed directly); pair_capacity <= limits.max_pairs
+ *  energy     device float64 scalar: E = sum of T over the pairs (accumulated in float64)
+ *  grad       n_verts x 3, float64 (TTIE_FP64) or float32 (TTIE_MIXED); every row written
+ *  flags      optional (may be NULL): pair_capacity bytes, TTIE_PAIR_* for the first n
+ *  pair_T     optional (may be NULL): pair_capacity float64, T of each of the first n pairs
+ *  row_ptr, col_idx, vals   optional BSR Hessian (all NULL to skip assembly): row_ptr is
+ *             n_verts + 1 int32, col_idx holds up to block_capacity int32 (sorted per row),
+ *             vals block_capacity x 3 x 3 (row-major blocks; float64 or float32 by
+ *             precision).  The pattern is the union over intersecting pairs of their 6x6
+ *             vertex blocks, stored symmetric in full.
+ *  n_blocks   optional device int64: number of non-zero blocks (nnzb); on overflow the
+ *             full count is written and TTIE_ERR_CAPACITY latched
+ *  n_hits     optional device int64: number of intersecting pairs
+ * The intersecting pairs and their derivative records are kept in the workspace for
+ * ttie_hvp and ttie_get_hits until the next ttie_eval.  No host synchronization. */
+ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                      int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags, double* pair_T,
+                      int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
+                      int64_t* n_hits, void* stream);
+
+/* Copies the last evaluation's intersecting pairs, sorted by (i, j), to HOST buffers of
+ * `capacity` entries: pair indices (i, j) int32 x 2, t_c (float64 x 2), T (float64) and the
+ * interval gradients a = dt_c^0, b = dt_c^1 (float64 x 18 each, converted from the
+ * evaluation's precision).  Synchronizes `stream`; *count_host receives the hit count
+ * (TTIE_ERR_CAPACITY if it exceeds capacity).  Any output pointer may be NULL. */
+ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij_host, double* tc_host, double* T_host,
+                          double* a_host, double* b_host, int64_t* count_host, void* stream);
+
+/* Hessian-vector product of the energy at the positions of the last ttie_eval (same mesh
+ * and x): Hv = H v, v and Hv n_verts x 3 in the evaluation's precision.  mode
+ * TTIE_HVP_EXACT: the exact Hessian of the summed energy (forward-mode differentiation of
+ * the gradient along v, through the line direction and the lerp weights); TTIE_HVP_PSD:
+ * the assembled Hessian of the evaluation's PSD mode applied matrix-free. */
+ttie_status ttie_hvp(ttie_ctx* ctx, const ttie_mesh* mesh, const void* v, void* Hv, int mode, void* stream);
+
+/* y = H x with a BSR matrix from ttie_eval (precision as in opts->precision); n_rows =
+ * n_verts.  Used by the Newton consumer. */
+ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                        const void* vals, const void* x, void* y, int precision, void* stream);
+
+/* ---- stage timers ---------------------------------------------------------------------
+ * When enabled (mask of 1 << TTIE_STAGE_*), the following calls record a HIP event pair on
+ * their stream around every kernel of the selected stages.  ttie_read_timers waits for the
+ * recorded events and returns, for stages 0..n_stages-1, the number of timed launches and
+ * their summed duration in milliseconds since the previous read, then resets them. */
+enum {
+  TTIE_STAGE_BP_BOXES = 0,    /* triangle boxes, scene bounds, Morton codes */
+  TTIE_STAGE_BP_SORT = 1,     /* radix sort of the Morton codes */
+  TTIE_STAGE_BP_BUILD = 2,    /* radix-tree build and bottom-up refit */
+  TTIE_STAGE_BP_TRAVERSE = 3, /* tree self-traversal / brute-force enumeration, pair emission */
+  TTIE_STAGE_SCREEN = 4,      /* per-candidate screening with FP64 filters */
+  TTIE_STAGE_SCREEN_EXACT = 5,/* re-screening of the deferred candidates with exact predicates */
+  TTIE_STAGE_DERIVS = 6,      /* per-hit interval gradients, energy, gradient, Hessian core */
+  TTIE_STAGE_ASSEMBLY = 7,    /* incidence lists, BSR pattern, rows of gradient and Hessian */
+  TTIE_STAGE_HVP = 8,         /* Hessian-vector products */
+  TTIE_STAGE_COUNT = 9
+};
+ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask);
+ttie_status ttie_read_timers(ttie_ctx* ctx, int n_stages, int64_t* launches_host, double* total_ms_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTIE_H */

@@ -38,6 +38,8 @@ def lib():
         if not os.path.exists(path):
             build_oracle.build()
         L = ctypes.CDLL(path)
+        L.ttie_oracle_threads.argtypes = []
+        L.ttie_oracle_threads.restype = ctypes.c_int
         L.ttie_oracle_orient_sign.argtypes = [_dp] * 4
         L.ttie_oracle_orient_sign.restype = ctypes.c_int
         L.ttie_oracle_pair.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -81,6 +83,11 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use (OMP_NUM_THREADS or all cores)."""
+    return lib().ttie_oracle_threads()
 
 
 def orient_sign(a, b, c, p) -> int:

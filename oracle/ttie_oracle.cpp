@@ -889,6 +889,9 @@ std::vector<int32_t> pairs_boxes(const Mesh& m) {
 // ============================================================================================
 extern "C" {
 
+// threads the parallel loops use by default
+int ttie_oracle_threads(void) { return n_threads_or_default(0); }
+
 // exact sign of det[b-a, c-a, p-a]
 int ttie_oracle_orient_sign(const double* a, const double* b, const double* c, const double* p) {
   return side(a, b, c, p).sign;

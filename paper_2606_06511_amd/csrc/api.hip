@@ -1,0 +1,409 @@
+// C ABI of libttie.so: context, workspace carve-up, argument checks, status handling.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ttie {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort_bytes) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const size_t H = (size_t)lim.max_hits, V = (size_t)lim.max_verts + 1, T = (size_t)std::max<int64_t>(lim.max_tris, 1);
+  L.counters = take(sizeof(Counters));
+  L.hits = take(H * sizeof(HitGeom));
+  L.defer = take((size_t)lim.max_pairs * 4);
+  L.recs = take(H * sizeof(AsmRec<double>));
+  L.cnt = take(V * 4);
+  L.cur = take(V * 4);
+  L.off = take(V * 4);
+  L.ncol = take(V * 4);
+  L.inc = take(6 * H * sizeof(Incidence));
+  L.colbuf = take(36 * H * 4);
+  L.hvbuf = take(18 * H * 8);
+  L.epart = take(kRowBlocks * 8);
+  L.scan_tmp_bytes = scan_bytes;
+  L.scan_tmp = take(scan_bytes);
+  L.bvh_keys = take(T * 4);
+  L.bvh_keys2 = take(T * 4);
+  L.bvh_vals = take(T * 4);
+  L.bvh_vals2 = take(T * 4);
+  L.bvh_sort_tmp_bytes = sort_bytes;
+  L.bvh_sort_tmp = take(sort_bytes);
+  L.bvh_nodes = take(5 * T * 4);
+  L.bvh_leafparent = take(T * 4);
+  L.bvh_boxes = take(2 * T * 6 * 4);
+  L.bvh_tbox = take(T * 6 * 8);
+  L.bvh_visit = take(T * 4);
+  L.bvh_centroid = take(T * 3 * 4);
+  L.total = o;
+  return L;
+}
+
+static hipEvent_t pool_get(Ctx* c) {
+  if (c->n_pool > 0) return c->event_pool[--c->n_pool];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void pool_put(Ctx* c, hipEvent_t e) {
+  if (!e) return;
+  if (c->n_pool == c->cap_pool) {
+    const int cap = c->cap_pool ? 2 * c->cap_pool : 64;
+    auto* np = static_cast<hipEvent_t*>(realloc(c->event_pool, cap * sizeof(hipEvent_t)));
+    if (!np) {
+      (void)hipEventDestroy(e);
+      return;
+    }
+    c->event_pool = np;
+    c->cap_pool = cap;
+  }
+  c->event_pool[c->n_pool++] = e;
+}
+
+void stage_begin(Ctx* c, int stage, hipStream_t s) {
+  if (!(c->timing_mask & (1u << stage))) return;
+  if (c->n_timers == c->cap_timers) {
+    const int cap = c->cap_timers ? 2 * c->cap_timers : 64;
+    auto* nt = static_cast<TimerRec*>(realloc(c->timers, cap * sizeof(TimerRec)));
+    if (!nt) return;
+    c->timers = nt;
+    c->cap_timers = cap;
+  }
+  TimerRec& r = c->timers[c->n_timers];
+  r.stage = stage;
+  r.start = pool_get(c);
+  r.stop = nullptr;
+  if (!r.start || hipEventRecord(r.start, s) != hipSuccess) {
+    pool_put(c, r.start);
+    return;
+  }
+  ++c->n_timers;
+}
+
+void stage_end(Ctx* c, int stage, hipStream_t s) {
+  if (!(c->timing_mask & (1u << stage)) || c->n_timers == 0) return;
+  TimerRec& r = c->timers[c->n_timers - 1];
+  if (r.stage != stage || r.stop) return;
+  r.stop = pool_get(c);
+  if (r.stop && hipEventRecord(r.stop, s) != hipSuccess) {
+    pool_put(c, r.stop);
+    r.stop = nullptr;
+  }
+}
+
+}  // namespace ttie
+
+using namespace ttie;
+
+struct ttie_ctx : public Ctx {};
+
+namespace {
+
+thread_local std::string g_err;
+
+ttie_status fail(ttie_status st, const char* msg) {
+  g_err = msg;
+  return st;
+}
+
+ttie_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return TTIE_ERR_HIP;
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = prev == dev || hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool limits_ok(const ttie_limits* l) {
+  return l && l->max_verts >= 0 && l->max_tris >= 0 && l->max_pairs >= 0 && l->max_hits >= 0 &&
+         l->max_blocks >= 0 && l->max_verts < (1ll << 30) && l->max_tris < (1ll << 31) &&
+         l->max_pairs < (1ll << 32) && l->max_hits < (1ll << 26) && 36 * l->max_hits < (1ll << 31);
+}
+
+ttie_status check_mesh(ttie_ctx* c, const ttie_mesh* m) {
+  if (!m) return fail(TTIE_ERR_INVALID_ARGUMENT, "mesh is NULL");
+  if (m->n_verts < 0 || m->n_tris < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "negative mesh size");
+  if ((m->n_verts > 0 && !m->x) || (m->n_tris > 0 && !m->tris))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "mesh array is NULL");
+  if (m->n_verts > c->lim.max_verts) return fail(TTIE_ERR_CAPACITY, "n_verts exceeds the workspace limit");
+  if (m->n_tris > c->lim.max_tris) return fail(TTIE_ERR_CAPACITY, "n_tris exceeds the workspace limit");
+  return TTIE_OK;
+}
+
+ttie_status need_ws(ttie_ctx* c) {
+  if (!c) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  if (!c->have_ws) return fail(TTIE_ERR_INVALID_ARGUMENT, "no workspace set (ttie_set_workspace)");
+  return TTIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ttie_version(void) { return "ttie 0.1.0 (gfx950)"; }
+
+const char* ttie_last_error(void) { return g_err.c_str(); }
+
+ttie_status ttie_create(int device, ttie_ctx** out) {
+  if (!out) return fail(TTIE_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(TTIE_ERR_NO_DEVICE, "no HIP device");
+  if (device < 0 || device >= n) return fail(TTIE_ERR_INVALID_ARGUMENT, "device index out of range");
+  auto* c = new ttie_ctx();
+  std::memset(static_cast<Ctx*>(c), 0, sizeof(Ctx));
+  c->device = device;
+  *out = c;
+  g_err.clear();
+  return TTIE_OK;
+}
+
+ttie_status ttie_destroy(ttie_ctx* ctx) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  for (int k = 0; k < ctx->n_timers; ++k) {
+    if (ctx->timers[k].start) (void)hipEventDestroy(ctx->timers[k].start);
+    if (ctx->timers[k].stop) (void)hipEventDestroy(ctx->timers[k].stop);
+  }
+  for (int k = 0; k < ctx->n_pool; ++k) (void)hipEventDestroy(ctx->event_pool[k]);
+  free(ctx->timers);
+  free(ctx->event_pool);
+  delete ctx;
+  return TTIE_OK;
+}
+
+ttie_status ttie_workspace_size(ttie_ctx* ctx, const ttie_limits* limits, size_t* bytes_host) {
+  if (!ctx || !bytes_host) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!limits_ok(limits)) return fail(TTIE_ERR_INVALID_ARGUMENT, "limits out of range");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
+  const size_t scan = scan_temp_bytes(limits->max_verts + 1);
+  const size_t sort = sort_temp_bytes(std::max<int64_t>(limits->max_tris, 2));
+  *bytes_host = layout_with(*limits, scan, sort).total;
+  return TTIE_OK;
+}
+
+ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* dptr, size_t bytes, void* stream) {
+  if (!ctx || !dptr) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!limits_ok(limits)) return fail(TTIE_ERR_INVALID_ARGUMENT, "limits out of range");
+  if (((uintptr_t)dptr) & 255) return fail(TTIE_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
+  const size_t scan = scan_temp_bytes(limits->max_verts + 1);
+  const size_t sort = sort_temp_bytes(std::max<int64_t>(limits->max_tris, 2));
+  Layout L = layout_with(*limits, scan, sort);
+  if (bytes < L.total) return fail(TTIE_ERR_CAPACITY, "workspace smaller than ttie_workspace_size");
+  ctx->lim = *limits;
+  ctx->ws = static_cast<char*>(dptr);
+  ctx->ws_bytes = bytes;
+  ctx->L = L;
+  ctx->have_ws = 1;
+  ctx->last_valid = 0;
+  hipStream_t s = (hipStream_t)stream;
+  // the counters and the per-vertex incidence counts start (and are kept) at zero
+  hipError_t e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.counters), sizeof(Counters) / 4, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cnt), limits->max_verts + 1, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cur), limits->max_verts + 1, s);
+  if (e != hipSuccess) return hip_fail(e, "ttie_set_workspace");
+  return TTIE_OK;
+}
+
+ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_host) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!status_host) return fail(TTIE_ERR_INVALID_ARGUMENT, "status_host is NULL");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  int32_t v = 0;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(&v, ctx->ws + ctx->L.counters, sizeof(v), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, ctx->L.counters), 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "ttie_get_status");
+  *status_host = (ttie_status)v;
+  return TTIE_OK;
+}
+
+ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, int32_t* pairs, int64_t capacity,
+                            int64_t* n_pairs, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+  if (method != TTIE_BROAD_BRUTE && method != TTIE_BROAD_LBVH) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad method");
+  if (!n_pairs || (capacity > 0 && !pairs) || capacity < 0)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad pair output");
+  if (capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "capacity exceeds limits.max_pairs");
+  if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
+    return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_broadphase(ctx, mesh, method, pairs, capacity, n_pairs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_broadphase");
+  return TTIE_OK;
+}
+
+ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                      int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags, double* pair_T,
+                      int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
+                      int64_t* n_hits, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+  if (!opts) return fail(TTIE_ERR_INVALID_ARGUMENT, "options are NULL");
+  if (opts->precision != TTIE_FP64 && opts->precision != TTIE_MIXED) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad precision");
+  if (opts->psd_mode < 0 || opts->psd_mode > 3) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad psd_mode");
+  if (opts->interval != TTIE_INTERVAL_EQ1 && opts->interval != TTIE_INTERVAL_APPENDIX_HALF)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad interval");
+  if (opts->reserved != 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "reserved must be 0");
+  if ((!pairs && pair_capacity > 0) || !n_pairs || !energy || (!grad && mesh->n_verts > 0))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL required argument");
+  if (pair_capacity < 0 || pair_capacity > ctx->lim.max_pairs)
+    return fail(TTIE_ERR_CAPACITY, "pair_capacity outside [0, limits.max_pairs]");
+  const bool bsr = row_ptr || col_idx || vals;
+  if (bsr && (!row_ptr || !col_idx || !vals)) return fail(TTIE_ERR_INVALID_ARGUMENT, "partial BSR output");
+  if (bsr && (block_capacity < 0 || block_capacity > ctx->lim.max_blocks))
+    return fail(TTIE_ERR_CAPACITY, "block_capacity exceeds limits.max_blocks");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_eval(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, bsr ? row_ptr : nullptr,
+                             col_idx, vals, bsr ? block_capacity : 0, n_blocks, n_hits, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_eval");
+  ctx->last_precision = opts->precision;
+  ctx->last_psd = opts->psd_mode;
+  ctx->last_interval = opts->interval;
+  ctx->last_nverts = mesh->n_verts;
+  ctx->last_valid = 1;
+  return TTIE_OK;
+}
+
+ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij, double* tc, double* T, double* a, double* b,
+                          int64_t* count_host, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation yet");
+  if (!count_host || capacity < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad argument");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  Counters ctr;
+  if (e == hipSuccess) e = hipMemcpy(&ctr, ctx->ws + ctx->L.counters, sizeof(ctr), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "ttie_get_hits");
+  const int64_t H = std::min<int64_t>(ctr.n_hits, ctx->lim.max_hits);
+  *count_host = ctr.n_hits;
+  if ((int64_t)ctr.n_hits > capacity) return fail(TTIE_ERR_CAPACITY, "more hits than capacity");
+  std::vector<HitGeom> hg(H);
+  const bool fp64 = ctx->last_precision == TTIE_FP64;
+  const size_t rs = fp64 ? sizeof(AsmRec<double>) : sizeof(AsmRec<float>);
+  std::vector<char> rec(H * rs);
+  if (H > 0) {
+    e = hipMemcpy(hg.data(), ctx->ws + ctx->L.hits, H * sizeof(HitGeom), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(rec.data(), ctx->ws + ctx->L.recs, H * rs, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ttie_get_hits");
+  }
+  std::vector<int64_t> order(H);
+  for (int64_t k = 0; k < H; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return hg[x].key < hg[y].key; });
+  for (int64_t q = 0; q < H; ++q) {
+    const int64_t k = order[q];
+    const HitGeom& h = hg[k];
+    if (ij) {
+      ij[2 * q] = (int32_t)(h.key >> 32);
+      ij[2 * q + 1] = (int32_t)(h.key & 0xffffffff);
+    }
+    if (tc) {
+      tc[2 * q] = h.t0;
+      tc[2 * q + 1] = h.t1;
+    }
+    for (int z = 0; z < 18; ++z) {
+      double av, bv;
+      if (fp64) {
+        const auto* r = reinterpret_cast<const AsmRec<double>*>(rec.data() + k * rs);
+        av = r->a[z];
+        bv = r->b[z];
+        if (T && z == 0) T[q] = r->T;
+      } else {
+        const auto* r = reinterpret_cast<const AsmRec<float>*>(rec.data() + k * rs);
+        av = r->a[z];
+        bv = r->b[z];
+        if (T && z == 0) T[q] = r->T;
+      }
+      if (a) a[18 * q + z] = av;
+      if (b) b[18 * q + z] = bv;
+    }
+  }
+  return TTIE_OK;
+}
+
+ttie_status ttie_hvp(ttie_ctx* ctx, const ttie_mesh* mesh, const void* v, void* Hv, int mode, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation yet");
+  if (mesh->n_verts != ctx->last_nverts) return fail(TTIE_ERR_INVALID_ARGUMENT, "mesh differs from the evaluation");
+  if (mode != TTIE_HVP_EXACT && mode != TTIE_HVP_PSD) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad mode");
+  if ((!v || !Hv) && mesh->n_verts > 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL vector");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_hvp(ctx, mesh, v, Hv, mode, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_hvp");
+  return TTIE_OK;
+}
+
+ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                        const void* vals, const void* x, void* y, int precision, void* stream) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  if (n_rows < 0 || (n_rows > 0 && (!row_ptr || !x || !y)))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad argument");
+  if (precision != TTIE_FP64 && precision != TTIE_MIXED) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad precision");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_bsr_mv(n_rows, row_ptr, col_idx, vals, x, y, precision, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_bsr_mv");
+  return TTIE_OK;
+}
+
+ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  ctx->timing_mask = stage_mask & ((1u << TTIE_STAGE_COUNT) - 1u);
+  return TTIE_OK;
+}
+
+ttie_status ttie_read_timers(ttie_ctx* ctx, int n_stages, int64_t* launches, double* total_ms) {
+  if (!ctx || n_stages < 0 || (n_stages > 0 && (!launches || !total_ms)))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad argument");
+  DeviceGuard g(ctx->device);
+  for (int k = 0; k < n_stages; ++k) {
+    launches[k] = 0;
+    total_ms[k] = 0.0;
+  }
+  ttie_status st = TTIE_OK;
+  for (int k = 0; k < ctx->n_timers; ++k) {
+    TimerRec& r = ctx->timers[k];
+    if (r.stop && r.stage < n_stages) {
+      float ms = 0.f;
+      if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+        launches[r.stage] += 1;
+        total_ms[r.stage] += ms;
+      } else {
+        st = fail(TTIE_ERR_HIP, "event timing failed");
+      }
+    }
+    pool_put(ctx, r.start);
+    pool_put(ctx, r.stop);
+  }
+  ctx->n_timers = 0;
+  return st;
+}
+
+}  // extern "C"

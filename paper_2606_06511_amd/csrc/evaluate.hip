@@ -1,0 +1,623 @@
+// Evaluation kernels: screening of the candidate pairs, per-hit derivatives, and the
+// deterministic (no floating-point atomics) assembly of energy, gradient and BSR Hessian.
+//
+// Pipeline on one stream, no host synchronization:
+//   k_eval_init      reset the per-evaluation counters
+//   k_screen         one lane per candidate: adjacency, exact plane sides, exact flag, FP64
+//                    interval ends; hits appended with one atomic per wave (ballot + mbcnt)
+//   k_derivs<S>      one lane per hit: a = dt_c^0, b = dt_c^1, T, g (Eq. 3), 2x2 Hessian core;
+//                    counts the hit's six vertices
+//   scan             exclusive scan of the per-vertex incidence counts
+//   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists
+//   k_rows_sort<S>   per touched vertex: sort its incidences by pair key (the summation
+//                    order), and count the distinct neighbour vertices (BSR columns)
+//   scan             BSR row pointers from the column counts
+//   k_rows_asm<S>    per vertex: gradient row, BSR row (blocks J_k^T M J_l summed in pair-key
+//                    order), energy partial; clears the counters it used; the last block sums
+//                    the energy partials in block order
+#include <rocprim/device/device_scan.hpp>
+
+#include "internal.h"
+
+namespace ttie {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void latch(int32_t* status, int code) { atomicCAS(status, 0, code); }
+
+__global__ void k_fill_zero_i32(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// resets the per-evaluation counters and checks every coordinate: finite, and 0 or of
+// magnitude in [2^-200, 2^200] (the domain on which the exact predicates are exact)
+__global__ void k_eval_init(Counters* c, const double* __restrict__ x, int64_t n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->n_hits = 0;
+    c->n_defer = 0;
+    c->ticket = 0;
+  }
+  int code = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = fabs(x[i]);
+    if (!(v <= 1.7976931348623157e308)) code = STATUS_NONFINITE;
+    else if (v != 0.0 && (v < 6.223015277861142e-61 || v > 1.6069380442589903e60)) code = code ? code : STATUS_UNSUPPORTED;
+  }
+  if (code) latch(&c->status, code);
+}
+
+__device__ __forceinline__ bool load_tri(const double* x, int64_t nv, const int32_t* tris, int64_t t, int32_t vid[3],
+                                         Tri64& T) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    vid[k] = tris[3 * t + k];
+    ok = ok && vid[k] >= 0 && vid[k] < nv;
+  }
+  if (!ok) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T.p[k][c] = x[3 * (int64_t)vid[k] + c];
+  return true;
+}
+
+// wave-aggregated append to a counter-indexed list: one atomic per wave
+__device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {
+  const uint64_t mask = __ballot(want);
+  if (!mask) return 0xffffffffu;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  return want ? base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)) : 0xffffffffu;
+}
+
+// Screens candidate p (p < 0: inactive lane).  Every lane of the wave must call it.
+template <bool kExact>
+__device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__ x, int64_t nv,
+                                           const int32_t* __restrict__ tris, int64_t nt,
+                                           const int32_t* __restrict__ pairs, double half, HitGeom* __restrict__ hits,
+                                           uint32_t max_hits, int32_t* __restrict__ defer, int64_t max_defer,
+                                           Counters* ctr, uint8_t* __restrict__ flags, double* __restrict__ pair_T,
+                                           int& status) {
+  int kind = PAIR_NONE;
+  Screen sc;
+  sc.t0 = sc.t1 = 0.0;
+  sc.desc = 0;
+  int32_t i = 0, j = 0;
+  if (p >= 0) {
+    i = pairs[2 * p];
+    j = pairs[2 * p + 1];
+    int32_t vi[3], vj[3];
+    Tri64 A, B;
+    if (i < 0 || j < 0 || i >= nt || j >= nt || i == j || !load_tri(x, nv, tris, i, vi, A) ||
+        !load_tri(x, nv, tris, j, vj, B)) {
+      status = STATUS_INDEX;
+    } else {
+      bool adj = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) adj |= vi[a] == vj[b];
+      if (adj) {
+        kind = PAIR_ADJACENT;
+      } else {
+        sc = screen_pair<kExact>(A, B, half, status);
+        kind = sc.kind;
+      }
+    }
+    if (kind != PAIR_DEFER) {
+      if (flags) flags[p] = (uint8_t)kind;
+      if (pair_T) {
+        const double pr = sc.t0 * sc.t1;
+        pair_T[p] = kind == PAIR_HIT ? pr * pr : 0.0;
+      }
+    }
+  }
+  if (!kExact) {
+    const uint32_t ds = wave_slot(kind == PAIR_DEFER, &ctr->n_defer);
+    if (kind == PAIR_DEFER) {
+      if ((int64_t)ds < max_defer) defer[ds] = (int32_t)p;
+      else status = STATUS_CAPACITY;
+    }
+  }
+  const bool is_hit = kind == PAIR_HIT;
+  const uint32_t slot = wave_slot(is_hit, &ctr->n_hits);
+  if (is_hit) {
+    if (slot < max_hits) {
+      HitGeom g;
+      g.key = ((int64_t)i << 32) | (int64_t)(uint32_t)j;
+      g.pair = (int32_t)p;
+      g.desc = sc.desc;
+      g.t0 = sc.t0;
+      g.t1 = sc.t1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        g.da[k] = sc.da[k];
+        g.db[k] = sc.db[k];
+      }
+      hits[slot] = g;
+    } else {
+      status = STATUS_CAPACITY;
+    }
+  }
+}
+
+// fast pass over every candidate: FP64 filters only, uncertain pairs deferred
+__global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
+                                                   const int32_t* __restrict__ tris, int64_t nt,
+                                                   const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
+                                                   int64_t max_pairs, double half, HitGeom* __restrict__ hits,
+                                                   uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
+                                                   uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
+  const int64_t np = min(*n_pairs_dev, max_pairs);
+  int status = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = base + threadIdx.x;
+    screen_one<false>(p < np ? p : -1, x, nv, tris, nt, pairs, half, hits, max_hits, defer, max_pairs, ctr, flags,
+                      pair_T, status);
+  }
+  if (status) latch(&ctr->status, status);
+}
+
+// exact pass over the deferred candidates
+__global__ void __launch_bounds__(kBlock) k_screen_exact(const double* __restrict__ x, int64_t nv,
+                                                         const int32_t* __restrict__ tris, int64_t nt,
+                                                         const int32_t* __restrict__ pairs, int64_t max_pairs,
+                                                         double half, HitGeom* __restrict__ hits, uint32_t max_hits,
+                                                         const int32_t* __restrict__ defer, Counters* ctr,
+                                                         uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
+  const int64_t nd = min((int64_t)ctr->n_defer, max_pairs);
+  int status = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nd; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + threadIdx.x;
+    screen_one<true>(q < nd ? (int64_t)defer[q] : -1, x, nv, tris, nt, pairs, half, hits, max_hits, nullptr, 0, ctr,
+                     flags, pair_T, status);
+  }
+  if (status) latch(&ctr->status, status);
+}
+
+// pair-local coordinates (origin u0) of a hit, in scalar S
+template <class S>
+__device__ __forceinline__ void local_coords(const double* x, const int32_t vid[6], V3<S> X[6]) {
+  const double o0 = x[3 * (int64_t)vid[0]], o1 = x[3 * (int64_t)vid[0] + 1], o2 = x[3 * (int64_t)vid[0] + 2];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double* p = x + 3 * (int64_t)vid[k];
+    X[k] = V3<S>{Sc<S>::c(p[0] - o0), Sc<S>::c(p[1] - o1), Sc<S>::c(p[2] - o2)};
+  }
+}
+
+__device__ __forceinline__ void hit_vids(const int32_t* tris, int64_t key, int32_t vid[6]) {
+  const int64_t i = key >> 32, j = key & 0xffffffffll;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    vid[k] = tris[3 * i + k];
+    vid[3 + k] = tris[3 * j + k];
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_derivs(const double* __restrict__ x, const int32_t* __restrict__ tris,
+                                                   const HitGeom* __restrict__ hits, const Counters* ctr,
+                                                   uint32_t max_hits, int psd_mode, double half,
+                                                   AsmRec<S>* __restrict__ recs, int32_t* __restrict__ cnt) {
+  const uint32_t H = min(ctr->n_hits, max_hits);
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+    const HitGeom g = hits[h];
+    AsmRec<S> r;
+    hit_vids(tris, g.key, r.vid);
+    r.pad = 0;
+    r.key = g.key;
+    V3<S> X[6];
+    local_coords<S>(x, r.vid, X);
+    interval_grads<S>(X, g.da, g.db, g.desc, half, r.a, r.b);
+    const double t0 = g.t0, t1 = g.t1;
+    const double pr = t0 * t1;
+    r.T = pr * pr;
+    // Eq. 3: dT = 2 t0 t1^2 a + 2 t1 t0^2 b
+    const S ca = Sc<S>::c(2.0 * pr * t1), cb = Sc<S>::c(2.0 * pr * t0);
+    double aa = 0, bb = 0, ab = 0;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+      r.g[k] = ca * r.a[k] + cb * r.b[k];
+      aa += (double)r.a[k] * (double)r.a[k];
+      bb += (double)r.b[k] * (double)r.b[k];
+      ab += (double)r.a[k] * (double)r.b[k];
+    }
+    double M[3];
+    hessian_core(psd_mode, t0, t1, aa, bb, ab, M);
+    r.M[0] = Sc<S>::c(M[0]);
+    r.M[1] = Sc<S>::c(M[1]);
+    r.M[2] = Sc<S>::c(M[2]);
+    recs[h] = r;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) atomicAdd(&cnt[r.vid[k]], 1);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ recs, const Counters* ctr,
+                                                 uint32_t max_hits, const int32_t* __restrict__ off,
+                                                 int32_t* __restrict__ cur, Incidence* __restrict__ inc) {
+  const uint32_t H = min(ctr->n_hits, max_hits);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 6 * H; t += gridDim.x * blockDim.x) {
+    const uint32_t h = t / 6, k = t % 6;
+    const int32_t v = recs[h].vid[k];
+    const int32_t pos = off[v] + atomicAdd(&cur[v], 1);
+    inc[pos] = Incidence{recs[h].key, (int32_t)h, (int32_t)k};
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_rows_sort(int64_t nv, const int32_t* __restrict__ off,
+                                                      Incidence* __restrict__ inc, const AsmRec<S>* __restrict__ recs,
+                                                      int32_t* __restrict__ colbuf, int32_t* __restrict__ ncol,
+                                                      int want_bsr) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = off[v], e = off[v + 1];
+    if (e == b) {
+      if (want_bsr) ncol[v] = 0;
+      continue;
+    }
+    // insertion sort by pair key: rows touch few hits
+    for (int32_t k = b + 1; k < e; ++k) {
+      const Incidence cur = inc[k];
+      int32_t m = k - 1;
+      while (m >= b && inc[m].key > cur.key) {
+        inc[m + 1] = inc[m];
+        --m;
+      }
+      inc[m + 1] = cur;
+    }
+    if (!want_bsr) continue;
+    int32_t* cb = colbuf + 6 * (int64_t)b;
+    int32_t n = 0;
+    for (int32_t k = b; k < e; ++k) {
+      const AsmRec<S>& r = recs[inc[k].hit];
+      for (int s = 0; s < 6; ++s) {
+        const int32_t c = r.vid[s];
+        int32_t m = n - 1;  // insert keeping cb[0..n) sorted and unique
+        bool dup = false;
+        while (m >= 0 && cb[m] >= c) {
+          if (cb[m] == c) {
+            dup = true;
+            break;
+          }
+          --m;
+        }
+        if (dup) continue;
+        for (int32_t z = n; z > m + 1; --z) cb[z] = cb[z - 1];
+        cb[m + 1] = c;
+        ++n;
+      }
+    }
+    ncol[v] = n;
+  }
+  if (want_bsr && blockIdx.x == 0 && threadIdx.x == 0) ncol[nv] = 0;
+}
+
+template <class S>
+__device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[9]) {
+  // J_s^T M J_l = M00 a_s a_l^T + M01 (a_s b_l^T + b_s a_l^T) + M11 b_s b_l^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const S as = r.a[3 * s + i], bs = r.b[3 * s + i], al = r.a[3 * l + j], bl = r.b[3 * l + j];
+      B[3 * i + j] = B[3 * i + j] + (r.M[0] * as * al + r.M[1] * (as * bl + bs * al) + r.M[2] * bs * bl);
+    }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_rows_asm(int64_t nv, const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc,
+                                                     const AsmRec<S>* __restrict__ recs,
+                                                     const int32_t* __restrict__ colbuf,
+                                                     const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+                                                     S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
+                                                     int32_t* __restrict__ cnt, int32_t* __restrict__ cur,
+                                                     double* __restrict__ blockpart, Counters* ctr, uint32_t max_hits,
+                                                     double* energy, int64_t* n_blocks, int64_t* n_hits) {
+  __shared__ double red[kBlock];
+  double esum = 0.0;
+  int status = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = off[v], e = off[v + 1];
+    S G[3] = {Sc<S>::c(0.0), Sc<S>::c(0.0), Sc<S>::c(0.0)};
+    double erow = 0.0;
+    for (int32_t k = b; k < e; ++k) {
+      const Incidence in = inc[k];
+      const AsmRec<S>& r = recs[in.hit];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G[c] = G[c] + r.g[3 * in.slot + c];
+      if (in.slot == 0) erow += r.T;  // each hit's energy is counted at its first vertex
+    }
+    grad[3 * v] = G[0];
+    grad[3 * v + 1] = G[1];
+    grad[3 * v + 2] = G[2];
+    esum += erow;
+    if (row_ptr && e > b) {
+      const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
+      const int32_t* cb = colbuf + 6 * (int64_t)b;
+      for (int32_t q = 0; q < nc; ++q) {
+        const int32_t col = cb[q];
+        S B[9];
+#pragma unroll
+        for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
+        for (int32_t k = b; k < e; ++k) {
+          const Incidence in = inc[k];
+          const AsmRec<S>& r = recs[in.hit];
+          for (int l = 0; l < 6; ++l)
+            if (r.vid[l] == col) block_jmj(r, in.slot, l, B);
+        }
+        const int64_t pos = (int64_t)rp + q;
+        if (pos < block_cap) {
+          col_idx[pos] = col;
+#pragma unroll
+          for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
+        } else {
+          status = STATUS_CAPACITY;
+        }
+      }
+    }
+    if (e > b) {
+      cnt[v] = 0;
+      cur[v] = 0;
+    }
+  }
+  if (status) latch(&ctr->status, status);
+  // energy: fixed-order tree in the block, then blocks in order by the last block
+  red[threadIdx.x] = esum;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    blockpart[blockIdx.x] = red[0];
+    __threadfence();
+    last = atomicAdd(&ctr->ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    double E = 0.0;
+    for (unsigned k = 0; k < gridDim.x; ++k) E += blockpart[k];
+    *energy = E;
+    const uint32_t H = ctr->n_hits;
+    if (n_hits) *n_hits = (int64_t)H;
+    if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
+    if (row_ptr) {
+      const int64_t nb = row_ptr[nv];
+      if (n_blocks) *n_blocks = nb;
+      if (nb > block_cap) latch(&ctr->status, STATUS_CAPACITY);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Hessian-vector products
+// ------------------------------------------------------------------------------------------
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_hvp_exact(const double* __restrict__ x, const S* __restrict__ v,
+                                                      const HitGeom* __restrict__ hits, const AsmRec<S>* __restrict__ recs,
+                                                      const Counters* ctr, uint32_t max_hits, double half,
+                                                      S* __restrict__ hv) {
+  using DS = Dual<S>;
+  const uint32_t H = min(ctr->n_hits, max_hits);
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+    const HitGeom g = hits[h];
+    const AsmRec<S>& r = recs[h];
+    V3<S> Xv[6];
+    local_coords<S>(x, r.vid, Xv);
+    V3<DS> X[6];
+    S vv[18];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vv[3 * k + c] = v[3 * (int64_t)r.vid[k] + c];
+      X[k] = V3<DS>{DS{Xv[k].x, vv[3 * k]}, DS{Xv[k].y, vv[3 * k + 1]}, DS{Xv[k].z, vv[3 * k + 2]}};
+    }
+    DS a[18], b[18];
+    interval_grads<DS>(X, g.da, g.db, g.desc, half, a, b);
+    // first-order tangents of t_c^0, t_c^1 along v
+    S t0d = S(0), t1d = S(0);
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+      t0d = t0d + a[k].v * vv[k];
+      t1d = t1d + b[k].v * vv[k];
+    }
+    const DS t0{Sc<S>::c(g.t0), t0d}, t1{Sc<S>::c(g.t1), t1d};
+    const DS two{Sc<S>::c(2.0), S(0)};
+    const DS ca = two * t0 * t1 * t1, cb = two * t1 * t0 * t0;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) hv[18 * (int64_t)h + k] = (ca * a[k] + cb * b[k]).d;
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_hvp_psd(const S* __restrict__ v, const AsmRec<S>* __restrict__ recs,
+                                                    const Counters* ctr, uint32_t max_hits, S* __restrict__ hv) {
+  const uint32_t H = min(ctr->n_hits, max_hits);
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+    const AsmRec<S>& r = recs[h];
+    S av = S(0), bv = S(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const S vk = v[3 * (int64_t)r.vid[k] + c];
+        av = av + r.a[3 * k + c] * vk;
+        bv = bv + r.b[3 * k + c] * vk;
+      }
+    const S ca = r.M[0] * av + r.M[1] * bv, cb = r.M[1] * av + r.M[2] * bv;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) hv[18 * (int64_t)h + k] = ca * r.a[k] + cb * r.b[k];
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_hvp_rows(int64_t nv, const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc, const S* __restrict__ hv,
+                                                     S* __restrict__ out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    S acc[3] = {S(0), S(0), S(0)};
+    for (int32_t k = off[v]; k < off[v + 1]; ++k) {
+      const Incidence in = inc[k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = acc[c] + hv[18 * (int64_t)in.hit + 3 * in.slot + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[3 * v + c] = acc[c];
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_bsr_mv(int64_t n_rows, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx, const S* __restrict__ vals,
+                                                   const S* __restrict__ xin, S* __restrict__ y) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += (int64_t)gridDim.x * blockDim.x) {
+    S acc[3] = {S(0), S(0), S(0)};
+    for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+      const int64_t c = col_idx[k];
+      const S x0 = xin[3 * c], x1 = xin[3 * c + 1], x2 = xin[3 * c + 2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] = acc[i] + vals[9 * (int64_t)k + 3 * i] * x0 +
+                                           vals[9 * (int64_t)k + 3 * i + 1] * x1 + vals[9 * (int64_t)k + 3 * i + 2] * x2;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[3 * r + i] = acc[i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------------------------
+static unsigned grid_for(int64_t n, unsigned cap = 4096) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_fill_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  k_fill_zero_i32<<<grid_for(n), kBlock, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+size_t scan_temp_bytes(int64_t n) {
+  size_t bytes = 0;
+  int32_t* dummy = nullptr;
+  if (rocprim::exclusive_scan(nullptr, bytes, dummy, dummy, 0, (size_t)n, rocprim::plus<int32_t>()) != hipSuccess)
+    return 0;
+  return bytes;
+}
+
+static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  size_t bytes = c->L.scan_tmp_bytes;
+  return rocprim::exclusive_scan(c->ws + c->L.scan_tmp, bytes, in, out, 0, (size_t)n, rocprim::plus<int32_t>(), s);
+}
+
+template <class S>
+static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
+                            int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags, double* pair_T,
+                            int32_t* row_ptr, int32_t* col_idx, S* vals, int64_t block_cap, int64_t* n_blocks,
+                            int64_t* n_hits, hipStream_t s) {
+  const Layout& L = c->L;
+  Counters* ctr = wsp<Counters>(c, L.counters);
+  HitGeom* hits = wsp<HitGeom>(c, L.hits);
+  AsmRec<S>* recs = wsp<AsmRec<S>>(c, L.recs);
+  int32_t* cnt = wsp<int32_t>(c, L.cnt);
+  int32_t* cur = wsp<int32_t>(c, L.cur);
+  int32_t* off = wsp<int32_t>(c, L.off);
+  int32_t* ncol = wsp<int32_t>(c, L.ncol);
+  Incidence* inc = wsp<Incidence>(c, L.inc);
+  int32_t* colbuf = wsp<int32_t>(c, L.colbuf);
+  double* blockpart = wsp<double>(c, L.epart);
+  const uint32_t max_hits = (uint32_t)c->lim.max_hits;
+  const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
+  const int64_t nv = m->n_verts;
+  const bool bsr = row_ptr != nullptr;
+
+  k_eval_init<<<grid_for(3 * nv, 1024), kBlock, 0, s>>>(ctr, m->x, 3 * nv);
+  int32_t* defer = wsp<int32_t>(c, L.defer);
+  stage_begin(c, TTIE_STAGE_SCREEN, s);
+  k_screen<<<grid_for(pair_cap, 2048), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
+                                                       hits, max_hits, defer, ctr, flags, pair_T);
+  stage_end(c, TTIE_STAGE_SCREEN, s);
+  stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
+  k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, hits,
+                                                            max_hits, defer, ctr, flags, pair_T);
+  stage_end(c, TTIE_STAGE_SCREEN_EXACT, s);
+  const unsigned gh = grid_for(c->lim.max_hits, 1024);
+  stage_begin(c, TTIE_STAGE_DERIVS, s);
+  k_derivs<S><<<gh, kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode, half, recs, cnt);
+  stage_end(c, TTIE_STAGE_DERIVS, s);
+  stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
+  hipError_t err = scan_i32(c, cnt, off, nv + 1, s);
+  if (err != hipSuccess) return err;
+  k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, off, cur, inc);
+  k_rows_sort<S><<<grid_for(nv, 2048), kBlock, 0, s>>>(nv, off, inc, recs, colbuf, ncol, bsr ? 1 : 0);
+  if (bsr) {
+    err = scan_i32(c, ncol, row_ptr, nv + 1, s);
+    if (err != hipSuccess) return err;
+  }
+  k_rows_asm<S><<<kRowBlocks, kBlock, 0, s>>>(nv, off, inc, recs, colbuf, bsr ? row_ptr : nullptr, col_idx, vals,
+                                              block_cap, grad, cnt, cur, blockpart, ctr, max_hits, energy, n_blocks,
+                                              n_hits);
+  stage_end(c, TTIE_STAGE_ASSEMBLY, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
+                       int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
+                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
+                       int64_t* n_hits, hipStream_t s) {
+  if (o->precision == TTIE_FP64)
+    return eval_impl<double>(c, m, pairs, n_pairs, pair_capacity, o, energy, (double*)grad, flags, pair_T, row_ptr, col_idx,
+                             (double*)vals, block_capacity, n_blocks, n_hits, s);
+  return eval_impl<float>(c, m, pairs, n_pairs, pair_capacity, o, energy, (float*)grad, flags, pair_T, row_ptr, col_idx,
+                          (float*)vals, block_capacity, n_blocks, n_hits, s);
+}
+
+template <class S>
+static hipError_t hvp_impl(Ctx* c, const ttie_mesh* m, const S* v, S* Hv, int mode, hipStream_t s) {
+  const Layout& L = c->L;
+  Counters* ctr = wsp<Counters>(c, L.counters);
+  const uint32_t max_hits = (uint32_t)c->lim.max_hits;
+  S* hvbuf = wsp<S>(c, L.hvbuf);
+  const unsigned gh = grid_for(c->lim.max_hits, 1024);
+  const double half = c->last_interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
+  stage_begin(c, TTIE_STAGE_HVP, s);
+  if (mode == TTIE_HVP_EXACT)
+    k_hvp_exact<S><<<gh, kBlock, 0, s>>>(m->x, v, wsp<HitGeom>(c, L.hits), wsp<AsmRec<S>>(c, L.recs), ctr, max_hits,
+                                         half, hvbuf);
+  else
+    k_hvp_psd<S><<<gh, kBlock, 0, s>>>(v, wsp<AsmRec<S>>(c, L.recs), ctr, max_hits, hvbuf);
+  k_hvp_rows<S><<<grid_for(m->n_verts, 2048), kBlock, 0, s>>>(m->n_verts, wsp<int32_t>(c, L.off),
+                                                               wsp<Incidence>(c, L.inc), hvbuf, Hv);
+  stage_end(c, TTIE_STAGE_HVP, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_hvp(Ctx* c, const ttie_mesh* m, const void* v, void* Hv, int mode, hipStream_t s) {
+  if (c->last_precision == TTIE_FP64) return hvp_impl<double>(c, m, (const double*)v, (double*)Hv, mode, s);
+  return hvp_impl<float>(c, m, (const float*)v, (float*)Hv, mode, s);
+}
+
+hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                         const void* x, void* y, int precision, hipStream_t s) {
+  if (precision == TTIE_FP64)
+    k_bsr_mv<double><<<grid_for(n_rows, 4096), kBlock, 0, s>>>(n_rows, row_ptr, col_idx, (const double*)vals,
+                                                               (const double*)x, (double*)y);
+  else
+    k_bsr_mv<float><<<grid_for(n_rows, 4096), kBlock, 0, s>>>(n_rows, row_ptr, col_idx, (const float*)vals,
+                                                              (const float*)x, (float*)y);
+  return hipGetLastError();
+}
+
+}  // namespace ttie

@@ -1,0 +1,101 @@
+// Library-internal declarations: the context, the workspace carve-up and the launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ttie.h"
+#include "pair.h"
+
+namespace ttie {
+
+// blocks of the row-assembly kernel (fixed, so the energy partial sums have a fixed order)
+constexpr int kRowBlocks = 512;
+
+// Per-hit assembly record in the evaluation's precision S.
+template <class S>
+struct AsmRec {
+  int32_t vid[6];
+  int32_t pad;
+  int64_t key;
+  double T;
+  S a[18], b[18], g[18];
+  S M[3];
+};
+
+// One vertex incidence of a hit: which hit, which of its six slots, and the hit's pair key
+// (the per-row summation order).
+struct Incidence {
+  int64_t key;
+  int32_t hit;
+  int32_t slot;
+};
+
+// Device counters and scalars at the head of the workspace.
+struct Counters {
+  int32_t status;          // latched TTIE status (first error wins)
+  uint32_t n_hits;         // intersecting pairs found by the last screening
+  uint32_t n_pairs;        // candidates emitted by the last broad phase
+  uint32_t ticket;         // last-block ticket of the row kernel
+  uint32_t bounds[6];      // scene bounds of the broad phase (order-preserving float bits)
+  uint32_t n_defer;        // candidates whose signs need the exact fallback
+};
+
+struct Layout {
+  size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, hvbuf, epart, scan_tmp, scan_tmp_bytes;
+  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_sort_tmp, bvh_sort_tmp_bytes, bvh_nodes, bvh_leafparent,
+      bvh_boxes, bvh_tbox, bvh_visit, bvh_centroid;
+  size_t total;
+};
+
+struct TimerRec {
+  int stage;
+  hipEvent_t start, stop;
+};
+
+struct Ctx {
+  int device;
+  uint32_t timing_mask;
+  TimerRec* timers;        // pending event pairs (library-owned host array)
+  int n_timers, cap_timers;
+  hipEvent_t* event_pool;  // reusable events
+  int n_pool, cap_pool;
+  ttie_limits lim;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  int have_ws;
+  // the last evaluation (for hvp / get_hits)
+  int last_precision;
+  int last_psd;
+  int last_interval;
+  int64_t last_nverts;
+  int last_valid;
+};
+
+template <class T>
+inline T* wsp(Ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+// Stage timers: begin/end record an event pair around the kernels of `stage` when enabled.
+void stage_begin(Ctx* c, int stage, hipStream_t s);
+void stage_end(Ctx* c, int stage, hipStream_t s);
+
+// launchers (return hipSuccess or the first error)
+hipError_t launch_fill_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pairs, int64_t capacity,
+                             int64_t* n_pairs, hipStream_t s);
+hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
+                       int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
+                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
+                       int64_t* n_hits, hipStream_t s);
+hipError_t launch_hvp(Ctx* c, const ttie_mesh* m, const void* v, void* Hv, int mode, hipStream_t s);
+hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                         const void* x, void* y, int precision, hipStream_t s);
+hipError_t launch_init_counters(Ctx* c, hipStream_t s);
+size_t scan_temp_bytes(int64_t n);
+size_t sort_temp_bytes(int64_t n);
+
+}  // namespace ttie

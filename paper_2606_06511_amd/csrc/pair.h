@@ -1,0 +1,384 @@
+// Per-pair device code: Moeller screening with exact decisions, and the hand-derived
+// derivatives of the two interval ends.
+//
+// Notation (Sec. 1): T_a = (u0,u1,u2), T_b = (v0,v1,v2); n_a = (u1-u0) x (u2-u0),
+// n_b = (v1-v0) x (v2-v0); D = n_a x n_b spans the intersection line L; t(P) = D.P/|D|.
+// d_k = n_b.(u_k - v0) are T_a's plane sides against T_b, e_k = n_a.(v_k - u0) T_b's
+// against T_a.  Each triangle's cut is a segment with two endpoints, each either a vertex on
+// the other plane or the lerp u_p + lam (u_q - u_p), lam = d_p / (d_p - d_q), on an edge whose
+// ends lie strictly on opposite sides (the appendix's case table).  I_a = [t_a^0, t_a^1] and
+// I_b by min/max, and Eq. 1 gives t_c^0 = t_a^0 - t_b^1, t_c^1 = t_a^1 - t_b^0.
+//
+// Exact flag.  For P on edge (p, q) of T_a and Q on edge (r, s) of T_b (an on-plane vertex p
+// is the edge (p, q) with lam = 0 for any q off the plane), both on L:
+//     det[q-p, r-p, s-p] = D.(Q-P)/|D|^2 * (d_q - d_p) * (e_s - e_r) * |D|... up to a positive
+// factor: substituting p = P - lam (q-p) and r = Q - mu (s-r) leaves det[q-p, Q-P, s-r], and
+// with Q - P parallel to D, (q-p).(D x (s-r)) = (n_b.(q-p)) (n_a.(s-r)) because n_a.(q-p) = 0
+// and n_b.(s-r) = 0.  Hence sign(t(Q) - t(P)) = sign(orient(p,q,r,s)) sign(d_q - d_p)
+// sign(e_s - e_r), where the last two signs are known exactly from the classification.
+// The open interval (t_c^0, t_c^1) contains 0 iff some T_a endpoint lies strictly after
+// some T_b endpoint and some strictly before: four exact orientation signs decide it.
+//
+// Derivatives.  All four endpoints lie on L, so d t(P) = Dh . dP with the line direction
+// Dh = D/|D| held fixed (its variation is orthogonal to Dh and P - Q is parallel to Dh).  For a
+// lerp endpoint  dP = (1-lam) du_p + lam du_q + (u_q - u_p) dlam,
+// dlam = (d_p dd_q - d_q dd_p) / (d_p - d_q)^2, and d_x = det[v1-v0, v2-v0, x-v0] has partials
+// n_b (x), (v2-v0) x (x-v0) (v1), (x-v0) x (v1-v0) (v2) and minus their sum (v0).  So each
+// endpoint adds 3-vectors at five vertex slots; a = dt_c^0 and b = dt_c^1 are two such sums.
+#pragma once
+
+#include "device_math.h"
+#include "predicates.h"
+
+namespace ttie {
+
+enum { PAIR_NONE = 0, PAIR_HIT = 1, PAIR_ADJACENT = 2, PAIR_BAD_FRAME = 3, PAIR_DEFER = 4 };
+enum { STATUS_OK = 0, STATUS_INDEX = 2, STATUS_NONFINITE = 3, STATUS_CAPACITY = 4, STATUS_UNSUPPORTED = 7 };
+
+// Geometry of a screened pair: kept for every intersecting pair.
+struct HitGeom {
+  int64_t key;      // (i << 32) | j
+  int32_t pair;     // index into the candidate list
+  uint32_t desc;    // endpoint descriptors and min/max picks
+  double t0, t1;    // Eq. 1 interval ends (already scaled for the appendix half)
+  double da[3];     // d_k = n_b.(u_k - v0) as used by the lerps
+  double db[3];     // e_k = n_a.(v_k - u0)
+};
+
+// Descriptor layout: endpoint k (0,1) of cut c (0 = T_a on plane b, 1 = T_b on plane a) at
+// bit 8c + 4k: vertex p in bits 0-1, q in bits 2-3 (q = 3: the endpoint is vertex p itself).
+// Bits 16..19: which endpoint is the min of I_a, the max of I_a, the min of I_b, the max of
+// I_b.
+__device__ __forceinline__ int desc_p(uint32_t d, int c, int k) { return (d >> (8 * c + 4 * k)) & 3; }
+__device__ __forceinline__ int desc_q(uint32_t d, int c, int k) { return (d >> (8 * c + 4 * k + 2)) & 3; }
+__device__ __forceinline__ int desc_pick(uint32_t d, int which) { return (d >> (16 + which)) & 1; }
+
+struct Cut {
+  int s[3];        // exact side signs
+  int p[2], q[2];  // q = 3: on-plane vertex
+  int straddle;
+};
+
+// The appendix's case table: lone vertex k on its side gives the edges (k, k+1) and (k, k+2)
+// in index order; one vertex on the plane gives that vertex and the crossing of the
+// opposite edge.
+__device__ __forceinline__ Cut make_cut(int s0, int s1, int s2) {
+  Cut c;
+  c.s[0] = s0; c.s[1] = s1; c.s[2] = s2;
+  const int pos = (s0 > 0) + (s1 > 0) + (s2 > 0);
+  const int neg = (s0 < 0) + (s1 < 0) + (s2 < 0);
+  c.straddle = pos > 0 && neg > 0;
+  c.p[0] = c.p[1] = 0;
+  c.q[0] = c.q[1] = 3;
+  if (!c.straddle) return c;
+  if (pos == 2 || neg == 2) {
+    const int lone = pos == 2 ? -1 : 1;
+    const int k = s0 == lone ? 0 : (s1 == lone ? 1 : 2);
+    c.p[0] = k; c.q[0] = k == 0 ? 1 : 0;
+    c.p[1] = k; c.q[1] = k == 2 ? 1 : 2;
+  } else {
+    const int k = s0 == 0 ? 0 : (s1 == 0 ? 1 : 2);
+    c.p[0] = k; c.q[0] = 3;
+    // crossing of the opposite edge, written from the next vertex as the appendix does:
+    // vertex 0 on the plane -> (1,2); vertex 1 -> (2,0); vertex 2 -> (0,1)
+    c.p[1] = (k + 1) % 3; c.q[1] = (k + 2) % 3;
+  }
+  return c;
+}
+
+struct Tri64 {
+  double p[3][3];
+};
+
+// exact plane sides of the three vertices of `cut` against the plane of `pl`.  Without
+// kExact a sign the FP64 filter cannot certify returns false (the pair is deferred).
+template <bool kExact>
+__device__ __forceinline__ bool plane_sides(const Tri64& pl, const Tri64& cut, int s[3], double d[3], int& status) {
+  const V3<double> o{pl.p[0][0], pl.p[0][1], pl.p[0][2]};
+  const V3<double> e1 = V3<double>{pl.p[1][0], pl.p[1][1], pl.p[1][2]} - o;
+  const V3<double> e2 = V3<double>{pl.p[2][0], pl.p[2][1], pl.p[2][2]} - o;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const V3<double> w = V3<double>{cut.p[k][0], cut.p[k][1], cut.p[k][2]} - o;
+    double det, bound;
+    orient_fp64(e1, e2, w, det, bound);
+    if (fabs(det) > bound) {
+      s[k] = det > 0 ? 1 : -1;
+      d[k] = det;
+    } else {
+      if (!kExact) return false;
+      OrientResult r = orient_exact(pl.p[0], pl.p[1], pl.p[2], cut.p[k]);
+      if (r.overflow) status = STATUS_UNSUPPORTED;
+      s[k] = r.sign;
+      d[k] = r.value;
+    }
+  }
+  return true;
+}
+
+// register selects: the candidates are passed by value so that a runtime index becomes a
+// conditional move instead of a runtime address into a local array (which spills it)
+__device__ __forceinline__ int pick(int a, int b, int c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+__device__ __forceinline__ double pick(double a, double b, double c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+__device__ __forceinline__ int seli(const int (&a)[3], int i) { return pick(a[0], a[1], a[2], i); }
+__device__ __forceinline__ double seld(const double (&a)[3], int i) { return pick(a[0], a[1], a[2], i); }
+__device__ __forceinline__ V3<double> selv(const Tri64& T, int i) {
+  return V3<double>{pick(T.p[0][0], T.p[1][0], T.p[2][0], i), pick(T.p[0][1], T.p[1][1], T.p[2][1], i),
+                    pick(T.p[0][2], T.p[1][2], T.p[2][2], i)};
+}
+
+// the vertex paired with an on-plane vertex to form a degenerate edge: any vertex off the plane
+__device__ __forceinline__ int partner(const Cut& c, int k) {
+  const int p = k == 0 ? c.p[0] : c.p[1], q = k == 0 ? c.q[0] : c.q[1];
+  return q != 3 ? q : (seli(c.s, (p + 1) % 3) != 0 ? (p + 1) % 3 : (p + 2) % 3);
+}
+
+// sign of orient(p, q, r, s) = det[q-p, r-p, s-p]; 2 when only the exact path could tell
+// and kExact is off
+template <bool kExact>
+__device__ __forceinline__ int orient_sign(const V3<double>& p, const V3<double>& q, const V3<double>& r,
+                                           const V3<double>& s, int& status) {
+  double det, bound;
+  orient_fp64(q - p, r - p, s - p, det, bound);
+  if (fabs(det) > bound) return det > 0 ? 1 : -1;
+  if (!kExact) return 2;
+  const double P[3] = {p.x, p.y, p.z}, Q[3] = {q.x, q.y, q.z}, R[3] = {r.x, r.y, r.z}, S[3] = {s.x, s.y, s.z};
+  OrientResult o = orient_exact(P, Q, R, S);
+  if (o.overflow) status = STATUS_UNSUPPORTED;
+  return o.sign;
+}
+
+struct Screen {
+  int kind;  // PAIR_*
+  uint32_t desc;
+  double t0, t1;
+  double da[3], db[3];
+};
+
+// Full screening of one non-adjacent pair in FP64 with exact decisions.  Without kExact,
+// a pair needing the exact fallback for any sign comes back as PAIR_DEFER.
+template <bool kExact>
+__device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, double half, int& status) {
+  Screen out;
+  out.kind = PAIR_NONE;
+  out.desc = 0;
+  out.t0 = out.t1 = 0.0;
+  int sa[3], sb[3];
+  // T_a cut by the plane of T_b first, as the appendix does
+  if (!plane_sides<kExact>(B, A, sa, out.da, status)) {
+    out.kind = PAIR_DEFER;
+    return out;
+  }
+  const Cut ca = make_cut(sa[0], sa[1], sa[2]);
+  if (!ca.straddle) return out;
+  if (!plane_sides<kExact>(A, B, sb, out.db, status)) {
+    out.kind = PAIR_DEFER;
+    return out;
+  }
+  const Cut cb = make_cut(sb[0], sb[1], sb[2]);
+  if (!cb.straddle) return out;
+
+  // exact flag from four orientation signs
+  bool after = false, before = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int p = ca.p[i], q = partner(ca, i);
+    const V3<double> P = selv(A, p), Q = selv(A, q);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = cb.p[j], s = partner(cb, j);
+      // sign(t(Q) - t(P)) = sign(orient(p,q,r,s)) * sign(d_q - d_p) * sign(e_s - e_r)
+      const int o = orient_sign<kExact>(P, Q, selv(B, r), selv(B, s), status);
+      if (o == 2) {
+        out.kind = PAIR_DEFER;
+        return out;
+      }
+      const int tau = o * seli(ca.s, q) * seli(cb.s, s);
+      after |= tau < 0;   // t(P) > t(Q)
+      before |= tau > 0;  // t(P) < t(Q)
+    }
+  }
+  if (!(after && before)) return out;
+
+  // FP64 interval ends on pair-local coordinates (origin u0)
+  const V3<double> o = selv(A, 0);
+  const V3<double> na = cross(selv(A, 1) - o, selv(A, 2) - o);
+  const V3<double> nb = cross(selv(B, 1) - selv(B, 0), selv(B, 2) - selv(B, 0));
+  const V3<double> D = cross(na, nb);
+  const double len = sqrt(dot(D, D));
+  double ta[2], tb[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    V3<double> P = selv(A, ca.p[k]) - o;
+    if (ca.q[k] != 3) {
+      const double dp = seld(out.da, ca.p[k]), dq = seld(out.da, ca.q[k]);
+      P = P + (dp / (dp - dq)) * (selv(A, ca.q[k]) - selv(A, ca.p[k]));
+    }
+    ta[k] = dot(D, P);
+    V3<double> Q = selv(B, cb.p[k]) - o;
+    if (cb.q[k] != 3) {
+      const double ep = seld(out.db, cb.p[k]), eq = seld(out.db, cb.q[k]);
+      Q = Q + (ep / (ep - eq)) * (selv(B, cb.q[k]) - selv(B, cb.p[k]));
+    }
+    tb[k] = dot(D, Q);
+  }
+  // min/max keep the first argument on ties
+  const int amin = ta[1] < ta[0] ? 1 : 0, amax = ta[1] > ta[0] ? 1 : 0;
+  const int bmin = tb[1] < tb[0] ? 1 : 0, bmax = tb[1] > tb[0] ? 1 : 0;
+  uint32_t desc = 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    desc |= (uint32_t)(ca.p[k] | (ca.q[k] << 2)) << (4 * k);
+    desc |= (uint32_t)(cb.p[k] | (cb.q[k] << 2)) << (8 + 4 * k);
+  }
+  desc |= (uint32_t)amin << 16 | (uint32_t)amax << 17 | (uint32_t)bmin << 18 | (uint32_t)bmax << 19;
+  out.desc = desc;
+  if (!(len > 0.0)) {
+    out.kind = PAIR_BAD_FRAME;
+    return out;
+  }
+  const double inv = half / len;
+  out.t0 = ((amin ? ta[1] : ta[0]) - (bmax ? tb[1] : tb[0])) * inv;
+  out.t1 = ((amax ? ta[1] : ta[0]) - (bmin ? tb[1] : tb[0])) * inv;
+  out.kind = PAIR_HIT;
+  return out;
+}
+
+// ------------------------------------------------------------------------------------------
+// Derivatives of t_c^0 and t_c^1 (a and b, 18 each, slots u0,u1,u2,v0,v1,v2) for a hit.
+// X holds pair-local coordinates in scalar S; dstored the FP64 plane sides of the screening.
+// ------------------------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ void add_endpoint(V3<S> out[6], S sgn, int p, int q, const V3<S>* C, const V3<S>* P,
+                                             const S* d, const V3<S>& n, const V3<S>& Dh, int cs, int ps) {
+  if (q == 3) {
+    out[cs + p] = out[cs + p] + sgn * Dh;
+    return;
+  }
+  const S dp = d[p], dq = d[q];
+  const S den = dp - dq;
+  const S lam = dp / den;
+  const S w = dot(Dh, C[q] - C[p]) / (den * den);
+  const S one = Sc<S>::c(1.0);
+  out[cs + p] = out[cs + p] + sgn * ((one - lam) * Dh - (w * dq) * n);
+  out[cs + q] = out[cs + q] + sgn * (lam * Dh + (w * dp) * n);
+  const V3<S> Y = dp * (C[q] - P[0]) - dq * (C[p] - P[0]);
+  const V3<S> g1 = w * cross(P[2] - P[0], Y);
+  const V3<S> g2 = w * cross(Y, P[1] - P[0]);
+  out[ps + 1] = out[ps + 1] + sgn * g1;
+  out[ps + 2] = out[ps + 2] + sgn * g2;
+  out[ps + 0] = out[ps + 0] - sgn * ((w * den) * n + g1 + g2);
+}
+
+template <class S>
+__device__ __forceinline__ void interval_grads(const V3<S> X[6], const double dstored_a[3], const double dstored_b[3],
+                                               uint32_t desc, double half, S a[18], S b[18]) {
+  const V3<S>* U = X;
+  const V3<S>* V = X + 3;
+  const V3<S> na = cross(U[1] - U[0], U[2] - U[0]);
+  const V3<S> nb = cross(V[1] - V[0], V[2] - V[0]);
+  const V3<S> D = cross(na, nb);
+  const S len = Sc<S>::sqrt_(dot(D, D));
+  const V3<S> Dh = (Sc<S>::c(1.0) / len) * D;
+  S da[3], db[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    // the screening's values (exact where the filter failed); tangents from the formula
+    da[k] = Sc<S>::with_value(dot(nb, U[k] - V[0]), dstored_a[k]);
+    db[k] = Sc<S>::with_value(dot(na, V[k] - U[0]), dstored_b[k]);
+  }
+  V3<S> ga[6], gb[6];
+  const S zero = Sc<S>::c(0.0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ga[k] = gb[k] = V3<S>{zero, zero, zero};
+  const S pos = Sc<S>::c(half), neg = Sc<S>::c(-half);
+  const int amin = desc_pick(desc, 0), amax = desc_pick(desc, 1);
+  const int bmin = desc_pick(desc, 2), bmax = desc_pick(desc, 3);
+  // a = d(t(P_amin) - t(Q_bmax)), b = d(t(P_amax) - t(Q_bmin))
+  add_endpoint(ga, pos, desc_p(desc, 0, amin), desc_q(desc, 0, amin), U, V, da, nb, Dh, 0, 3);
+  add_endpoint(ga, neg, desc_p(desc, 1, bmax), desc_q(desc, 1, bmax), V, U, db, na, Dh, 3, 0);
+  add_endpoint(gb, pos, desc_p(desc, 0, amax), desc_q(desc, 0, amax), U, V, da, nb, Dh, 0, 3);
+  add_endpoint(gb, neg, desc_p(desc, 1, bmin), desc_q(desc, 1, bmin), V, U, db, na, Dh, 3, 0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[3 * k] = ga[k].x; a[3 * k + 1] = ga[k].y; a[3 * k + 2] = ga[k].z;
+    b[3 * k] = gb[k].x; b[3 * k + 1] = gb[k].y; b[3 * k + 2] = gb[k].z;
+  }
+}
+
+// 2x2 core M of the per-pair Hessian J^T M J for each PSD mode (see ttie.h), in FP64.
+__device__ __forceinline__ void hessian_core(int mode, double t0, double t1, double aa, double bb, double ab,
+                                             double M[3]) {
+  const double s = t0 * t1;
+  if (mode == 0) {  // per part
+    const double na = sqrt(aa), nb = sqrt(bb);
+    const bool ok = na > 0.0 && nb > 0.0;
+    M[0] = 2.0 * t1 * t1 + (ok ? 2.0 * fabs(s) * nb / na : 0.0);
+    M[1] = ok ? 2.0 * s : 0.0;
+    M[2] = 2.0 * t0 * t0 + (ok ? 2.0 * fabs(s) * na / nb : 0.0);
+    return;
+  }
+  if (mode == 2) {  // paper-literal
+    M[0] = 2.0 * t1 * t1;
+    M[1] = 8.0 * s * ab > 0.0 ? 4.0 * s : 0.0;
+    M[2] = 2.0 * t0 * t0;
+    return;
+  }
+  M[0] = 2.0 * t1 * t1;
+  M[1] = 4.0 * s;
+  M[2] = 2.0 * t0 * t0;
+  if (mode != 1) return;  // raw Eq. 4
+  // nearest PSD: the non-zero spectrum of J^T M J is that of K = G^1/2 M G^1/2 with the Gram
+  // matrix G = J J^T; clamp K's eigenvalues and map back with the pseudo-inverse root of G.
+  auto eig2 = [](double p, double r, double q, double& l0, double& l1, double& c, double& sn) {
+    const double m = 0.5 * (p + q), h = 0.5 * (p - q);
+    const double rad = sqrt(h * h + r * r);
+    l0 = m + rad;
+    l1 = m - rad;
+    if (rad == 0.0) {
+      c = 1.0; sn = 0.0;
+    } else {  // eigenvector of l0: (h + rad, r) or (r, rad - h), whichever is larger
+      double vx, vy;
+      if (h >= 0) { vx = h + rad; vy = r; } else { vx = r; vy = rad - h; }
+      const double nv = sqrt(vx * vx + vy * vy);
+      c = vx / nv; sn = vy / nv;
+    }
+  };
+  double g0, g1, gc, gs;
+  eig2(aa, ab, bb, g0, g1, gc, gs);
+  const double gmax = fmax(fabs(g0), fabs(g1));
+  const double tol = 1e-14 * gmax;
+  const double r0 = g0 > tol ? sqrt(g0) : 0.0, r1 = g1 > tol ? sqrt(g1) : 0.0;
+  const double i0 = r0 > 0 ? 1.0 / r0 : 0.0, i1 = r1 > 0 ? 1.0 / r1 : 0.0;
+  // R = [[gc, -gs],[gs, gc]] (columns: eigenvectors); root = R diag R^T
+  auto sym = [&](double e0, double e1, double out[3]) {
+    out[0] = gc * gc * e0 + gs * gs * e1;
+    out[1] = gc * gs * (e0 - e1);
+    out[2] = gs * gs * e0 + gc * gc * e1;
+  };
+  double Sq[3], Si[3];
+  sym(r0, r1, Sq);
+  sym(i0, i1, Si);
+  auto mul = [](const double A[3], const double B[3], double C[4]) {  // C = A B (2x2 row-major)
+    C[0] = A[0] * B[0] + A[1] * B[1];
+    C[1] = A[0] * B[1] + A[1] * B[2];
+    C[2] = A[1] * B[0] + A[2] * B[1];
+    C[3] = A[1] * B[1] + A[2] * B[2];
+  };
+  double T[4], K[3];
+  mul(Sq, M, T);  // Sq M
+  K[0] = T[0] * Sq[0] + T[1] * Sq[1];
+  K[1] = T[0] * Sq[1] + T[1] * Sq[2];
+  K[2] = T[2] * Sq[1] + T[3] * Sq[2];
+  double k0, k1, kc, ks;
+  eig2(K[0], K[1], K[2], k0, k1, kc, ks);
+  k0 = fmax(k0, 0.0);
+  k1 = fmax(k1, 0.0);
+  double Kp[3] = {kc * kc * k0 + ks * ks * k1, kc * ks * (k0 - k1), ks * ks * k0 + kc * kc * k1};
+  mul(Si, Kp, T);  // Si K+
+  M[0] = T[0] * Si[0] + T[1] * Si[1];
+  M[1] = T[0] * Si[1] + T[1] * Si[2];
+  M[2] = T[2] * Si[1] + T[3] * Si[2];
+}
+
+}  // namespace ttie

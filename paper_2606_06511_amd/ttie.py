@@ -1,0 +1,258 @@
+"""Thin Python binding of ``libttie.so`` (the C ABI declared in ``include/ttie.h``).
+
+Argument marshalling only: PyTorch provides device memory and the stream, every step of
+the computation runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing or no GPU is visible the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # imported before the library so that it binds to torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttie.so")
+
+TTIE_OK = 0
+STATUS_NAMES = {
+    0: "OK", 1: "INVALID_ARGUMENT", 2: "INDEX_OUT_OF_RANGE", 3: "NONFINITE_INPUT", 4: "CAPACITY",
+    5: "HIP", 6: "NO_DEVICE", 7: "UNSUPPORTED",
+}
+FP64, MIXED = 0, 1
+PSD_PER_PART, PSD_NEAREST, PSD_PAPER_LITERAL, PSD_RAW_EQ4 = 0, 1, 2, 3
+INTERVAL_EQ1, INTERVAL_APPENDIX_HALF = 0, 1
+BROAD_BRUTE, BROAD_LBVH = 0, 1
+HVP_EXACT, HVP_PSD = 0, 1
+PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME = 0, 1, 2, 3
+
+# every function the header declares, with (restype, argtypes)
+_vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+
+
+class Limits(ctypes.Structure):
+    _fields_ = [("max_verts", _i64), ("max_tris", _i64), ("max_pairs", _i64), ("max_hits", _i64),
+                ("max_blocks", _i64)]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("x", _vp), ("n_verts", _i64), ("tris", _vp), ("n_tris", _i64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("psd_mode", ctypes.c_int32), ("interval", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+SIGNATURES = {
+    "ttie_version": (ctypes.c_char_p, []),
+    "ttie_last_error": (ctypes.c_char_p, []),
+    "ttie_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "ttie_destroy": (_i32, [_vp]),
+    "ttie_workspace_size": (_i32, [_vp, ctypes.POINTER(Limits), ctypes.POINTER(_sz)]),
+    "ttie_set_workspace": (_i32, [_vp, ctypes.POINTER(Limits), _vp, _sz, _vp]),
+    "ttie_get_status": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
+    "ttie_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _i64, _vp, _vp]),
+    "ttie_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, ctypes.POINTER(Options), _vp, _vp, _vp,
+                         _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ttie_get_hits": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ttie_hvp": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i32, _vp]),
+    "ttie_bsr_mv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "ttie_set_timing": (_i32, [_vp, ctypes.c_uint32]),
+    "ttie_read_timers": (_i32, [_vp, _i32, _vp, _vp]),
+}
+
+STAGES = ["bp_boxes", "bp_sort", "bp_build", "bp_traverse", "screen", "screen_exact", "derivs", "assembly", "hvp"]
+
+_lib = None
+
+
+class TTIEError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"ttie: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def lib():
+    """Loads libttie.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_06511_amd/build_lib.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != TTIE_OK:
+        raise TTIEError(st, lib().ttie_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version() -> str:
+    return lib().ttie_version().decode()
+
+
+class Context:
+    """A library context on one GPU plus the workspace tensor it runs in."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(lib().ttie_create(device, ctypes.byref(h)))
+        self.handle = h
+        self.workspace = None
+        self.limits = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.ttie_destroy(self.handle)
+            self.handle = None
+
+    def reserve(self, n_verts, n_tris, max_pairs, max_hits=None, max_blocks=None):
+        """Sizes the workspace for meshes up to these sizes (reallocates when they grow)."""
+        if max_hits is None:
+            max_hits = max(1024, min(max_pairs, 1 << 20))
+        if max_blocks is None:
+            max_blocks = 36 * max_hits
+        want = (int(n_verts), int(n_tris), int(max_pairs), int(max_hits), int(max_blocks))
+        if self.limits is not None and all(w <= h for w, h in zip(want, self.limits)):
+            return
+        lim = Limits(*want)
+        nbytes = ctypes.c_size_t()
+        _check(lib().ttie_workspace_size(self.handle, ctypes.byref(lim), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(lib().ttie_set_workspace(self.handle, ctypes.byref(lim), ctypes.c_void_p(aligned), nbytes.value,
+                                        _stream()))
+        self.limits = want
+
+    @staticmethod
+    def _mesh(x, tris):
+        assert x.dtype == torch.float64 and x.is_contiguous() and x.shape[-1] == 3
+        assert tris.dtype == torch.int32 and tris.is_contiguous() and tris.shape[-1] == 3
+        return Mesh(x.data_ptr(), x.shape[0], tris.data_ptr(), tris.shape[0])
+
+    def status(self):
+        st = ctypes.c_int(0)
+        _check(lib().ttie_get_status(self.handle, _stream(), ctypes.byref(st)))
+        return st.value
+
+    def check(self):
+        st = self.status()
+        if st != TTIE_OK:
+            raise TTIEError(st, "reported by a kernel")
+
+    def broadphase(self, x, tris, method=BROAD_LBVH, capacity=None, out=None):
+        """Candidate pairs: returns (pairs (capacity, 2) int32, n_pairs (1,) int64), both on the GPU."""
+        if capacity is None:
+            capacity = self.limits[2]
+        m = self._mesh(x, tris)
+        if out is None:
+            pairs = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=self.device)
+            n = torch.zeros(1, dtype=torch.int64, device=self.device)
+        else:
+            pairs, n = out
+        _check(lib().ttie_broadphase(self.handle, ctypes.byref(m), method, _ptr(pairs), capacity, _ptr(n), _stream()))
+        return pairs, n
+
+    def evaluate(self, x, tris, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1,
+                 hessian=True, flags=False, pair_T=False, out=None):
+        """Energy, gradient and (optionally) the BSR Hessian.  Returns a dict of GPU tensors:
+        energy (1,) f64, grad (N,3), and when hessian: row_ptr, col_idx, vals, n_blocks;
+        n_hits; flags (P,) u8 and pair_T (P,) f64 when asked."""
+        m = self._mesh(x, tris)
+        dev = self.device
+        if n_pairs is None:
+            n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=dev)
+        dt = torch.float64 if precision == FP64 else torch.float32
+        nv = x.shape[0]
+        if out is None:
+            out = {"energy": torch.zeros(1, dtype=torch.float64, device=dev),
+                   "grad": torch.empty((nv, 3), dtype=dt, device=dev),
+                   "n_hits": torch.zeros(1, dtype=torch.int64, device=dev)}
+            if hessian:
+                cap = self.limits[4]
+                out.update(row_ptr=torch.empty(nv + 1, dtype=torch.int32, device=dev),
+                           col_idx=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                           vals=torch.empty((max(cap, 1), 3, 3), dtype=dt, device=dev),
+                           n_blocks=torch.zeros(1, dtype=torch.int64, device=dev))
+            if flags:
+                out["flags"] = torch.empty(pairs.shape[0], dtype=torch.uint8, device=dev)
+            if pair_T:
+                out["pair_T"] = torch.empty(pairs.shape[0], dtype=torch.float64, device=dev)
+        opts = Options(precision, psd, interval, 0)
+        cap = out["col_idx"].shape[0] if hessian else 0
+        _check(lib().ttie_eval(self.handle, ctypes.byref(m), _ptr(pairs), _ptr(n_pairs), pairs.shape[0],
+                               ctypes.byref(opts),
+                               _ptr(out["energy"]), _ptr(out["grad"]), _ptr(out.get("flags")),
+                               _ptr(out.get("pair_T")), _ptr(out.get("row_ptr")) if hessian else None,
+                               _ptr(out.get("col_idx")) if hessian else None,
+                               _ptr(out.get("vals")) if hessian else None, cap,
+                               _ptr(out.get("n_blocks")) if hessian else None, _ptr(out["n_hits"]), _stream()))
+        return out
+
+    def hits(self, capacity=None):
+        """The last evaluation's hits, sorted by (i, j), as numpy arrays (synchronizes)."""
+        import numpy as np
+
+        if capacity is None:
+            capacity = self.limits[3]
+        ij = np.zeros((capacity, 2), np.int32)
+        tc = np.zeros((capacity, 2))
+        T = np.zeros(capacity)
+        a = np.zeros((capacity, 18))
+        b = np.zeros((capacity, 18))
+        n = ctypes.c_int64(0)
+        _check(lib().ttie_get_hits(self.handle, capacity, ij.ctypes.data_as(_vp), tc.ctypes.data_as(_vp),
+                                   T.ctypes.data_as(_vp), a.ctypes.data_as(_vp), b.ctypes.data_as(_vp),
+                                   ctypes.byref(n), _stream()))
+        k = n.value
+        return dict(ij=ij[:k], t=tc[:k], T=T[:k], a=a[:k], b=b[:k])
+
+    def hvp(self, x, tris, v, mode=HVP_EXACT, out=None):
+        """H v at the last evaluation's positions (v in the evaluation's precision)."""
+        m = self._mesh(x, tris)
+        if out is None:
+            out = torch.empty_like(v)
+        _check(lib().ttie_hvp(self.handle, ctypes.byref(m), _ptr(v), _ptr(out), mode, _stream()))
+        return out
+
+    def set_timing(self, stages=None):
+        """Enables the stage timers for the named stages (None: all, []: none)."""
+        names = STAGES if stages is None else stages
+        mask = 0
+        for nm in names:
+            mask |= 1 << STAGES.index(nm)
+        _check(lib().ttie_set_timing(self.handle, mask))
+
+    def read_timers(self):
+        """{stage: (launches, total_ms)} since the last read (synchronizes on the events)."""
+        import numpy as np
+
+        n = np.zeros(len(STAGES), np.int64)
+        ms = np.zeros(len(STAGES))
+        _check(lib().ttie_read_timers(self.handle, len(STAGES), n.ctypes.data_as(_vp), ms.ctypes.data_as(_vp)))
+        return {s: (int(n[k]), float(ms[k])) for k, s in enumerate(STAGES) if n[k] > 0}
+
+    def bsr_mv(self, row_ptr, col_idx, vals, xin, out=None):
+        precision = FP64 if vals.dtype == torch.float64 else MIXED
+        if out is None:
+            out = torch.empty_like(xin)
+        _check(lib().ttie_bsr_mv(self.handle, row_ptr.shape[0] - 1, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                                 _ptr(xin), _ptr(out), precision, _stream()))
+        return out

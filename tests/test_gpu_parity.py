@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: candidate lists, per-pair flags and BSR patterns bit-exact; energy, gradient, Hessian
+values and Hessian-vector products within relative 1e-10 (FP64 path) or 1e-4 (mixed path),
+norm-wise over the global outputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_06511_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_06511_amd import ttie
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = ttie.Context(0)
+    c.reserve(2_200_000, 4_200_000, 4_000_000, max_hits=200_000, max_blocks=4_000_000)
+    return c
+
+
+def _dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _sorted_pairs(pairs, n):
+    p = pairs[: int(n.item())].cpu().numpy()
+    key = p[:, 0].astype(np.int64) << 32 | p[:, 1].astype(np.int64)
+    return p[np.argsort(key)]
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def _bsr_check(out, ref, nv, tol):
+    nb = int(out["n_blocks"].item())
+    rp = out["row_ptr"].cpu().numpy()
+    ci = out["col_idx"][:nb].cpu().numpy()
+    va = out["vals"][:nb].cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(rp, ref["row_ptr"])
+    np.testing.assert_array_equal(ci, ref["col_idx"])
+    assert _rel(va, ref["vals"]) <= tol
+
+
+def _run(ctx, x, tris, pairs, precision, psd=0, interval=0, flags=True):
+    from paper_2606_06511_amd import ttie
+
+    xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
+    out = ctx.evaluate(xd, td, pd, precision=precision, psd=psd, interval=interval, flags=flags, pair_T=flags)
+    assert ctx.status() == ttie.TTIE_OK
+    return out, (xd, td, pd)
+
+
+def _compare_eval(ctx, x, tris, pairs, precision, psd=0, interval=0):
+    from paper_2606_06511_amd import ttie
+
+    tol = FP64_TOL if precision == ttie.FP64 else MIXED_TOL
+    ref = oracle.evaluate(x, tris, pairs, interval=interval, psd=psd)
+    out, dev = _run(ctx, x, tris, pairs, precision, psd, interval)
+    flags = out["flags"].cpu().numpy()
+    np.testing.assert_array_equal(flags, ref["flags"])
+    assert int(out["n_hits"].item()) == len(ref["hit_pair"])
+    E = out["energy"].item()
+    assert abs(E - ref["E"]) <= FP64_TOL * max(abs(ref["E"]), 1e-300) * (1 if precision == ttie.FP64 else 1e3)
+    pT = out["pair_T"].cpu().numpy()
+    assert _rel(pT, ref["T"]) <= FP64_TOL
+    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= tol
+    _bsr_check(out, ref, len(x), tol)
+    # per hit: interval ends and their gradients
+    h = ctx.hits()
+    ij = pairs[ref["hit_pair"]]
+    np.testing.assert_array_equal(h["ij"], ij)
+    assert _rel(h["t"], ref["hit_t"]) <= FP64_TOL
+    assert _rel(h["a"], ref["hit_a"]) <= tol and _rel(h["b"], ref["hit_b"]) <= tol
+    return ref, out, dev
+
+
+# ---------------------------------------------------------------------------------------
+# broad phase
+# ---------------------------------------------------------------------------------------
+def test_brute_force_pairs_two_icospheres(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.two_icospheres(0)
+    ref = oracle.pairs(x, tris, oracle.BROAD_BRUTE)
+    pairs, n = ctx.broadphase(_dev(x, torch.float64), _dev(tris, torch.int32), ttie.BROAD_BRUTE)
+    assert ctx.status() == ttie.TTIE_OK
+    assert int(n.item()) == len(ref) == 3_260_220
+    np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+
+
+@pytest.mark.parametrize("which", ["cloth", "sphere_small", "icospheres"])
+def test_lbvh_pairs(ctx, which):
+    from paper_2606_06511_amd import ttie
+
+    if which == "cloth":
+        x, tris = workloads.folded_cloth(0)
+    elif which == "sphere_small":
+        x, tris = workloads.noisy_sphere(1, n_lon=128, n_bands=65)
+    else:
+        x, tris = workloads.two_icospheres(2)
+    ref = oracle.pairs(x, tris, oracle.BROAD_BOXES)
+    pairs, n = ctx.broadphase(_dev(x, torch.float64), _dev(tris, torch.int32), ttie.BROAD_LBVH)
+    assert ctx.status() == ttie.TTIE_OK
+    assert int(n.item()) == len(ref)
+    np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+
+
+def test_lbvh_capacity_overflow_reports_count(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=64)
+    ref = oracle.pairs(x, tris, oracle.BROAD_BOXES)
+    pairs, n = ctx.broadphase(_dev(x, torch.float64), _dev(tris, torch.int32), ttie.BROAD_LBVH, capacity=100)
+    assert ctx.status() == 4  # TTIE_ERR_CAPACITY latched
+    assert int(n.item()) == len(ref)
+    # the pairs that were written are genuine candidates
+    got = pairs[:100].cpu().numpy()
+    ref_set = set(map(tuple, ref.tolist()))
+    assert all(tuple(p) in ref_set for p in got.tolist())
+
+
+# ---------------------------------------------------------------------------------------
+# evaluation
+# ---------------------------------------------------------------------------------------
+def test_eval_fp64_two_icospheres_brute(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.two_icospheres(0)
+    pairs = oracle.pairs(x, tris, oracle.BROAD_BRUTE)
+    ref, out, _ = _compare_eval(ctx, x, tris, pairs, ttie.FP64)
+    assert len(ref["hit_pair"]) == 180
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_cloth(ctx, precision):
+    x, tris = workloads.folded_cloth(0)
+    pairs = oracle.pairs(x, tris)
+    _compare_eval(ctx, x, tris, pairs, precision)
+
+
+@pytest.mark.parametrize("psd", [0, 1, 2, 3])
+@pytest.mark.parametrize("interval", [0, 1])
+def test_eval_psd_modes_and_interval(ctx, psd, interval):
+    x, tris = workloads.folded_cloth(1, n=64)
+    pairs = oracle.pairs(x, tris)
+    _compare_eval(ctx, x, tris, pairs, 0, psd=psd, interval=interval)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_eval_degenerate_integer_triangles(ctx, seed):
+    # exact-fallback path: every coordinate an integer in {-3..3}
+    import itertools
+
+    x, tris = workloads.integer_grid_triangles(seed, 60)
+    pairs = np.array(list(itertools.combinations(range(len(tris)), 2)), np.int32)
+    ref = oracle.evaluate(x, tris, pairs)
+    out, _ = _run(ctx, x, tris, pairs, 0)
+    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
+    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= FP64_TOL
+
+
+def test_eval_empty_and_ragged(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(2, n=48)
+    pairs = oracle.pairs(x, tris)
+    for n in [0, 1, 255, 257, len(pairs) - 1]:
+        sub = pairs[:n] if n > 0 else np.zeros((1, 2), np.int32)
+        xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(sub, torch.int32)
+        cnt = torch.tensor([n], dtype=torch.int64, device="cuda")
+        out = ctx.evaluate(xd, td, pd, cnt)
+        assert ctx.status() == ttie.TTIE_OK
+        ref = oracle.evaluate(x, tris, pairs[:n]) if n > 0 else None
+        if ref is None:
+            assert out["energy"].item() == 0.0 and int(out["n_blocks"].item()) == 0
+            assert torch.count_nonzero(out["grad"]).item() == 0
+        else:
+            assert abs(out["energy"].item() - ref["E"]) <= FP64_TOL * max(ref["E"], 1e-300)
+            assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= FP64_TOL
+
+
+def test_eval_adjacent_pairs_are_zero(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=16)
+    # every pair including adjacent ones
+    import itertools
+
+    pairs = np.array(list(itertools.combinations(range(len(tris)), 2)), np.int32)
+    ref = oracle.evaluate(x, tris, pairs)
+    out, _ = _run(ctx, x, tris, pairs, ttie.FP64)
+    f = out["flags"].cpu().numpy()
+    np.testing.assert_array_equal(f, ref["flags"])
+    assert np.sum(f == ttie.PAIR_ADJACENT) > 0
+
+
+def test_eval_deterministic(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0)
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    res = []
+    for _ in range(2):
+        pairs, n = ctx.broadphase(xd, td, ttie.BROAD_LBVH)
+        out = ctx.evaluate(xd, td, pairs, n)
+        nb = int(out["n_blocks"].item())
+        res.append((out["energy"].cpu().numpy().tobytes(), out["grad"].cpu().numpy().tobytes(),
+                    out["vals"][:nb].cpu().numpy().tobytes(), out["col_idx"][:nb].cpu().numpy().tobytes()))
+    assert res[0] == res[1]
+
+
+def test_eval_index_out_of_range_is_reported(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=8)
+    pairs = np.array([[0, 5], [1, 10_000]], np.int32)
+    xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
+    ctx.evaluate(xd, td, pd)
+    assert ctx.status() == 2
+
+
+def test_eval_nonfinite_is_reported(ctx):
+    x, tris = workloads.folded_cloth(0, n=8)
+    x[3, 1] = np.nan
+    pairs = np.array([[0, 5]], np.int32)
+    ctx.evaluate(_dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32))
+    assert ctx.status() == 3
+
+
+# ---------------------------------------------------------------------------------------
+# Hessian-vector products
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hvp_exact_and_psd(ctx, precision):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=96)
+    pairs = oracle.pairs(x, tris)
+    out, (xd, td, pd) = _run(ctx, x, tris, pairs, precision)
+    rng = np.random.default_rng(0)
+    v = rng.normal(size=x.shape)
+    v /= np.linalg.norm(v)
+    dt = torch.float64 if precision == 0 else torch.float32
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    hv = ctx.hvp(xd, td, _dev(v, dt), ttie.HVP_EXACT).cpu().numpy()
+    ref = oracle.hvp(x, tris, pairs, v, exact=True)
+    assert _rel(hv, ref) <= tol * 10
+    hp = ctx.hvp(xd, td, _dev(v, dt), ttie.HVP_PSD).cpu().numpy()
+    refp = oracle.hvp(x, tris, pairs, v, exact=False)
+    assert _rel(hp, refp) <= tol
+    # the PSD product equals the assembled matrix applied by the BSR kernel
+    y = ctx.bsr_mv(out["row_ptr"], out["col_idx"], out["vals"], _dev(v, dt)).cpu().numpy()
+    assert _rel(y, refp) <= tol
