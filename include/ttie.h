@@ -128,7 +128,7 @@ ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_hos
  * Writes the canonical candidate set {(i, j) : i < j, no shared vertex index} of the mesh
  * -- for TTIE_BROAD_LBVH restricted to pairs whose closed float64 bounding boxes overlap
  * on all three axes (Sec. 1.2 uses spatial hashing for this step; this is an LBVH over
- * 30-bit Morton codes) -- into pairs (capacity x 2 int32) in an unspecified order, and the
+ * 30-bit Morton codes) -- into pairs (capacity x 2 int32, 8-byte aligned) in an unspecified order, and the
  * number of candidates into *n_pairs (device int64).  When the count exceeds `capacity`
  * only the first `capacity` pairs are written, *n_pairs still receives the full count and
  * TTIE_ERR_CAPACITY is latched.  capacity must not exceed limits.max_pairs. */

@@ -30,8 +30,10 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort
   L.ncol = take(V * 4);
   L.inc = take(6 * H * sizeof(Incidence));
   L.colbuf = take(36 * H * 4);
+  L.cstage = take(36 * H * 4 + 36 * H);  // candidate values, then one flag byte each
   L.hvbuf = take(18 * H * 8);
   L.epart = take(kRowBlocks * 8);
+  L.epart_v = take(V * 8);
   L.scan_tmp_bytes = scan_bytes;
   L.scan_tmp = take(scan_bytes);
   L.bvh_keys = take(T * 4);
@@ -40,12 +42,13 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort
   L.bvh_vals2 = take(T * 4);
   L.bvh_sort_tmp_bytes = sort_bytes;
   L.bvh_sort_tmp = take(sort_bytes);
-  L.bvh_nodes = take(5 * T * 4);
-  L.bvh_leafparent = take(T * 4);
-  L.bvh_boxes = take(2 * T * 6 * 4);
+  L.bvh_boxes = take((2 * T + 64) * 32);  // implicit tree: at most 2T nodes of 32 B
+  L.bvh_leaves = take(T * 64);            // sorted leaf records
   L.bvh_tbox = take(T * 6 * 8);
-  L.bvh_visit = take(T * 4);
   L.bvh_centroid = take(T * 3 * 4);
+  L.bvh_part = take(512 * 6 * 4);
+  L.touched = take(6 * H * 4);
+  L.inc2 = take(6 * H * sizeof(Incidence));
   L.total = o;
   return L;
 }
@@ -225,6 +228,8 @@ ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* d
   hipError_t e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.counters), sizeof(Counters) / 4, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cnt), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cur), limits->max_verts + 1, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.ncol), limits->max_verts + 1, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.epart_v), 2 * (limits->max_verts + 1), s);
   if (e != hipSuccess) return hip_fail(e, "ttie_set_workspace");
   return TTIE_OK;
 }
@@ -252,6 +257,7 @@ ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, in
   if (!n_pairs || (capacity > 0 && !pairs) || capacity < 0)
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad pair output");
   if (capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "capacity exceeds limits.max_pairs");
+  if (((uintptr_t)pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "pairs must be 8-byte aligned");
   if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
     return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
   DeviceGuard g(ctx->device);
@@ -302,9 +308,9 @@ ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij, double* 
   Counters ctr;
   if (e == hipSuccess) e = hipMemcpy(&ctr, ctx->ws + ctx->L.counters, sizeof(ctr), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "ttie_get_hits");
-  const int64_t H = std::min<int64_t>(ctr.n_hits, ctx->lim.max_hits);
-  *count_host = ctr.n_hits;
-  if ((int64_t)ctr.n_hits > capacity) return fail(TTIE_ERR_CAPACITY, "more hits than capacity");
+  const int64_t H = ctr.last_hits;
+  *count_host = H;
+  if (H > capacity) return fail(TTIE_ERR_CAPACITY, "more hits than capacity");
   std::vector<HitGeom> hg(H);
   const bool fp64 = ctx->last_precision == TTIE_FP64;
   const size_t rs = fp64 ? sizeof(AsmRec<double>) : sizeof(AsmRec<float>);

@@ -1,20 +1,21 @@
 // Broad phase: candidate triangle pairs for the per-pair energy (Sec. 1.2 removes redundant
-// pair tests with a spatial structure; this is a linear BVH).
+// pair tests with a spatial structure; this is a linear BVH over Morton-sorted triangles).
 //
-//   k_bp_init      reset the pair counter and the scene bounds
-//   k_tri_boxes    exact FP64 bounding box per triangle; centroid bounds (order-preserving
-//                  integer atomics, so the result does not depend on the order)
-//   k_morton       30-bit Morton code of each box centre
+//   k_bp_init      reset the pair counter
+//   k_tri_boxes    exact FP64 bounding box per triangle; per-block bounds of the box centres
+//                  (order-preserving integer keys)
+//   k_morton       reduce those bounds, then a 30-bit Morton code per box centre
 //   radix sort     (code, triangle) pairs by code (rocPRIM), stable
-//   k_build        binary radix tree over the sorted codes (Karras 2012): every internal node
-//                  finds its key range from common-prefix lengths; equal codes are split by
-//                  position, so the tree exists for any input
-//   k_refit        bottom-up FP32 node boxes, rounded outwards from the FP64 leaf boxes; the
-//                  second child to arrive at a node builds it
-//   k_traverse     one lane per leaf, depth-first over the tree, reporting only leaves after
-//                  itself in sorted order (every unordered pair once); a leaf is confirmed by
-//                  the exact closed FP64 box test and the shared-vertex test; pairs are
-//                  appended with one atomic per wave (ballot + popcount)
+//   k_levels       an implicit complete 4-ary tree over the sorted leaves: node (l, k) covers
+//                  leaves [k 4^l, (k+1) 4^l); boxes are reduced level by level in LDS, four
+//                  levels per launch, so building needs no atomics and no fences.  The first
+//                  launch also writes the sorted leaf records (FP64 box, vertex ids).
+//   k_traverse     one lane per leaf s, depth first over the subtrees holding leaves after s,
+//                  four child boxes per visit and a 64-bit mask stack, descending where the
+//                  FP32 boxes (rounded outwards) overlap, so every unordered pair is reported
+//                  once; a leaf is confirmed by the exact closed FP64 box test and the
+//                  shared-vertex test; pairs are staged per wave in LDS (ballot + mbcnt) and
+//                  flushed with one atomic per full buffer
 //   k_brute        all i < j without a shared vertex (no box test)
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -23,8 +24,7 @@
 namespace ttie {
 
 constexpr int kBpBlock = 256;
-constexpr int32_t kLeafBit = (int32_t)0x80000000;
-constexpr int kStack = 64;
+constexpr int kBoundsBlocks = 512;  // partial-bounds slots in the workspace
 
 __device__ __forceinline__ uint32_t f2key(float f) {
   const uint32_t b = __float_as_uint(f);
@@ -37,17 +37,13 @@ __device__ __forceinline__ float key2f(uint32_t k) {
 __global__ void k_bp_init(Counters* c) {
   if (threadIdx.x == 0) {
     c->n_pairs = 0;
-    for (int k = 0; k < 3; ++k) {
-      c->bounds[k] = 0xffffffffu;  // running minimum
-      c->bounds[3 + k] = 0u;       // running maximum
-    }
   }
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict__ x, int64_t nv,
                                                         const int32_t* __restrict__ tris, int64_t nt,
                                                         double* __restrict__ tbox, float* __restrict__ centre,
-                                                        Counters* ctr) {
+                                                        uint32_t* __restrict__ part, Counters* ctr) {
   __shared__ uint32_t smin[3][kBpBlock], smax[3][kBpBlock];
   uint32_t lmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, lmax[3] = {0u, 0u, 0u};
   bool bad = false;
@@ -90,10 +86,11 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
       }
     __syncthreads();
   }
+  // per-block partial bounds; k_morton reduces them (the kernel boundary orders the two)
   if (threadIdx.x == 0)
     for (int c = 0; c < 3; ++c) {
-      atomicMin(&ctr->bounds[c], smin[c][0]);
-      atomicMax(&ctr->bounds[3 + c], smax[c][0]);
+      part[6 * blockIdx.x + c] = smin[c][0];
+      part[6 * blockIdx.x + 3 + c] = smax[c][0];
     }
 }
 
@@ -107,12 +104,31 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
-__global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ centre, int64_t nt, const Counters* ctr,
+__global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ centre, int64_t nt,
+                                                     const uint32_t* __restrict__ part, int nparts,
                                                      uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  // every block reduces the per-block bounds of k_tri_boxes (a few KB, cached): a strided
+  // pass per thread, then a tree in LDS
+  __shared__ uint32_t red[6][kBpBlock];
+  __shared__ uint32_t sb[6];
+  uint32_t v[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
+  for (int b = threadIdx.x; b < nparts; b += kBpBlock)
+    for (int c = 0; c < 6; ++c) v[c] = c < 3 ? min(v[c], part[6 * b + c]) : max(v[c], part[6 * b + c]);
+  for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int w = kBpBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 6; ++c)
+        red[c][threadIdx.x] = c < 3 ? min(red[c][threadIdx.x], red[c][threadIdx.x + w])
+                                    : max(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) sb[threadIdx.x] = red[threadIdx.x][0];
+  __syncthreads();
   float lo[3], inv[3];
   for (int c = 0; c < 3; ++c) {
-    lo[c] = key2f(ctr->bounds[c]);
-    const float ext = key2f(ctr->bounds[3 + c]) - lo[c];
+    lo[c] = key2f(sb[c]);
+    const float ext = key2f(sb[3 + c]) - lo[c];
     inv[c] = ext > 0.f ? 1023.f / ext : 0.f;
   }
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
@@ -126,178 +142,299 @@ __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ c
   }
 }
 
-// length of the common prefix of sorted keys i and j (positions break ties); -1 outside
-__device__ __forceinline__ int prefix(const uint32_t* keys, int n, int i, int j) {
-  if (j < 0 || j >= n) return -1;
-  const uint32_t a = keys[i], b = keys[j];
-  if (a == b) return 32 + __clz((uint32_t)(i ^ j));
-  return __clz(a ^ b);
-}
+// Level geometry of the implicit 4-ary tree: m[l] = ceil(n / 4^l) nodes at level l, stored
+// from off[l]; node (l, k) covers leaves [k 4^l, (k+1) 4^l) and its children are
+// (l-1, 4k .. 4k+3), contiguous in memory; level L (m[L] = 1) is the root.
+struct Levels {
+  int L;
+  int64_t m[24];
+  int64_t off[24];
+};
 
-__global__ void __launch_bounds__(kBpBlock) k_build(const uint32_t* __restrict__ keys, int n, int32_t* __restrict__ left,
-                                                    int32_t* __restrict__ right, int32_t* __restrict__ first,
-                                                    int32_t* __restrict__ last, int32_t* __restrict__ parent,
-                                                    int32_t* __restrict__ leafparent, int32_t* __restrict__ visit) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n - 1; i += gridDim.x * blockDim.x) {
-    // direction of the node's range: towards the neighbour sharing the longer prefix
-    const int d = prefix(keys, n, i, i + 1) > prefix(keys, n, i, i - 1) ? 1 : -1;
-    const int dmin = prefix(keys, n, i, i - d);
-    int lmax = 2;
-    while (prefix(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int l = 0;
-    for (int t = lmax >> 1; t >= 1; t >>= 1)
-      if (prefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
-    const int j = i + l * d;
-    const int dnode = prefix(keys, n, i, j);
-    // split: the last position sharing more than dnode bits with i
-    int s = 0, t = l;
-    do {
-      t = (t + 1) >> 1;
-      if (prefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
-    } while (t > 1);
-    const int g = i + s * d + min(d, 0);
-    const int lo = min(i, j), hi = max(i, j);
-    const int32_t lc = lo == g ? (g | kLeafBit) : g;
-    const int32_t rc = hi == g + 1 ? ((g + 1) | kLeafBit) : g + 1;
-    left[i] = lc;
-    right[i] = rc;
-    first[i] = lo;
-    last[i] = hi;
-    visit[i] = 0;
-    if (lc & kLeafBit) leafparent[lc & ~kLeafBit] = i; else parent[lc] = i;
-    if (rc & kLeafBit) leafparent[rc & ~kLeafBit] = i; else parent[rc] = i;
-    if (i == 0) parent[0] = -1;
-  }
-}
+// FP32 node box, padded to two 16-byte halves
+struct Box32 {
+  float lo[4];
+  float hi[4];
+};
 
-__global__ void __launch_bounds__(kBpBlock) k_refit(const double* __restrict__ tbox, const int32_t* __restrict__ ids,
-                                                    int n, const int32_t* __restrict__ left,
-                                                    const int32_t* __restrict__ right,
-                                                    const int32_t* __restrict__ parent,
-                                                    const int32_t* __restrict__ leafparent, int32_t* visit,
-                                                    float* leafbox, float* nodebox, Counters* ctr) {
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-    const int64_t t = ids[s];
-    for (int c = 0; c < 3; ++c) {
-      leafbox[6 * s + c] = __double2float_rd(tbox[6 * t + c]);
-      leafbox[6 * s + 3 + c] = __double2float_ru(tbox[6 * t + 3 + c]);
-    }
-    __threadfence();
-    int node = leafparent[s];
-    // a radix tree over 62-bit keys is at most 63 levels deep; the cap only guards a
-    // malformed tree from looping
-    for (int level = 0; node >= 0; ++level) {
-      if (level > 2 * kStack) {
-        atomicCAS(&ctr->status, 0, STATUS_CAPACITY);
-        break;
-      }
-      if (atomicAdd(&visit[node], 1) == 0) break;  // first child to arrive: the sibling finishes
-      __threadfence();
-      const int32_t lc = left[node], rc = right[node];
-      const float* bl = (lc & kLeafBit) ? leafbox + 6 * (lc & ~kLeafBit) : nodebox + 6 * lc;
-      const float* br = (rc & kLeafBit) ? leafbox + 6 * (rc & ~kLeafBit) : nodebox + 6 * rc;
-      for (int c = 0; c < 3; ++c) {
-        nodebox[6 * node + c] = fminf(__builtin_nontemporal_load(bl + c), __builtin_nontemporal_load(br + c));
-        nodebox[6 * node + 3 + c] =
-            fmaxf(__builtin_nontemporal_load(bl + 3 + c), __builtin_nontemporal_load(br + 3 + c));
-      }
-      __threadfence();
-      node = parent[node];
-    }
-  }
-}
+// sorted leaf record: the triangle's FP64 box, its vertex ids and its index
+struct LeafRec {
+  double lo[3], hi[3];
+  int32_t v[3];
+  int32_t tri;
+};
 
-__device__ __forceinline__ bool overlap32(const float q[6], const float* b) {
-  return q[0] <= b[3] && b[0] <= q[3] && q[1] <= b[4] && b[1] <= q[4] && q[2] <= b[5] && b[2] <= q[5];
-}
-
-// wave-aggregated append of (a, b) pairs: one atomic per wave
-__device__ __forceinline__ void emit_pair(bool want, int32_t a, int32_t b, int32_t* pairs, int64_t cap, Counters* ctr) {
-  const uint64_t mask = __ballot(want);
-  if (!mask) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(&ctr->n_pairs, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  if (want) {
-    const int64_t slot = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
-    if (slot < cap) {
-      pairs[2 * slot] = min(a, b);
-      pairs[2 * slot + 1] = max(a, b);
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kBpBlock) k_traverse(int n, const int32_t* __restrict__ tris,
-                                                       const double* __restrict__ tbox, const int32_t* __restrict__ ids,
-                                                       const float* __restrict__ leafbox,
-                                                       const float* __restrict__ nodebox,
-                                                       const int32_t* __restrict__ left,
-                                                       const int32_t* __restrict__ right,
-                                                       const int32_t* __restrict__ last, int32_t* pairs, int64_t cap,
-                                                       Counters* ctr) {
-  int status = 0;
-  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const int s = base + threadIdx.x;
-    const bool live = s < n;
-    float q[6];
-    int32_t t = 0, vt[3] = {-1, -1, -1};
-    double qb[6];
-    int stack[kStack];
-    int sp = 0;
-    if (live) {
-      t = ids[s];
-      for (int c = 0; c < 6; ++c) {
-        q[c] = leafbox[6 * s + c];
-        qb[c] = tbox[6 * (int64_t)t + c];
-      }
-      for (int k = 0; k < 3; ++k) vt[k] = tris[3 * (int64_t)t + k];
-      if (s < n - 1) stack[sp++] = 0;  // the root covers every leaf; skip if s is the last
-    }
-    // every lane runs the loop until the whole wave is done, so the ballots converge; a lane
-    // visits each internal node at most once, so n iterations bound a well-formed tree
-    for (int iter = 0; __ballot(sp > 0); ++iter) {
-      if (iter > n + kStack) {
-        status = STATUS_CAPACITY;
-        break;
-      }
-      int node = -1;
-      if (sp > 0) node = stack[--sp];
+__device__ __forceinline__ Box32 box_union(const Box32& a, const Box32& b) {
+  Box32 r;
 #pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        bool want = false;
-        int32_t t2 = 0;
-        if (node >= 0) {
-          const int32_t ch = side == 0 ? left[node] : right[node];
-          if (ch & kLeafBit) {
-            const int pos = ch & ~kLeafBit;
-            if (pos > s && overlap32(q, leafbox + 6 * pos)) {
-              t2 = ids[pos];
-              const double* b = tbox + 6 * (int64_t)t2;
-              bool ov = true;
-              for (int c = 0; c < 3; ++c) ov = ov && qb[c] <= b[3 + c] && b[c] <= qb[3 + c];
-              bool adj = false;
-              for (int k = 0; k < 3; ++k) {
-                const int32_t w = tris[3 * (int64_t)t2 + k];
-                adj |= w == vt[0] || w == vt[1] || w == vt[2];
-              }
-              want = ov && !adj;
-            }
-          } else if (last[ch] > s && overlap32(q, nodebox + 6 * ch)) {
-            if (sp < kStack) stack[sp++] = ch;
-            else status = STATUS_CAPACITY;
-          }
-        }
-        emit_pair(want, t, t2, pairs, cap, ctr);
+  for (int c = 0; c < 4; ++c) {
+    r.lo[c] = fminf(a.lo[c], b.lo[c]);
+    r.hi[c] = fmaxf(a.hi[c], b.hi[c]);
+  }
+  return r;
+}
+
+// Reduces levels l0+1 .. l0+4 from the boxes of level l0 (l0 = 0: made from the sorted
+// leaves, which are written too).  Block b owns level-l0 nodes [256 b, 256 b + 256).
+__global__ void __launch_bounds__(kBpBlock) k_levels(int l0, Levels lv, const double* __restrict__ tbox,
+                                                     const int32_t* __restrict__ ids,
+                                                     const int32_t* __restrict__ tris, Box32* __restrict__ boxes,
+                                                     LeafRec* __restrict__ leaves) {
+  __shared__ Box32 sh[kBpBlock];
+  const int64_t k = (int64_t)blockIdx.x * kBpBlock + threadIdx.x;
+  Box32 bx;
+  for (int c = 0; c < 4; ++c) {
+    bx.lo[c] = 3.0e38f;
+    bx.hi[c] = -3.0e38f;
+  }
+  if (k < lv.m[l0]) {
+    if (l0 == 0) {
+      const int32_t t = ids[k];
+      LeafRec r;
+      for (int c = 0; c < 3; ++c) {
+        r.lo[c] = tbox[6 * (int64_t)t + c];
+        r.hi[c] = tbox[6 * (int64_t)t + 3 + c];
+        bx.lo[c] = __double2float_rd(r.lo[c]);
+        bx.hi[c] = __double2float_ru(r.hi[c]);
+        r.v[c] = tris[3 * (int64_t)t + c];
+      }
+      r.tri = t;
+      leaves[k] = r;
+      boxes[lv.off[0] + k] = bx;
+    } else {
+      bx = boxes[lv.off[l0] + k];
+    }
+  }
+  sh[threadIdx.x] = bx;
+  __syncthreads();
+  for (int j = 1; j <= 4 && l0 + j <= lv.L; ++j) {
+    const int cnt = kBpBlock >> (2 * j);
+    Box32 r;
+    const bool act = threadIdx.x < cnt;
+    if (act) r = box_union(box_union(sh[4 * threadIdx.x], sh[4 * threadIdx.x + 1]),
+                           box_union(sh[4 * threadIdx.x + 2], sh[4 * threadIdx.x + 3]));
+    __syncthreads();
+    if (act) {
+      sh[threadIdx.x] = r;
+      const int64_t node = (int64_t)blockIdx.x * cnt + threadIdx.x;
+      if (node < lv.m[l0 + j]) boxes[lv.off[l0 + j] + node] = r;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool overlap32(const float q[6], const Box32& b) {
+  return q[0] <= b.hi[0] && b.lo[0] <= q[3] && q[1] <= b.hi[1] && b.lo[1] <= q[4] && q[2] <= b.hi[2] &&
+         b.lo[2] <= q[5];
+}
+
+// Per-wave LDS staging of emitted pairs.  Each step every lane of the wave offers at most one
+// pair; positions come from a ballot and the lanes below (mbcnt), so the staging needs no
+// atomics.  Only a flush -- when the wave's buffer is nearly full, and once at the end --
+// reserves global space, with one atomic for the whole buffer.
+constexpr int kEmitCap = 512;
+
+struct WaveEmitter {
+  int2* buf;       // this wave's kEmitCap slots in LDS
+  int count;       // wave-uniform fill level
+
+  __device__ __forceinline__ void flush(int32_t* pairs, int64_t cap, Counters* ctr) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int lane = __lane_id();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&ctr->n_pairs, (uint32_t)count);
+    base = __shfl(base, 0);
+    for (int i = lane; i < count; i += 64) {
+      const int64_t slot = (int64_t)base + i;
+      if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = buf[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    count = 0;
+  }
+
+  __device__ __forceinline__ void push(bool want, int32_t a, int32_t b, int32_t* pairs, int64_t cap, Counters* ctr) {
+    const uint64_t mask = __ballot(want);
+    if (!mask) return;
+    if (want) {
+      const int lane = __lane_id();
+      buf[count + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2(min(a, b), max(a, b));
+    }
+    count += __popcll(mask);
+    if (count > kEmitCap - 64) flush(pairs, cap, ctr);
+  }
+};
+
+// Blocks are dealt to the XCDs round-robin; renumbering them so that each XCD runs a
+// contiguous range of logical blocks keeps each XCD's L2 on one region of the Morton order.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t per = nblocks / 8;
+  return (b % 8) * per + b / 8;
+}
+
+// One lane per leaf s: depth-first over the subtrees holding leaves after s.  A visited node
+// tests its four children at once (one contiguous load); the pending children of every level
+// on the current path are kept as 4-bit masks in one 64-bit word, so no stack is needed.
+// Block b's 256 queries are exactly the leaves of the level-4 node b, so that subtree (leaf
+// records, leaf boxes and the 84 boxes above them) is staged in LDS first and most visits
+// never leave the CU; only right-hand neighbours outside it are read from global memory.
+constexpr int kSubLevels = 4;                       // 4^4 = 256 = kBpBlock leaves per block
+constexpr int kSubInner = 64 + 16 + 4;              // boxes of levels 1..3 inside the subtree
+
+__global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
+                                                       const LeafRec* __restrict__ leaves, int32_t* pairs,
+                                                       int64_t cap, Counters* ctr) {
+  __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+  __shared__ int64_t lm[24], loff[24];  // the level table, indexed by each lane's own level
+  __shared__ int wcount[kBpBlock / 64];
+  __shared__ uint32_t bbase;
+  __shared__ LeafRec sleaf[kBpBlock];
+  __shared__ Box32 sbox[kBpBlock + kSubInner];     // level 0 at [0,256), level 1 at 256.., 2, 3
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  if (threadIdx.x < 24) {
+    lm[threadIdx.x] = lv.m[threadIdx.x];
+    loff[threadIdx.x] = lv.off[threadIdx.x];
+  }
+  // stage the block's subtree
+  const int64_t s = blk * kBpBlock + threadIdx.x;
+  if (s < n) {
+    sleaf[threadIdx.x] = leaves[s];
+    sbox[threadIdx.x] = boxes[s];
+  }
+  {
+    const int t = threadIdx.x;
+    int l = 0, local = 0, base = kBpBlock;  // thread t < 84 loads inner box t
+    if (t < 64) { l = 1; local = t; base = kBpBlock; }
+    else if (t < 80) { l = 2; local = t - 64; base = kBpBlock + 64; }
+    else if (t < 84) { l = 3; local = t - 80; base = kBpBlock + 80; }
+    if (l > 0 && l <= lv.L) {
+      const int64_t k = (blk << (2 * (kSubLevels - l))) + local;
+      if (k < lv.m[l]) sbox[base + local] = boxes[lv.off[l] + k];
+    }
+  }
+  __syncthreads();
+  // node (l, k) lies in the staged subtree when l < 4 and k >> 2(4-l) == blk
+
+  WaveEmitter em{stage[threadIdx.x / 64], 0};
+  int status = 0;
+  bool active = s < n;
+  float q[6];
+  LeafRec me;
+  int l = lv.L;
+  int64_t k = 0;
+  uint64_t pend = 0;  // level j's remaining children at bits [4(j-1), 4j)
+  if (active) {
+    me = sleaf[threadIdx.x];
+    const Box32 b = sbox[threadIdx.x];
+    for (int c = 0; c < 3; ++c) {
+      q[c] = b.lo[c];
+      q[3 + c] = b.hi[c];
+    }
+  }
+  // every node is visited at most once; the cap only guards against corruption
+  for (int64_t iter = 0; __ballot(active); ++iter) {
+    if (iter > 2 * n + 64) {
+      status = STATUS_CAPACITY;
+      break;
+    }
+    uint32_t mask = 0;
+    int64_t c0 = 0;
+    bool local_children = false;
+    if (active) {
+      // children of (l, k): (l-1, 4k+i); only those holding leaves after s
+      c0 = 4 * k;
+      const int lc = l - 1;
+      const int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
+      const int64_t mcount = lm[lc];
+      local_children = lc < kSubLevels && (c0 >> (2 * (kSubLevels - lc))) == blk;
+      Box32 cb[4];
+      if (local_children) {
+        const int lb = (lc == 0 ? 0 : (lc == 1 ? kBpBlock : (lc == 2 ? kBpBlock + 64 : kBpBlock + 80)));
+        const int64_t li = c0 - (blk << (2 * (kSubLevels - lc)));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cb[i] = sbox[lb + li + i];
+      } else {
+        const Box32* g = boxes + loff[lc] + c0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (c0 + i < mcount) cb[i] = g[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t c = c0 + i;
+        if (c < mcount && c >= first && overlap32(q, cb[i])) mask |= 1u << i;
       }
     }
+    // leaves: exact FP64 box test and the shared-vertex test, four candidates per visit
+    const bool leaf_level = active && l == 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bool want = false;
+      int32_t other = 0;
+      if (leaf_level && (mask & (1u << i))) {
+        const LeafRec o = local_children ? sleaf[c0 + i - blk * kBpBlock] : leaves[c0 + i];
+        bool exact = true;
+        for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o.hi[c] && o.lo[c] <= me.hi[c];
+        bool adj = false;
+        for (int a2 = 0; a2 < 3; ++a2)
+          for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o.v[b2];
+        want = exact && !adj;
+        other = o.tri;
+      }
+      em.push(want, me.tri, other, pairs, cap, ctr);
+    }
+    if (active) {
+      if (leaf_level) mask = 0;
+      if (mask) {
+        // descend into the first child; the others wait in this level's slot
+        const int i = __builtin_ctz(mask);
+        pend |= (uint64_t)(mask & ~(1u << i)) << (4 * (l - 1));
+        --l;
+        k = c0 + i;
+      } else {
+        // climb to the nearest level with a pending child and move to that child
+        for (;;) {
+          if (l >= lv.L) {
+            active = false;
+            break;
+          }
+          const uint32_t pm = (uint32_t)(pend >> (4 * l)) & 15u;
+          if (pm) {
+            const int i = __builtin_ctz(pm);
+            pend &= ~(1ull << (4 * l + i));
+            k = ((k >> 2) << 2) + i;
+            break;
+          }
+          ++l;
+          k >>= 2;
+        }
+      }
+    }
+  }
+  // block-level final flush: one atomic reserves the space of all four waves
+  const int wave = threadIdx.x / 64;
+  if (__lane_id() == 0) wcount[wave] = em.count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kBpBlock / 64; ++w) tot += wcount[w];
+    bbase = tot ? atomicAdd(&ctr->n_pairs, tot) : 0u;
+  }
+  __syncthreads();
+  int64_t mybase = bbase;
+  for (int w = 0; w < wave; ++w) mybase += wcount[w];
+  for (int i = __lane_id(); i < em.count; i += 64) {
+    const int64_t slot = mybase + i;
+    if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = em.buf[i];
   }
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ tris, int64_t nt, int32_t* pairs,
                                                     int64_t cap, Counters* ctr) {
+  __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+  WaveEmitter em{stage[threadIdx.x / 64], 0};
   for (int64_t i = blockIdx.y; i < nt; i += gridDim.y) {
     int32_t vi[3];
     for (int k = 0; k < 3; ++k) vi[k] = tris[3 * i + k];
@@ -312,9 +449,10 @@ __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ 
         }
         want = !adj;
       }
-      emit_pair(want, (int32_t)i, (int32_t)j, pairs, cap, ctr);
+      em.push(want, (int32_t)i, (int32_t)j, pairs, cap, ctr);
     }
   }
+  if (em.count > 0) em.flush(pairs, cap, ctr);
 }
 
 __global__ void k_bp_finish(Counters* ctr, int64_t cap, int64_t* n_pairs) {
@@ -340,6 +478,21 @@ static unsigned bp_grid(int64_t n, unsigned cap = 4096) {
   return (unsigned)g;
 }
 
+Levels make_levels(int64_t n) {
+  Levels lv{};
+  int64_t off = 0, m = n;
+  int l = 0;
+  for (;; ++l) {
+    lv.m[l] = m;
+    lv.off[l] = off;
+    off += m;
+    if (m <= 1) break;
+    m = (m + 3) / 4;
+  }
+  lv.L = l;
+  return lv;
+}
+
 hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pairs, int64_t capacity,
                              int64_t* n_pairs, hipStream_t s) {
   const Layout& L = c->L;
@@ -358,32 +511,29 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pa
     uint32_t* k2 = wsp<uint32_t>(c, L.bvh_keys2);
     int32_t* v1 = wsp<int32_t>(c, L.bvh_vals);
     int32_t* v2 = wsp<int32_t>(c, L.bvh_vals2);
-    int32_t* nodes = wsp<int32_t>(c, L.bvh_nodes);
-    const int n = (int)nt;
-    int32_t *left = nodes, *right = nodes + n, *first = nodes + 2 * (int64_t)n, *last = nodes + 3 * (int64_t)n,
-            *parent = nodes + 4 * (int64_t)n;
-    int32_t* leafparent = wsp<int32_t>(c, L.bvh_leafparent);
-    int32_t* visit = wsp<int32_t>(c, L.bvh_visit);
-    float* boxes = wsp<float>(c, L.bvh_boxes);
-    float* nodebox = boxes;
-    float* leafbox = boxes + 6 * (int64_t)n;
+    Box32* boxes = wsp<Box32>(c, L.bvh_boxes);
+    LeafRec* leaves = wsp<LeafRec>(c, L.bvh_leaves);
+    const Levels lv = make_levels(nt);
     stage_begin(c, TTIE_STAGE_BP_BOXES, s);
-    k_tri_boxes<<<bp_grid(nt, 1024), kBpBlock, 0, s>>>(m->x, m->n_verts, m->tris, nt, tbox, centre, ctr);
-    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, ctr, k1, v1);
+    const unsigned gb = bp_grid(nt, kBoundsBlocks);
+    k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, m->n_verts, m->tris, nt, tbox, centre, wsp<uint32_t>(c, L.bvh_part),
+                                        ctr);
+    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, k1, v1);
     stage_end(c, TTIE_STAGE_BP_BOXES, s);
     size_t bytes = L.bvh_sort_tmp_bytes;
     stage_begin(c, TTIE_STAGE_BP_SORT, s);
-    hipError_t e = rocprim::radix_sort_pairs(c->ws + L.bvh_sort_tmp, bytes, k1, k2, v1, v2, (unsigned)n, 0, 30, s);
+    hipError_t e = rocprim::radix_sort_pairs(c->ws + L.bvh_sort_tmp, bytes, k1, k2, v1, v2, (unsigned)nt, 0, 30, s);
     stage_end(c, TTIE_STAGE_BP_SORT, s);
     if (e != hipSuccess) return e;
     stage_begin(c, TTIE_STAGE_BP_BUILD, s);
-    k_build<<<bp_grid(n - 1), kBpBlock, 0, s>>>(k2, n, left, right, first, last, parent, leafparent, visit);
-    k_refit<<<bp_grid(n), kBpBlock, 0, s>>>(tbox, v2, n, left, right, parent, leafparent, visit, leafbox, nodebox,
-                                             ctr);
+    for (int l0 = 0; l0 < lv.L; l0 += 4)
+      k_levels<<<(unsigned)((lv.m[l0] + kBpBlock - 1) / kBpBlock), kBpBlock, 0, s>>>(l0, lv, tbox, v2, m->tris, boxes,
+                                                                                    leaves);
     stage_end(c, TTIE_STAGE_BP_BUILD, s);
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
-    k_traverse<<<bp_grid(n), kBpBlock, 0, s>>>(n, m->tris, tbox, v2, leafbox, nodebox, left, right, last, pairs,
-                                                capacity, ctr);
+    // one lane per leaf, block count rounded up to a multiple of the 8 XCDs
+    const int64_t nb = ((nt + kBpBlock - 1) / kBpBlock + 7) / 8 * 8;
+    k_traverse<<<(unsigned)nb, kBpBlock, 0, s>>>(nt, lv, boxes, leaves, pairs, capacity, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
   k_bp_finish<<<1, 64, 0, s>>>(ctr, capacity, n_pairs);

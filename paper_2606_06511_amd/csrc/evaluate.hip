@@ -2,19 +2,24 @@
 // deterministic (no floating-point atomics) assembly of energy, gradient and BSR Hessian.
 //
 // Pipeline on one stream, no host synchronization:
-//   k_eval_init      reset the per-evaluation counters
-//   k_screen         one lane per candidate: adjacency, exact plane sides, exact flag, FP64
-//                    interval ends; hits appended with one atomic per wave (ballot + mbcnt)
+//   k_screen         one lane per candidate: adjacency, FP64-filtered plane sides and flag,
+//                    FP64 interval ends; hits and filter-uncertain candidates are appended
+//                    with one atomic per wave (ballot + mbcnt)
+//   k_screen_exact   the uncertain candidates again, with the exact fallback
 //   k_derivs<S>      one lane per hit: a = dt_c^0, b = dt_c^1, T, g (Eq. 3), 2x2 Hessian core;
-//                    counts the hit's six vertices
+//                    counts the hit's six vertices and lists the vertices touched first
 //   scan             exclusive scan of the per-vertex incidence counts
 //   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists
-//   k_rows_sort<S>   per touched vertex: sort its incidences by pair key (the summation
-//                    order), and count the distinct neighbour vertices (BSR columns)
+//   k_rows_sort<S>   one wave per touched vertex: rank-sort its incidences by pair key (the
+//                    summation order) and list its distinct neighbour vertices (BSR columns)
 //   scan             BSR row pointers from the column counts
-//   k_rows_asm<S>    per vertex: gradient row, BSR row (blocks J_k^T M J_l summed in pair-key
-//                    order), energy partial; clears the counters it used; the last block sums
-//                    the energy partials in block order
+//   k_rows_asm<S>    one wave per touched vertex, a lane per column: blocks J_k^T M J_l summed
+//                    in pair-key order; the gradient row and the row's energy share
+//   k_rows_final<S>  every vertex: zero gradient rows, energy summed in vertex order (fixed
+//                    tree per block), coordinate checks, per-vertex counters cleared
+//   k_eval_finish    block partials summed in block order; scalar outputs; counters reset
+#include <algorithm>
+
 #include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
@@ -27,23 +32,6 @@ __device__ __forceinline__ void latch(int32_t* status, int code) { atomicCAS(sta
 
 __global__ void k_fill_zero_i32(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
-}
-
-// resets the per-evaluation counters and checks every coordinate: finite, and 0 or of
-// magnitude in [2^-200, 2^200] (the domain on which the exact predicates are exact)
-__global__ void k_eval_init(Counters* c, const double* __restrict__ x, int64_t n) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    c->n_hits = 0;
-    c->n_defer = 0;
-    c->ticket = 0;
-  }
-  int code = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = fabs(x[i]);
-    if (!(v <= 1.7976931348623157e308)) code = STATUS_NONFINITE;
-    else if (v != 0.0 && (v < 6.223015277861142e-61 || v > 1.6069380442589903e60)) code = code ? code : STATUS_UNSUPPORTED;
-  }
-  if (code) latch(&c->status, code);
 }
 
 __device__ __forceinline__ bool load_tri(const double* x, int64_t nv, const int32_t* tris, int64_t t, int32_t vid[3],
@@ -201,40 +189,52 @@ __device__ __forceinline__ void hit_vids(const int32_t* tris, int64_t key, int32
 
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_derivs(const double* __restrict__ x, const int32_t* __restrict__ tris,
-                                                   const HitGeom* __restrict__ hits, const Counters* ctr,
-                                                   uint32_t max_hits, int psd_mode, double half,
-                                                   AsmRec<S>* __restrict__ recs, int32_t* __restrict__ cnt) {
+                                                   const HitGeom* __restrict__ hits, Counters* ctr, uint32_t max_hits,
+                                                   int psd_mode, double half, AsmRec<S>* __restrict__ recs,
+                                                   int32_t* __restrict__ cnt, int32_t* __restrict__ touched) {
   const uint32_t H = min(ctr->n_hits, max_hits);
-  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
-    const HitGeom g = hits[h];
-    AsmRec<S> r;
-    hit_vids(tris, g.key, r.vid);
-    r.pad = 0;
-    r.key = g.key;
-    V3<S> X[6];
-    local_coords<S>(x, r.vid, X);
-    interval_grads<S>(X, g.da, g.db, g.desc, half, r.a, r.b);
-    const double t0 = g.t0, t1 = g.t1;
-    const double pr = t0 * t1;
-    r.T = pr * pr;
-    // Eq. 3: dT = 2 t0 t1^2 a + 2 t1 t0^2 b
-    const S ca = Sc<S>::c(2.0 * pr * t1), cb = Sc<S>::c(2.0 * pr * t0);
-    double aa = 0, bb = 0, ab = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < H; base += gridDim.x * blockDim.x) {
+    const uint32_t h = base + threadIdx.x;
+    const bool active = h < H;
+    int32_t vid[6] = {0, 0, 0, 0, 0, 0};
+    if (active) {
+      const HitGeom g = hits[h];
+      AsmRec<S> r;
+      hit_vids(tris, g.key, r.vid);
+      r.pad = 0;
+      r.key = g.key;
+      V3<S> X[6];
+      local_coords<S>(x, r.vid, X);
+      interval_grads<S>(X, g.da, g.db, g.desc, half, r.a, r.b);
+      const double t0 = g.t0, t1 = g.t1;
+      const double pr = t0 * t1;
+      r.T = pr * pr;
+      // Eq. 3: dT = 2 t0 t1^2 a + 2 t1 t0^2 b
+      const S ca = Sc<S>::c(2.0 * pr * t1), cb = Sc<S>::c(2.0 * pr * t0);
+      double aa = 0, bb = 0, ab = 0;
 #pragma unroll
-    for (int k = 0; k < 18; ++k) {
-      r.g[k] = ca * r.a[k] + cb * r.b[k];
-      aa += (double)r.a[k] * (double)r.a[k];
-      bb += (double)r.b[k] * (double)r.b[k];
-      ab += (double)r.a[k] * (double)r.b[k];
+      for (int k = 0; k < 18; ++k) {
+        r.g[k] = ca * r.a[k] + cb * r.b[k];
+        aa += (double)r.a[k] * (double)r.a[k];
+        bb += (double)r.b[k] * (double)r.b[k];
+        ab += (double)r.a[k] * (double)r.b[k];
+      }
+      double M[3];
+      hessian_core(psd_mode, t0, t1, aa, bb, ab, M);
+      r.M[0] = Sc<S>::c(M[0]);
+      r.M[1] = Sc<S>::c(M[1]);
+      r.M[2] = Sc<S>::c(M[2]);
+      recs[h] = r;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) vid[k] = r.vid[k];
     }
-    double M[3];
-    hessian_core(psd_mode, t0, t1, aa, bb, ab, M);
-    r.M[0] = Sc<S>::c(M[0]);
-    r.M[1] = Sc<S>::c(M[1]);
-    r.M[2] = Sc<S>::c(M[2]);
-    recs[h] = r;
+    // count the six incidences; a vertex whose count leaves 0 joins the touched list
 #pragma unroll
-    for (int k = 0; k < 6; ++k) atomicAdd(&cnt[r.vid[k]], 1);
+    for (int k = 0; k < 6; ++k) {
+      const bool first = active && atomicAdd(&cnt[vid[k]], 1) == 0;
+      const uint32_t slot = wave_slot(first, &ctr->n_touched);
+      if (first) touched[slot] = vid[k];
+    }
   }
 }
 
@@ -251,52 +251,68 @@ __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ r
   }
 }
 
+constexpr int kWaves = kBlock / 64;
+constexpr int kCandCap = 256;  // column candidates staged in LDS per wave
+
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_sort(int64_t nv, const int32_t* __restrict__ off,
-                                                      Incidence* __restrict__ inc, const AsmRec<S>* __restrict__ recs,
-                                                      int32_t* __restrict__ colbuf, int32_t* __restrict__ ncol,
-                                                      int want_bsr) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t b = off[v], e = off[v + 1];
-    if (e == b) {
-      if (want_bsr) ncol[v] = 0;
-      continue;
-    }
-    // insertion sort by pair key: rows touch few hits
-    for (int32_t k = b + 1; k < e; ++k) {
-      const Incidence cur = inc[k];
-      int32_t m = k - 1;
-      while (m >= b && inc[m].key > cur.key) {
-        inc[m + 1] = inc[m];
-        --m;
+__global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict__ touched, const Counters* ctr,
+                                                      const int32_t* __restrict__ off,
+                                                      const Incidence* __restrict__ inc,
+                                                      Incidence* __restrict__ inc2, const AsmRec<S>* __restrict__ recs,
+                                                      int32_t* __restrict__ colbuf, int32_t* __restrict__ cstage,
+                                                      int64_t cstage_len, int32_t* __restrict__ ncol, int want_bsr) {
+  __shared__ int32_t lcand[kWaves][kCandCap];
+  __shared__ uint8_t lflag[kWaves][kCandCap];
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  const uint32_t U = ctr->n_touched;
+  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
+    const int32_t v = touched[u];
+    const int32_t b = off[v], n = off[v + 1] - b;
+    // rank sort of the row's incidences by (pair key, position): the ranks are a permutation
+    // even if a caller repeats a pair
+    for (int32_t i = lane; i < n; i += 64) {
+      const Incidence me = inc[b + i];
+      int32_t rank = 0;
+      for (int32_t j = 0; j < n; ++j) {
+        const int64_t kj = inc[b + j].key;
+        rank += kj < me.key || (kj == me.key && j < i);
       }
-      inc[m + 1] = cur;
+      inc2[b + rank] = me;
     }
     if (!want_bsr) continue;
-    int32_t* cb = colbuf + 6 * (int64_t)b;
-    int32_t n = 0;
-    for (int32_t k = b; k < e; ++k) {
-      const AsmRec<S>& r = recs[inc[k].hit];
-      for (int s = 0; s < 6; ++s) {
-        const int32_t c = r.vid[s];
-        int32_t m = n - 1;  // insert keeping cb[0..n) sorted and unique
-        bool dup = false;
-        while (m >= 0 && cb[m] >= c) {
-          if (cb[m] == c) {
-            dup = true;
-            break;
-          }
-          --m;
-        }
-        if (dup) continue;
-        for (int32_t z = n; z > m + 1; --z) cb[z] = cb[z - 1];
-        cb[m + 1] = c;
-        ++n;
-      }
+    // candidate columns: the six vertices of every incident hit, staged in LDS (or, for very
+    // large rows, in the workspace) with a first-occurrence flag each
+    const int32_t m = 6 * n;
+    const bool in_lds = m <= kCandCap;
+    int32_t* cand = in_lds ? lcand[wave] : cstage + 6 * (int64_t)b;
+    uint8_t* first = in_lds ? lflag[wave] : reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b;
+    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[inc[b + c / 6].hit].vid[c % 6];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t c = lane; c < m; c += 64) {
+      const int32_t val = cand[c];
+      bool f = true;
+      for (int32_t j = 0; j < c && f; ++j) f = cand[j] != val;
+      first[c] = f ? 1 : 0;
     }
-    ncol[v] = n;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // a kept candidate goes to the number of kept candidates with a smaller vertex id
+    int32_t kept = 0;
+    for (int32_t c = lane; c < m; c += 64) {
+      if (!first[c]) continue;
+      const int32_t val = cand[c];
+      int32_t pos = 0;
+      for (int32_t j = 0; j < m; ++j) pos += first[j] && cand[j] < val;
+      colbuf[6 * (int64_t)b + pos] = val;
+      ++kept;
+    }
+    // wave sum of kept
+    for (int w = 32; w > 0; w >>= 1) kept += __shfl_xor(kept, w);
+    if (lane == 0) ncol[v] = kept;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  if (want_bsr && blockIdx.x == 0 && threadIdx.x == 0) ncol[nv] = 0;
 }
 
 template <class S>
@@ -312,91 +328,130 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
 }
 
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_asm(int64_t nv, const int32_t* __restrict__ off,
-                                                     const Incidence* __restrict__ inc,
+__global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__ touched, const Counters* ctr,
+                                                     const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs,
                                                      const int32_t* __restrict__ colbuf,
                                                      const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                      S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
-                                                     int32_t* __restrict__ cnt, int32_t* __restrict__ cur,
-                                                     double* __restrict__ blockpart, Counters* ctr, uint32_t max_hits,
-                                                     double* energy, int64_t* n_blocks, int64_t* n_hits) {
-  __shared__ double red[kBlock];
-  double esum = 0.0;
+                                                     double* __restrict__ epart, int32_t* status_word) {
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  const uint32_t U = ctr->n_touched;
   int status = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
+    const int32_t v = touched[u];
     const int32_t b = off[v], e = off[v + 1];
-    S G[3] = {Sc<S>::c(0.0), Sc<S>::c(0.0), Sc<S>::c(0.0)};
-    double erow = 0.0;
-    for (int32_t k = b; k < e; ++k) {
-      const Incidence in = inc[k];
-      const AsmRec<S>& r = recs[in.hit];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) G[c] = G[c] + r.g[3 * in.slot + c];
-      if (in.slot == 0) erow += r.T;  // each hit's energy is counted at its first vertex
+    // gradient row (lanes 0-2) and the energy of the hits this vertex owns (lane 3), in
+    // pair-key order
+    if (lane < 4) {
+      S acc = Sc<S>::c(0.0);
+      double erow = 0.0;
+      for (int32_t k = b; k < e; ++k) {
+        const Incidence in = inc2[k];
+        if (lane < 3) acc = acc + recs[in.hit].g[3 * in.slot + lane];
+        else if (in.slot == 0) erow += recs[in.hit].T;  // each hit counted at its first vertex
+      }
+      if (lane < 3) grad[3 * (int64_t)v + lane] = acc;
+      else epart[v] = erow;
     }
-    grad[3 * v] = G[0];
-    grad[3 * v + 1] = G[1];
-    grad[3 * v + 2] = G[2];
-    esum += erow;
-    if (row_ptr && e > b) {
-      const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
-      const int32_t* cb = colbuf + 6 * (int64_t)b;
-      for (int32_t q = 0; q < nc; ++q) {
-        const int32_t col = cb[q];
-        S B[9];
+    if (!row_ptr) continue;
+    const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
+    for (int32_t q = lane; q < nc; q += 64) {
+      const int32_t col = colbuf[6 * (int64_t)b + q];
+      S B[9];
 #pragma unroll
-        for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
-        for (int32_t k = b; k < e; ++k) {
-          const Incidence in = inc[k];
-          const AsmRec<S>& r = recs[in.hit];
-          for (int l = 0; l < 6; ++l)
-            if (r.vid[l] == col) block_jmj(r, in.slot, l, B);
-        }
-        const int64_t pos = (int64_t)rp + q;
-        if (pos < block_cap) {
-          col_idx[pos] = col;
+      for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
+      for (int32_t k = b; k < e; ++k) {
+        const Incidence in = inc2[k];
+        const AsmRec<S>& r = recs[in.hit];
+        for (int l = 0; l < 6; ++l)
+          if (r.vid[l] == col) block_jmj(r, in.slot, l, B);
+      }
+      const int64_t pos = (int64_t)rp + q;
+      if (pos < block_cap) {
+        col_idx[pos] = col;
 #pragma unroll
-          for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
-        } else {
-          status = STATUS_CAPACITY;
-        }
+        for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
+      } else {
+        status = STATUS_CAPACITY;
       }
     }
-    if (e > b) {
+  }
+  if (status) latch(status_word, status);
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_rows_final(int64_t nv, const double* __restrict__ x,
+                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ cur,
+                                                       int32_t* __restrict__ ncol, double* __restrict__ epart,
+                                                       S* __restrict__ grad, double* __restrict__ blockpart,
+                                                       Counters* ctr) {
+  __shared__ double red[kBlock];
+  double esum = 0.0;
+  int code = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    if (cnt[v] > 0) {
+      esum += epart[v];
       cnt[v] = 0;
       cur[v] = 0;
+      ncol[v] = 0;
+      epart[v] = 0.0;
+    } else {
+      grad[3 * v] = Sc<S>::c(0.0);
+      grad[3 * v + 1] = Sc<S>::c(0.0);
+      grad[3 * v + 2] = Sc<S>::c(0.0);
+    }
+    // every coordinate: finite, and 0 or of magnitude in [2^-200, 2^200] (the domain on which
+    // the exact predicates are exact)
+    for (int c = 0; c < 3; ++c) {
+      const double q = fabs(x[3 * v + c]);
+      if (!(q <= 1.7976931348623157e308)) code = STATUS_NONFINITE;
+      else if (q != 0.0 && (q < 6.223015277861142e-61 || q > 1.6069380442589903e60) && !code)
+        code = STATUS_UNSUPPORTED;
     }
   }
-  if (status) latch(&ctr->status, status);
-  // energy: fixed-order tree in the block, then blocks in order by the last block
+  if (code) latch(&ctr->status, code);
   red[threadIdx.x] = esum;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  __shared__ bool last;
-  if (threadIdx.x == 0) {
-    blockpart[blockIdx.x] = red[0];
-    __threadfence();
-    last = atomicAdd(&ctr->ticket, 1u) == gridDim.x - 1;
-  }
+  if (threadIdx.x == 0) blockpart[blockIdx.x] = red[0];
+}
+
+// Sums the block partials in block order, writes the scalar outputs, hands the hit list to
+// hvp / get_hits and resets the counters for the next evaluation (one wave).
+__global__ void __launch_bounds__(kBlock) k_eval_finish(int nblocks, const double* __restrict__ blockpart, Counters* ctr,
+                                                        uint32_t max_hits, const int32_t* __restrict__ row_ptr,
+                                                        int64_t nv, int64_t block_cap, double* energy,
+                                                        int64_t* n_blocks, int64_t* n_hits) {
+  // fixed-order sum: thread t adds partials t, t + 256, ..., then a tree
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += kBlock) acc += blockpart[k];
+  red[threadIdx.x] = acc;
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    double E = 0.0;
-    for (unsigned k = 0; k < gridDim.x; ++k) E += blockpart[k];
-    *energy = E;
-    const uint32_t H = ctr->n_hits;
-    if (n_hits) *n_hits = (int64_t)H;
-    if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
-    if (row_ptr) {
-      const int64_t nb = row_ptr[nv];
-      if (n_blocks) *n_blocks = nb;
-      if (nb > block_cap) latch(&ctr->status, STATUS_CAPACITY);
-    }
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x != 0) return;
+  const double E = red[0];
+  *energy = E;
+  const uint32_t H = ctr->n_hits;
+  if (n_hits) *n_hits = (int64_t)H;
+  if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
+  if (row_ptr) {
+    const int64_t nb = row_ptr[nv];
+    if (n_blocks) *n_blocks = nb;
+    if (nb > block_cap) latch(&ctr->status, STATUS_CAPACITY);
+  }
+  ctr->last_hits = min(H, max_hits);
+  ctr->n_hits = 0;
+  ctr->n_defer = 0;
+  ctr->n_touched = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -408,7 +463,7 @@ __global__ void __launch_bounds__(kBlock) k_hvp_exact(const double* __restrict__
                                                       const Counters* ctr, uint32_t max_hits, double half,
                                                       S* __restrict__ hv) {
   using DS = Dual<S>;
-  const uint32_t H = min(ctr->n_hits, max_hits);
+  const uint32_t H = ctr->last_hits;
   for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
     const HitGeom g = hits[h];
     const AsmRec<S>& r = recs[h];
@@ -442,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_hvp_exact(const double* __restrict__
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_hvp_psd(const S* __restrict__ v, const AsmRec<S>* __restrict__ recs,
                                                     const Counters* ctr, uint32_t max_hits, S* __restrict__ hv) {
-  const uint32_t H = min(ctr->n_hits, max_hits);
+  const uint32_t H = ctr->last_hits;
   for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
     const AsmRec<S>& r = recs[h];
     S av = S(0), bv = S(0);
@@ -524,9 +579,9 @@ static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, h
 
 template <class S>
 static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
-                            int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags, double* pair_T,
-                            int32_t* row_ptr, int32_t* col_idx, S* vals, int64_t block_cap, int64_t* n_blocks,
-                            int64_t* n_hits, hipStream_t s) {
+                            int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags,
+                            double* pair_T, int32_t* row_ptr, int32_t* col_idx, S* vals, int64_t block_cap,
+                            int64_t* n_blocks, int64_t* n_hits, hipStream_t s) {
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   HitGeom* hits = wsp<HitGeom>(c, L.hits);
@@ -536,15 +591,18 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   int32_t* off = wsp<int32_t>(c, L.off);
   int32_t* ncol = wsp<int32_t>(c, L.ncol);
   Incidence* inc = wsp<Incidence>(c, L.inc);
+  Incidence* inc2 = wsp<Incidence>(c, L.inc2);
   int32_t* colbuf = wsp<int32_t>(c, L.colbuf);
+  int32_t* cstage = wsp<int32_t>(c, L.cstage);
+  int32_t* touched = wsp<int32_t>(c, L.touched);
+  double* epart = wsp<double>(c, L.epart_v);
   double* blockpart = wsp<double>(c, L.epart);
+  int32_t* defer = wsp<int32_t>(c, L.defer);
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
   const int64_t nv = m->n_verts;
   const bool bsr = row_ptr != nullptr;
 
-  k_eval_init<<<grid_for(3 * nv, 1024), kBlock, 0, s>>>(ctr, m->x, 3 * nv);
-  int32_t* defer = wsp<int32_t>(c, L.defer);
   stage_begin(c, TTIE_STAGE_SCREEN, s);
   k_screen<<<grid_for(pair_cap, 2048), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
                                                        hits, max_hits, defer, ctr, flags, pair_T);
@@ -553,22 +611,26 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, hits,
                                                             max_hits, defer, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN_EXACT, s);
-  const unsigned gh = grid_for(c->lim.max_hits, 1024);
   stage_begin(c, TTIE_STAGE_DERIVS, s);
-  k_derivs<S><<<gh, kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode, half, recs, cnt);
+  k_derivs<S><<<grid_for(c->lim.max_hits, 1024), kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode,
+                                                                 half, recs, cnt, touched);
   stage_end(c, TTIE_STAGE_DERIVS, s);
   stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
   hipError_t err = scan_i32(c, cnt, off, nv + 1, s);
   if (err != hipSuccess) return err;
   k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, off, cur, inc);
-  k_rows_sort<S><<<grid_for(nv, 2048), kBlock, 0, s>>>(nv, off, inc, recs, colbuf, ncol, bsr ? 1 : 0);
+  const unsigned grows = (unsigned)std::min<int64_t>(2048, (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
+  k_rows_sort<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc, inc2, recs, colbuf, cstage, 36 * c->lim.max_hits,
+                                          ncol, bsr ? 1 : 0);
   if (bsr) {
     err = scan_i32(c, ncol, row_ptr, nv + 1, s);
     if (err != hipSuccess) return err;
   }
-  k_rows_asm<S><<<kRowBlocks, kBlock, 0, s>>>(nv, off, inc, recs, colbuf, bsr ? row_ptr : nullptr, col_idx, vals,
-                                              block_cap, grad, cnt, cur, blockpart, ctr, max_hits, energy, n_blocks,
-                                              n_hits);
+  k_rows_asm<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc2, recs, colbuf, bsr ? row_ptr : nullptr, col_idx,
+                                         vals, block_cap, grad, epart, &ctr->status);
+  k_rows_final<S><<<kRowBlocks, kBlock, 0, s>>>(nv, m->x, cnt, cur, ncol, epart, grad, blockpart, ctr);
+  k_eval_finish<<<1, kBlock, 0, s>>>(kRowBlocks, blockpart, ctr, max_hits, bsr ? row_ptr : nullptr, nv, block_cap, energy,
+                                 n_blocks, n_hits);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
   return hipGetLastError();
 }
@@ -599,7 +661,7 @@ static hipError_t hvp_impl(Ctx* c, const ttie_mesh* m, const S* v, S* Hv, int mo
   else
     k_hvp_psd<S><<<gh, kBlock, 0, s>>>(v, wsp<AsmRec<S>>(c, L.recs), ctr, max_hits, hvbuf);
   k_hvp_rows<S><<<grid_for(m->n_verts, 2048), kBlock, 0, s>>>(m->n_verts, wsp<int32_t>(c, L.off),
-                                                               wsp<Incidence>(c, L.inc), hvbuf, Hv);
+                                                               wsp<Incidence>(c, L.inc2), hvbuf, Hv);
   stage_end(c, TTIE_STAGE_HVP, s);
   return hipGetLastError();
 }

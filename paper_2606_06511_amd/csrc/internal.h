@@ -37,15 +37,16 @@ struct Counters {
   int32_t status;          // latched TTIE status (first error wins)
   uint32_t n_hits;         // intersecting pairs found by the last screening
   uint32_t n_pairs;        // candidates emitted by the last broad phase
-  uint32_t ticket;         // last-block ticket of the row kernel
-  uint32_t bounds[6];      // scene bounds of the broad phase (order-preserving float bits)
   uint32_t n_defer;        // candidates whose signs need the exact fallback
+  uint32_t n_touched;      // vertices touched by the hits of the current evaluation
+  uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
 };
 
 struct Layout {
-  size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, hvbuf, epart, scan_tmp, scan_tmp_bytes;
-  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_sort_tmp, bvh_sort_tmp_bytes, bvh_nodes, bvh_leafparent,
-      bvh_boxes, bvh_tbox, bvh_visit, bvh_centroid;
+  size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
+      scan_tmp_bytes;
+  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_sort_tmp, bvh_sort_tmp_bytes, bvh_boxes, bvh_leaves,
+      bvh_tbox, bvh_centroid, bvh_part, touched, inc2;
   size_t total;
 };
 

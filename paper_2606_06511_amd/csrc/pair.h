@@ -105,6 +105,10 @@ __device__ __forceinline__ bool plane_sides(const Tri64& pl, const Tri64& cut, i
     if (fabs(det) > bound) {
       s[k] = det > 0 ? 1 : -1;
       d[k] = det;
+    } else if (bound == 0.0) {
+      // every monomial has an exactly zero difference factor: the determinant is exactly 0
+      s[k] = 0;
+      d[k] = 0.0;
     } else {
       if (!kExact) return false;
       OrientResult r = orient_exact(pl.p[0], pl.p[1], pl.p[2], cut.p[k]);
@@ -141,6 +145,7 @@ __device__ __forceinline__ int orient_sign(const V3<double>& p, const V3<double>
   double det, bound;
   orient_fp64(q - p, r - p, s - p, det, bound);
   if (fabs(det) > bound) return det > 0 ? 1 : -1;
+  if (bound == 0.0) return 0;
   if (!kExact) return 2;
   const double P[3] = {p.x, p.y, p.z}, Q[3] = {q.x, q.y, q.z}, R[3] = {r.x, r.y, r.z}, S[3] = {s.x, s.y, s.z};
   OrientResult o = orient_exact(P, Q, R, S);
@@ -248,21 +253,36 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
 // Derivatives of t_c^0 and t_c^1 (a and b, 18 each, slots u0,u1,u2,v0,v1,v2) for a hit.
 // X holds pair-local coordinates in scalar S; dstored the FP64 plane sides of the screening.
 // ------------------------------------------------------------------------------------------
+// by-value selects for any scalar (see pick above) and slot accumulation with static indices
+template <class T> __device__ __forceinline__ T pickt(T a, T b, T c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+template <class S> __device__ __forceinline__ V3<S> pick3(const V3<S> (&v)[3], int i) {
+  return V3<S>{pickt(v[0].x, v[1].x, v[2].x, i), pickt(v[0].y, v[1].y, v[2].y, i), pickt(v[0].z, v[1].z, v[2].z, i)};
+}
+template <class S> __device__ __forceinline__ void add_at(V3<S> (&out)[6], int slot, const V3<S>& v) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    if (k == slot) out[k] = out[k] + v;
+}
+
+// adds sgn * Dh . dP for endpoint (p, q) of the cut triangle C (slots cs..cs+2) against the
+// plane of triangle P (slots ps..ps+2), d the cut triangle's plane sides, n the plane normal
 template <class S>
-__device__ __forceinline__ void add_endpoint(V3<S> out[6], S sgn, int p, int q, const V3<S>* C, const V3<S>* P,
-                                             const S* d, const V3<S>& n, const V3<S>& Dh, int cs, int ps) {
+__device__ __forceinline__ void add_endpoint(V3<S> (&out)[6], S sgn, int p, int q, const V3<S> (&C)[3],
+                                             const V3<S> (&P)[3], const S (&d)[3], const V3<S>& n, const V3<S>& Dh,
+                                             int cs, int ps) {
   if (q == 3) {
-    out[cs + p] = out[cs + p] + sgn * Dh;
+    add_at(out, cs + p, sgn * Dh);
     return;
   }
-  const S dp = d[p], dq = d[q];
+  const V3<S> Cp = pick3(C, p), Cq = pick3(C, q);
+  const S dp = pickt(d[0], d[1], d[2], p), dq = pickt(d[0], d[1], d[2], q);
   const S den = dp - dq;
   const S lam = dp / den;
-  const S w = dot(Dh, C[q] - C[p]) / (den * den);
+  const S w = dot(Dh, Cq - Cp) / (den * den);
   const S one = Sc<S>::c(1.0);
-  out[cs + p] = out[cs + p] + sgn * ((one - lam) * Dh - (w * dq) * n);
-  out[cs + q] = out[cs + q] + sgn * (lam * Dh + (w * dp) * n);
-  const V3<S> Y = dp * (C[q] - P[0]) - dq * (C[p] - P[0]);
+  add_at(out, cs + p, sgn * ((one - lam) * Dh - (w * dq) * n));
+  add_at(out, cs + q, sgn * (lam * Dh + (w * dp) * n));
+  const V3<S> Y = dp * (Cq - P[0]) - dq * (Cp - P[0]);
   const V3<S> g1 = w * cross(P[2] - P[0], Y);
   const V3<S> g2 = w * cross(Y, P[1] - P[0]);
   out[ps + 1] = out[ps + 1] + sgn * g1;
@@ -271,10 +291,11 @@ __device__ __forceinline__ void add_endpoint(V3<S> out[6], S sgn, int p, int q, 
 }
 
 template <class S>
-__device__ __forceinline__ void interval_grads(const V3<S> X[6], const double dstored_a[3], const double dstored_b[3],
-                                               uint32_t desc, double half, S a[18], S b[18]) {
-  const V3<S>* U = X;
-  const V3<S>* V = X + 3;
+__device__ __forceinline__ void interval_grads(const V3<S> (&X)[6], const double dstored_a[3],
+                                               const double dstored_b[3], uint32_t desc, double half, S a[18],
+                                               S b[18]) {
+  const V3<S> U[3] = {X[0], X[1], X[2]};
+  const V3<S> V[3] = {X[3], X[4], X[5]};
   const V3<S> na = cross(U[1] - U[0], U[2] - U[0]);
   const V3<S> nb = cross(V[1] - V[0], V[2] - V[0]);
   const V3<S> D = cross(na, nb);

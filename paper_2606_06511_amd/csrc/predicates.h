@@ -11,6 +11,9 @@
 // determinant passes through at most 8 roundings, so |fl(det) - det| <= gamma_8 * perm with
 // perm = sum of |monomials| (computed from the rounded differences; the bound below keeps
 // a margin for perm's own rounding).  When |fl(det)| exceeds that bound its sign is exact.
+// When perm is exactly 0 every monomial has a zero difference factor (a difference of
+// doubles rounds to 0 only when it is 0, and products cannot underflow on the input domain),
+// so the determinant is exactly 0.
 // Otherwise the determinant is recomputed exactly from the 24 signed triple products of the
 // raw coordinates (det[b-a,c-a,p-a] = D(b,c,p) - D(a,b,c) + D(a,b,p) - D(a,c,p) with
 // D(x,y,z) = x.(y x z)) in a two's-complement fixed-point accumulator spanning the exponent
@@ -188,6 +191,7 @@ __device__ __forceinline__ OrientResult orient(const double* a, const double* b,
   double det, bound;
   orient_fp64(e1, e2, w, det, bound);
   if (fabs(det) > bound) return {det, det > 0 ? 1 : -1, 0, 0};
+  if (bound == 0.0) return {0.0, 0, 0, 0};
   return orient_exact(a, b, c, p);
 }
 
