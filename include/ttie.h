@@ -128,12 +128,15 @@ ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_hos
  * Writes the canonical candidate set {(i, j) : i < j, no shared vertex index} of the mesh
  * -- for TTIE_BROAD_LBVH restricted to pairs whose closed float64 bounding boxes overlap
  * on all three axes (Sec. 1.2 uses spatial hashing for this step; this is an LBVH over
- * 30-bit Morton codes) -- into pairs (capacity x 2 int32, 8-byte aligned) in an unspecified order, and the
- * number of candidates into *n_pairs (device int64).  When the count exceeds `capacity`
- * only the first `capacity` pairs are written, *n_pairs still receives the full count and
+ * 30-bit Morton codes) -- into pairs (capacity x 2 int32, 8-byte aligned) in an unspecified
+ * order, and the number of candidates into *n_pairs (device int64).  x_end (nullable,
+ * n_verts x 3 float64) makes every box cover the triangle at both x and x_end, so the list
+ * holds every pair that can intersect anywhere on the straight path from x to x_end (the
+ * line search of the Newton consumer).  When the count exceeds `capacity` only the first
+ * `capacity` pairs are written, *n_pairs still receives the full count and
  * TTIE_ERR_CAPACITY is latched.  capacity must not exceed limits.max_pairs. */
-ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, int32_t* pairs, int64_t capacity,
-                            int64_t* n_pairs, void* stream);
+ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, const double* x_end, int32_t* pairs,
+                            int64_t capacity, int64_t* n_pairs, void* stream);
 
 /* ---- evaluation -----------------------------------------------------------------------
  * Evaluates the candidate pairs and assembles the energy, gradient and Hessian.
@@ -179,6 +182,22 @@ ttie_status ttie_hvp(ttie_ctx* ctx, const ttie_mesh* mesh, const void* v, void* 
 ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                         const void* vals, const void* x, void* y, int precision, void* stream);
 
+/* ---- inexact Newton consumer (the abstract's GPU inexact-Newton route) -----------------
+ * Jacobi-preconditioned conjugate gradients on (H + mu I) x = scale * b, entirely on the
+ * device (no host synchronization): H is a BSR matrix from ttie_eval (n_rows = n_verts),
+ * mu = mu_rel * (mean diagonal entry of H over the rows that hold blocks), the Jacobi
+ * preconditioner is the diagonal of H + mu I, x starts at 0, and the iteration stops after
+ * max_iter steps or when |r| <= tol |scale b|.  b and x are n_rows x 3 in the precision of
+ * vals; reductions accumulate in float64 in a fixed order.  info (device, 4 float64, may be
+ * NULL) receives {iterations, |r| / |b|, mu, x . (scale b)}. */
+ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                     const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
+                     double* info, void* stream);
+
+/* out = x + alpha * d for n_verts x 3 positions: x and out float64, d in `precision`. */
+ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double* x, const void* d, double* out,
+                      int precision, void* stream);
+
 /* ---- stage timers ---------------------------------------------------------------------
  * When enabled (mask of 1 << TTIE_STAGE_*), the following calls record a HIP event pair on
  * their stream around every kernel of the selected stages.  ttie_read_timers waits for the
@@ -194,7 +213,8 @@ enum {
   TTIE_STAGE_DERIVS = 6,      /* per-hit interval gradients, energy, gradient, Hessian core */
   TTIE_STAGE_ASSEMBLY = 7,    /* incidence lists, BSR pattern, rows of gradient and Hessian */
   TTIE_STAGE_HVP = 8,         /* Hessian-vector products */
-  TTIE_STAGE_COUNT = 9
+  TTIE_STAGE_PCG = 9,         /* the preconditioned conjugate-gradient solve */
+  TTIE_STAGE_COUNT = 10
 };
 ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask);
 ttie_status ttie_read_timers(ttie_ctx* ctx, int n_stages, int64_t* launches_host, double* total_ms_host);

@@ -52,6 +52,13 @@ def lib():
         L.ttie_oracle_pairs.restype = ctypes.c_void_p
         L.ttie_oracle_free.argtypes = [ctypes.c_void_p]
         L.ttie_oracle_free.restype = None
+        L.ttie_oracle_pairs_swept.argtypes = [_dp, _dp, ctypes.c_int64, _ip, ctypes.c_int64, _lp]
+        L.ttie_oracle_pairs_swept.restype = ctypes.c_void_p
+        L.ttie_oracle_newton.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                         ctypes.POINTER(ctypes.c_int)]
+        L.ttie_oracle_newton.restype = ctypes.c_int
         L.ttie_oracle_eval.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, _ip, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ttie_oracle_eval.restype = ctypes.c_void_p
@@ -140,6 +147,33 @@ def pairs(x, tris, method=BROAD_BOXES):
     finally:
         lib().ttie_oracle_free(ptr)
     return out.reshape(-1, 2)
+
+
+def pairs_swept(x, x_end, tris):
+    """Candidates whose boxes, swept from x to x_end, overlap (canonical sorted list)."""
+    x, x_end, tris = _f64(x), _f64(x_end), _i32(tris)
+    n = ctypes.c_int64(0)
+    ptr = lib().ttie_oracle_pairs_swept(_d(x), _d(x_end), len(x), _i(tris), len(tris), ctypes.byref(n))
+    try:
+        out = np.ctypeslib.as_array(ctypes.cast(ptr, _ip), shape=(max(1, 2 * n.value),))[: 2 * n.value].copy()
+    finally:
+        lib().ttie_oracle_free(ptr)
+    return out.reshape(-1, 2)
+
+
+def newton(x, tris, steps=20, pcg_iters=50, pcg_tol=1e-6, mu_rel=1e-3, armijo_c=1e-4, beta=0.5, max_halvings=30,
+           interval=INTERVAL_EQ1, psd=PSD_PER_PART, threads=0):
+    """Inexact Newton with the PSD Hessian, Jacobi-PCG and Armijo backtracking (FP64).
+    Returns (x_final, energies (steps+1,), step lengths (steps,), PCG iterations (steps,))."""
+    x = _f64(x).copy()
+    tris = _i32(tris)
+    E = np.zeros(steps + 1)
+    al = np.zeros(steps)
+    its = np.zeros(steps, np.int32)
+    lib().ttie_oracle_newton(_d(x), len(x), _i(tris), len(tris), steps, pcg_iters, pcg_tol, mu_rel, armijo_c, beta,
+                             max_halvings, interval, psd, threads, _d(E), _d(al),
+                             its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return x, E, al, its
 
 
 def evaluate(x, tris, pair_list, interval=INTERVAL_EQ1, psd=PSD_PER_PART, hessian=True, threads=0):

@@ -225,7 +225,6 @@ const double kInf = std::numeric_limits<double>::infinity();
 Iv iv(double x) { return {x, x}; }
 Iv operator+(Iv a, Iv b) { return {std::nextafter(a.lo + b.lo, -kInf), std::nextafter(a.hi + b.hi, kInf)}; }
 Iv operator-(Iv a, Iv b) { return {std::nextafter(a.lo - b.hi, -kInf), std::nextafter(a.hi - b.lo, kInf)}; }
-Iv operator-(Iv a) { return {-a.hi, -a.lo}; }
 Iv operator*(Iv a, Iv b) {
   double p[4] = {a.lo * b.lo, a.lo * b.hi, a.hi * b.lo, a.hi * b.hi};
   double lo = p[0], hi = p[0];
@@ -826,7 +825,8 @@ std::vector<int32_t> pairs_brute(const Mesh& m) {
   return out;
 }
 
-std::vector<int32_t> pairs_boxes(const Mesh& m) {
+// x_end (nullable): boxes cover each triangle at x and at x_end (swept candidates)
+std::vector<int32_t> pairs_boxes(const Mesh& m, const double* x_end = nullptr) {
   std::vector<double> lo(3 * m.nt), hi(3 * m.nt);
   double ext = 0;
   for (int64_t t = 0; t < m.nt; ++t) {
@@ -834,6 +834,12 @@ std::vector<int32_t> pairs_boxes(const Mesh& m) {
     for (int c = 0; c < 3; ++c) {
       lo[3 * t + c] = std::min({tr.p[0][c], tr.p[1][c], tr.p[2][c]});
       hi[3 * t + c] = std::max({tr.p[0][c], tr.p[1][c], tr.p[2][c]});
+      if (x_end)
+        for (int k = 0; k < 3; ++k) {
+          const double e = x_end[3 * (int64_t)m.tris[3 * t + k] + c];
+          lo[3 * t + c] = std::min(lo[3 * t + c], e);
+          hi[3 * t + c] = std::max(hi[3 * t + c], e);
+        }
       ext = std::max(ext, hi[3 * t + c] - lo[3 * t + c]);
     }
   }
@@ -880,6 +886,123 @@ std::vector<int32_t> pairs_boxes(const Mesh& m) {
     out.push_back(pq.second);
   }
   return out;
+}
+
+// ============================================================================================
+// Inexact Newton loop (the abstract's optimization route; its parameters are not given in
+// the paper): H = the PSD Hessian, (H + mu I) d = -g by Jacobi-preconditioned CG from d = 0
+// with mu = mu_rel * mean diagonal entry over the rows holding blocks, then Armijo
+// backtracking on E along d with candidates from boxes swept from x to x + d.
+// ============================================================================================
+struct NewtonParams {
+  int steps, pcg_iters;
+  double pcg_tol, mu_rel, armijo_c, beta;
+  int max_halvings, interval_mode, psd_mode, nthreads;
+};
+
+void bsr_apply(const EvalResult& R, int64_t nv, const std::vector<double>& v, double mu, std::vector<double>& out) {
+  for (int64_t r = 0; r < nv; ++r)
+    for (int a = 0; a < 3; ++a) {
+      double acc = mu * v[3 * r + a];
+      for (int32_t k = R.row_ptr[r]; k < R.row_ptr[r + 1]; ++k)
+        for (int b = 0; b < 3; ++b) acc += R.vals[9 * (size_t)k + 3 * a + b] * v[3 * (size_t)R.col_idx[k] + b];
+      out[3 * r + a] = acc;
+    }
+}
+
+double dotv(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+int newton(double* x, int64_t nv, const int32_t* tris, int64_t nt, const NewtonParams& P, double* energies,
+           double* alphas, int* pcg_iters_out) {
+  int done = 0;
+  std::vector<double> xt(3 * nv);
+  for (int k = 0; k < P.steps; ++k) {
+    Mesh m{x, nv, tris, nt};
+    std::vector<int32_t> pl = pairs_boxes(m);
+    EvalResult* R = evaluate(m, pl.data(), (int64_t)pl.size() / 2, P.interval_mode, P.psd_mode, 1, P.nthreads);
+    const double E = R->E;
+    energies[k] = E;
+    if (E == 0.0) {
+      delete R;
+      done = k;
+      for (int j = k; j <= P.steps; ++j) energies[j] = 0.0;
+      return done;
+    }
+    // Jacobi-PCG on (H + mu I) d = -g
+    double dsum = 0, dcnt = 0;
+    std::vector<double> diag(3 * nv, 0.0);
+    for (int64_t r = 0; r < nv; ++r)
+      for (int32_t q = R->row_ptr[r]; q < R->row_ptr[r + 1]; ++q)
+        if (R->col_idx[q] == r)
+          for (int a = 0; a < 3; ++a) {
+            diag[3 * r + a] = R->vals[9 * (size_t)q + 4 * a];
+            dsum += diag[3 * r + a];
+            dcnt += 1;
+          }
+    const double mu = P.mu_rel * (dcnt > 0 ? dsum / dcnt : 1.0);
+    std::vector<double> b(3 * nv), d(3 * nv, 0.0), r(3 * nv), z(3 * nv), p(3 * nv), q(3 * nv), dinv(3 * nv);
+    for (int64_t i = 0; i < 3 * nv; ++i) {
+      b[i] = -R->G[i];
+      const double dg = diag[i] + mu;
+      dinv[i] = dg > 0 ? 1.0 / dg : 1.0;
+      r[i] = b[i];
+      z[i] = dinv[i] * r[i];
+      p[i] = z[i];
+    }
+    double rz = dotv(r, z);
+    const double bb = dotv(b, b);
+    int it = 0;
+    for (; it < P.pcg_iters; ++it) {
+      bsr_apply(*R, nv, p, mu, q);
+      const double pq = dotv(p, q);
+      if (!(pq > 0)) break;
+      const double alpha = rz / pq;
+      for (int64_t i = 0; i < 3 * nv; ++i) {
+        d[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+        z[i] = dinv[i] * r[i];
+      }
+      const double rzn = dotv(r, z), rr = dotv(r, r);
+      if (rr <= P.pcg_tol * P.pcg_tol * bb) {
+        ++it;
+        break;
+      }
+      const double beta = rz > 0 ? rzn / rz : 0.0;
+      for (int64_t i = 0; i < 3 * nv; ++i) p[i] = z[i] + beta * p[i];
+      rz = rzn;
+    }
+    if (pcg_iters_out) pcg_iters_out[k] = it;
+    double gd = 0;
+    for (int64_t i = 0; i < 3 * nv; ++i) gd += R->G[i] * d[i];
+    delete R;
+    // Armijo backtracking with candidates swept from x to x + d
+    std::vector<double> xe(3 * nv);
+    for (int64_t i = 0; i < 3 * nv; ++i) xe[i] = x[i] + d[i];
+    std::vector<int32_t> sw = pairs_boxes(m, xe.data());
+    double alpha = 1.0;
+    for (int h = 0; h < P.max_halvings; ++h) {
+      for (int64_t i = 0; i < 3 * nv; ++i) xt[i] = x[i] + alpha * d[i];
+      Mesh mt{xt.data(), nv, tris, nt};
+      EvalResult* Rt = evaluate(mt, sw.data(), (int64_t)sw.size() / 2, P.interval_mode, P.psd_mode, 0, P.nthreads);
+      const double Et = Rt->E;
+      delete Rt;
+      if (Et <= E + P.armijo_c * alpha * gd) break;
+      if (h + 1 < P.max_halvings) alpha *= P.beta;
+    }
+    if (alphas) alphas[k] = alpha;
+    for (int64_t i = 0; i < 3 * nv; ++i) x[i] = xt[i];
+    done = k + 1;
+  }
+  Mesh m{x, nv, tris, nt};
+  std::vector<int32_t> pl = pairs_boxes(m);
+  EvalResult* R = evaluate(m, pl.data(), (int64_t)pl.size() / 2, P.interval_mode, P.psd_mode, 0, P.nthreads);
+  energies[P.steps] = R->E;
+  delete R;
+  return done;
 }
 
 }  // namespace
@@ -936,6 +1059,27 @@ int32_t* ttie_oracle_pairs(const double* x, int64_t nv, const int32_t* tris, int
 }
 
 void ttie_oracle_free(void* p) { std::free(p); }
+
+// candidates with boxes swept from x to x_end
+int32_t* ttie_oracle_pairs_swept(const double* x, const double* x_end, int64_t nv, const int32_t* tris, int64_t nt,
+                                 int64_t* n_out) {
+  Mesh m{x, nv, tris, nt};
+  std::vector<int32_t> p = pairs_boxes(m, x_end);
+  *n_out = (int64_t)(p.size() / 2);
+  int32_t* out = (int32_t*)std::malloc(std::max<size_t>(1, p.size()) * sizeof(int32_t));
+  if (!p.empty()) std::memcpy(out, p.data(), p.size() * sizeof(int32_t));
+  return out;
+}
+
+// x is updated in place; energies has steps + 1 entries (the last at the final x)
+int ttie_oracle_newton(double* x, int64_t nv, const int32_t* tris, int64_t nt, int steps, int pcg_iters,
+                       double pcg_tol, double mu_rel, double armijo_c, double beta, int max_halvings,
+                       int interval_mode, int psd_mode, int nthreads, double* energies, double* alphas,
+                       int* pcg_iters_out) {
+  NewtonParams P{steps, pcg_iters, pcg_tol, mu_rel, armijo_c, beta, max_halvings, interval_mode, psd_mode,
+                 nthreads};
+  return newton(x, nv, tris, nt, P, energies, alphas, pcg_iters_out);
+}
 
 void* ttie_oracle_eval(const double* x, int64_t nv, const int32_t* tris, int64_t nt, const int32_t* pairs,
                        int64_t np, int interval_mode, int psd_mode, int want_hessian, int nthreads) {

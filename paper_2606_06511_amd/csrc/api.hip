@@ -11,7 +11,12 @@ namespace ttie {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort_bytes) {
+constexpr int64_t kMaxBuckets = (int64_t)1 << 20;  // Morton buckets of the broad-phase sort
+
+// one scan scratch serves every scan: the vertex-sized ones and the bucket counts
+static int64_t scan_len(const ttie_limits& lim) { return std::max<int64_t>(lim.max_verts, kMaxBuckets) + 1; }
+
+static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -40,8 +45,8 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort
   L.bvh_keys2 = take(T * 4);
   L.bvh_vals = take(T * 4);
   L.bvh_vals2 = take(T * 4);
-  L.bvh_sort_tmp_bytes = sort_bytes;
-  L.bvh_sort_tmp = take(sort_bytes);
+  L.bvh_hist = take((size_t)kMaxBuckets * 4);
+  L.bvh_offset = take(((size_t)kMaxBuckets + 1) * 4);
   L.bvh_boxes = take((2 * T + 64) * 32);  // implicit tree: at most 2T nodes of 32 B
   L.bvh_leaves = take(T * 64);            // sorted leaf records
   L.bvh_tbox = take(T * 6 * 8);
@@ -49,6 +54,9 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, size_t sort
   L.bvh_part = take(512 * 6 * 4);
   L.touched = take(6 * H * 4);
   L.inc2 = take(6 * H * sizeof(Incidence));
+  L.pcg_vec = take(5 * 3 * (size_t)lim.max_verts * 8);
+  L.pcg_part = take(5 * 256 * 4 * 8);
+  L.pcg_state = take(64);
   L.total = o;
   return L;
 }
@@ -201,9 +209,8 @@ ttie_status ttie_workspace_size(ttie_ctx* ctx, const ttie_limits* limits, size_t
   if (!limits_ok(limits)) return fail(TTIE_ERR_INVALID_ARGUMENT, "limits out of range");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
-  const size_t scan = scan_temp_bytes(limits->max_verts + 1);
-  const size_t sort = sort_temp_bytes(std::max<int64_t>(limits->max_tris, 2));
-  *bytes_host = layout_with(*limits, scan, sort).total;
+  const size_t scan = scan_temp_bytes(scan_len(*limits));
+  *bytes_host = layout_with(*limits, scan).total;
   return TTIE_OK;
 }
 
@@ -213,9 +220,8 @@ ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* d
   if (((uintptr_t)dptr) & 255) return fail(TTIE_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
-  const size_t scan = scan_temp_bytes(limits->max_verts + 1);
-  const size_t sort = sort_temp_bytes(std::max<int64_t>(limits->max_tris, 2));
-  Layout L = layout_with(*limits, scan, sort);
+  const size_t scan = scan_temp_bytes(scan_len(*limits));
+  Layout L = layout_with(*limits, scan);
   if (bytes < L.total) return fail(TTIE_ERR_CAPACITY, "workspace smaller than ttie_workspace_size");
   ctx->lim = *limits;
   ctx->ws = static_cast<char*>(dptr);
@@ -229,6 +235,7 @@ ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* d
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cnt), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cur), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.ncol), limits->max_verts + 1, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.bvh_hist), kMaxBuckets, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.epart_v), 2 * (limits->max_verts + 1), s);
   if (e != hipSuccess) return hip_fail(e, "ttie_set_workspace");
   return TTIE_OK;
@@ -249,8 +256,8 @@ ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_hos
   return TTIE_OK;
 }
 
-ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, int32_t* pairs, int64_t capacity,
-                            int64_t* n_pairs, void* stream) {
+ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, const double* x_end, int32_t* pairs,
+                            int64_t capacity, int64_t* n_pairs, void* stream) {
   if (ttie_status st = need_ws(ctx)) return st;
   if (ttie_status st = check_mesh(ctx, mesh)) return st;
   if (method != TTIE_BROAD_BRUTE && method != TTIE_BROAD_LBVH) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad method");
@@ -261,7 +268,7 @@ ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, in
   if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
     return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_broadphase(ctx, mesh, method, pairs, capacity, n_pairs, (hipStream_t)stream);
+  hipError_t e = launch_broadphase(ctx, mesh, method, x_end, pairs, capacity, n_pairs, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ttie_broadphase");
   return TTIE_OK;
 }
@@ -376,6 +383,32 @@ ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, c
   DeviceGuard g(ctx->device);
   hipError_t e = launch_bsr_mv(n_rows, row_ptr, col_idx, vals, x, y, precision, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ttie_bsr_mv");
+  return TTIE_OK;
+}
+
+ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                     const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
+                     double* info, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (n_rows < 0 || n_rows > ctx->lim.max_verts) return fail(TTIE_ERR_CAPACITY, "n_rows outside [0, max_verts]");
+  if (n_rows > 0 && (!row_ptr || !col_idx || !vals || !b || !x)) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL array");
+  if (precision != TTIE_FP64 && precision != TTIE_MIXED) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad precision");
+  if (max_iter < 0 || !(tol >= 0.0) || !(mu_rel >= 0.0)) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad parameters");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_pcg(ctx, n_rows, row_ptr, col_idx, vals, b, scale, x, mu_rel, max_iter, tol, precision, info,
+                            (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_pcg");
+  return TTIE_OK;
+}
+
+ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double* x, const void* d, double* out,
+                      int precision, void* stream) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  if (n_verts < 0 || (n_verts > 0 && (!x || !d || !out))) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad argument");
+  if (precision != TTIE_FP64 && precision != TTIE_MIXED) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad precision");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_axpy(n_verts, alpha, x, d, out, precision, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_axpy");
   return TTIE_OK;
 }
 

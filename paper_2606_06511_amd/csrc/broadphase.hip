@@ -2,22 +2,26 @@
 // pair tests with a spatial structure; this is a linear BVH over Morton-sorted triangles).
 //
 //   k_bp_init      reset the pair counter
-//   k_tri_boxes    exact FP64 bounding box per triangle; per-block bounds of the box centres
+//   k_tri_boxes    exact FP64 bounding box per triangle (optionally swept to a second position);
+//                  per-block bounds of the box centres
 //                  (order-preserving integer keys)
-//   k_morton       reduce those bounds, then a 30-bit Morton code per box centre
-//   radix sort     (code, triangle) pairs by code (rocPRIM), stable
+//   k_morton       reduce those bounds, then a 30-bit Morton code per box centre; counts of
+//                  the top bits (about two triangles per bucket), each triangle taking its
+//                  rank inside its bucket from the counting atomic
+//   scan, scatter  counting sort of the triangles by bucket (order inside a bucket arbitrary)
 //   k_levels       an implicit complete 4-ary tree over the sorted leaves: node (l, k) covers
 //                  leaves [k 4^l, (k+1) 4^l); boxes are reduced level by level in LDS, four
 //                  levels per launch, so building needs no atomics and no fences.  The first
 //                  launch also writes the sorted leaf records (FP64 box, vertex ids).
-//   k_traverse     one lane per leaf s, depth first over the subtrees holding leaves after s,
+//   k_traverse     two lanes per leaf s (its own 256-leaf subtree, staged in LDS, and the rest
+//                  of the tree), depth first over the subtrees holding leaves after s,
 //                  four child boxes per visit and a 64-bit mask stack, descending where the
 //                  FP32 boxes (rounded outwards) overlap, so every unordered pair is reported
 //                  once; a leaf is confirmed by the exact closed FP64 box test and the
 //                  shared-vertex test; pairs are staged per wave in LDS (ballot + mbcnt) and
 //                  flushed with one atomic per full buffer
 //   k_brute        all i < j without a shared vertex (no box test)
-#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 
@@ -40,8 +44,8 @@ __global__ void k_bp_init(Counters* c) {
   }
 }
 
-__global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict__ x, int64_t nv,
-                                                        const int32_t* __restrict__ tris, int64_t nt,
+__global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict__ x, const double* __restrict__ x_end,
+                                                        int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
                                                         double* __restrict__ tbox, float* __restrict__ centre,
                                                         uint32_t* __restrict__ part, Counters* ctr) {
   __shared__ uint32_t smin[3][kBpBlock], smax[3][kBpBlock];
@@ -60,6 +64,11 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
         const double q = x[3 * (int64_t)v + c];
         lo[c] = k == 0 ? q : fmin(lo[c], q);
         hi[c] = k == 0 ? q : fmax(hi[c], q);
+        if (x_end) {  // swept box: the triangle at both ends of the straight path
+          const double e = x_end[3 * (int64_t)v + c];
+          lo[c] = fmin(lo[c], e);
+          hi[c] = fmax(hi[c], e);
+        }
       }
     }
     if (!ok) bad = true;
@@ -105,8 +114,9 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ centre, int64_t nt,
-                                                     const uint32_t* __restrict__ part, int nparts,
-                                                     uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                                                     const uint32_t* __restrict__ part, int nparts, int bucket_shift,
+                                                     int32_t* __restrict__ hist, uint32_t* __restrict__ bucket,
+                                                     int32_t* __restrict__ rank) {
   // every block reduces the per-block bounds of k_tri_boxes (a few KB, cached): a strided
   // pass per thread, then a tree in LDS
   __shared__ uint32_t red[6][kBpBlock];
@@ -137,8 +147,23 @@ __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ c
       const float f = (centre[3 * t + c] - lo[c]) * inv[c];
       q[c] = (uint32_t)fminf(fmaxf(f, 0.f), 1023.f);
     }
-    keys[t] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    vals[t] = (int32_t)t;
+    const uint32_t code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    const uint32_t bk = code >> bucket_shift;
+    bucket[t] = bk;
+    rank[t] = atomicAdd(&hist[bk], 1);  // the order inside a bucket is arbitrary
+  }
+}
+
+// counting-sort scatter: triangle t goes to offset[bucket] + rank; then every bucket count is
+// cleared for the next call
+__global__ void __launch_bounds__(kBpBlock) k_scatter(int64_t nt, int64_t nbuckets, const uint32_t* __restrict__ bucket,
+                                                      const int32_t* __restrict__ rank,
+                                                      const int32_t* __restrict__ offset, int32_t* __restrict__ ids,
+                                                      int32_t* __restrict__ hist) {
+  const int64_t n = nt > nbuckets ? nt : nbuckets;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < nt) ids[offset[bucket[t]] + rank[t]] = (int32_t)t;
+    if (t < nbuckets) hist[t] = 0;
   }
 }
 
@@ -232,7 +257,7 @@ __device__ __forceinline__ bool overlap32(const float q[6], const Box32& b) {
 // pair; positions come from a ballot and the lanes below (mbcnt), so the staging needs no
 // atomics.  Only a flush -- when the wave's buffer is nearly full, and once at the end --
 // reserves global space, with one atomic for the whole buffer.
-constexpr int kEmitCap = 512;
+constexpr int kEmitCap = 256;
 
 struct WaveEmitter {
   int2* buf;       // this wave's kEmitCap slots in LDS
@@ -273,37 +298,42 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
   return (b % 8) * per + b / 8;
 }
 
-// One lane per leaf s: depth-first over the subtrees holding leaves after s.  A visited node
+// Two lanes per leaf s, depth-first over the subtrees holding leaves after s.  A visited node
 // tests its four children at once (one contiguous load); the pending children of every level
 // on the current path are kept as 4-bit masks in one 64-bit word, so no stack is needed.
-// Block b's 256 queries are exactly the leaves of the level-4 node b, so that subtree (leaf
-// records, leaf boxes and the 84 boxes above them) is staged in LDS first and most visits
-// never leave the CU; only right-hand neighbours outside it are read from global memory.
+// Block b's 256 queries are exactly the leaves of the level-4 node b.  That subtree (leaf
+// records, leaf boxes and the 84 boxes above them) is staged in LDS; waves 0-3 search it
+// (the local part, LDS only) while waves 4-7 search everything after it from the root (the
+// global part), so each query costs the larger of the two instead of their sum.
 constexpr int kSubLevels = 4;                       // 4^4 = 256 = kBpBlock leaves per block
 constexpr int kSubInner = 64 + 16 + 4;              // boxes of levels 1..3 inside the subtree
+constexpr int kTravThreads = 2 * kBpBlock;          // a local and a global lane per query
+constexpr int kTravWaves = kTravThreads / 64;
 
-__global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
-                                                       const LeafRec* __restrict__ leaves, int32_t* pairs,
-                                                       int64_t cap, Counters* ctr) {
-  __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+__global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
+                                                           const LeafRec* __restrict__ leaves, int32_t* pairs,
+                                                           int64_t cap, Counters* ctr) {
+  __shared__ int2 stage[kTravWaves][kEmitCap];
   __shared__ int64_t lm[24], loff[24];  // the level table, indexed by each lane's own level
-  __shared__ int wcount[kBpBlock / 64];
+  __shared__ int wcount[kTravWaves];
   __shared__ uint32_t bbase;
   __shared__ LeafRec sleaf[kBpBlock];
   __shared__ Box32 sbox[kBpBlock + kSubInner];     // level 0 at [0,256), level 1 at 256.., 2, 3
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int qi = threadIdx.x % kBpBlock;             // query within the block
+  const bool global_part = threadIdx.x >= kBpBlock;
   if (threadIdx.x < 24) {
     lm[threadIdx.x] = lv.m[threadIdx.x];
     loff[threadIdx.x] = lv.off[threadIdx.x];
   }
   // stage the block's subtree
-  const int64_t s = blk * kBpBlock + threadIdx.x;
-  if (s < n) {
-    sleaf[threadIdx.x] = leaves[s];
-    sbox[threadIdx.x] = boxes[s];
+  const int64_t s = blk * kBpBlock + qi;
+  if (!global_part && s < n) {
+    sleaf[qi] = leaves[s];
+    sbox[qi] = boxes[s];
   }
-  {
-    const int t = threadIdx.x;
+  if (global_part) {
+    const int t = qi;
     int l = 0, local = 0, base = kBpBlock;  // thread t < 84 loads inner box t
     if (t < 64) { l = 1; local = t; base = kBpBlock; }
     else if (t < 80) { l = 2; local = t - 64; base = kBpBlock + 64; }
@@ -314,19 +344,22 @@ __global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, con
     }
   }
   __syncthreads();
-  // node (l, k) lies in the staged subtree when l < 4 and k >> 2(4-l) == blk
 
   WaveEmitter em{stage[threadIdx.x / 64], 0};
   int status = 0;
-  bool active = s < n;
+  // the local part starts at the block's level-4 node (the root if the tree is lower); the
+  // global part starts at the root and skips that node
+  const bool small_tree = lv.L <= kSubLevels;
+  bool active = s < n && !(global_part && small_tree);
   float q[6];
   LeafRec me;
-  int l = lv.L;
-  int64_t k = 0;
+  int l = global_part || small_tree ? lv.L : kSubLevels;
+  int64_t k = global_part || small_tree ? 0 : blk;
+  const int top = l;  // the traversal ends when it climbs past this level
   uint64_t pend = 0;  // level j's remaining children at bits [4(j-1), 4j)
   if (active) {
-    me = sleaf[threadIdx.x];
-    const Box32 b = sbox[threadIdx.x];
+    me = sleaf[qi];
+    const Box32 b = sbox[qi];
     for (int c = 0; c < 3; ++c) {
       q[c] = b.lo[c];
       q[3 + c] = b.hi[c];
@@ -342,10 +375,12 @@ __global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, con
     int64_t c0 = 0;
     bool local_children = false;
     if (active) {
-      // children of (l, k): (l-1, 4k+i); only those holding leaves after s
+      // children of (l, k): (l-1, 4k+i); only those holding leaves after s, and in the
+      // global part never the block's own subtree
       c0 = 4 * k;
       const int lc = l - 1;
-      const int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
+      int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
+      if (global_part && lc == kSubLevels) first = blk + 1;
       const int64_t mcount = lm[lc];
       local_children = lc < kSubLevels && (c0 >> (2 * (kSubLevels - lc))) == blk;
       Box32 cb[4];
@@ -395,7 +430,7 @@ __global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, con
       } else {
         // climb to the nearest level with a pending child and move to that child
         for (;;) {
-          if (l >= lv.L) {
+          if (l >= top) {
             active = false;
             break;
           }
@@ -412,13 +447,13 @@ __global__ void __launch_bounds__(kBpBlock) k_traverse(int64_t n, Levels lv, con
       }
     }
   }
-  // block-level final flush: one atomic reserves the space of all four waves
+  // block-level final flush: one atomic reserves the space of all the block's waves
   const int wave = threadIdx.x / 64;
   if (__lane_id() == 0) wcount[wave] = em.count;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tot = 0;
-    for (int w = 0; w < kBpBlock / 64; ++w) tot += wcount[w];
+    for (int w = 0; w < kTravWaves; ++w) tot += wcount[w];
     bbase = tot ? atomicAdd(&ctr->n_pairs, tot) : 0u;
   }
   __syncthreads();
@@ -463,14 +498,6 @@ __global__ void k_bp_finish(Counters* ctr, int64_t cap, int64_t* n_pairs) {
   }
 }
 
-size_t sort_temp_bytes(int64_t n) {
-  size_t bytes = 0;
-  uint32_t* k = nullptr;
-  int32_t* v = nullptr;
-  if (rocprim::radix_sort_pairs(nullptr, bytes, k, k, v, v, (unsigned)n, 0, 30) != hipSuccess) return 0;
-  return bytes;
-}
-
 static unsigned bp_grid(int64_t n, unsigned cap = 4096) {
   int64_t g = (n + kBpBlock - 1) / kBpBlock;
   if (g < 1) g = 1;
@@ -493,8 +520,8 @@ Levels make_levels(int64_t n) {
   return lv;
 }
 
-hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pairs, int64_t capacity,
-                             int64_t* n_pairs, hipStream_t s) {
+hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int32_t* pairs,
+                             int64_t capacity, int64_t* n_pairs, hipStream_t s) {
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   const int64_t nt = m->n_tris;
@@ -508,7 +535,6 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pa
     double* tbox = wsp<double>(c, L.bvh_tbox);
     float* centre = wsp<float>(c, L.bvh_centroid);
     uint32_t* k1 = wsp<uint32_t>(c, L.bvh_keys);
-    uint32_t* k2 = wsp<uint32_t>(c, L.bvh_keys2);
     int32_t* v1 = wsp<int32_t>(c, L.bvh_vals);
     int32_t* v2 = wsp<int32_t>(c, L.bvh_vals2);
     Box32* boxes = wsp<Box32>(c, L.bvh_boxes);
@@ -516,15 +542,24 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pa
     const Levels lv = make_levels(nt);
     stage_begin(c, TTIE_STAGE_BP_BOXES, s);
     const unsigned gb = bp_grid(nt, kBoundsBlocks);
-    k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, m->n_verts, m->tris, nt, tbox, centre, wsp<uint32_t>(c, L.bvh_part),
-                                        ctr);
-    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, k1, v1);
+    // buckets: the top bits of the 30-bit code, about two triangles per bucket
+    int bits = 8;
+    while (bits < 20 && ((int64_t)1 << (bits + 1)) <= nt) ++bits;
+    const int64_t nbuckets = (int64_t)1 << bits;
+    int32_t* hist = wsp<int32_t>(c, L.bvh_hist);
+    int32_t* offset = wsp<int32_t>(c, L.bvh_offset);
+    k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, x_end, m->n_verts, m->tris, nt, tbox, centre,
+                                        wsp<uint32_t>(c, L.bvh_part), ctr);
+    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, 30 - bits, hist, k1,
+                                              v1);
     stage_end(c, TTIE_STAGE_BP_BOXES, s);
-    size_t bytes = L.bvh_sort_tmp_bytes;
     stage_begin(c, TTIE_STAGE_BP_SORT, s);
-    hipError_t e = rocprim::radix_sort_pairs(c->ws + L.bvh_sort_tmp, bytes, k1, k2, v1, v2, (unsigned)nt, 0, 30, s);
-    stage_end(c, TTIE_STAGE_BP_SORT, s);
+    size_t bytes = L.scan_tmp_bytes;
+    hipError_t e = rocprim::exclusive_scan(c->ws + L.scan_tmp, bytes, hist, offset, 0, (size_t)nbuckets,
+                                           rocprim::plus<int32_t>(), s);
     if (e != hipSuccess) return e;
+    k_scatter<<<bp_grid(std::max<int64_t>(nt, nbuckets)), kBpBlock, 0, s>>>(nt, nbuckets, k1, v1, offset, v2, hist);
+    stage_end(c, TTIE_STAGE_BP_SORT, s);
     stage_begin(c, TTIE_STAGE_BP_BUILD, s);
     for (int l0 = 0; l0 < lv.L; l0 += 4)
       k_levels<<<(unsigned)((lv.m[l0] + kBpBlock - 1) / kBpBlock), kBpBlock, 0, s>>>(l0, lv, tbox, v2, m->tris, boxes,
@@ -533,7 +568,7 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pa
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     // one lane per leaf, block count rounded up to a multiple of the 8 XCDs
     const int64_t nb = ((nt + kBpBlock - 1) / kBpBlock + 7) / 8 * 8;
-    k_traverse<<<(unsigned)nb, kBpBlock, 0, s>>>(nt, lv, boxes, leaves, pairs, capacity, ctr);
+    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, pairs, capacity, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
   k_bp_finish<<<1, 64, 0, s>>>(ctr, capacity, n_pairs);

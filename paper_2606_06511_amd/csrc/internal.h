@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/ttie.h"
 #include "pair.h"
 
@@ -45,8 +47,8 @@ struct Counters {
 struct Layout {
   size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
       scan_tmp_bytes;
-  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_sort_tmp, bvh_sort_tmp_bytes, bvh_boxes, bvh_leaves,
-      bvh_tbox, bvh_centroid, bvh_part, touched, inc2;
+  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
+      bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state;
   size_t total;
 };
 
@@ -86,8 +88,13 @@ void stage_end(Ctx* c, int stage, hipStream_t s);
 
 // launchers (return hipSuccess or the first error)
 hipError_t launch_fill_zero_i32(int32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, int32_t* pairs, int64_t capacity,
-                             int64_t* n_pairs, hipStream_t s);
+hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int32_t* pairs,
+                             int64_t capacity, int64_t* n_pairs, hipStream_t s);
+hipError_t launch_pcg(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                      const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
+                      double* info, hipStream_t s);
+hipError_t launch_axpy(int64_t n_verts, double alpha, const double* x, const void* d, double* out, int precision,
+                       hipStream_t s);
 hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                        int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
@@ -97,6 +104,5 @@ hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* 
                          const void* x, void* y, int precision, hipStream_t s);
 hipError_t launch_init_counters(Ctx* c, hipStream_t s);
 size_t scan_temp_bytes(int64_t n);
-size_t sort_temp_bytes(int64_t n);
 
 }  // namespace ttie

@@ -53,17 +53,21 @@ SIGNATURES = {
     "ttie_workspace_size": (_i32, [_vp, ctypes.POINTER(Limits), ctypes.POINTER(_sz)]),
     "ttie_set_workspace": (_i32, [_vp, ctypes.POINTER(Limits), _vp, _sz, _vp]),
     "ttie_get_status": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
-    "ttie_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _i64, _vp, _vp]),
+    "ttie_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _i64, _vp, _vp]),
     "ttie_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, ctypes.POINTER(Options), _vp, _vp, _vp,
                          _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "ttie_get_hits": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
     "ttie_hvp": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i32, _vp]),
     "ttie_bsr_mv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "ttie_pcg": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32,
+                        ctypes.c_double, _i32, _vp, _vp]),
+    "ttie_axpy": (_i32, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, _i32, _vp]),
     "ttie_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "ttie_read_timers": (_i32, [_vp, _i32, _vp, _vp]),
 }
 
-STAGES = ["bp_boxes", "bp_sort", "bp_build", "bp_traverse", "screen", "screen_exact", "derivs", "assembly", "hvp"]
+STAGES = ["bp_boxes", "bp_sort", "bp_build", "bp_traverse", "screen", "screen_exact", "derivs", "assembly", "hvp",
+          "pcg"]
 
 _lib = None
 
@@ -157,8 +161,9 @@ class Context:
         if st != TTIE_OK:
             raise TTIEError(st, "reported by a kernel")
 
-    def broadphase(self, x, tris, method=BROAD_LBVH, capacity=None, out=None):
-        """Candidate pairs: returns (pairs (capacity, 2) int32, n_pairs (1,) int64), both on the GPU."""
+    def broadphase(self, x, tris, method=BROAD_LBVH, capacity=None, out=None, x_end=None):
+        """Candidate pairs: returns (pairs (capacity, 2) int32, n_pairs (1,) int64), both on the GPU.
+        With x_end, boxes cover the triangles at x and at x_end (swept candidates)."""
         if capacity is None:
             capacity = self.limits[2]
         m = self._mesh(x, tris)
@@ -167,7 +172,10 @@ class Context:
             n = torch.zeros(1, dtype=torch.int64, device=self.device)
         else:
             pairs, n = out
-        _check(lib().ttie_broadphase(self.handle, ctypes.byref(m), method, _ptr(pairs), capacity, _ptr(n), _stream()))
+        if x_end is not None:
+            assert x_end.dtype == torch.float64 and x_end.is_contiguous() and x_end.shape == x.shape
+        _check(lib().ttie_broadphase(self.handle, ctypes.byref(m), method, _ptr(x_end), _ptr(pairs), capacity, _ptr(n),
+                                     _stream()))
         return pairs, n
 
     def evaluate(self, x, tris, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1,
@@ -230,6 +238,27 @@ class Context:
         if out is None:
             out = torch.empty_like(v)
         _check(lib().ttie_hvp(self.handle, ctypes.byref(m), _ptr(v), _ptr(out), mode, _stream()))
+        return out
+
+    def pcg(self, row_ptr, col_idx, vals, b, scale=1.0, mu_rel=1e-3, max_iter=50, tol=1e-6, out=None, info=None):
+        """Jacobi-PCG on (H + mu I) x = scale * b on the device; returns (x, info) with info a
+        (4,) float64 GPU tensor {iterations, relative residual, mu, x . (scale b)}."""
+        precision = FP64 if vals.dtype == torch.float64 else MIXED
+        if out is None:
+            out = torch.empty_like(b)
+        if info is None:
+            info = torch.zeros(4, dtype=torch.float64, device=b.device)
+        _check(lib().ttie_pcg(self.handle, row_ptr.shape[0] - 1, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(b),
+                              float(scale), _ptr(out), float(mu_rel), int(max_iter), float(tol), precision, _ptr(info),
+                              _stream()))
+        return out, info
+
+    def axpy(self, x, alpha, d, out=None):
+        """out = x + alpha * d (x, out float64 positions; d in either precision)."""
+        precision = FP64 if d.dtype == torch.float64 else MIXED
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().ttie_axpy(self.handle, x.shape[0], float(alpha), _ptr(x), _ptr(d), _ptr(out), precision, _stream()))
         return out
 
     def set_timing(self, stages=None):

@@ -44,6 +44,7 @@ __all__ = [
     "batch_problems",
     "union",
     "integer_grid_triangles",
+    "submesh_near",
 ]
 
 
@@ -324,3 +325,18 @@ def integer_grid_triangles(seed: int, n: int, lo: int = -3, hi: int = 3):
     x = rng.integers(lo, hi + 1, size=(3 * n, 3)).astype(np.float64)
     tris = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
     return _finish(x, tris)
+
+
+def submesh_near(x, tris, point, n_tris: int):
+    """The n_tris triangles whose centroids are nearest to ``point`` (ties by index), with
+    their vertices re-indexed in order of first appearance."""
+    cent = x[tris].mean(axis=1)
+    d2 = np.sum((cent - np.asarray(point, dtype=np.float64)) ** 2, axis=1)
+    order = np.lexsort((np.arange(len(tris)), d2))[:n_tris]
+    sel = tris[np.sort(order)]
+    flat = sel.ravel()
+    _, first = np.unique(flat, return_index=True)
+    old_ids = flat[np.sort(first)]
+    remap = np.full(len(x), -1, dtype=np.int64)
+    remap[old_ids] = np.arange(len(old_ids))
+    return _finish(x[old_ids], remap[sel])

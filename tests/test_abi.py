@@ -65,7 +65,7 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.ttie_workspace_size(None, ctypes.byref(lim), ctypes.byref(size)) == 1
     assert lib.ttie_eval(None, None, None, None, 0, None, None, None, None, None, None, None, None, 0, None,
                          None, None) == 1
-    assert lib.ttie_broadphase(None, None, 0, None, 0, None, None) == 1
+    assert lib.ttie_broadphase(None, None, 0, None, None, 0, None, None) == 1
     assert lib.ttie_hvp(None, None, None, None, 0, None) == 1
     with pytest.raises(ttie.TTIEError):
         ttie.Context(0)
