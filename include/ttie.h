@@ -72,7 +72,7 @@ enum { TTIE_FP64 = 0, TTIE_MIXED = 1 };
  *  RAW_EQ4       Eq. 4 unchanged (indefinite on every intersecting pair) */
 enum { TTIE_PSD_PER_PART = 0, TTIE_PSD_NEAREST = 1, TTIE_PSD_PAPER_LITERAL = 2, TTIE_PSD_RAW_EQ4 = 3 };
 enum { TTIE_INTERVAL_EQ1 = 0, TTIE_INTERVAL_APPENDIX_HALF = 1 };
-enum { TTIE_BROAD_BRUTE = 0, TTIE_BROAD_LBVH = 1 };
+enum { TTIE_BROAD_BRUTE = 0, TTIE_BROAD_LBVH = 1, TTIE_BROAD_HASH = 2 };
 enum { TTIE_HVP_EXACT = 0, TTIE_HVP_PSD = 1 };
 /* per-pair flag codes written by ttie_eval */
 enum { TTIE_PAIR_NONE = 0, TTIE_PAIR_HIT = 1, TTIE_PAIR_ADJACENT = 2, TTIE_PAIR_DEGENERATE_FRAME = 3 };
@@ -126,10 +126,14 @@ ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_hos
 
 /* ---- broad phase (candidate pairs) ---------------------------------------------------
  * Writes the canonical candidate set {(i, j) : i < j, no shared vertex index} of the mesh
- * -- for TTIE_BROAD_LBVH restricted to pairs whose closed float64 bounding boxes overlap
- * on all three axes (Sec. 1.2 uses spatial hashing for this step; this is an LBVH over
- * 30-bit Morton codes) -- into pairs (capacity x 2 int32, 8-byte aligned) in an unspecified
- * order, and the number of candidates into *n_pairs (device int64).  x_end (nullable,
+ * -- for TTIE_BROAD_LBVH and TTIE_BROAD_HASH restricted to pairs whose closed float64
+ * bounding boxes overlap on all three axes -- into pairs (capacity x 2 int32, 8-byte aligned)
+ * in an unspecified order, and the number of candidates into *n_pairs (device int64).
+ * TTIE_BROAD_LBVH: a BVH over 30-bit Morton codes.  TTIE_BROAD_HASH: the spatial hashing of
+ * Sec. 1.2 -- a uniform grid (cell size twice the mean largest box extent) whose cells are
+ * hashed into buckets; it suits meshes of even triangle size: a box covering more than
+ * 2^20 cells or lying far outside the grid latches TTIE_ERR_UNSUPPORTED, and more than
+ * 8 (cell, triangle) entries per triangle of limits.max_tris latch TTIE_ERR_CAPACITY.  x_end (nullable,
  * n_verts x 3 float64) makes every box cover the triangle at both x and x_end, so the list
  * holds every pair that can intersect anywhere on the straight path from x to x_end (the
  * line search of the Newton consumer).  When the count exceeds `capacity` only the first
@@ -162,6 +166,36 @@ ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs
                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
                       int64_t* n_hits, void* stream);
 
+/* ---- batches of independent problems --------------------------------------------------
+ * Many independent problems (each a mesh, or the union of several meshes, whose pairs are
+ * evaluated among themselves only) in one call: the hot path of Sec. 1 applied problem by
+ * problem, with every stage one launch for the whole batch.  The caller concatenates the
+ * problems into one ttie_mesh: problem p owns vertices [vert_off[p], vert_off[p+1]) and
+ * triangles [tri_off[p], tri_off[p+1]), and its triangles index vertices with global ids.
+ * vert_off and tri_off are DEVICE int64 arrays of n_problems + 1 entries, non-decreasing, from
+ * 0 to n_verts and n_tris.  1 <= n_problems <= TTIE_MAX_PROBLEMS. */
+#define TTIE_MAX_PROBLEMS 4096
+
+/* LBVH broad phase of a batch: as ttie_broadphase with TTIE_BROAD_LBVH, except that no pair
+ * joins triangles of two problems (one tree over the batch; each query searches only the
+ * sorted range of its own problem).  tri_off that does not tile [0, n_tris) latches
+ * TTIE_ERR_INVALID_ARGUMENT. */
+ttie_status ttie_batch_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems, const int64_t* tri_off,
+                                  const double* x_end, int32_t* pairs, int64_t capacity, int64_t* n_pairs,
+                                  void* stream);
+
+/* Evaluation of a batch: exactly ttie_eval over the concatenated mesh (the Hessian of a
+ * batch is block diagonal, problem by problem, when no pair joins two problems), plus
+ * energies (device float64, n_problems): energies[p] is the sum of T over the intersecting
+ * pairs whose first vertex (vertex 0 of the pair's first triangle) lies in problem p, summed
+ * per vertex and then in vertex order.  vert_off that does not tile [0, n_verts) latches
+ * TTIE_ERR_INVALID_ARGUMENT. */
+ttie_status ttie_batch_eval(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems, const int64_t* vert_off,
+                            const int32_t* pairs, const int64_t* n_pairs, int64_t pair_capacity,
+                            const ttie_options* opts, double* energies, double* energy, void* grad, uint8_t* flags,
+                            double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity,
+                            int64_t* n_blocks, int64_t* n_hits, void* stream);
+
 /* Copies the last evaluation's intersecting pairs, sorted by (i, j), to HOST buffers of
  * `capacity` entries: pair indices (i, j) int32 x 2, t_c (float64 x 2), T (float64) and the
  * interval gradients a = dt_c^0, b = dt_c^1 (float64 x 18 each, converted from the
@@ -193,6 +227,14 @@ ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, c
 ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                      const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
                      double* info, void* stream);
+
+/* Matrix-free variant of ttie_pcg (the same iteration, mu and preconditioner): H is the PSD
+ * Hessian of the last ttie_eval, applied from its per-hit records as the sum over hits of
+ * J^T M J (J = [a^T; b^T], Eq. 4 with the evaluation's PSD core) without assembling the BSR
+ * matrix; its diagonal comes from the same records.  n_rows must equal the last evaluation's
+ * n_verts; b and x are in that evaluation's precision.  Valid until the next ttie_eval. */
+ttie_status ttie_pcg_mf(ttie_ctx* ctx, int64_t n_rows, const void* b, double scale, void* x, double mu_rel,
+                        int max_iter, double tol, double* info, void* stream);
 
 /* out = x + alpha * d for n_verts x 3 positions: x and out float64, d in `precision`. */
 ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double* x, const void* d, double* out,

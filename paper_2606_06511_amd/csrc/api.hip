@@ -11,7 +11,7 @@ namespace ttie {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int64_t kMaxBuckets = (int64_t)1 << 20;  // Morton buckets of the broad-phase sort
+constexpr int64_t kMaxBuckets = (int64_t)1 << kMortonBucketBits;  // buckets of the broad-phase sort
 
 // one scan scratch serves every scan: the vertex-sized ones and the bucket counts
 static int64_t scan_len(const ttie_limits& lim) { return std::max<int64_t>(lim.max_verts, kMaxBuckets) + 1; }
@@ -42,7 +42,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.scan_tmp_bytes = scan_bytes;
   L.scan_tmp = take(scan_bytes);
   L.bvh_keys = take(T * 4);
-  L.bvh_keys2 = take(T * 4);
+  L.bvh_qend = take(T * 4);
   L.bvh_vals = take(T * 4);
   L.bvh_vals2 = take(T * 4);
   L.bvh_hist = take((size_t)kMaxBuckets * 4);
@@ -52,6 +52,14 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.bvh_tbox = take(T * 6 * 8);
   L.bvh_centroid = take(T * 3 * 4);
   L.bvh_part = take(512 * 6 * 4);
+  L.bvh_ext = take(512 * 8);
+  L.hash_grid = take(64);
+  const size_t E = (size_t)kHashEntriesPerTri * T;
+  L.hash_key = take(E * 8);
+  L.hash_tri = take(E * 4);
+  L.hash_rank = take(E * 4);
+  L.hash_skey = take(E * 8);
+  L.hash_stri = take(E * 4);
   L.touched = take(6 * H * 4);
   L.inc2 = take(6 * H * sizeof(Incidence));
   L.pcg_vec = take(5 * 3 * (size_t)lim.max_verts * 8);
@@ -256,11 +264,13 @@ ttie_status ttie_get_status(ttie_ctx* ctx, void* stream, ttie_status* status_hos
   return TTIE_OK;
 }
 
-ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, const double* x_end, int32_t* pairs,
-                            int64_t capacity, int64_t* n_pairs, void* stream) {
+static ttie_status broadphase_impl(ttie_ctx* ctx, const ttie_mesh* mesh, int method, int n_prob, const int64_t* tri_off,
+                                   const double* x_end, int32_t* pairs, int64_t capacity, int64_t* n_pairs,
+                                   void* stream, const char* who) {
   if (ttie_status st = need_ws(ctx)) return st;
   if (ttie_status st = check_mesh(ctx, mesh)) return st;
-  if (method != TTIE_BROAD_BRUTE && method != TTIE_BROAD_LBVH) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad method");
+  if (method != TTIE_BROAD_BRUTE && method != TTIE_BROAD_LBVH && method != TTIE_BROAD_HASH)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad method");
   if (!n_pairs || (capacity > 0 && !pairs) || capacity < 0)
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad pair output");
   if (capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "capacity exceeds limits.max_pairs");
@@ -268,15 +278,32 @@ ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, co
   if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
     return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_broadphase(ctx, mesh, method, x_end, pairs, capacity, n_pairs, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "ttie_broadphase");
+  hipError_t e = launch_broadphase(ctx, mesh, method, x_end, n_prob, tri_off, pairs, capacity, n_pairs,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, who);
   return TTIE_OK;
 }
 
-ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
-                      int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags, double* pair_T,
-                      int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
-                      int64_t* n_hits, void* stream) {
+ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, const double* x_end, int32_t* pairs,
+                            int64_t capacity, int64_t* n_pairs, void* stream) {
+  return broadphase_impl(ctx, mesh, method, 1, nullptr, x_end, pairs, capacity, n_pairs, stream, "ttie_broadphase");
+}
+
+ttie_status ttie_batch_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems, const int64_t* tri_off,
+                                  const double* x_end, int32_t* pairs, int64_t capacity, int64_t* n_pairs,
+                                  void* stream) {
+  if (n_problems < 1 || n_problems > TTIE_MAX_PROBLEMS)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "n_problems outside [1, TTIE_MAX_PROBLEMS]");
+  if (!tri_off) return fail(TTIE_ERR_INVALID_ARGUMENT, "tri_off is NULL");
+  return broadphase_impl(ctx, mesh, TTIE_BROAD_LBVH, n_problems, tri_off, x_end, pairs, capacity, n_pairs, stream,
+                         "ttie_batch_broadphase");
+}
+
+static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                              int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags,
+                              double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity,
+                              int64_t* n_blocks, int64_t* n_hits, int n_prob, const int64_t* vert_off,
+                              double* energies, void* stream, const char* who) {
   if (ttie_status st = need_ws(ctx)) return st;
   if (ttie_status st = check_mesh(ctx, mesh)) return st;
   if (!opts) return fail(TTIE_ERR_INVALID_ARGUMENT, "options are NULL");
@@ -295,14 +322,35 @@ ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs
     return fail(TTIE_ERR_CAPACITY, "block_capacity exceeds limits.max_blocks");
   DeviceGuard g(ctx->device);
   hipError_t e = launch_eval(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, bsr ? row_ptr : nullptr,
-                             col_idx, vals, bsr ? block_capacity : 0, n_blocks, n_hits, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "ttie_eval");
+                             col_idx, vals, bsr ? block_capacity : 0, n_blocks, n_hits, n_prob, vert_off, energies,
+                             (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, who);
   ctx->last_precision = opts->precision;
   ctx->last_psd = opts->psd_mode;
   ctx->last_interval = opts->interval;
   ctx->last_nverts = mesh->n_verts;
   ctx->last_valid = 1;
   return TTIE_OK;
+}
+
+ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                      int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags, double* pair_T,
+                      int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
+                      int64_t* n_hits, void* stream) {
+  return eval_entry(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, row_ptr, col_idx, vals,
+                    block_capacity, n_blocks, n_hits, 0, nullptr, nullptr, stream, "ttie_eval");
+}
+
+ttie_status ttie_batch_eval(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems, const int64_t* vert_off,
+                            const int32_t* pairs, const int64_t* n_pairs, int64_t pair_capacity,
+                            const ttie_options* opts, double* energies, double* energy, void* grad, uint8_t* flags,
+                            double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity,
+                            int64_t* n_blocks, int64_t* n_hits, void* stream) {
+  if (n_problems < 1 || n_problems > TTIE_MAX_PROBLEMS)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "n_problems outside [1, TTIE_MAX_PROBLEMS]");
+  if (!vert_off || !energies) return fail(TTIE_ERR_INVALID_ARGUMENT, "vert_off or energies is NULL");
+  return eval_entry(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, row_ptr, col_idx, vals,
+                    block_capacity, n_blocks, n_hits, n_problems, vert_off, energies, stream, "ttie_batch_eval");
 }
 
 ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij, double* tc, double* T, double* a, double* b,
@@ -398,6 +446,19 @@ ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, cons
   hipError_t e = launch_pcg(ctx, n_rows, row_ptr, col_idx, vals, b, scale, x, mu_rel, max_iter, tol, precision, info,
                             (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ttie_pcg");
+  return TTIE_OK;
+}
+
+ttie_status ttie_pcg_mf(ttie_ctx* ctx, int64_t n_rows, const void* b, double scale, void* x, double mu_rel, int max_iter,
+                        double tol, double* info, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation to take the Hessian from");
+  if (n_rows != ctx->last_nverts) return fail(TTIE_ERR_INVALID_ARGUMENT, "n_rows differs from the last evaluation");
+  if (n_rows > 0 && (!b || !x)) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL array");
+  if (max_iter < 0 || !(tol >= 0.0) || !(mu_rel >= 0.0)) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad parameters");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_pcg_mf(ctx, n_rows, b, scale, x, mu_rel, max_iter, tol, info, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_pcg_mf");
   return TTIE_OK;
 }
 

@@ -41,15 +41,19 @@ __device__ __forceinline__ float key2f(uint32_t k) {
 __global__ void k_bp_init(Counters* c) {
   if (threadIdx.x == 0) {
     c->n_pairs = 0;
+    c->n_entries = 0;
   }
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict__ x, const double* __restrict__ x_end,
                                                         int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
                                                         double* __restrict__ tbox, float* __restrict__ centre,
-                                                        uint32_t* __restrict__ part, Counters* ctr) {
+                                                        uint32_t* __restrict__ part, double* __restrict__ ext_part,
+                                                        Counters* ctr) {
   __shared__ uint32_t smin[3][kBpBlock], smax[3][kBpBlock];
+  __shared__ double sext[kBpBlock];
   uint32_t lmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, lmax[3] = {0u, 0u, 0u};
+  double ext = 0.0;  // sum of the boxes' largest extents (the hash grid's cell size)
   bool bad = false;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -72,6 +76,7 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
       }
     }
     if (!ok) bad = true;
+    ext += fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
     for (int c = 0; c < 3; ++c) {
       tbox[6 * t + c] = lo[c];
       tbox[6 * t + 3 + c] = hi[c];
@@ -86,21 +91,27 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
     smin[c][threadIdx.x] = lmin[c];
     smax[c][threadIdx.x] = lmax[c];
   }
+  sext[threadIdx.x] = ext;
   __syncthreads();
   for (int w = kBpBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if (threadIdx.x < w) {
       for (int c = 0; c < 3; ++c) {
         smin[c][threadIdx.x] = min(smin[c][threadIdx.x], smin[c][threadIdx.x + w]);
         smax[c][threadIdx.x] = max(smax[c][threadIdx.x], smax[c][threadIdx.x + w]);
       }
+      sext[threadIdx.x] += sext[threadIdx.x + w];
+    }
     __syncthreads();
   }
-  // per-block partial bounds; k_morton reduces them (the kernel boundary orders the two)
-  if (threadIdx.x == 0)
+  // per-block partial bounds and extent sums; the next kernel reduces them (the kernel
+  // boundary orders the two)
+  if (threadIdx.x == 0) {
     for (int c = 0; c < 3; ++c) {
       part[6 * blockIdx.x + c] = smin[c][0];
       part[6 * blockIdx.x + 3 + c] = smax[c][0];
     }
+    ext_part[blockIdx.x] = sext[0];
+  }
 }
 
 // spread the low 10 bits of v to every third bit
@@ -113,10 +124,30 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
+// the problem owning item t: the last p with off[p] <= t, clamped to [0, n_prob)
+__device__ __forceinline__ int problem_of(const int64_t* __restrict__ off, int n_prob, int64_t t) {
+  int lo = 0, hi = n_prob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bucket of a triangle: its problem in the top bits, then the top mbits of its Morton code, so
+// every problem's triangles form one contiguous range of the sorted order.
 __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ centre, int64_t nt,
-                                                     const uint32_t* __restrict__ part, int nparts, int bucket_shift,
+                                                     const uint32_t* __restrict__ part, int nparts,
+                                                     const int64_t* __restrict__ tri_off, int n_prob, int mbits,
                                                      int32_t* __restrict__ hist, uint32_t* __restrict__ bucket,
-                                                     int32_t* __restrict__ rank) {
+                                                     int32_t* __restrict__ rank, Counters* ctr) {
+  if (tri_off && blockIdx.x == 0) {
+    // the problem ranges must tile [0, nt)
+    bool bad = threadIdx.x == 0 && (tri_off[0] != 0 || tri_off[n_prob] != nt);
+    for (int p = threadIdx.x; p < n_prob; p += kBpBlock) bad |= tri_off[p] > tri_off[p + 1];
+    if (bad) atomicCAS(&ctr->status, 0, STATUS_INVALID);
+  }
   // every block reduces the per-block bounds of k_tri_boxes (a few KB, cached): a strided
   // pass per thread, then a tree in LDS
   __shared__ uint32_t red[6][kBpBlock];
@@ -148,7 +179,8 @@ __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ c
       q[c] = (uint32_t)fminf(fmaxf(f, 0.f), 1023.f);
     }
     const uint32_t code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    const uint32_t bk = code >> bucket_shift;
+    const uint32_t p = tri_off ? (uint32_t)problem_of(tri_off, n_prob, t) : 0u;
+    const uint32_t bk = (p << mbits) | (code >> (30 - mbits));
     bucket[t] = bk;
     rank[t] = atomicAdd(&hist[bk], 1);  // the order inside a bucket is arbitrary
   }
@@ -172,6 +204,7 @@ __global__ void __launch_bounds__(kBpBlock) k_scatter(int64_t nt, int64_t nbucke
 // (l-1, 4k .. 4k+3), contiguous in memory; level L (m[L] = 1) is the root.
 struct Levels {
   int L;
+  int lt;  // levels lt..L are staged in LDS by the traversal (lt > L: none)
   int64_t m[24];
   int64_t off[24];
 };
@@ -201,10 +234,14 @@ __device__ __forceinline__ Box32 box_union(const Box32& a, const Box32& b) {
 
 // Reduces levels l0+1 .. l0+4 from the boxes of level l0 (l0 = 0: made from the sorted
 // leaves, which are written too).  Block b owns level-l0 nodes [256 b, 256 b + 256).
+// For a batch (tri_off != NULL) the leaf pass also writes qend[k]: the end of the sorted range of
+// the problem owning leaf k (problem p + 1 starts at the offset of its first bucket).
 __global__ void __launch_bounds__(kBpBlock) k_levels(int l0, Levels lv, const double* __restrict__ tbox,
                                                      const int32_t* __restrict__ ids,
                                                      const int32_t* __restrict__ tris, Box32* __restrict__ boxes,
-                                                     LeafRec* __restrict__ leaves) {
+                                                     LeafRec* __restrict__ leaves, const int64_t* __restrict__ tri_off,
+                                                     int n_prob, int mbits, const int32_t* __restrict__ offset,
+                                                     int32_t* __restrict__ qend) {
   __shared__ Box32 sh[kBpBlock];
   const int64_t k = (int64_t)blockIdx.x * kBpBlock + threadIdx.x;
   Box32 bx;
@@ -225,6 +262,10 @@ __global__ void __launch_bounds__(kBpBlock) k_levels(int l0, Levels lv, const do
       }
       r.tri = t;
       leaves[k] = r;
+      if (tri_off) {
+        const int p = problem_of(tri_off, n_prob, t);
+        qend[k] = p + 1 < n_prob ? offset[(int64_t)(p + 1) << mbits] : (int32_t)lv.m[0];
+      }
       boxes[lv.off[0] + k] = bx;
     } else {
       bx = boxes[lv.off[l0] + k];
@@ -257,7 +298,7 @@ __device__ __forceinline__ bool overlap32(const float q[6], const Box32& b) {
 // pair; positions come from a ballot and the lanes below (mbcnt), so the staging needs no
 // atomics.  Only a flush -- when the wave's buffer is nearly full, and once at the end --
 // reserves global space, with one atomic for the whole buffer.
-constexpr int kEmitCap = 256;
+constexpr int kEmitCap = 128;
 
 struct WaveEmitter {
   int2* buf;       // this wave's kEmitCap slots in LDS
@@ -305,13 +346,17 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
 // records, leaf boxes and the 84 boxes above them) is staged in LDS; waves 0-3 search it
 // (the local part, LDS only) while waves 4-7 search everything after it from the root (the
 // global part), so each query costs the larger of the two instead of their sum.
+// The top levels of the tree (those that fit kTopCap boxes, never below level 4) are staged
+// in LDS too, so the global part reads only the levels 3..0 of other blocks' subtrees.
 constexpr int kSubLevels = 4;                       // 4^4 = 256 = kBpBlock leaves per block
 constexpr int kSubInner = 64 + 16 + 4;              // boxes of levels 1..3 inside the subtree
 constexpr int kTravThreads = 2 * kBpBlock;          // a local and a global lane per query
 constexpr int kTravWaves = kTravThreads / 64;
+constexpr int kTopCap = 864;                        // 27 KB of top-level boxes
 
 __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
-                                                           const LeafRec* __restrict__ leaves, int32_t* pairs,
+                                                           const LeafRec* __restrict__ leaves,
+                                                           const int32_t* __restrict__ qend, int32_t* pairs,
                                                            int64_t cap, Counters* ctr) {
   __shared__ int2 stage[kTravWaves][kEmitCap];
   __shared__ int64_t lm[24], loff[24];  // the level table, indexed by each lane's own level
@@ -319,7 +364,12 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
   __shared__ uint32_t bbase;
   __shared__ LeafRec sleaf[kBpBlock];
   __shared__ Box32 sbox[kBpBlock + kSubInner];     // level 0 at [0,256), level 1 at 256.., 2, 3
+  __shared__ Box32 stop[kTopCap];                   // levels lt..L, in storage order
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int lt = lv.lt;
+  const int64_t tbase = lt <= lv.L ? lv.off[lt] : 0;
+  const int ntop = lt <= lv.L ? (int)(lv.off[lv.L] + 1 - tbase) : 0;
+  for (int i = threadIdx.x; i < ntop; i += kTravThreads) stop[i] = boxes[tbase + i];
   const int qi = threadIdx.x % kBpBlock;             // query within the block
   const bool global_part = threadIdx.x >= kBpBlock;
   if (threadIdx.x < 24) {
@@ -353,11 +403,14 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
   bool active = s < n && !(global_part && small_tree);
   float q[6];
   LeafRec me;
+  // leaves after s up to the end of the query's problem (the whole tree without a batch)
+  int64_t last = n;
   int l = global_part || small_tree ? lv.L : kSubLevels;
   int64_t k = global_part || small_tree ? 0 : blk;
   const int top = l;  // the traversal ends when it climbs past this level
   uint64_t pend = 0;  // level j's remaining children at bits [4(j-1), 4j)
   if (active) {
+    if (qend) last = qend[s];
     me = sleaf[qi];
     const Box32 b = sbox[qi];
     for (int c = 0; c < 3; ++c) {
@@ -381,6 +434,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
       const int lc = l - 1;
       int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
       if (global_part && lc == kSubLevels) first = blk + 1;
+      const int64_t lastc = (last - 1) >> (2 * lc);  // the node holding the problem's last leaf
       const int64_t mcount = lm[lc];
       local_children = lc < kSubLevels && (c0 >> (2 * (kSubLevels - lc))) == blk;
       Box32 cb[4];
@@ -390,7 +444,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
 #pragma unroll
         for (int i = 0; i < 4; ++i) cb[i] = sbox[lb + li + i];
       } else {
-        const Box32* g = boxes + loff[lc] + c0;
+        const Box32* g = lc >= lt ? stop + (loff[lc] - tbase) + c0 : boxes + loff[lc] + c0;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (c0 + i < mcount) cb[i] = g[i];
@@ -398,7 +452,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t c = c0 + i;
-        if (c < mcount && c >= first && overlap32(q, cb[i])) mask |= 1u << i;
+        if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i])) mask |= 1u << i;
       }
     }
     // leaves: exact FP64 box test and the shared-vertex test, four candidates per visit
@@ -490,6 +544,216 @@ __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ 
   if (em.count > 0) em.flush(pairs, cap, ctr);
 }
 
+// ---- spatial hashing (the broad phase of Sec. 1.2) -----------------------------------------
+// A uniform grid of cell size h (twice the mean largest box extent) anchored at the lowest box
+// centre.  Every triangle is entered in each cell its FP64 box covers; entries are counting-
+// sorted by a hash of the cell (MurmurHash3's 64-bit finalizer), and a thread per entry tests
+// the later entries of its bucket that name the same cell.  A pair is reported only from its
+// reference cell -- the componentwise maximum of the two boxes' lowest cells, which both boxes
+// cover exactly when they overlap -- so each overlapping pair is found once, and the result is
+// the same canonical set as the LBVH's.
+//
+//   k_hash_cells    grid parameters (every block reduces the box partials the same way), cell
+//                   ranges, entries reserved per wave with one atomic, bucket ranks
+//   scan            bucket offsets
+//   k_hash_scatter  entries to their sorted places; bucket counts cleared for the next call
+//   k_hash_pairs    same-cell tests within buckets, exact box and shared-vertex tests, emission
+constexpr int kCellBits = 21;             // signed cell coordinates packed into 63 bits
+constexpr int64_t kCellLimit = 1 << 20;   // |cell index| bound
+
+struct HashGrid {
+  double org[3];
+  double h;
+};
+
+__device__ __forceinline__ int64_t cell_of(double v, double org, double h) { return (int64_t)floor((v - org) / h); }
+
+__device__ __forceinline__ uint64_t cell_key(int64_t cx, int64_t cy, int64_t cz) {
+  const uint64_t m = (1ull << kCellBits) - 1;
+  return (((uint64_t)cx & m) << (2 * kCellBits)) | (((uint64_t)cy & m) << kCellBits) | ((uint64_t)cz & m);
+}
+
+__device__ __forceinline__ uint32_t hash_bucket(uint64_t k, int bits) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return (uint32_t)(k >> (64 - bits));
+}
+
+__global__ void __launch_bounds__(kBpBlock) k_hash_cells(const double* __restrict__ tbox, int64_t nt,
+                                                         const uint32_t* __restrict__ part,
+                                                         const double* __restrict__ ext_part, int nparts, int hbits,
+                                                         int32_t* __restrict__ hist, uint64_t* __restrict__ key,
+                                                         int32_t* __restrict__ tri, int32_t* __restrict__ rank,
+                                                         int64_t ecap, HashGrid* grid, Counters* ctr) {
+  __shared__ uint32_t red[6][kBpBlock];
+  __shared__ double rext[kBpBlock];
+  __shared__ HashGrid sg;
+  uint32_t v[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
+  double e = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kBpBlock) {
+    for (int c = 0; c < 6; ++c) v[c] = c < 3 ? min(v[c], part[6 * b + c]) : max(v[c], part[6 * b + c]);
+    e += ext_part[b];
+  }
+  for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+  rext[threadIdx.x] = e;
+  __syncthreads();
+  for (int w = kBpBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      for (int c = 0; c < 6; ++c)
+        red[c][threadIdx.x] = c < 3 ? min(red[c][threadIdx.x], red[c][threadIdx.x + w])
+                                    : max(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+      rext[threadIdx.x] += rext[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double span = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      sg.org[c] = (double)key2f(red[c][0]);
+      span = fmax(span, (double)key2f(red[3 + c][0]) - sg.org[c]);
+    }
+    double h = 2.0 * rext[0] / (double)nt;
+    // keep the cell indices of the scene far inside the packed range
+    const double hmin = span / (double)(kCellLimit / 4);
+    if (!(h > hmin)) h = hmin;
+    if (!(h > 0.0) || !(h < 1.0e300)) h = 1.0;
+    sg.h = h;
+    if (blockIdx.x == 0) *grid = sg;
+  }
+  __syncthreads();
+  const HashGrid g = sg;
+  int status = 0;
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * kBpBlock; base < nt; base += (int64_t)gridDim.x * kBpBlock) {
+    const int64_t t = base + threadIdx.x;
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+    uint32_t n = 0;
+    if (t < nt) {
+      bool ok = true;
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = cell_of(tbox[6 * t + c], g.org[c], g.h);
+        hi[c] = cell_of(tbox[6 * t + 3 + c], g.org[c], g.h);
+        ok = ok && lo[c] > -kCellLimit && hi[c] < kCellLimit && hi[c] >= lo[c] && hi[c] - lo[c] < 1024;
+      }
+      if (ok) {
+        const int64_t cnt = (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+        if (cnt <= (1 << 20)) n = (uint32_t)cnt;
+        else ok = false;
+      }
+      if (!ok) status = STATUS_UNSUPPORTED;  // a box far outside the grid or over a million cells
+    }
+    // wave prefix sum of the entry counts, one atomic per wave
+    uint32_t incl = n;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    uint64_t wbase = 0;
+    if (lane == 63 && total) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->n_entries), (unsigned long long)total);
+    wbase = __shfl(wbase, 63);
+    int64_t slot = (int64_t)wbase + incl - n;
+    for (int64_t cx = lo[0]; cx <= hi[0] && n; ++cx)
+      for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
+        for (int64_t cz = lo[2]; cz <= hi[2]; ++cz, ++slot) {
+          if (slot >= ecap) {
+            status = STATUS_CAPACITY;
+            continue;
+          }
+          const uint64_t k = cell_key(cx, cy, cz);
+          key[slot] = k;
+          tri[slot] = (int32_t)t;
+          rank[slot] = atomicAdd(&hist[hash_bucket(k, hbits)], 1);
+        }
+  }
+  if (status) atomicCAS(&ctr->status, 0, status);
+}
+
+__global__ void __launch_bounds__(kBpBlock) k_hash_scatter(const Counters* ctr, int64_t ecap, int64_t nbuckets, int hbits,
+                                                           const uint64_t* __restrict__ key,
+                                                           const int32_t* __restrict__ tri,
+                                                           const int32_t* __restrict__ rank,
+                                                           const int32_t* __restrict__ offset,
+                                                           uint64_t* __restrict__ skey, int32_t* __restrict__ stri,
+                                                           int32_t* __restrict__ hist) {
+  const int64_t ne = min((int64_t)ctr->n_entries, ecap);
+  const int64_t n = ne > nbuckets ? ne : nbuckets;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < ne) {
+      const uint64_t k = key[e];
+      const int64_t pos = (int64_t)offset[hash_bucket(k, hbits)] + rank[e];
+      skey[pos] = k;
+      stri[pos] = tri[e];
+    }
+    if (e < nbuckets) hist[e] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, int64_t ecap, int64_t nbuckets, int hbits,
+                                                         const int32_t* __restrict__ offset,
+                                                         const uint64_t* __restrict__ skey,
+                                                         const int32_t* __restrict__ stri,
+                                                         const double* __restrict__ tbox,
+                                                         const int32_t* __restrict__ tris, const HashGrid* grid,
+                                                         int32_t* pairs, int64_t cap, Counters* out_ctr) {
+  __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+  WaveEmitter em{stage[threadIdx.x / 64], 0};
+  const int64_t ne = min((int64_t)ctr->n_entries, ecap);
+  const HashGrid g = *grid;
+  for (int64_t base = (int64_t)blockIdx.x * kBpBlock; base < ne; base += (int64_t)gridDim.x * kBpBlock) {
+    const int64_t e = base + threadIdx.x;
+    const bool active = e < ne;
+    uint64_t ka = 0;
+    int32_t a = 0;
+    int64_t end = 0;
+    double alo[3] = {0, 0, 0}, ahi[3] = {0, 0, 0};
+    int64_t acell[3] = {0, 0, 0};
+    int32_t av[3] = {0, 0, 0};
+    if (active) {
+      ka = skey[e];
+      a = stri[e];
+      const uint32_t b = hash_bucket(ka, hbits);
+      end = (int64_t)b + 1 < nbuckets ? offset[b + 1] : ne;
+      for (int c = 0; c < 3; ++c) {
+        alo[c] = tbox[6 * (int64_t)a + c];
+        ahi[c] = tbox[6 * (int64_t)a + 3 + c];
+        acell[c] = cell_of(alo[c], g.org[c], g.h);
+        av[c] = tris[3 * (int64_t)a + c];
+      }
+    }
+    // every lane walks the rest of its bucket; the loop runs while any lane has work, so the
+    // emitter always sees the whole wave
+    for (int64_t j = e + 1; __ballot(active && j < end); ++j) {
+      bool want = false;
+      int32_t other = 0;
+      if (active && j < end && skey[j] == ka) {
+        other = stri[j];
+        bool hit = true;
+        int64_t ref[3];
+        for (int c = 0; c < 3; ++c) {
+          const double blo = tbox[6 * (int64_t)other + c], bhi = tbox[6 * (int64_t)other + 3 + c];
+          hit = hit && alo[c] <= bhi && blo <= ahi[c];
+          const int64_t bc = cell_of(blo, g.org[c], g.h);
+          ref[c] = acell[c] > bc ? acell[c] : bc;
+        }
+        if (hit && cell_key(ref[0], ref[1], ref[2]) == ka) {
+          bool adj = false;
+          for (int k = 0; k < 3; ++k) {
+            const int32_t w = tris[3 * (int64_t)other + k];
+            adj |= w == av[0] || w == av[1] || w == av[2];
+          }
+          want = !adj;
+        }
+      }
+      em.push(want, a, other, pairs, cap, out_ctr);
+    }
+  }
+  if (em.count > 0) em.flush(pairs, cap, out_ctr);
+}
+
 __global__ void k_bp_finish(Counters* ctr, int64_t cap, int64_t* n_pairs) {
   if (threadIdx.x == 0) {
     const uint32_t np = ctr->n_pairs;
@@ -517,11 +781,19 @@ Levels make_levels(int64_t n) {
     m = (m + 3) / 4;
   }
   lv.L = l;
+  // the highest levels whose boxes fit the traversal's LDS cache, never below level 4
+  int64_t cum = 0;
+  lv.lt = l + 1;
+  for (int k = l; k >= kSubLevels; --k) {
+    if (cum + lv.m[k] > kTopCap) break;
+    cum += lv.m[k];
+    lv.lt = k;
+  }
   return lv;
 }
 
-hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int32_t* pairs,
-                             int64_t capacity, int64_t* n_pairs, hipStream_t s) {
+hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int n_prob,
+                             const int64_t* tri_off, int32_t* pairs, int64_t capacity, int64_t* n_pairs, hipStream_t s) {
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   const int64_t nt = m->n_tris;
@@ -531,7 +803,40 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     k_brute<<<grid, kBpBlock, 0, s>>>(m->tris, nt, pairs, capacity, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
-  } else if (nt >= 2) {
+  } else if (method == TTIE_BROAD_HASH && nt >= 2) {
+    double* tbox = wsp<double>(c, L.bvh_tbox);
+    const unsigned gb = bp_grid(nt, kBoundsBlocks);
+    int hbits = 8;
+    while (hbits < kMortonBucketBits && ((int64_t)1 << hbits) < 2 * nt) ++hbits;
+    const int64_t nbuckets = (int64_t)1 << hbits;
+    const int64_t ecap = (int64_t)kHashEntriesPerTri * c->lim.max_tris;
+    int32_t* hist = wsp<int32_t>(c, L.bvh_hist);
+    int32_t* offset = wsp<int32_t>(c, L.bvh_offset);
+    uint64_t* key = wsp<uint64_t>(c, L.hash_key);
+    int32_t* tri = wsp<int32_t>(c, L.hash_tri);
+    uint64_t* skey = wsp<uint64_t>(c, L.hash_skey);
+    int32_t* stri = wsp<int32_t>(c, L.hash_stri);
+    HashGrid* grid = wsp<HashGrid>(c, L.hash_grid);
+    stage_begin(c, TTIE_STAGE_BP_BOXES, s);
+    k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, x_end, m->n_verts, m->tris, nt, tbox, wsp<float>(c, L.bvh_centroid),
+                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), ctr);
+    k_hash_cells<<<bp_grid(nt), kBpBlock, 0, s>>>(tbox, nt, wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext),
+                                                  (int)gb, hbits, hist, key, tri, wsp<int32_t>(c, L.hash_rank), ecap,
+                                                  grid, ctr);
+    stage_end(c, TTIE_STAGE_BP_BOXES, s);
+    stage_begin(c, TTIE_STAGE_BP_SORT, s);
+    size_t bytes = L.scan_tmp_bytes;
+    hipError_t e = rocprim::exclusive_scan(c->ws + L.scan_tmp, bytes, hist, offset, 0, (size_t)nbuckets,
+                                           rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    k_hash_scatter<<<bp_grid(std::max<int64_t>(4 * nt, nbuckets)), kBpBlock, 0, s>>>(
+        ctr, ecap, nbuckets, hbits, key, tri, wsp<int32_t>(c, L.hash_rank), offset, skey, stri, hist);
+    stage_end(c, TTIE_STAGE_BP_SORT, s);
+    stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
+    k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
+                                                           m->tris, grid, pairs, capacity, ctr);
+    stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
+  } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
     float* centre = wsp<float>(c, L.bvh_centroid);
     uint32_t* k1 = wsp<uint32_t>(c, L.bvh_keys);
@@ -539,19 +844,24 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     int32_t* v2 = wsp<int32_t>(c, L.bvh_vals2);
     Box32* boxes = wsp<Box32>(c, L.bvh_boxes);
     LeafRec* leaves = wsp<LeafRec>(c, L.bvh_leaves);
+    int32_t* qend = wsp<int32_t>(c, L.bvh_qend);
     const Levels lv = make_levels(nt);
     stage_begin(c, TTIE_STAGE_BP_BOXES, s);
     const unsigned gb = bp_grid(nt, kBoundsBlocks);
-    // buckets: the top bits of the 30-bit code, about two triangles per bucket
+    // buckets: about two triangles per bucket; a batch spends the top bits on the problem
     int bits = 8;
-    while (bits < 20 && ((int64_t)1 << (bits + 1)) <= nt) ++bits;
-    const int64_t nbuckets = (int64_t)1 << bits;
+    while (bits < kMortonBucketBits && ((int64_t)1 << (bits + 1)) <= nt) ++bits;
+    int pbits = 0;
+    if (!tri_off) n_prob = 1;
+    while ((1 << pbits) < n_prob) ++pbits;
+    const int mbits = std::min(std::max(bits - pbits, 3), kMortonBucketBits - pbits);
+    const int64_t nbuckets = (int64_t)1 << (pbits + mbits);
     int32_t* hist = wsp<int32_t>(c, L.bvh_hist);
     int32_t* offset = wsp<int32_t>(c, L.bvh_offset);
     k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, x_end, m->n_verts, m->tris, nt, tbox, centre,
-                                        wsp<uint32_t>(c, L.bvh_part), ctr);
-    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, 30 - bits, hist, k1,
-                                              v1);
+                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), ctr);
+    k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, tri_off, n_prob,
+                                              mbits, hist, k1, v1, ctr);
     stage_end(c, TTIE_STAGE_BP_BOXES, s);
     stage_begin(c, TTIE_STAGE_BP_SORT, s);
     size_t bytes = L.scan_tmp_bytes;
@@ -562,13 +872,14 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     stage_end(c, TTIE_STAGE_BP_SORT, s);
     stage_begin(c, TTIE_STAGE_BP_BUILD, s);
     for (int l0 = 0; l0 < lv.L; l0 += 4)
-      k_levels<<<(unsigned)((lv.m[l0] + kBpBlock - 1) / kBpBlock), kBpBlock, 0, s>>>(l0, lv, tbox, v2, m->tris, boxes,
-                                                                                    leaves);
+      k_levels<<<(unsigned)((lv.m[l0] + kBpBlock - 1) / kBpBlock), kBpBlock, 0, s>>>(
+          l0, lv, tbox, v2, m->tris, boxes, leaves, tri_off, n_prob, mbits, offset, qend);
     stage_end(c, TTIE_STAGE_BP_BUILD, s);
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     // one lane per leaf, block count rounded up to a multiple of the 8 XCDs
     const int64_t nb = ((nt + kBpBlock - 1) / kBpBlock + 7) / 8 * 8;
-    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, pairs, capacity, ctr);
+    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, pairs, capacity,
+                                                     ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
   k_bp_finish<<<1, 64, 0, s>>>(ctr, capacity, n_pairs);

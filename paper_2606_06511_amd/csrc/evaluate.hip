@@ -381,6 +381,29 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
   if (status) latch(status_word, status);
 }
 
+// Energy of each problem of a batch: block p sums the per-vertex energies of its vertex range
+// in a fixed order (thread-strided, then a tree).  Runs before k_rows_final clears them.
+__global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_prob, const int64_t* __restrict__ vert_off,
+                                                           const double* __restrict__ epart, double* __restrict__ energies,
+                                                           Counters* ctr) {
+  __shared__ double red[kBlock];
+  const int p = blockIdx.x;
+  int64_t b = vert_off[p], e = vert_off[p + 1];
+  if (threadIdx.x == 0 && (b > e || b < 0 || e > nv || (p == 0 && b != 0) || (p == n_prob - 1 && e != nv)))
+    latch(&ctr->status, STATUS_INVALID);
+  b = max((int64_t)0, min(b, nv));
+  e = max(b, min(e, nv));
+  double acc = 0.0;
+  for (int64_t v = b + threadIdx.x; v < e; v += kBlock) acc += epart[v];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energies[p] = red[0];
+}
+
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_rows_final(int64_t nv, const double* __restrict__ x,
                                                        int32_t* __restrict__ cnt, int32_t* __restrict__ cur,
@@ -581,7 +604,8 @@ template <class S>
 static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                             int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags,
                             double* pair_T, int32_t* row_ptr, int32_t* col_idx, S* vals, int64_t block_cap,
-                            int64_t* n_blocks, int64_t* n_hits, hipStream_t s) {
+                            int64_t* n_blocks, int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies,
+                            hipStream_t s) {
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   HitGeom* hits = wsp<HitGeom>(c, L.hits);
@@ -628,6 +652,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   }
   k_rows_asm<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc2, recs, colbuf, bsr ? row_ptr : nullptr, col_idx,
                                          vals, block_cap, grad, epart, &ctr->status);
+  if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, epart, energies, ctr);
   k_rows_final<S><<<kRowBlocks, kBlock, 0, s>>>(nv, m->x, cnt, cur, ncol, epart, grad, blockpart, ctr);
   k_eval_finish<<<1, kBlock, 0, s>>>(kRowBlocks, blockpart, ctr, max_hits, bsr ? row_ptr : nullptr, nv, block_cap, energy,
                                  n_blocks, n_hits);
@@ -638,12 +663,12 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
 hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                        int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
-                       int64_t* n_hits, hipStream_t s) {
+                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, hipStream_t s) {
   if (o->precision == TTIE_FP64)
     return eval_impl<double>(c, m, pairs, n_pairs, pair_capacity, o, energy, (double*)grad, flags, pair_T, row_ptr, col_idx,
-                             (double*)vals, block_capacity, n_blocks, n_hits, s);
+                             (double*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
   return eval_impl<float>(c, m, pairs, n_pairs, pair_capacity, o, energy, (float*)grad, flags, pair_T, row_ptr, col_idx,
-                          (float*)vals, block_capacity, n_blocks, n_hits, s);
+                          (float*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
 }
 
 template <class S>

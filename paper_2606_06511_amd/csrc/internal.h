@@ -14,6 +14,9 @@ namespace ttie {
 
 // blocks of the row-assembly kernel (fixed, so the energy partial sums have a fixed order)
 constexpr int kRowBlocks = 512;
+constexpr int kMortonBucketBits = 22;  // at most 2^22 buckets in the broad-phase counting sort
+constexpr int kMaxProblems = TTIE_MAX_PROBLEMS;
+constexpr int kHashEntriesPerTri = 8;  // spatial-hash entries reserved per triangle
 
 // Per-hit assembly record in the evaluation's precision S.
 template <class S>
@@ -42,12 +45,13 @@ struct Counters {
   uint32_t n_defer;        // candidates whose signs need the exact fallback
   uint32_t n_touched;      // vertices touched by the hits of the current evaluation
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
+  uint64_t n_entries;      // (cell, triangle) entries of the spatial-hash broad phase
 };
 
 struct Layout {
   size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
       scan_tmp_bytes;
-  size_t bvh_keys, bvh_keys2, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
+  size_t bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state;
   size_t total;
 };
@@ -88,17 +92,21 @@ void stage_end(Ctx* c, int stage, hipStream_t s);
 
 // launchers (return hipSuccess or the first error)
 hipError_t launch_fill_zero_i32(int32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int32_t* pairs,
-                             int64_t capacity, int64_t* n_pairs, hipStream_t s);
+// n_prob problems own the triangle ranges [tri_off[p], tri_off[p + 1]) (device array; NULL:
+// one problem); no pair joins two problems
+hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const double* x_end, int n_prob,
+                             const int64_t* tri_off, int32_t* pairs, int64_t capacity, int64_t* n_pairs, hipStream_t s);
 hipError_t launch_pcg(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                       const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
                       double* info, hipStream_t s);
+hipError_t launch_pcg_mf(Ctx* c, int64_t n, const void* b, double scale, void* x, double mu_rel, int max_iter,
+                         double tol, double* info, hipStream_t s);
 hipError_t launch_axpy(int64_t n_verts, double alpha, const double* x, const void* d, double* out, int precision,
                        hipStream_t s);
 hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                        int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
-                       int64_t* n_hits, hipStream_t s);
+                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, hipStream_t s);
 hipError_t launch_hvp(Ctx* c, const ttie_mesh* m, const void* v, void* Hv, int mode, hipStream_t s);
 hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                          const void* x, void* y, int precision, hipStream_t s);

@@ -193,6 +193,128 @@ __global__ void __launch_bounds__(kPB) k_pcg_dir(int64_t n, S* __restrict__ p, c
     p[i] = (S)((double)z[i] + beta * (double)p[i]);
 }
 
+// ---- matrix-free variant: H applied from the last evaluation's per-hit records -------------
+// H = sum over hits of J^T M J with J = [a^T; b^T] (2 x 18), the PSD core M of the
+// evaluation.  Rows gather their incidences in pair-key order (the sorted lists the
+// evaluation leaves behind), so the products are deterministic.
+
+// raw diagonal of H per dof into dg (0 for untouched rows), partials of (sum, count) over the
+// rows holding hits, as the BSR variant takes them over the rows holding blocks
+template <class S>
+__global__ void __launch_bounds__(kPB) k_pcg_diag_mf(int64_t n, const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc,
+                                                     const AsmRec<S>* __restrict__ recs, S* __restrict__ dg,
+                                                     double* __restrict__ part) {
+  __shared__ double red[kPB];
+  double sum = 0.0, cnt = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+    const int32_t b = off[i], e = off[i + 1];
+    double d[3] = {0.0, 0.0, 0.0};
+    for (int32_t k = b; k < e; ++k) {
+      const Incidence in = inc[k];
+      const AsmRec<S>& r = recs[in.hit];
+      const int s = in.slot;
+      for (int l = 0; l < 6; ++l) {
+        if (r.vid[l] != r.vid[s]) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double as = r.a[3 * s + c], bs = r.b[3 * s + c], al = r.a[3 * l + c], bl = r.b[3 * l + c];
+          d[c] += (double)r.M[0] * as * al + (double)r.M[1] * (as * bl + bs * al) + (double)r.M[2] * bs * bl;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dg[3 * i + c] = (S)d[c];
+    if (e > b) {
+      sum += d[0] + d[1] + d[2];
+      cnt += 3.0;
+    }
+  }
+  block_partials(sum, cnt, part, red);
+}
+
+// as k_pcg_setup, with the diagonal from dinv (holding the raw diagonal on entry)
+template <class S>
+__global__ void __launch_bounds__(kPB) k_pcg_setup_mf(int64_t n, const S* __restrict__ b, double scale, S* __restrict__ x,
+                                                      S* __restrict__ r, S* __restrict__ z, S* __restrict__ p,
+                                                      S* __restrict__ dinv, double mu_rel,
+                                                      const double* __restrict__ pdiag, double* __restrict__ pout,
+                                                      PcgState* st) {
+  __shared__ double red[kPB];
+  const double dsum = grid_sum(pdiag, 0, red), dcnt = grid_sum(pdiag, 1, red);
+  const double mu = mu_rel * (dcnt > 0.0 ? dsum / dcnt : 1.0);
+  double rz = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * kPB) {
+    const double dg = (double)dinv[i] + mu;
+    const double di = dg > 0.0 ? 1.0 / dg : 1.0;
+    const double ri = scale * (double)b[i];
+    const double zi = di * ri;
+    dinv[i] = (S)di;
+    x[i] = (S)0.0;
+    r[i] = (S)ri;
+    z[i] = (S)zi;
+    p[i] = (S)zi;
+    rz += ri * zi;
+    bb += ri * ri;
+  }
+  block_partials(rz, bb, pout, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->mu = mu;
+    st->done = 0;
+    st->iters = 0;
+  }
+}
+
+// per hit: hv = J^T M (J p_local), 18 values
+template <class S>
+__global__ void __launch_bounds__(kPB) k_pcg_hits_mf(const AsmRec<S>* __restrict__ recs, const Counters* ctr,
+                                                     uint32_t max_hits, const S* __restrict__ p, S* __restrict__ hv,
+                                                     const PcgState* st) {
+  if (st->done) return;
+  const uint32_t H = min(ctr->last_hits, max_hits);
+  for (uint32_t h = blockIdx.x * kPB + threadIdx.x; h < H; h += gridDim.x * kPB) {
+    const AsmRec<S>& r = recs[h];
+    double ua = 0.0, ub = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double pv = p[3 * (int64_t)r.vid[k] + c];
+        ua += (double)r.a[3 * k + c] * pv;
+        ub += (double)r.b[3 * k + c] * pv;
+      }
+    const double wa = (double)r.M[0] * ua + (double)r.M[1] * ub, wb = (double)r.M[1] * ua + (double)r.M[2] * ub;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) hv[18 * (int64_t)h + k] = (S)(wa * (double)r.a[k] + wb * (double)r.b[k]);
+  }
+}
+
+// q = (H + mu I) p from the per-hit products, row by row in pair-key order; partials of p.q
+template <class S>
+__global__ void __launch_bounds__(kPB) k_pcg_rows_mf(int64_t n, const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc, const S* __restrict__ hv,
+                                                     const S* __restrict__ p, S* __restrict__ q,
+                                                     double* __restrict__ pq_part, const PcgState* st) {
+  if (st->done) return;
+  __shared__ double red[kPB];
+  const double mu = st->mu;
+  double pq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+    double acc[3] = {mu * (double)p[3 * i], mu * (double)p[3 * i + 1], mu * (double)p[3 * i + 2]};
+    for (int32_t k = off[i]; k < off[i + 1]; ++k) {
+      const Incidence in = inc[k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += (double)hv[18 * (int64_t)in.hit + 3 * in.slot + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[3 * i + c] = (S)acc[c];
+      pq += (double)p[3 * i + c] * acc[c];
+    }
+  }
+  block_partials(pq, 0.0, pq_part, red);
+}
+
 template <class S>
 __global__ void __launch_bounds__(kPB) k_pcg_xb(int64_t n, const S* __restrict__ x, const S* __restrict__ b,
                                                 double scale, double* __restrict__ part) {
@@ -249,6 +371,50 @@ static hipError_t pcg_impl(Ctx* c, int64_t n, const int32_t* row_ptr, const int3
   }
   stage_end(c, TTIE_STAGE_PCG, s);
   return hipGetLastError();
+}
+
+template <class S>
+static hipError_t pcg_mf_impl(Ctx* c, int64_t n, const S* b, double scale, S* x, double mu_rel, int max_iter, double tol,
+                              double* info, hipStream_t s) {
+  const Layout& L = c->L;
+  S* base = wsp<S>(c, L.pcg_vec);
+  const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
+  S *r = base, *z = base + m3, *p = base + 2 * m3, *q = base + 3 * m3, *dinv = base + 4 * m3;
+  double* part = wsp<double>(c, L.pcg_part);
+  double *pdiag = part, *pset = part + 4 * kPB, *pq = part + 8 * kPB, *pA = part + 12 * kPB, *pB = part + 16 * kPB;
+  PcgState* st = wsp<PcgState>(c, L.pcg_state);
+  const AsmRec<S>* recs = wsp<AsmRec<S>>(c, L.recs);
+  const int32_t* off = wsp<int32_t>(c, L.off);
+  const Incidence* inc = wsp<Incidence>(c, L.inc2);
+  S* hv = wsp<S>(c, L.hvbuf);
+  const Counters* ctr = wsp<Counters>(c, L.counters);
+  const uint32_t max_hits = (uint32_t)c->lim.max_hits;
+  const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (c->lim.max_hits + kPB - 1) / kPB));
+  stage_begin(c, TTIE_STAGE_PCG, s);
+  k_pcg_diag_mf<S><<<kPB, kPB, 0, s>>>(n, off, inc, recs, dinv, pdiag);
+  k_pcg_setup_mf<S><<<kPB, kPB, 0, s>>>(n, b, scale, x, r, z, p, dinv, mu_rel, pdiag, pset, st);
+  const double* rz_old = pset;
+  for (int it = 0; it < max_iter; ++it) {
+    double* rz_new = (it % 2 == 0) ? pA : pB;
+    k_pcg_hits_mf<S><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, p, hv, st);
+    k_pcg_rows_mf<S><<<kPB, kPB, 0, s>>>(n, off, inc, hv, p, q, pq, st);
+    k_pcg_update<S><<<kPB, kPB, 0, s>>>(n, x, r, z, p, q, dinv, rz_old, pq, rz_new, st);
+    k_pcg_dir<S><<<kPB, kPB, 0, s>>>(n, p, z, rz_old, rz_new, pset, tol, it, st);
+    rz_old = rz_new;
+  }
+  if (info) {
+    k_pcg_xb<S><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
+    k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
+  }
+  stage_end(c, TTIE_STAGE_PCG, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_mf(Ctx* c, int64_t n, const void* b, double scale, void* x, double mu_rel, int max_iter,
+                         double tol, double* info, hipStream_t s) {
+  if (c->last_precision == TTIE_FP64)
+    return pcg_mf_impl<double>(c, n, (const double*)b, scale, (double*)x, mu_rel, max_iter, tol, info, s);
+  return pcg_mf_impl<float>(c, n, (const float*)b, scale, (float*)x, mu_rel, max_iter, tol, info, s);
 }
 
 hipError_t launch_pcg(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,

@@ -18,23 +18,28 @@ from .energy import TTIE
 
 
 def newton(model: TTIE, x: torch.Tensor, steps: int = 20, pcg_iters: int = 50, pcg_tol: float = 1e-6,
-           mu_rel: float = 1e-3, armijo_c: float = 1e-4, beta: float = 0.5, max_halvings: int = 30):
+           mu_rel: float = 1e-3, armijo_c: float = 1e-4, beta: float = 0.5, max_halvings: int = 30,
+           matrix_free: bool = False):
     """Runs up to ``steps`` Newton steps from x (float64 on the GPU).  Returns the final
     positions and a list of per-step records {E, alpha, pcg_iters, pcg_resid, pairs, hits,
-    ms}; the last record holds the final energy."""
+    ms}; the last record holds the final energy.  ``matrix_free`` solves with the per-hit
+    Hessian records instead of the assembled BSR matrix (same system, no assembly)."""
     ctx = model.ctx
     x = x.detach().clone().contiguous()
     hist = []
     for _ in range(steps):
         t0 = time.perf_counter()
-        out = model.evaluate(x, hessian=True)
+        out = model.evaluate(x, hessian=not matrix_free)
         E = out["energy"].item()
         rec = {"E": E, "pairs": int(model.n_pairs.item()), "hits": int(out["n_hits"].item())}
         if E == 0.0:
             hist.append(rec)
             break
-        d, info = ctx.pcg(out["row_ptr"], out["col_idx"], out["vals"], out["grad"], scale=-1.0, mu_rel=mu_rel,
-                          max_iter=pcg_iters, tol=pcg_tol)
+        if matrix_free:
+            d, info = ctx.pcg_mf(out["grad"], scale=-1.0, mu_rel=mu_rel, max_iter=pcg_iters, tol=pcg_tol)
+        else:
+            d, info = ctx.pcg(out["row_ptr"], out["col_idx"], out["vals"], out["grad"], scale=-1.0, mu_rel=mu_rel,
+                              max_iter=pcg_iters, tol=pcg_tol)
         inf = info.cpu().tolist()
         gd = -inf[3]  # info[3] = d . (-g)
         pairs, n = model.candidates(x, ctx.axpy(x, 1.0, d))

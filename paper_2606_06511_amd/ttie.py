@@ -23,9 +23,10 @@ STATUS_NAMES = {
 FP64, MIXED = 0, 1
 PSD_PER_PART, PSD_NEAREST, PSD_PAPER_LITERAL, PSD_RAW_EQ4 = 0, 1, 2, 3
 INTERVAL_EQ1, INTERVAL_APPENDIX_HALF = 0, 1
-BROAD_BRUTE, BROAD_LBVH = 0, 1
+BROAD_BRUTE, BROAD_LBVH, BROAD_HASH = 0, 1, 2
 HVP_EXACT, HVP_PSD = 0, 1
 PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME = 0, 1, 2, 3
+MAX_PROBLEMS = 4096
 
 # every function the header declares, with (restype, argtypes)
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
@@ -56,11 +57,15 @@ SIGNATURES = {
     "ttie_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _i64, _vp, _vp]),
     "ttie_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, ctypes.POINTER(Options), _vp, _vp, _vp,
                          _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ttie_batch_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "ttie_batch_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(Options), _vp,
+                               _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "ttie_get_hits": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
     "ttie_hvp": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i32, _vp]),
     "ttie_bsr_mv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "ttie_pcg": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32,
                         ctypes.c_double, _i32, _vp, _vp]),
+    "ttie_pcg_mf": (_i32, [_vp, _i64, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32, ctypes.c_double, _vp, _vp]),
     "ttie_axpy": (_i32, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, _i32, _vp]),
     "ttie_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "ttie_read_timers": (_i32, [_vp, _i32, _vp, _vp]),
@@ -178,15 +183,49 @@ class Context:
                                      _stream()))
         return pairs, n
 
-    def evaluate(self, x, tris, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1,
-                 hessian=True, flags=False, pair_T=False, out=None):
-        """Energy, gradient and (optionally) the BSR Hessian.  Returns a dict of GPU tensors:
-        energy (1,) f64, grad (N,3), and when hessian: row_ptr, col_idx, vals, n_blocks;
-        n_hits; flags (P,) u8 and pair_T (P,) f64 when asked."""
+    def batch_broadphase(self, x, tris, tri_off, capacity=None, out=None, x_end=None):
+        """LBVH candidates of a batch of problems (tri_off: (n_problems + 1,) int64 on the GPU);
+        no pair joins two problems.  Returns (pairs, n_pairs) like ``broadphase``."""
+        if capacity is None:
+            capacity = self.limits[2]
         m = self._mesh(x, tris)
-        dev = self.device
+        assert tri_off.dtype == torch.int64 and tri_off.is_contiguous() and tri_off.device == self.device
+        if out is None:
+            pairs = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=self.device)
+            n = torch.zeros(1, dtype=torch.int64, device=self.device)
+        else:
+            pairs, n = out
+        if x_end is not None:
+            assert x_end.dtype == torch.float64 and x_end.is_contiguous() and x_end.shape == x.shape
+        _check(lib().ttie_batch_broadphase(self.handle, ctypes.byref(m), tri_off.shape[0] - 1, _ptr(tri_off),
+                                           _ptr(x_end), _ptr(pairs), capacity, _ptr(n), _stream()))
+        return pairs, n
+
+    def batch_evaluate(self, x, tris, vert_off, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART,
+                       interval=INTERVAL_EQ1, hessian=True, flags=False, pair_T=False, out=None):
+        """``evaluate`` over a batch (vert_off: (n_problems + 1,) int64 on the GPU), adding
+        ``energies`` (n_problems,) f64: the energy of every problem."""
+        assert vert_off.dtype == torch.int64 and vert_off.is_contiguous() and vert_off.device == self.device
+        n_prob = vert_off.shape[0] - 1
+        out = self._eval_outputs(x, pairs, precision, hessian, flags, pair_T, out)
+        if "energies" not in out:
+            out["energies"] = torch.zeros(n_prob, dtype=torch.float64, device=self.device)
+        m = self._mesh(x, tris)
         if n_pairs is None:
-            n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=dev)
+            n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=self.device)
+        opts = Options(precision, psd, interval, 0)
+        cap = out["col_idx"].shape[0] if hessian else 0
+        _check(lib().ttie_batch_eval(self.handle, ctypes.byref(m), n_prob, _ptr(vert_off), _ptr(pairs), _ptr(n_pairs),
+                                     pairs.shape[0], ctypes.byref(opts), _ptr(out["energies"]),
+                                     _ptr(out["energy"]), _ptr(out["grad"]), _ptr(out.get("flags")),
+                                     _ptr(out.get("pair_T")), _ptr(out.get("row_ptr")) if hessian else None,
+                                     _ptr(out.get("col_idx")) if hessian else None,
+                                     _ptr(out.get("vals")) if hessian else None, cap,
+                                     _ptr(out.get("n_blocks")) if hessian else None, _ptr(out["n_hits"]), _stream()))
+        return out
+
+    def _eval_outputs(self, x, pairs, precision, hessian, flags, pair_T, out):
+        dev = self.device
         dt = torch.float64 if precision == FP64 else torch.float32
         nv = x.shape[0]
         if out is None:
@@ -203,6 +242,18 @@ class Context:
                 out["flags"] = torch.empty(pairs.shape[0], dtype=torch.uint8, device=dev)
             if pair_T:
                 out["pair_T"] = torch.empty(pairs.shape[0], dtype=torch.float64, device=dev)
+        return out
+
+    def evaluate(self, x, tris, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1,
+                 hessian=True, flags=False, pair_T=False, out=None):
+        """Energy, gradient and (optionally) the BSR Hessian.  Returns a dict of GPU tensors:
+        energy (1,) f64, grad (N,3), and when hessian: row_ptr, col_idx, vals, n_blocks;
+        n_hits; flags (P,) u8 and pair_T (P,) f64 when asked."""
+        m = self._mesh(x, tris)
+        dev = self.device
+        if n_pairs is None:
+            n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=dev)
+        out = self._eval_outputs(x, pairs, precision, hessian, flags, pair_T, out)
         opts = Options(precision, psd, interval, 0)
         cap = out["col_idx"].shape[0] if hessian else 0
         _check(lib().ttie_eval(self.handle, ctypes.byref(m), _ptr(pairs), _ptr(n_pairs), pairs.shape[0],
@@ -251,6 +302,17 @@ class Context:
         _check(lib().ttie_pcg(self.handle, row_ptr.shape[0] - 1, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(b),
                               float(scale), _ptr(out), float(mu_rel), int(max_iter), float(tol), precision, _ptr(info),
                               _stream()))
+        return out, info
+
+    def pcg_mf(self, b, scale=1.0, mu_rel=1e-3, max_iter=50, tol=1e-6, out=None, info=None):
+        """Matrix-free Jacobi-PCG with the PSD Hessian of the last evaluation (no BSR matrix);
+        b in that evaluation's precision.  Returns (x, info) like ``pcg``."""
+        if out is None:
+            out = torch.empty_like(b)
+        if info is None:
+            info = torch.zeros(4, dtype=torch.float64, device=b.device)
+        _check(lib().ttie_pcg_mf(self.handle, b.shape[0], _ptr(b), float(scale), _ptr(out), float(mu_rel),
+                                 int(max_iter), float(tol), _ptr(info), _stream()))
         return out, info
 
     def axpy(self, x, alpha, d, out=None):

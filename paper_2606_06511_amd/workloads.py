@@ -315,6 +315,22 @@ def batch_problems(seed: int = 0, n_problems: int = 64, smin: float = 2e3, smax:
     return out
 
 
+def concat_problems(problems):
+    """One batched mesh from independent problems ``(x, tris, ...)``: the vertices and
+    triangles concatenated (triangle indices re-based to global vertex ids) and the offsets
+    ``vert_off``, ``tri_off`` (int64, n + 1) of each problem's ranges."""
+    xs, ts = [], []
+    vert_off, tri_off = [0], [0]
+    for prob in problems:
+        x, t = prob[0], prob[1]
+        xs.append(x)
+        ts.append(t + vert_off[-1])
+        vert_off.append(vert_off[-1] + len(x))
+        tri_off.append(tri_off[-1] + len(t))
+    x, t = _finish(np.concatenate(xs), np.concatenate(ts))
+    return x, t, np.asarray(vert_off, np.int64), np.asarray(tri_off, np.int64)
+
+
 def integer_grid_triangles(seed: int, n: int, lo: int = -3, hi: int = 3):
     """n random triangles with integer vertices in {lo..hi}^3, each on its own 3 vertices.
 

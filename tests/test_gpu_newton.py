@@ -47,6 +47,34 @@ def test_pcg_matches_dense_solve(precision):
     assert info2.cpu().numpy()[0] == 3
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_matrix_free_pcg_matches_dense_and_bsr(precision):
+    x, tris = workloads.folded_cloth(seed=0, n=40)
+    m = _model(x, tris, max_pairs=1 << 16, max_hits=1 << 12, precision=precision)
+    out = m.evaluate(torch.from_numpy(x).cuda(), hessian=True)
+    nb = int(out["n_blocks"].item())
+    Hd = oracle.bsr_to_dense(out["row_ptr"].cpu().numpy(), out["col_idx"][:nb].cpu().numpy(),
+                             out["vals"][:nb].cpu().numpy().astype(np.float64), len(x))
+    g = out["grad"].cpu().numpy().astype(np.float64).ravel()
+    touched = np.repeat(np.diff(out["row_ptr"].cpu().numpy()) > 0, 3)
+    mu = 1e-3 * np.diag(Hd)[touched].mean()
+    d_ref = np.linalg.solve(Hd + mu * np.eye(len(g)), -g)
+    tol = 1e-12 if precision == 0 else 1e-6
+    d_mf, info_mf = m.ctx.pcg_mf(out["grad"], scale=-1.0, mu_rel=1e-3, max_iter=2000, tol=tol)
+    d_bsr, info_bsr = m.ctx.pcg(out["row_ptr"], out["col_idx"], out["vals"], out["grad"], scale=-1.0, mu_rel=1e-3,
+                                max_iter=2000, tol=tol)
+    i_mf, i_bsr = info_mf.cpu().numpy(), info_bsr.cpu().numpy()
+    assert i_mf[2] == pytest.approx(mu, rel=1e-12 if precision == 0 else 1e-6)
+    assert i_mf[2] == pytest.approx(i_bsr[2], rel=1e-12 if precision == 0 else 1e-6)
+    assert _rel(d_mf.cpu().numpy().ravel(), d_ref) <= (1e-8 if precision == 0 else 1e-3)
+    assert _rel(d_mf.cpu().numpy(), d_bsr.cpu().numpy()) <= (1e-8 if precision == 0 else 1e-3)
+    # without an evaluation of the same mesh there is no Hessian to use
+    from paper_2606_06511_amd import ttie
+
+    with pytest.raises(ttie.TTIEError):
+        m.ctx.pcg_mf(out["grad"][:-1].contiguous())
+
+
 def test_swept_candidates_match_oracle():
     x, tris = workloads.folded_cloth(seed=2, n=96)
     rng = np.random.default_rng(0)
@@ -105,6 +133,18 @@ def test_newton_subset_fp64_against_oracle(sphere_subset):
     assert E[0] == pytest.approx(E_ref[0], rel=1e-10)
     assert np.all(np.diff(E) <= 0) and np.all(np.diff(E_ref) <= 0)
     assert E[-1] <= 0.3 * E[0] and E_ref[-1] <= 0.3 * E_ref[0]
+
+
+def test_newton_subset_matrix_free_against_oracle(sphere_subset):
+    from paper_2606_06511_amd.newton import newton
+
+    x, tris = sphere_subset
+    m = _model(x, tris, max_pairs=1 << 20, max_hits=1 << 16)
+    _, E_ref, al_ref, _ = oracle.newton(x, tris, steps=8, pcg_iters=20)
+    _, hist = newton(m, torch.from_numpy(x).cuda(), steps=8, pcg_iters=20, matrix_free=True)
+    E = np.array([h["E"] for h in hist])
+    np.testing.assert_allclose(E, E_ref, rtol=1e-6)
+    assert [h["alpha"] for h in hist[:-1]] == list(al_ref)
 
 
 def test_newton_subset_mixed_decreases(sphere_subset):

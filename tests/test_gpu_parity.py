@@ -119,6 +119,45 @@ def test_lbvh_pairs(ctx, which):
     np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
 
 
+@pytest.mark.parametrize("which", ["cloth", "sphere_small", "icospheres", "integer_grid", "tiny"])
+def test_hash_pairs(ctx, which):
+    """The spatial-hash broad phase yields exactly the canonical set of the LBVH / the oracle."""
+    from paper_2606_06511_amd import ttie
+
+    if which == "cloth":
+        x, tris = workloads.folded_cloth(0)
+    elif which == "sphere_small":
+        x, tris = workloads.noisy_sphere(1, n_lon=128, n_bands=65)
+    elif which == "icospheres":
+        x, tris = workloads.two_icospheres(2)
+    elif which == "integer_grid":
+        x, tris = workloads.integer_grid_triangles(0, 300)  # many identical and touching boxes
+    else:
+        x, tris = workloads.integer_grid_triangles(1, 3)
+    ref = oracle.pairs(x, tris, oracle.BROAD_BOXES)
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    pairs, n = ctx.broadphase(xd, td, ttie.BROAD_HASH)
+    assert ctx.status() == ttie.TTIE_OK
+    assert int(n.item()) == len(ref)
+    np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+    # a second call reuses the cleared bucket counts
+    pairs, n = ctx.broadphase(xd, td, ttie.BROAD_HASH)
+    assert ctx.status() == ttie.TTIE_OK
+    np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+
+
+def test_hash_swept_pairs(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(2, n=96)
+    x_end = x + 0.01 * np.random.default_rng(0).normal(size=x.shape)
+    ref = oracle.pairs_swept(x, x_end, tris)
+    pairs, n = ctx.broadphase(_dev(x, torch.float64), _dev(tris, torch.int32), ttie.BROAD_HASH,
+                              x_end=_dev(x_end, torch.float64))
+    assert ctx.status() == ttie.TTIE_OK
+    np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+
+
 def test_lbvh_capacity_overflow_reports_count(ctx):
     from paper_2606_06511_amd import ttie
 
