@@ -48,11 +48,14 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.bvh_hist = take((size_t)kMaxBuckets * 4);
   L.bvh_offset = take(((size_t)kMaxBuckets + 1) * 4);
   L.bvh_boxes = take((2 * T + 64) * 32);  // implicit tree: at most 2T nodes of 32 B
-  L.bvh_leaves = take(T * 64);            // sorted leaf records
+  L.bvh_leaves = take((T + 4) * 64);      // sorted leaf records, padded to a multiple of 4
   L.bvh_tbox = take(T * 6 * 8);
   L.bvh_centroid = take(T * 3 * 4);
   L.bvh_part = take(512 * 6 * 4);
   L.bvh_ext = take(512 * 8);
+  // saved traversal states (32 B each) of the queries handed to the wave-cooperative kernel
+  L.bvh_heavy_bytes = (size_t)std::min<int64_t>(2 * T, (int64_t)1 << 20) * 32;
+  L.bvh_heavy = take(L.bvh_heavy_bytes);
   L.hash_grid = take(64);
   const size_t E = (size_t)kHashEntriesPerTri * T;
   L.hash_key = take(E * 8);

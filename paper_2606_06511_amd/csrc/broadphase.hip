@@ -42,6 +42,7 @@ __global__ void k_bp_init(Counters* c) {
   if (threadIdx.x == 0) {
     c->n_pairs = 0;
     c->n_entries = 0;
+    c->n_heavy = 0;
   }
 }
 
@@ -332,6 +333,28 @@ struct WaveEmitter {
   }
 };
 
+// End of an emitting kernel: one atomic reserves the space of all the block's waves (every
+// thread of the block must arrive here).
+template <int kWaves>
+__device__ __forceinline__ void block_flush(WaveEmitter& em, int* wcount, uint32_t* bbase, int32_t* pairs,
+                                            int64_t cap, Counters* ctr) {
+  const int wave = threadIdx.x / 64;
+  if (__lane_id() == 0) wcount[wave] = em.count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kWaves; ++w) tot += wcount[w];
+    *bbase = tot ? atomicAdd(&ctr->n_pairs, tot) : 0u;
+  }
+  __syncthreads();
+  int64_t base = *bbase;
+  for (int w = 0; w < wave; ++w) base += wcount[w];
+  for (int i = __lane_id(); i < em.count; i += 64) {
+    const int64_t slot = base + i;
+    if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = em.buf[i];
+  }
+}
+
 // Blocks are dealt to the XCDs round-robin; renumbering them so that each XCD runs a
 // contiguous range of logical blocks keeps each XCD's L2 on one region of the Morton order.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
@@ -354,10 +377,26 @@ constexpr int kTravThreads = 2 * kBpBlock;          // a local and a global lane
 constexpr int kTravWaves = kTravThreads / 64;
 constexpr int kTopCap = 864;                        // 27 KB of top-level boxes
 
+// A lane that has visited kTravBudget nodes hands the rest of its search to k_traverse_heavy
+// (one wave per query), by saving its depth-first state: the node it is about to visit and the
+// pending siblings of every ancestor up to its starting level.  Few queries get there -- those
+// whose boxes overlap hundreds of others, as in the fan of thin triangles around a pole.
+constexpr int kTravBudget = 128;
+
+struct TravState {
+  int32_t s;      // query leaf (sorted position)
+  int32_t part;   // 1: global part (skips the query's own level-4 subtree)
+  int32_t l, k;   // node about to be visited
+  uint64_t pend;  // pending children per level, 4 bits each
+  int32_t top;    // starting level
+  int32_t last;   // end of the query's problem (leaves)
+};
+
 __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
                                                            const LeafRec* __restrict__ leaves,
-                                                           const int32_t* __restrict__ qend, int32_t* pairs,
-                                                           int64_t cap, Counters* ctr) {
+                                                           const int32_t* __restrict__ qend, TravState* heavy,
+                                                           int64_t heavy_cap, int32_t* pairs, int64_t cap,
+                                                           Counters* ctr) {
   __shared__ int2 stage[kTravWaves][kEmitCap];
   __shared__ int64_t lm[24], loff[24];  // the level table, indexed by each lane's own level
   __shared__ int wcount[kTravWaves];
@@ -368,7 +407,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int lt = lv.lt;
   const int64_t tbase = lt <= lv.L ? lv.off[lt] : 0;
-  const int ntop = lt <= lv.L ? (int)(lv.off[lv.L] + 1 - tbase) : 0;
+  const int ntop = lt <= lv.L ? (int)(lv.off[lv.L] + 4 - tbase) : 0;  // through the padded root level
   for (int i = threadIdx.x; i < ntop; i += kTravThreads) stop[i] = boxes[tbase + i];
   const int qi = threadIdx.x % kBpBlock;             // query within the block
   const bool global_part = threadIdx.x >= kBpBlock;
@@ -419,11 +458,30 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
     }
   }
   // every node is visited at most once; the cap only guards against corruption
+  int visits = 0;
+  bool may_defer = true;  // one attempt: with the list full the lane finishes its own search
   for (int64_t iter = 0; __ballot(active); ++iter) {
     if (iter > 2 * n + 64) {
       status = STATUS_CAPACITY;
       break;
     }
+    // over budget: hand the remaining search to a wave of its own (when the list has room)
+    const bool over = active && may_defer && visits >= kTravBudget;
+    const uint32_t hs = wave_slot(over, &ctr->n_heavy);
+    if (over) may_defer = false;
+    if (over && (int64_t)hs < heavy_cap) {
+      TravState t;
+      t.s = (int32_t)s;
+      t.part = global_part ? 1 : 0;
+      t.l = l;
+      t.k = (int32_t)k;
+      t.pend = pend;
+      t.top = top;
+      t.last = (int32_t)last;
+      heavy[hs] = t;
+      active = false;
+    }
+    ++visits;
     uint32_t mask = 0;
     int64_t c0 = 0;
     bool local_children = false;
@@ -437,17 +495,22 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
       const int64_t lastc = (last - 1) >> (2 * lc);  // the node holding the problem's last leaf
       const int64_t mcount = lm[lc];
       local_children = lc < kSubLevels && (c0 >> (2 * (kSubLevels - lc))) == blk;
+      // the four child boxes in one batch, from the LDS copy of the block's subtree, the LDS
+      // copy of the top levels, or global memory (levels are padded to multiples of 4)
       Box32 cb[4];
       if (local_children) {
         const int lb = (lc == 0 ? 0 : (lc == 1 ? kBpBlock : (lc == 2 ? kBpBlock + 64 : kBpBlock + 80)));
         const int64_t li = c0 - (blk << (2 * (kSubLevels - lc)));
 #pragma unroll
         for (int i = 0; i < 4; ++i) cb[i] = sbox[lb + li + i];
-      } else {
-        const Box32* g = lc >= lt ? stop + (loff[lc] - tbase) + c0 : boxes + loff[lc] + c0;
+      } else if (lc >= lt) {
+        const int64_t ti = loff[lc] - tbase + c0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (c0 + i < mcount) cb[i] = g[i];
+        for (int i = 0; i < 4; ++i) cb[i] = stop[ti + i];
+      } else {
+        const Box32* g = boxes + loff[lc] + c0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cb[i] = g[i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -455,24 +518,34 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
         if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i])) mask |= 1u << i;
       }
     }
-    // leaves: exact FP64 box test and the shared-vertex test, four candidates per visit
+    // leaves: exact FP64 box test and the shared-vertex test, four candidates per visit; the
+    // four records are loaded together (the leaf array is padded like the levels)
     const bool leaf_level = active && l == 1;
+    bool want[4] = {false, false, false, false};
+    int32_t other[4] = {0, 0, 0, 0};
+    if (leaf_level && mask) {
+      LeafRec o[4];
+      if (local_children) {
+        const int64_t li = c0 - blk * kBpBlock;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      bool want = false;
-      int32_t other = 0;
-      if (leaf_level && (mask & (1u << i))) {
-        const LeafRec o = local_children ? sleaf[c0 + i - blk * kBpBlock] : leaves[c0 + i];
-        bool exact = true;
-        for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o.hi[c] && o.lo[c] <= me.hi[c];
+        for (int i = 0; i < 4; ++i) o[i] = sleaf[li + i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = leaves[c0 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bool exact = (mask >> i) & 1u;
+        for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o[i].hi[c] && o[i].lo[c] <= me.hi[c];
         bool adj = false;
         for (int a2 = 0; a2 < 3; ++a2)
-          for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o.v[b2];
-        want = exact && !adj;
-        other = o.tri;
+          for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o[i].v[b2];
+        want[i] = exact && !adj;
+        other[i] = o[i].tri;
       }
-      em.push(want, me.tri, other, pairs, cap, ctr);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], pairs, cap, ctr);
     if (active) {
       if (leaf_level) mask = 0;
       if (mask) {
@@ -501,22 +574,121 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
       }
     }
   }
-  // block-level final flush: one atomic reserves the space of all the block's waves
-  const int wave = threadIdx.x / 64;
-  if (__lane_id() == 0) wcount[wave] = em.count;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t tot = 0;
-    for (int w = 0; w < kTravWaves; ++w) tot += wcount[w];
-    bbase = tot ? atomicAdd(&ctr->n_pairs, tot) : 0u;
+  block_flush<kTravWaves>(em, wcount, &bbase, pairs, cap, ctr);
+  if (status) atomicCAS(&ctr->status, 0, status);
+}
+
+// One wave per saved query: the remaining nodes form a stack in LDS; every step each lane
+// takes one node, tests its four children, and pushes the overlapping inner children (or tests
+// the leaves), so a query that overlaps hundreds of leaves needs tens of steps instead of
+// hundreds of serial visits.  Everything is read from global memory.
+constexpr int kHeavyStack = 4096;
+
+__global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* __restrict__ boxes,
+                                                       const LeafRec* __restrict__ leaves,
+                                                       const TravState* __restrict__ heavy, int64_t heavy_cap,
+                                                       int32_t* pairs, int64_t cap, Counters* ctr) {
+  __shared__ int2 stack[kHeavyStack];
+  __shared__ int2 stage[kEmitCap];
+  __shared__ int wcount[1];
+  __shared__ uint32_t bbase;
+  WaveEmitter em{stage, 0};
+  const int lane = __lane_id();
+  int status = 0;
+  const int64_t nh = min((int64_t)ctr->n_heavy, heavy_cap);
+  for (int64_t it = blockIdx.x; it < nh; it += gridDim.x) {
+    const TravState t = heavy[it];
+    const int64_t s = t.s, blk = s / kBpBlock, last = t.last;
+    const bool global_part = t.part != 0;
+    const Box32 qb = boxes[lv.off[0] + s];
+    float q[6];
+    for (int c = 0; c < 3; ++c) {
+      q[c] = qb.lo[c];
+      q[3 + c] = qb.hi[c];
+    }
+    const LeafRec me = leaves[s];
+    // the remaining search: the node about to be visited and the pending siblings of its
+    // ancestors (slot j of pend: siblings at level j)
+    int sp = 0;
+    if (lane == 0) {
+      stack[sp++] = make_int2(t.l, t.k);
+      for (int j = t.l; j < t.top; ++j) {
+        const uint32_t pm = (uint32_t)(t.pend >> (4 * j)) & 15u;
+        const int32_t anc = t.k >> (2 * (j - t.l));
+        for (int i = 0; i < 4; ++i)
+          if (pm & (1u << i)) stack[sp++] = make_int2(j, (anc & ~3) + i);
+      }
+    }
+    sp = __shfl(sp, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    while (sp > 0) {
+      const int take = sp < 64 ? sp : 64;
+      int2 node = make_int2(0, 0);
+      const bool act = lane < take;
+      if (act) node = stack[sp - 1 - lane];
+      sp -= take;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      uint32_t mask = 0;
+      const int lc = node.x - 1;
+      const int64_t c0 = 4 * (int64_t)node.y;
+      if (act) {
+        int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
+        if (global_part && lc == kSubLevels) first = blk + 1;
+        const int64_t lastc = (last - 1) >> (2 * lc);
+        const int64_t mcount = lv.m[lc];
+        const Box32* g = boxes + lv.off[lc] + c0;
+        Box32 cb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cb[i] = g[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t c = c0 + i;
+          if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i])) mask |= 1u << i;
+        }
+      }
+      // leaves: exact tests and emission
+      bool want[4] = {false, false, false, false};
+      int32_t other[4] = {0, 0, 0, 0};
+      if (act && lc == 0 && mask) {
+        LeafRec o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = leaves[c0 + i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          bool exact = (mask >> i) & 1u;
+          for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o[i].hi[c] && o[i].lo[c] <= me.hi[c];
+          bool adj = false;
+          for (int a2 = 0; a2 < 3; ++a2)
+            for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o[i].v[b2];
+          want[i] = exact && !adj;
+          other[i] = o[i].tri;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], pairs, cap, ctr);
+      // inner children: onto the stack (wave prefix sum of the counts)
+      const int cnt = act && lc > 0 ? __popc(mask) : 0;
+      int incl = cnt;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+      }
+      const int total = __shfl(incl, 63);
+      if (sp + total > kHeavyStack) {
+        status = STATUS_CAPACITY;  // cannot happen for trees of at most 24 levels; never silent
+        break;
+      }
+      int pos = sp + incl - cnt;
+      for (int i = 0; i < 4; ++i)
+        if (cnt && (mask & (1u << i))) stack[pos++] = make_int2(lc, (int32_t)(c0 + i));
+      sp += total;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
   }
-  __syncthreads();
-  int64_t mybase = bbase;
-  for (int w = 0; w < wave; ++w) mybase += wcount[w];
-  for (int i = __lane_id(); i < em.count; i += 64) {
-    const int64_t slot = mybase + i;
-    if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = em.buf[i];
-  }
+  block_flush<1>(em, wcount, &bbase, pairs, cap, ctr);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
@@ -692,66 +864,127 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_scatter(const Counters* ctr, 
   }
 }
 
+// one entry's view of its bucket: its triangle's FP64 box, lowest cell and vertices
+struct HashQuery {
+  uint64_t key;
+  int32_t tri;
+  int64_t end;  // end of the bucket in sorted order
+  double lo[3], hi[3];
+  int64_t cell[3];
+  int32_t v[3];
+};
+
+__device__ __forceinline__ HashQuery hash_query(int64_t e, int64_t ne, int64_t nbuckets, int hbits,
+                                                const int32_t* __restrict__ offset, const uint64_t* __restrict__ skey,
+                                                const int32_t* __restrict__ stri, const double* __restrict__ tbox,
+                                                const int32_t* __restrict__ tris, const HashGrid& g) {
+  HashQuery h;
+  h.key = skey[e];
+  h.tri = stri[e];
+  const uint32_t b = hash_bucket(h.key, hbits);
+  h.end = (int64_t)b + 1 < nbuckets ? offset[b + 1] : ne;
+  for (int c = 0; c < 3; ++c) {
+    h.lo[c] = tbox[6 * (int64_t)h.tri + c];
+    h.hi[c] = tbox[6 * (int64_t)h.tri + 3 + c];
+    h.cell[c] = cell_of(h.lo[c], g.org[c], g.h);
+    h.v[c] = tris[3 * (int64_t)h.tri + c];
+  }
+  return h;
+}
+
+// entry j of the same bucket: a candidate iff it names the same cell, the closed FP64 boxes
+// overlap, this cell is the pair's reference cell, and no vertex is shared
+__device__ __forceinline__ bool hash_test(const HashQuery& h, int64_t j, const uint64_t* __restrict__ skey,
+                                          const int32_t* __restrict__ stri, const double* __restrict__ tbox,
+                                          const int32_t* __restrict__ tris, const HashGrid& g, int32_t& other) {
+  if (skey[j] != h.key) return false;
+  other = stri[j];
+  bool hit = true;
+  int64_t ref[3];
+  for (int c = 0; c < 3; ++c) {
+    const double blo = tbox[6 * (int64_t)other + c], bhi = tbox[6 * (int64_t)other + 3 + c];
+    hit = hit && h.lo[c] <= bhi && blo <= h.hi[c];
+    const int64_t bc = cell_of(blo, g.org[c], g.h);
+    ref[c] = h.cell[c] > bc ? h.cell[c] : bc;
+  }
+  if (!hit || cell_key(ref[0], ref[1], ref[2]) != h.key) return false;
+  bool adj = false;
+  for (int k = 0; k < 3; ++k) {
+    const int32_t w = tris[3 * (int64_t)other + k];
+    adj |= w == h.v[0] || w == h.v[1] || w == h.v[2];
+  }
+  return !adj;
+}
+
+// A thread tests at most kHashBudget later entries of its bucket; the rest of a longer bucket
+// (the cells where many triangles meet, e.g. the fan around a pole) goes to k_hash_heavy, where
+// a whole wave shares it.
+constexpr int kHashBudget = 64;
+
 __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, int64_t ecap, int64_t nbuckets, int hbits,
                                                          const int32_t* __restrict__ offset,
                                                          const uint64_t* __restrict__ skey,
                                                          const int32_t* __restrict__ stri,
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
-                                                         int32_t* pairs, int64_t cap, Counters* out_ctr) {
+                                                         int32_t* __restrict__ heavy, int32_t* pairs, int64_t cap,
+                                                         Counters* out_ctr) {
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+  __shared__ int wcount[kBpBlock / 64];
+  __shared__ uint32_t bbase;
   WaveEmitter em{stage[threadIdx.x / 64], 0};
   const int64_t ne = min((int64_t)ctr->n_entries, ecap);
   const HashGrid g = *grid;
   for (int64_t base = (int64_t)blockIdx.x * kBpBlock; base < ne; base += (int64_t)gridDim.x * kBpBlock) {
     const int64_t e = base + threadIdx.x;
     const bool active = e < ne;
-    uint64_t ka = 0;
-    int32_t a = 0;
-    int64_t end = 0;
-    double alo[3] = {0, 0, 0}, ahi[3] = {0, 0, 0};
-    int64_t acell[3] = {0, 0, 0};
-    int32_t av[3] = {0, 0, 0};
+    HashQuery h;
+    int64_t stop = 0;
     if (active) {
-      ka = skey[e];
-      a = stri[e];
-      const uint32_t b = hash_bucket(ka, hbits);
-      end = (int64_t)b + 1 < nbuckets ? offset[b + 1] : ne;
-      for (int c = 0; c < 3; ++c) {
-        alo[c] = tbox[6 * (int64_t)a + c];
-        ahi[c] = tbox[6 * (int64_t)a + 3 + c];
-        acell[c] = cell_of(alo[c], g.org[c], g.h);
-        av[c] = tris[3 * (int64_t)a + c];
-      }
+      h = hash_query(e, ne, nbuckets, hbits, offset, skey, stri, tbox, tris, g);
+      stop = min(h.end, e + 1 + kHashBudget);
     }
-    // every lane walks the rest of its bucket; the loop runs while any lane has work, so the
-    // emitter always sees the whole wave
-    for (int64_t j = e + 1; __ballot(active && j < end); ++j) {
-      bool want = false;
+    const bool defer = active && h.end > stop;
+    const uint32_t slot = wave_slot(defer, &out_ctr->n_heavy);
+    if (defer) heavy[slot] = (int32_t)e;  // slot < ne <= ecap
+    // the loop runs while any lane has work, so the emitter always sees the whole wave
+    for (int64_t j = e + 1; __ballot(active && j < stop); ++j) {
       int32_t other = 0;
-      if (active && j < end && skey[j] == ka) {
-        other = stri[j];
-        bool hit = true;
-        int64_t ref[3];
-        for (int c = 0; c < 3; ++c) {
-          const double blo = tbox[6 * (int64_t)other + c], bhi = tbox[6 * (int64_t)other + 3 + c];
-          hit = hit && alo[c] <= bhi && blo <= ahi[c];
-          const int64_t bc = cell_of(blo, g.org[c], g.h);
-          ref[c] = acell[c] > bc ? acell[c] : bc;
-        }
-        if (hit && cell_key(ref[0], ref[1], ref[2]) == ka) {
-          bool adj = false;
-          for (int k = 0; k < 3; ++k) {
-            const int32_t w = tris[3 * (int64_t)other + k];
-            adj |= w == av[0] || w == av[1] || w == av[2];
-          }
-          want = !adj;
-        }
-      }
-      em.push(want, a, other, pairs, cap, out_ctr);
+      const bool want = active && j < stop && hash_test(h, j, skey, stri, tbox, tris, g, other);
+      em.push(want, h.tri, other, pairs, cap, out_ctr);
     }
   }
-  if (em.count > 0) em.flush(pairs, cap, out_ctr);
+  block_flush<kBpBlock / 64>(em, wcount, &bbase, pairs, cap, out_ctr);
+}
+
+// one wave per deferred entry: its lanes stride over the rest of the bucket
+__global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, int64_t ecap, int64_t nbuckets, int hbits,
+                                                         const int32_t* __restrict__ offset,
+                                                         const uint64_t* __restrict__ skey,
+                                                         const int32_t* __restrict__ stri,
+                                                         const double* __restrict__ tbox,
+                                                         const int32_t* __restrict__ tris, const HashGrid* grid,
+                                                         const int32_t* __restrict__ heavy, int32_t* pairs,
+                                                         int64_t cap, Counters* out_ctr) {
+  __shared__ int2 stage[kBpBlock / 64][kEmitCap];
+  __shared__ int wcount[kBpBlock / 64];
+  __shared__ uint32_t bbase;
+  WaveEmitter em{stage[threadIdx.x / 64], 0};
+  const int64_t ne = min((int64_t)ctr->n_entries, ecap);
+  const int64_t nh = min((int64_t)ctr->n_heavy, ne);
+  const HashGrid g = *grid;
+  const int waves = gridDim.x * (kBpBlock / 64);
+  for (int64_t it = (int64_t)blockIdx.x * (kBpBlock / 64) + threadIdx.x / 64; it < nh; it += waves) {
+    const int64_t e = heavy[it];
+    const HashQuery h = hash_query(e, ne, nbuckets, hbits, offset, skey, stri, tbox, tris, g);
+    for (int64_t jb = e + 1 + kHashBudget; jb < h.end; jb += 64) {
+      const int64_t j = jb + __lane_id();
+      int32_t other = 0;
+      const bool want = j < h.end && hash_test(h, j, skey, stri, tbox, tris, g, other);
+      em.push(want, h.tri, other, pairs, cap, out_ctr);
+    }
+  }
+  block_flush<kBpBlock / 64>(em, wcount, &bbase, pairs, cap, out_ctr);
 }
 
 __global__ void k_bp_finish(Counters* ctr, int64_t cap, int64_t* n_pairs) {
@@ -769,6 +1002,10 @@ static unsigned bp_grid(int64_t n, unsigned cap = 4096) {
   return (unsigned)g;
 }
 
+// Every level is stored padded to a multiple of 4 nodes, so the four children of any node can
+// be loaded together without bounds checks (padding slots are never selected: c < m[l]).
+static int64_t pad4(int64_t m) { return (m + 3) & ~(int64_t)3; }
+
 Levels make_levels(int64_t n) {
   Levels lv{};
   int64_t off = 0, m = n;
@@ -776,17 +1013,17 @@ Levels make_levels(int64_t n) {
   for (;; ++l) {
     lv.m[l] = m;
     lv.off[l] = off;
-    off += m;
+    off += pad4(m);
     if (m <= 1) break;
     m = (m + 3) / 4;
   }
   lv.L = l;
-  // the highest levels whose boxes fit the traversal's LDS cache, never below level 4
+  // the highest levels whose (padded) boxes fit the traversal's LDS cache, never below level 4
   int64_t cum = 0;
   lv.lt = l + 1;
   for (int k = l; k >= kSubLevels; --k) {
-    if (cum + lv.m[k] > kTopCap) break;
-    cum += lv.m[k];
+    if (cum + pad4(lv.m[k]) > kTopCap) break;
+    cum += pad4(lv.m[k]);
     lv.lt = k;
   }
   return lv;
@@ -833,8 +1070,11 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
         ctr, ecap, nbuckets, hbits, key, tri, wsp<int32_t>(c, L.hash_rank), offset, skey, stri, hist);
     stage_end(c, TTIE_STAGE_BP_SORT, s);
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
+    int32_t* heavy = wsp<int32_t>(c, L.hash_rank);  // the ranks are consumed by the scatter
     k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
-                                                           m->tris, grid, pairs, capacity, ctr);
+                                                           m->tris, grid, heavy, pairs, capacity, ctr);
+    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, heavy,
+                                          pairs, capacity, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
@@ -878,8 +1118,11 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     // one lane per leaf, block count rounded up to a multiple of the 8 XCDs
     const int64_t nb = ((nt + kBpBlock - 1) / kBpBlock + 7) / 8 * 8;
-    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, pairs, capacity,
-                                                     ctr);
+    TravState* heavy = wsp<TravState>(c, L.bvh_heavy);
+    const int64_t heavy_cap = (int64_t)(L.bvh_heavy_bytes / sizeof(TravState));
+    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy, heavy_cap,
+                                                     pairs, capacity, ctr);
+    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, pairs, capacity, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
   k_bp_finish<<<1, 64, 0, s>>>(ctr, capacity, n_pairs);

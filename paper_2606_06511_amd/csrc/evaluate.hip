@@ -50,17 +50,6 @@ __device__ __forceinline__ bool load_tri(const double* x, int64_t nv, const int3
   return true;
 }
 
-// wave-aggregated append to a counter-indexed list: one atomic per wave
-__device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {
-  const uint64_t mask = __ballot(want);
-  if (!mask) return 0xffffffffu;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  return want ? base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)) : 0xffffffffu;
-}
 
 // Screens candidate p (p < 0: inactive lane).  Every lane of the wave must call it.
 template <bool kExact>

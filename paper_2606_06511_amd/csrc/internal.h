@@ -46,12 +46,27 @@ struct Counters {
   uint32_t n_touched;      // vertices touched by the hits of the current evaluation
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
   uint64_t n_entries;      // (cell, triangle) entries of the spatial-hash broad phase
+  uint32_t n_heavy;        // broad-phase work items handed to a wave-cooperative kernel
+  uint32_t pad_;
 };
+
+// wave-aggregated append to a counter-indexed list: one atomic per wave; every lane of the wave
+// must call it
+__device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {
+  const uint64_t mask = __ballot(want);
+  if (!mask) return 0xffffffffu;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  return want ? base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)) : 0xffffffffu;
+}
 
 struct Layout {
   size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
       scan_tmp_bytes;
-  size_t bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
+  size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state;
   size_t total;
 };

@@ -146,6 +146,22 @@ def test_hash_pairs(ctx, which):
     np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
 
 
+def test_pairs_big_sphere_both_methods(ctx):
+    """1,048,576 triangles: the pole fans (1,024 thin triangles around one vertex) overlap each
+    other, so both broad phases hand work to their wave-cooperative kernels; the lists must
+    still be exactly the oracle's."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.noisy_sphere(0)
+    ref = oracle.pairs(x, tris, oracle.BROAD_BOXES)
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    for method in (ttie.BROAD_LBVH, ttie.BROAD_HASH):
+        pairs, n = ctx.broadphase(xd, td, method)
+        assert ctx.status() == ttie.TTIE_OK
+        assert int(n.item()) == len(ref), method
+        np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+
+
 def test_hash_swept_pairs(ctx):
     from paper_2606_06511_amd import ttie
 
