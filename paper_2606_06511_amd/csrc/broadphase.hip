@@ -392,76 +392,50 @@ struct TravState {
   int32_t last;   // end of the query's problem (leaves)
 };
 
-__global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv, const Box32* __restrict__ boxes,
-                                                           const LeafRec* __restrict__ leaves,
-                                                           const int32_t* __restrict__ qend, TravState* heavy,
-                                                           int64_t heavy_cap, int32_t* pairs, int64_t cap,
-                                                           Counters* ctr) {
-  __shared__ int2 stage[kTravWaves][kEmitCap];
-  __shared__ int64_t lm[24], loff[24];  // the level table, indexed by each lane's own level
-  __shared__ int wcount[kTravWaves];
-  __shared__ uint32_t bbase;
-  __shared__ LeafRec sleaf[kBpBlock];
-  __shared__ Box32 sbox[kBpBlock + kSubInner];     // level 0 at [0,256), level 1 at 256.., 2, 3
-  __shared__ Box32 stop[kTopCap];                   // levels lt..L, in storage order
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int lt = lv.lt;
-  const int64_t tbase = lt <= lv.L ? lv.off[lt] : 0;
-  const int ntop = lt <= lv.L ? (int)(lv.off[lv.L] + 4 - tbase) : 0;  // through the padded root level
-  for (int i = threadIdx.x; i < ntop; i += kTravThreads) stop[i] = boxes[tbase + i];
-  const int qi = threadIdx.x % kBpBlock;             // query within the block
-  const bool global_part = threadIdx.x >= kBpBlock;
-  if (threadIdx.x < 24) {
-    lm[threadIdx.x] = lv.m[threadIdx.x];
-    loff[threadIdx.x] = lv.off[threadIdx.x];
-  }
-  // stage the block's subtree
-  const int64_t s = blk * kBpBlock + qi;
-  if (!global_part && s < n) {
-    sleaf[qi] = leaves[s];
-    sbox[qi] = boxes[s];
-  }
-  if (global_part) {
-    const int t = qi;
-    int l = 0, local = 0, base = kBpBlock;  // thread t < 84 loads inner box t
-    if (t < 64) { l = 1; local = t; base = kBpBlock; }
-    else if (t < 80) { l = 2; local = t - 64; base = kBpBlock + 64; }
-    else if (t < 84) { l = 3; local = t - 80; base = kBpBlock + 80; }
-    if (l > 0 && l <= lv.L) {
-      const int64_t k = (blk << (2 * (kSubLevels - l))) + local;
-      if (k < lv.m[l]) sbox[base + local] = boxes[lv.off[l] + k];
-    }
-  }
-  __syncthreads();
+// LDS the traversal of one block works from
+struct TravShared {
+  int2 stage[kTravWaves][kEmitCap];
+  int32_t lm[24], loff[24];  // the level table (node counts and offsets fit 32 bits)
+  int wcount[kTravWaves];
+  uint32_t bbase;
+  LeafRec sleaf[kBpBlock];
+  Box32 sbox[kBpBlock + kSubInner];  // the block's subtree: level 0 at [0, 256), then 1, 2, 3
+  Box32 stop[kTopCap];               // levels lt..L, in storage order
+};
 
-  WaveEmitter em{stage[threadIdx.x / 64], 0};
-  int status = 0;
-  // the local part starts at the block's level-4 node (the root if the tree is lower); the
-  // global part starts at the root and skips that node
-  const bool small_tree = lv.L <= kSubLevels;
-  bool active = s < n && !(global_part && small_tree);
-  float q[6];
-  LeafRec me;
-  // leaves after s up to the end of the query's problem (the whole tree without a batch)
-  int64_t last = n;
-  int l = global_part || small_tree ? lv.L : kSubLevels;
-  int64_t k = global_part || small_tree ? 0 : blk;
-  const int top = l;  // the traversal ends when it climbs past this level
-  uint64_t pend = 0;  // level j's remaining children at bits [4(j-1), 4j)
+// The search of one part for the lane's query s.  kGlobal is wave-uniform (waves 0-3 search
+// the block's own subtree, waves 4-7 the rest of the tree), so the sources are fixed: the local
+// part reads only LDS, the global part reads the top levels from LDS and the lower levels and
+// the leaves from global memory.  Tests are written without short-circuit branches and the
+// climb takes the lowest pending bit, so the loop carries little divergence.
+template <bool kGlobal>
+__device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t blk, int32_t s, bool active, int lt,
+                                              int32_t tbase, int L, const Box32* __restrict__ boxes,
+                                              const LeafRec* __restrict__ leaves, const int32_t* __restrict__ qend,
+                                              TravState* heavy, int64_t heavy_cap, WaveEmitter& em, int32_t* pairs,
+                                              int64_t cap, Counters* ctr, int& status) {
+  const int qi = s - blk * kBpBlock;
+  const bool small_tree = L <= kSubLevels;
+  int l = kGlobal || small_tree ? L : kSubLevels;
+  int32_t k = kGlobal || small_tree ? 0 : blk;
+  const int top = l;   // the search ends when nothing is pending at or above this level
+  uint64_t pend = 0;   // pending children of level j's current node at bits [4j, 4j + 4)
+  float q[6] = {0, 0, 0, 0, 0, 0};
+  LeafRec me{};
+  int32_t last = n;    // leaves after s up to the end of the query's problem
   if (active) {
     if (qend) last = qend[s];
-    me = sleaf[qi];
-    const Box32 b = sbox[qi];
+    me = sh.sleaf[qi];
+    const Box32 b = sh.sbox[qi];
     for (int c = 0; c < 3; ++c) {
       q[c] = b.lo[c];
       q[3 + c] = b.hi[c];
     }
   }
-  // every node is visited at most once; the cap only guards against corruption
   int visits = 0;
   bool may_defer = true;  // one attempt: with the list full the lane finishes its own search
-  for (int64_t iter = 0; __ballot(active); ++iter) {
-    if (iter > 2 * n + 64) {
+  for (int32_t iter = 0; __ballot(active); ++iter) {
+    if (iter > 2 * n + 64) {  // every node is visited at most once: only corruption gets here
       status = STATUS_CAPACITY;
       break;
     }
@@ -471,110 +445,154 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n, Levels lv,
     if (over) may_defer = false;
     if (over && (int64_t)hs < heavy_cap) {
       TravState t;
-      t.s = (int32_t)s;
-      t.part = global_part ? 1 : 0;
+      t.s = s;
+      t.part = kGlobal ? 1 : 0;
       t.l = l;
-      t.k = (int32_t)k;
+      t.k = k;
       t.pend = pend;
       t.top = top;
-      t.last = (int32_t)last;
+      t.last = last;
       heavy[hs] = t;
       active = false;
     }
     ++visits;
+    // children of (l, k): (l - 1, 4k + i), only those holding leaves after s (and, in the
+    // global part, never the block's own subtree) up to the problem's last leaf
+    const int lc = l - 1;
+    const int32_t c0 = 4 * k;
     uint32_t mask = 0;
-    int64_t c0 = 0;
-    bool local_children = false;
     if (active) {
-      // children of (l, k): (l-1, 4k+i); only those holding leaves after s, and in the
-      // global part never the block's own subtree
-      c0 = 4 * k;
-      const int lc = l - 1;
-      int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
-      if (global_part && lc == kSubLevels) first = blk + 1;
-      const int64_t lastc = (last - 1) >> (2 * lc);  // the node holding the problem's last leaf
-      const int64_t mcount = lm[lc];
-      local_children = lc < kSubLevels && (c0 >> (2 * (kSubLevels - lc))) == blk;
-      // the four child boxes in one batch, from the LDS copy of the block's subtree, the LDS
-      // copy of the top levels, or global memory (levels are padded to multiples of 4)
+      int32_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
+      if (kGlobal && lc == kSubLevels) first = blk + 1;
+      const int32_t lastc = (last - 1) >> (2 * lc);
+      const int32_t hi = min(lastc, sh.lm[lc] - 1);
       Box32 cb[4];
-      if (local_children) {
+      if (!kGlobal) {
         const int lb = (lc == 0 ? 0 : (lc == 1 ? kBpBlock : (lc == 2 ? kBpBlock + 64 : kBpBlock + 80)));
-        const int64_t li = c0 - (blk << (2 * (kSubLevels - lc)));
+        const int li = c0 - (blk << (2 * (kSubLevels - lc)));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) cb[i] = sbox[lb + li + i];
+        for (int i = 0; i < 4; ++i) cb[i] = sh.sbox[lb + li + i];
       } else if (lc >= lt) {
-        const int64_t ti = loff[lc] - tbase + c0;
+        const int ti = sh.loff[lc] - tbase + c0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) cb[i] = stop[ti + i];
+        for (int i = 0; i < 4; ++i) cb[i] = sh.stop[ti + i];
       } else {
-        const Box32* g = boxes + loff[lc] + c0;
+        const Box32* g = boxes + sh.loff[lc] + c0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) cb[i] = g[i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t c = c0 + i;
-        if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i])) mask |= 1u << i;
+        const int32_t c = c0 + i;
+        const bool ov = (q[0] <= cb[i].hi[0]) & (cb[i].lo[0] <= q[3]) & (q[1] <= cb[i].hi[1]) &
+                        (cb[i].lo[1] <= q[4]) & (q[2] <= cb[i].hi[2]) & (cb[i].lo[2] <= q[5]);
+        mask |= (uint32_t)(ov & (c >= first) & (c <= hi)) << i;
       }
     }
-    // leaves: exact FP64 box test and the shared-vertex test, four candidates per visit; the
-    // four records are loaded together (the leaf array is padded like the levels)
-    const bool leaf_level = active && l == 1;
-    bool want[4] = {false, false, false, false};
+    // leaves: exact FP64 box test and the shared-vertex test
+    uint32_t want = 0;
     int32_t other[4] = {0, 0, 0, 0};
-    if (leaf_level && mask) {
+    if (active && lc == 0 && mask) {
       LeafRec o[4];
-      if (local_children) {
-        const int64_t li = c0 - blk * kBpBlock;
+      if (!kGlobal) {
+        const int li = c0 - blk * kBpBlock;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = sleaf[li + i];
+        for (int i = 0; i < 4; ++i) o[i] = sh.sleaf[li + i];
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] = leaves[c0 + i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        bool exact = (mask >> i) & 1u;
-        for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o[i].hi[c] && o[i].lo[c] <= me.hi[c];
+        bool ex = (mask >> i) & 1u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ex = ex & (me.lo[c] <= o[i].hi[c]) & (o[i].lo[c] <= me.hi[c]);
         bool adj = false;
+#pragma unroll
         for (int a2 = 0; a2 < 3; ++a2)
-          for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o[i].v[b2];
-        want[i] = exact && !adj;
+#pragma unroll
+          for (int b2 = 0; b2 < 3; ++b2) adj = adj | (me.v[a2] == o[i].v[b2]);
+        want |= (uint32_t)(ex & !adj) << i;
         other[i] = o[i].tri;
       }
     }
+    if (__ballot(want != 0)) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], pairs, cap, ctr);
+      for (int i = 0; i < 4; ++i) em.push((want >> i) & 1u, me.tri, other[i], pairs, cap, ctr);
+    }
     if (active) {
-      if (leaf_level) mask = 0;
+      if (lc == 0) mask = 0;
       if (mask) {
         // descend into the first child; the others wait in this level's slot
         const int i = __builtin_ctz(mask);
-        pend |= (uint64_t)(mask & ~(1u << i)) << (4 * (l - 1));
-        --l;
+        pend |= (uint64_t)(mask & ~(1u << i)) << (4 * lc);
+        l = lc;
         k = c0 + i;
       } else {
-        // climb to the nearest level with a pending child and move to that child
-        for (;;) {
-          if (l >= top) {
-            active = false;
-            break;
-          }
-          const uint32_t pm = (uint32_t)(pend >> (4 * l)) & 15u;
-          if (pm) {
-            const int i = __builtin_ctz(pm);
-            pend &= ~(1ull << (4 * l + i));
-            k = ((k >> 2) << 2) + i;
-            break;
-          }
-          ++l;
-          k >>= 2;
+        // resume at the lowest level at or above l with a pending child (slots above the
+        // starting level are never set)
+        const uint64_t rem = l < 16 ? pend >> (4 * l) : 0;
+        if (rem == 0) {
+          active = false;
+        } else {
+          const int b = __builtin_ctzll(rem);
+          const int j = l + (b >> 2);
+          pend &= ~(1ull << (4 * l + b));
+          k = ((k >> (2 * (j - l))) & ~3) + (b & 3);
+          l = j;
         }
       }
     }
   }
-  block_flush<kTravWaves>(em, wcount, &bbase, pairs, cap, ctr);
+}
+
+__global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels lv, const Box32* __restrict__ boxes,
+                                                           const LeafRec* __restrict__ leaves,
+                                                           const int32_t* __restrict__ qend, TravState* heavy,
+                                                           int64_t heavy_cap, int32_t* pairs, int64_t cap,
+                                                           Counters* ctr) {
+  __shared__ TravShared sh;
+  const int32_t n = (int32_t)n64;
+  const int32_t blk = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+  const int lt = lv.lt;
+  const int32_t tbase = lt <= lv.L ? (int32_t)lv.off[lt] : 0;
+  const int ntop = lt <= lv.L ? (int)(lv.off[lv.L] + 4 - tbase) : 0;  // through the padded root level
+  for (int i = threadIdx.x; i < ntop; i += kTravThreads) sh.stop[i] = boxes[tbase + i];
+  const int qi = threadIdx.x % kBpBlock;  // query within the block
+  const bool global_part = __builtin_amdgcn_readfirstlane(threadIdx.x) >= kBpBlock;  // wave-uniform
+  if (threadIdx.x < 24) {
+    sh.lm[threadIdx.x] = (int32_t)lv.m[threadIdx.x];
+    sh.loff[threadIdx.x] = (int32_t)lv.off[threadIdx.x];
+  }
+  // stage the block's subtree
+  const int32_t s = blk * kBpBlock + qi;
+  if (!global_part && s < n) {
+    sh.sleaf[qi] = leaves[s];
+    sh.sbox[qi] = boxes[s];
+  }
+  if (global_part) {
+    const int t = qi;
+    int l = 0, local = 0, base = kBpBlock;  // thread t < 84 loads inner box t
+    if (t < 64) { l = 1; local = t; base = kBpBlock; }
+    else if (t < 80) { l = 2; local = t - 64; base = kBpBlock + 64; }
+    else if (t < 84) { l = 3; local = t - 80; base = kBpBlock + 80; }
+    if (l > 0 && l <= lv.L) {
+      const int64_t k = ((int64_t)blk << (2 * (kSubLevels - l))) + local;
+      if (k < lv.m[l]) sh.sbox[base + local] = boxes[lv.off[l] + k];
+    }
+  }
+  __syncthreads();
+
+  WaveEmitter em{sh.stage[threadIdx.x / 64], 0};
+  int status = 0;
+  const bool small_tree = lv.L <= kSubLevels;
+  if (global_part)
+    traverse_part<true>(sh, n, blk, s, s < n && !small_tree, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap,
+                        em, pairs, cap, ctr, status);
+  else
+    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, em, pairs,
+                         cap, ctr, status);
+  block_flush<kTravWaves>(em, sh.wcount, &sh.bbase, pairs, cap, ctr);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
