@@ -162,6 +162,31 @@ def extra_configs(args, np, torch, ttie, workloads):
                       "problems": len(probs), "pairs": P, "hits": int(out["n_hits"].item()),
                       "ms_per_step": ms_graph, "pairs_per_s": P / (ms_graph * 1e-3),
                       "ms_per_step_eager": ms_eager, "graph_replay_matches_eager": same}
+    del ctx, pairs, out
+
+    # inexact Newton, 20 steps, on the 4,194,304-triangle sphere (Jacobi-PCG with 50 iterations)
+    from paper_2606_06511_amd.energy import TTIE
+    from paper_2606_06511_amd.newton import newton
+
+    x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
+    model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 25, max_hits=1 << 17, precision=ttie.MIXED)
+    xd = torch.from_numpy(x).to(dev)
+    newton(model, xd, steps=1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist = newton(model, xd, steps=20)
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    steps = [h for h in hist if "alpha" in h]
+    res["newton_4m"] = {
+        "workload": "noisy UV sphere 2048x1025 bands (2,097,154 verts, 4,194,304 tris), 20 inexact Newton steps, "
+                    "BSR Hessian + Jacobi-PCG (50), Armijo, swept LBVH candidates",
+        "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist], "pairs": [h["pairs"] for h in hist],
+        "alpha": [h["alpha"] for h in steps], "ms_per_newton_step": [round(h["ms"], 3) for h in steps],
+        "total_ms": total_ms, "E_final_over_E0": hist[-1]["E"] / hist[0]["E"] if hist[0]["E"] else None,
+        "pairs_per_s": sum(h["pairs"] for h in steps) / (sum(h["ms"] for h in steps) * 1e-3)}
+    del model
+
     return res
 
 
@@ -284,6 +309,12 @@ def main():
                    "step": "broadphase+screen+derivatives+energy+gradient+BSR Hessian"},
         other: {"value": P / (ms_other * 1e-3), "ms_per_step": ms_other},
         "stages_ms_per_step": {k: round(v, 5) for k, v in per_step_stage.items()},
+        # the same step split at the stage timers: evaluation only (screening through BSR
+        # assembly, candidate pairs per second of it) and the broad phase (triangles per second)
+        "eval_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if not k.startswith("bp_")),
+                      "pairs_per_s": P / (sum(v for k, v in per_step_stage.items() if not k.startswith("bp_")) * 1e-3)},
+        "broadphase_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if k.startswith("bp_")),
+                            "tris_per_s": nt / (sum(v for k, v in per_step_stage.items() if k.startswith("bp_")) * 1e-3)},
         "roofline": {"kernel_stage": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
                      "traffic_unit": "bytes per launch",

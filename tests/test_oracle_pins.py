@@ -6,6 +6,8 @@ invariance of the definition, or a library routine.
 """
 
 import itertools
+import json
+import os
 
 import numpy as np
 import pytest
@@ -21,26 +23,26 @@ from oracle import exact_moller
 # I_a = [-1.5, 0], I_b = [-1, -.5] and Eq. 1 gives t_c = [-1.5 + .5, 0 + 1] = [-1, 1],
 # so T = (t0 t1)^2 = 1 (Eq. 2).
 # ---------------------------------------------------------------------------------------
-WORKED = np.array([[0, 0, 0], [2, 0, 0], [0, 2, 0], [.5, .5, -1], [.5, .5, 1], [1.5, .5, 1]], float)
-
-# dt0/dX.  t0 = t(S_a at x=1.5) - t(S_b at x=.5).  The T_a endpoint at x = 1.5 is the lerp on
-# edge u1u2 (u1 = (2,0,0), u2 = (0,2,0)) at y = .5: weight 3/4 on u1, 1/4 on u2, and it moves
-# with the plane y = .5 of T_b, whose height is set by (v0,v1,v2)_y.  Derived by hand:
-A_WORKED = np.array([[0, 0, 0], [-.75, -.75, 0], [-.25, -.25, 0], [.5, .5, 0], [.5, -.5, 0], [0, 1, 0]])
-B_WORKED = np.array([[-.75, 0, .125], [0, 0, .25], [-.25, 0, .125], [.5, 0, -.25], [0, 0, 0], [.5, 0, -.25]])
+# the hand-derived values of this example, with their derivation, are the fixture
+# tests/golden/worked_example.json
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")))
+WORKED = np.array(GOLDEN["X"], float)
+A_WORKED = np.array(GOLDEN["a"], float)
+B_WORKED = np.array(GOLDEN["b"], float)
 
 
 def test_worked_example_values():
     r = oracle.pair(WORKED)
     assert r["status"] == oracle.ST_HIT
-    assert r["t0"] == -1.0 and r["t1"] == 1.0 and r["T"] == 1.0
+    assert r["t0"] == GOLDEN["t0"] and r["t1"] == GOLDEN["t1"] and r["T"] == GOLDEN["T"]
     np.testing.assert_allclose(r["a"].reshape(6, 3), A_WORKED, atol=1e-15)
     np.testing.assert_allclose(r["b"].reshape(6, 3), B_WORKED, atol=1e-15)
-    # Eq. 3 with t0 = -1, t1 = 1: g = 2 t0 t1^2 a + 2 t1 t0^2 b = -2a + 2b
-    np.testing.assert_allclose(r["g"].reshape(6, 3), -2 * A_WORKED + 2 * B_WORKED, atol=1e-15)
-    # |a|^2 = 13/4, |b|^2 = 43/32, a.b = 5/16 (exact dyadic sums of the rows above)
+    np.testing.assert_allclose(r["g"].reshape(6, 3), np.array(GOLDEN["g"]), atol=1e-15)
+    # exact dyadic sums of the rows above
     a, b = r["a"], r["b"]
-    assert a @ a == 13 / 4 and b @ b == 43 / 32 and a @ b == 5 / 16
+    assert a @ a == GOLDEN["a_dot_a"] and b @ b == GOLDEN["b_dot_b"] and a @ b == GOLDEN["a_dot_b"]
+    h = oracle.pair(WORKED, interval=oracle.INTERVAL_APPENDIX_HALF)
+    assert h["T"] == GOLDEN["T_appendix_half"]
 
 
 def test_worked_example_eigenanalysis():
@@ -49,7 +51,8 @@ def test_worked_example_eigenanalysis():
     # are 4 t0 t1 (a.b -+ |a||b|).
     raw = oracle.pair(WORKED, psd=oracle.PSD_RAW_EQ4)["H"]
     per = oracle.pair(WORKED, psd=oracle.PSD_PER_PART)["H"]
-    assert np.trace(raw) == pytest.approx(6.5 + 2.6875 - 2.5, abs=1e-13)
+    assert np.trace(raw) == pytest.approx(
+        GOLDEN["part1_eigenvalue"] + GOLDEN["part2_eigenvalue"] + GOLDEN["part3_stated_value"], abs=1e-13)
     na, nb = np.sqrt(13 / 4), np.sqrt(43 / 32)
     p3_neg = 4 * -1 * (5 / 16 + na * nb)      # the negative eigenvalue of part 3
     w = np.linalg.eigvalsh(raw - per)          # raw - per_part = the removed negative part of part 3
@@ -430,3 +433,55 @@ def test_assembly_consistency():
     Ep = oracle.evaluate(x + h * d, tris, pairs, hessian=False)["E"]
     Em = oracle.evaluate(x - h * d, tris, pairs, hessian=False)["E"]
     assert (Ep - Em) / (2 * h) == pytest.approx(np.sum(res["G"] * d), rel=1e-4)
+
+
+def test_swept_pairs_brute_force():
+    # swept candidates: every non-adjacent pair whose boxes over both positions overlap, by an
+    # O(N^2) numpy test
+    from paper_2606_06511_amd import workloads
+
+    x, tris = workloads.folded_cloth(3, n=20)
+    x_end = x + 0.02 * np.random.default_rng(4).normal(size=x.shape)
+    got = oracle.pairs_swept(x, x_end, tris)
+    lo = np.minimum(x[tris].min(1), x_end[tris].min(1))
+    hi = np.maximum(x[tris].max(1), x_end[tris].max(1))
+    ov = np.all((lo[:, None, :] <= hi[None, :, :]) & (lo[None, :, :] <= hi[:, None, :]), axis=2)
+    shared = (tris[:, None, :, None] == tris[None, :, None, :]).any(axis=(2, 3))
+    i, j = np.nonzero(np.triu(ov & ~shared, 1))
+    np.testing.assert_array_equal(got, np.stack([i, j], 1).astype(got.dtype))
+    assert len(got) > len(oracle.pairs(x, tris))
+
+
+def test_newton_matches_dense_newton():
+    """The oracle's inexact Newton against the same iteration written with dense linear algebra:
+    (H + mu I) d = -g solved exactly (PCG run to convergence must agree), mu = 1e-3 * mean
+    diagonal of the rows holding blocks, Armijo halving on E over the swept candidates."""
+    from paper_2606_06511_amd import workloads
+
+    x, tris = workloads.folded_cloth(0, n=24)
+    steps = 3
+    _, E_or, al_or, _ = oracle.newton(x, tris, steps=steps, pcg_iters=5000, pcg_tol=1e-14)
+    xc = x.copy()
+    E_ref, al_ref = [], []
+    for _ in range(steps):
+        r = oracle.evaluate(xc, tris, oracle.pairs(xc, tris), hessian=True)
+        E = r["E"]
+        E_ref.append(E)
+        H = oracle.bsr_to_dense(r["row_ptr"], r["col_idx"], r["vals"], len(xc))
+        g = r["G"].ravel()
+        rows = np.repeat(np.diff(r["row_ptr"]) > 0, 3)
+        mu = 1e-3 * np.diag(H)[rows].mean()
+        d = np.linalg.solve(H + mu * np.eye(len(g)), -g).reshape(-1, 3)
+        cand = oracle.pairs_swept(xc, xc + d, tris)
+        alpha = 1.0
+        for h in range(30):
+            Et = oracle.evaluate(xc + alpha * d, tris, cand, hessian=False)["E"]
+            if Et <= E + 1e-4 * alpha * float(g @ d.ravel()) or h == 29:
+                break
+            alpha *= 0.5
+        al_ref.append(alpha)
+        xc = xc + alpha * d
+    E_ref.append(oracle.evaluate(xc, tris, oracle.pairs(xc, tris), hessian=False)["E"])
+    assert E_ref[0] > 0
+    np.testing.assert_allclose(E_or, E_ref, rtol=1e-7)
+    assert list(al_or) == al_ref
