@@ -278,6 +278,7 @@ static ttie_status broadphase_impl(ttie_ctx* ctx, const ttie_mesh* mesh, int met
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad pair output");
   if (capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "capacity exceeds limits.max_pairs");
   if (((uintptr_t)pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "pairs must be 8-byte aligned");
+  if (((uintptr_t)n_pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "n_pairs must be 8-byte aligned");
   if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
     return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
   DeviceGuard g(ctx->device);

@@ -38,9 +38,11 @@ __device__ __forceinline__ float key2f(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-__global__ void k_bp_init(Counters* c) {
+// zeroes the caller's pair count and the broad phase's counters (the LBVH and the hash do it in
+// k_tri_boxes instead, saving a launch)
+__global__ void k_bp_init(Counters* c, unsigned long long* npairs) {
   if (threadIdx.x == 0) {
-    c->n_pairs = 0;
+    *npairs = 0;
     c->n_entries = 0;
     c->n_heavy = 0;
   }
@@ -50,7 +52,12 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
                                                         int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
                                                         double* __restrict__ tbox, float* __restrict__ centre,
                                                         uint32_t* __restrict__ part, double* __restrict__ ext_part,
-                                                        Counters* ctr) {
+                                                        unsigned long long* npairs, Counters* ctr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *npairs = 0;
+    ctr->n_entries = 0;
+    ctr->n_heavy = 0;
+  }
   __shared__ uint32_t smin[3][kBpBlock], smax[3][kBpBlock];
   __shared__ double sext[kBpBlock];
   uint32_t lmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, lmax[3] = {0u, 0u, 0u};
@@ -301,27 +308,43 @@ __device__ __forceinline__ bool overlap32(const float q[6], const Box32& b) {
 // reserves global space, with one atomic for the whole buffer.
 constexpr int kEmitCap = 128;
 
+// Where emitted pairs go: the pair array, its capacity, the caller's pair count (the
+// reservation counter itself, zeroed at the start of the broad phase) and the status word.
+struct PairSink {
+  int32_t* pairs;
+  int64_t cap;
+  unsigned long long* count;
+  int32_t* status;
+};
+
+// reserves n slots; past the capacity the count still grows and TTIE_ERR_CAPACITY is latched
+__device__ __forceinline__ int64_t sink_reserve(const PairSink& o, uint32_t n) {
+  const int64_t base = (int64_t)atomicAdd(o.count, (unsigned long long)n);
+  if (base + n > o.cap) atomicCAS(o.status, 0, STATUS_CAPACITY);
+  return base;
+}
+
 struct WaveEmitter {
   int2* buf;       // this wave's kEmitCap slots in LDS
   int count;       // wave-uniform fill level
 
-  __device__ __forceinline__ void flush(int32_t* pairs, int64_t cap, Counters* ctr) {
+  __device__ __forceinline__ void flush(const PairSink& o) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int lane = __lane_id();
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&ctr->n_pairs, (uint32_t)count);
+    int64_t base = 0;
+    if (lane == 0) base = sink_reserve(o, (uint32_t)count);
     base = __shfl(base, 0);
     for (int i = lane; i < count; i += 64) {
-      const int64_t slot = (int64_t)base + i;
-      if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = buf[i];
+      const int64_t slot = base + i;
+      if (slot < o.cap) reinterpret_cast<int2*>(o.pairs)[slot] = buf[i];
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     count = 0;
   }
 
-  __device__ __forceinline__ void push(bool want, int32_t a, int32_t b, int32_t* pairs, int64_t cap, Counters* ctr) {
+  __device__ __forceinline__ void push(bool want, int32_t a, int32_t b, const PairSink& o) {
     const uint64_t mask = __ballot(want);
     if (!mask) return;
     if (want) {
@@ -329,29 +352,28 @@ struct WaveEmitter {
       buf[count + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2(min(a, b), max(a, b));
     }
     count += __popcll(mask);
-    if (count > kEmitCap - 64) flush(pairs, cap, ctr);
+    if (count > kEmitCap - 64) flush(o);
   }
 };
 
 // End of an emitting kernel: one atomic reserves the space of all the block's waves (every
 // thread of the block must arrive here).
 template <int kWaves>
-__device__ __forceinline__ void block_flush(WaveEmitter& em, int* wcount, uint32_t* bbase, int32_t* pairs,
-                                            int64_t cap, Counters* ctr) {
+__device__ __forceinline__ void block_flush(WaveEmitter& em, int* wcount, int64_t* bbase, const PairSink& o) {
   const int wave = threadIdx.x / 64;
   if (__lane_id() == 0) wcount[wave] = em.count;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tot = 0;
     for (int w = 0; w < kWaves; ++w) tot += wcount[w];
-    *bbase = tot ? atomicAdd(&ctr->n_pairs, tot) : 0u;
+    *bbase = tot ? sink_reserve(o, tot) : 0;
   }
   __syncthreads();
   int64_t base = *bbase;
   for (int w = 0; w < wave; ++w) base += wcount[w];
   for (int i = __lane_id(); i < em.count; i += 64) {
     const int64_t slot = base + i;
-    if (slot < cap) reinterpret_cast<int2*>(pairs)[slot] = em.buf[i];
+    if (slot < o.cap) reinterpret_cast<int2*>(o.pairs)[slot] = em.buf[i];
   }
 }
 
@@ -397,7 +419,7 @@ struct TravShared {
   int2 stage[kTravWaves][kEmitCap];
   int32_t lm[24], loff[24];  // the level table (node counts and offsets fit 32 bits)
   int wcount[kTravWaves];
-  uint32_t bbase;
+  int64_t bbase;
   LeafRec sleaf[kBpBlock];
   Box32 sbox[kBpBlock + kSubInner];  // the block's subtree: level 0 at [0, 256), then 1, 2, 3
   Box32 stop[kTopCap];               // levels lt..L, in storage order
@@ -412,8 +434,8 @@ template <bool kGlobal>
 __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t blk, int32_t s, bool active, int lt,
                                               int32_t tbase, int L, const Box32* __restrict__ boxes,
                                               const LeafRec* __restrict__ leaves, const int32_t* __restrict__ qend,
-                                              TravState* heavy, int64_t heavy_cap, WaveEmitter& em, int32_t* pairs,
-                                              int64_t cap, Counters* ctr, int& status) {
+                                              TravState* heavy, int64_t heavy_cap, WaveEmitter& em,
+                                              const PairSink& sink, Counters* ctr, int& status) {
   const int qi = s - blk * kBpBlock;
   const bool small_tree = L <= kSubLevels;
   int l = kGlobal || small_tree ? L : kSubLevels;
@@ -518,7 +540,7 @@ __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t
     }
     if (__ballot(want != 0)) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) em.push((want >> i) & 1u, me.tri, other[i], pairs, cap, ctr);
+      for (int i = 0; i < 4; ++i) em.push((want >> i) & 1u, me.tri, other[i], sink);
     }
     if (active) {
       if (lc == 0) mask = 0;
@@ -550,8 +572,9 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
                                                            const LeafRec* __restrict__ leaves,
                                                            const int32_t* __restrict__ qend, TravState* heavy,
                                                            int64_t heavy_cap, int32_t* pairs, int64_t cap,
-                                                           Counters* ctr) {
+                                                           unsigned long long* npairs, Counters* ctr) {
   __shared__ TravShared sh;
+  const PairSink sink{pairs, cap, npairs, &ctr->status};
   const int32_t n = (int32_t)n64;
   const int32_t blk = (int32_t)xcd_block(blockIdx.x, gridDim.x);
   const int lt = lv.lt;
@@ -588,11 +611,11 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
   const bool small_tree = lv.L <= kSubLevels;
   if (global_part)
     traverse_part<true>(sh, n, blk, s, s < n && !small_tree, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap,
-                        em, pairs, cap, ctr, status);
+                        em, sink, ctr, status);
   else
-    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, em, pairs,
-                         cap, ctr, status);
-  block_flush<kTravWaves>(em, sh.wcount, &sh.bbase, pairs, cap, ctr);
+    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, em, sink,
+                         ctr, status);
+  block_flush<kTravWaves>(em, sh.wcount, &sh.bbase, sink);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
@@ -605,11 +628,13 @@ constexpr int kHeavyStack = 4096;
 __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* __restrict__ boxes,
                                                        const LeafRec* __restrict__ leaves,
                                                        const TravState* __restrict__ heavy, int64_t heavy_cap,
-                                                       int32_t* pairs, int64_t cap, Counters* ctr) {
+                                                       int32_t* pairs, int64_t cap, unsigned long long* npairs,
+                                                       Counters* ctr) {
+  const PairSink sink{pairs, cap, npairs, &ctr->status};
   __shared__ int2 stack[kHeavyStack];
   __shared__ int2 stage[kEmitCap];
   __shared__ int wcount[1];
-  __shared__ uint32_t bbase;
+  __shared__ int64_t bbase;
   WaveEmitter em{stage, 0};
   const int lane = __lane_id();
   int status = 0;
@@ -685,7 +710,7 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
         }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], pairs, cap, ctr);
+      for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], sink);
       // inner children: onto the stack (wave prefix sum of the counts)
       const int cnt = act && lc > 0 ? __popc(mask) : 0;
       int incl = cnt;
@@ -706,12 +731,13 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
       __builtin_amdgcn_wave_barrier();
     }
   }
-  block_flush<1>(em, wcount, &bbase, pairs, cap, ctr);
+  block_flush<1>(em, wcount, &bbase, sink);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ tris, int64_t nt, int32_t* pairs,
-                                                    int64_t cap, Counters* ctr) {
+                                                    int64_t cap, unsigned long long* npairs, Counters* ctr) {
+  const PairSink sink{pairs, cap, npairs, &ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
   WaveEmitter em{stage[threadIdx.x / 64], 0};
   for (int64_t i = blockIdx.y; i < nt; i += gridDim.y) {
@@ -728,10 +754,10 @@ __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ 
         }
         want = !adj;
       }
-      em.push(want, (int32_t)i, (int32_t)j, pairs, cap, ctr);
+      em.push(want, (int32_t)i, (int32_t)j, sink);
     }
   }
-  if (em.count > 0) em.flush(pairs, cap, ctr);
+  if (em.count > 0) em.flush(sink);
 }
 
 // ---- spatial hashing (the broad phase of Sec. 1.2) -----------------------------------------
@@ -946,10 +972,11 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
                                                          int32_t* __restrict__ heavy, int32_t* pairs, int64_t cap,
-                                                         Counters* out_ctr) {
+                                                         unsigned long long* npairs, Counters* out_ctr) {
+  const PairSink sink{pairs, cap, npairs, &out_ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
   __shared__ int wcount[kBpBlock / 64];
-  __shared__ uint32_t bbase;
+  __shared__ int64_t bbase;
   WaveEmitter em{stage[threadIdx.x / 64], 0};
   const int64_t ne = min((int64_t)ctr->n_entries, ecap);
   const HashGrid g = *grid;
@@ -969,10 +996,10 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
     for (int64_t j = e + 1; __ballot(active && j < stop); ++j) {
       int32_t other = 0;
       const bool want = active && j < stop && hash_test(h, j, skey, stri, tbox, tris, g, other);
-      em.push(want, h.tri, other, pairs, cap, out_ctr);
+      em.push(want, h.tri, other, sink);
     }
   }
-  block_flush<kBpBlock / 64>(em, wcount, &bbase, pairs, cap, out_ctr);
+  block_flush<kBpBlock / 64>(em, wcount, &bbase, sink);
 }
 
 // one wave per deferred entry: its lanes stride over the rest of the bucket
@@ -983,10 +1010,11 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
                                                          const int32_t* __restrict__ heavy, int32_t* pairs,
-                                                         int64_t cap, Counters* out_ctr) {
+                                                         int64_t cap, unsigned long long* npairs, Counters* out_ctr) {
+  const PairSink sink{pairs, cap, npairs, &out_ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
   __shared__ int wcount[kBpBlock / 64];
-  __shared__ uint32_t bbase;
+  __shared__ int64_t bbase;
   WaveEmitter em{stage[threadIdx.x / 64], 0};
   const int64_t ne = min((int64_t)ctr->n_entries, ecap);
   const int64_t nh = min((int64_t)ctr->n_heavy, ne);
@@ -999,19 +1027,13 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
       const int64_t j = jb + __lane_id();
       int32_t other = 0;
       const bool want = j < h.end && hash_test(h, j, skey, stri, tbox, tris, g, other);
-      em.push(want, h.tri, other, pairs, cap, out_ctr);
+      em.push(want, h.tri, other, sink);
     }
   }
-  block_flush<kBpBlock / 64>(em, wcount, &bbase, pairs, cap, out_ctr);
+  block_flush<kBpBlock / 64>(em, wcount, &bbase, sink);
 }
 
-__global__ void k_bp_finish(Counters* ctr, int64_t cap, int64_t* n_pairs) {
-  if (threadIdx.x == 0) {
-    const uint32_t np = ctr->n_pairs;
-    *n_pairs = (int64_t)np;
-    if ((int64_t)np > cap) atomicCAS(&ctr->status, 0, STATUS_CAPACITY);
-  }
-}
+
 
 static unsigned bp_grid(int64_t n, unsigned cap = 4096) {
   int64_t g = (n + kBpBlock - 1) / kBpBlock;
@@ -1052,11 +1074,12 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   const int64_t nt = m->n_tris;
-  k_bp_init<<<1, 64, 0, s>>>(ctr);
+  unsigned long long* npairs = reinterpret_cast<unsigned long long*>(n_pairs);
+  if (method == TTIE_BROAD_BRUTE || nt < 2) k_bp_init<<<1, 64, 0, s>>>(ctr, npairs);
   if (method == TTIE_BROAD_BRUTE) {
     dim3 grid(bp_grid(nt, 64), (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192));
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
-    k_brute<<<grid, kBpBlock, 0, s>>>(m->tris, nt, pairs, capacity, ctr);
+    k_brute<<<grid, kBpBlock, 0, s>>>(m->tris, nt, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_HASH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
@@ -1074,15 +1097,13 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     HashGrid* grid = wsp<HashGrid>(c, L.hash_grid);
     stage_begin(c, TTIE_STAGE_BP_BOXES, s);
     k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, x_end, m->n_verts, m->tris, nt, tbox, wsp<float>(c, L.bvh_centroid),
-                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), ctr);
+                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), npairs, ctr);
     k_hash_cells<<<bp_grid(nt), kBpBlock, 0, s>>>(tbox, nt, wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext),
                                                   (int)gb, hbits, hist, key, tri, wsp<int32_t>(c, L.hash_rank), ecap,
                                                   grid, ctr);
     stage_end(c, TTIE_STAGE_BP_BOXES, s);
     stage_begin(c, TTIE_STAGE_BP_SORT, s);
-    size_t bytes = L.scan_tmp_bytes;
-    hipError_t e = rocprim::exclusive_scan(c->ws + L.scan_tmp, bytes, hist, offset, 0, (size_t)nbuckets,
-                                           rocprim::plus<int32_t>(), s);
+    hipError_t e = launch_scan_i32(c, hist, offset, nbuckets, s);
     if (e != hipSuccess) return e;
     k_hash_scatter<<<bp_grid(std::max<int64_t>(4 * nt, nbuckets)), kBpBlock, 0, s>>>(
         ctr, ecap, nbuckets, hbits, key, tri, wsp<int32_t>(c, L.hash_rank), offset, skey, stri, hist);
@@ -1090,9 +1111,9 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     int32_t* heavy = wsp<int32_t>(c, L.hash_rank);  // the ranks are consumed by the scatter
     k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
-                                                           m->tris, grid, heavy, pairs, capacity, ctr);
+                                                           m->tris, grid, heavy, pairs, capacity, npairs, ctr);
     k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, heavy,
-                                          pairs, capacity, ctr);
+                                          pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
@@ -1117,14 +1138,12 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     int32_t* hist = wsp<int32_t>(c, L.bvh_hist);
     int32_t* offset = wsp<int32_t>(c, L.bvh_offset);
     k_tri_boxes<<<gb, kBpBlock, 0, s>>>(m->x, x_end, m->n_verts, m->tris, nt, tbox, centre,
-                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), ctr);
+                                        wsp<uint32_t>(c, L.bvh_part), wsp<double>(c, L.bvh_ext), npairs, ctr);
     k_morton<<<bp_grid(nt), kBpBlock, 0, s>>>(centre, nt, wsp<uint32_t>(c, L.bvh_part), (int)gb, tri_off, n_prob,
                                               mbits, hist, k1, v1, ctr);
     stage_end(c, TTIE_STAGE_BP_BOXES, s);
     stage_begin(c, TTIE_STAGE_BP_SORT, s);
-    size_t bytes = L.scan_tmp_bytes;
-    hipError_t e = rocprim::exclusive_scan(c->ws + L.scan_tmp, bytes, hist, offset, 0, (size_t)nbuckets,
-                                           rocprim::plus<int32_t>(), s);
+    hipError_t e = launch_scan_i32(c, hist, offset, nbuckets, s);
     if (e != hipSuccess) return e;
     k_scatter<<<bp_grid(std::max<int64_t>(nt, nbuckets)), kBpBlock, 0, s>>>(nt, nbuckets, k1, v1, offset, v2, hist);
     stage_end(c, TTIE_STAGE_BP_SORT, s);
@@ -1139,11 +1158,10 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     TravState* heavy = wsp<TravState>(c, L.bvh_heavy);
     const int64_t heavy_cap = (int64_t)(L.bvh_heavy_bytes / sizeof(TravState));
     k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy, heavy_cap,
-                                                     pairs, capacity, ctr);
-    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, pairs, capacity, ctr);
+                                                     pairs, capacity, npairs, ctr);
+    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
-  k_bp_finish<<<1, 64, 0, s>>>(ctr, capacity, n_pairs);
   return hipGetLastError();
 }
 

@@ -584,9 +584,14 @@ size_t scan_temp_bytes(int64_t n) {
   return bytes;
 }
 
-static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
   size_t bytes = c->L.scan_tmp_bytes;
   return rocprim::exclusive_scan(c->ws + c->L.scan_tmp, bytes, in, out, 0, (size_t)n, rocprim::plus<int32_t>(), s);
+}
+
+static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  return launch_scan_i32(c, in, out, n, s);
 }
 
 template <class S>

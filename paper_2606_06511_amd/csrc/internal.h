@@ -41,7 +41,7 @@ struct Incidence {
 struct Counters {
   int32_t status;          // latched TTIE status (first error wins)
   uint32_t n_hits;         // intersecting pairs found by the last screening
-  uint32_t n_pairs;        // candidates emitted by the last broad phase
+  uint32_t spare;          // (unused)
   uint32_t n_defer;        // candidates whose signs need the exact fallback
   uint32_t n_touched;      // vertices touched by the hits of the current evaluation
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
@@ -127,5 +127,7 @@ hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* 
                          const void* x, void* y, int precision, hipStream_t s);
 hipError_t launch_init_counters(Ctx* c, hipStream_t s);
 size_t scan_temp_bytes(int64_t n);
+// exclusive scan of n int32 (rocPRIM)
+hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 
 }  // namespace ttie
