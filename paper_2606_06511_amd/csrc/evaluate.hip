@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ r
 
 constexpr int kWaves = kBlock / 64;
 constexpr int kCandCap = 256;  // column candidates staged in LDS per wave
+constexpr int kRowStage = 16;  // incidences (and their hit records) a wave stages in LDS per row
 
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict__ touched, const Counters* ctr,
@@ -252,55 +253,76 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
                                                       int64_t cstage_len, int32_t* __restrict__ ncol, int want_bsr) {
   __shared__ int32_t lcand[kWaves][kCandCap];
   __shared__ uint8_t lflag[kWaves][kCandCap];
+  __shared__ Incidence sinc[kWaves][64];
   const int wave = threadIdx.x / 64, lane = __lane_id();
   const uint32_t U = ctr->n_touched;
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
     const int32_t v = touched[u];
     const int32_t b = off[v], n = off[v + 1] - b;
     // rank sort of the row's incidences by (pair key, position): the ranks are a permutation
-    // even if a caller repeats a pair
-    for (int32_t i = lane; i < n; i += 64) {
-      const Incidence me = inc[b + i];
-      int32_t rank = 0;
-      for (int32_t j = 0; j < n; ++j) {
-        const int64_t kj = inc[b + j].key;
-        rank += kj < me.key || (kj == me.key && j < i);
+    // even if a caller repeats a pair.  Rows of up to 64 (wave-uniform test) rank from LDS.
+    if (n <= 64) {
+      Incidence me{};
+      if (lane < n) sinc[wave][lane] = me = inc[b + lane];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < n) {
+        int32_t rank = 0;
+        for (int32_t j = 0; j < n; ++j) {
+          const int64_t kj = sinc[wave][j].key;
+          rank += (kj < me.key) | ((kj == me.key) & (j < lane));
+        }
+        inc2[b + rank] = me;
       }
-      inc2[b + rank] = me;
+    } else {
+      for (int32_t i = lane; i < n; i += 64) {
+        const Incidence me = inc[b + i];
+        int32_t rank = 0;
+        for (int32_t j = 0; j < n; ++j) {
+          const int64_t kj = inc[b + j].key;
+          rank += kj < me.key || (kj == me.key && j < i);
+        }
+        inc2[b + rank] = me;
+      }
     }
-    if (!want_bsr) continue;
-    // candidate columns: the six vertices of every incident hit, staged in LDS (or, for very
-    // large rows, in the workspace) with a first-occurrence flag each
-    const int32_t m = 6 * n;
-    const bool in_lds = m <= kCandCap;
-    int32_t* cand = in_lds ? lcand[wave] : cstage + 6 * (int64_t)b;
-    uint8_t* first = in_lds ? lflag[wave] : reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b;
-    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[inc[b + c / 6].hit].vid[c % 6];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int32_t c = lane; c < m; c += 64) {
-      const int32_t val = cand[c];
-      bool f = true;
-      for (int32_t j = 0; j < c && f; ++j) f = cand[j] != val;
-      first[c] = f ? 1 : 0;
+    if (want_bsr) {
+      // candidate columns: the six vertices of every incident hit, staged in LDS (or, for very
+      // large rows, in the workspace) with a first-occurrence flag each
+      const int32_t m = 6 * n;
+      const bool in_lds = m <= kCandCap;
+      int32_t* cand = in_lds ? lcand[wave] : cstage + 6 * (int64_t)b;
+      uint8_t* first = in_lds ? lflag[wave] : reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b;
+      if (n <= 64) {
+        for (int32_t c = lane; c < m; c += 64) cand[c] = recs[sinc[wave][c / 6].hit].vid[c % 6];
+      } else {
+        for (int32_t c = lane; c < m; c += 64) cand[c] = recs[inc[b + c / 6].hit].vid[c % 6];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int32_t c = lane; c < m; c += 64) {
+        const int32_t val = cand[c];
+        bool f = true;
+        for (int32_t j = 0; j < c && f; ++j) f = cand[j] != val;
+        first[c] = f ? 1 : 0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // a kept candidate goes to the number of kept candidates with a smaller vertex id
+      int32_t kept = 0;
+      for (int32_t c = lane; c < m; c += 64) {
+        if (!first[c]) continue;
+        const int32_t val = cand[c];
+        int32_t pos = 0;
+        for (int32_t j = 0; j < m; ++j) pos += first[j] && cand[j] < val;
+        colbuf[6 * (int64_t)b + pos] = val;
+        ++kept;
+      }
+      // wave sum of kept
+      for (int w = 32; w > 0; w >>= 1) kept += __shfl_xor(kept, w);
+      if (lane == 0) ncol[v] = kept;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // a kept candidate goes to the number of kept candidates with a smaller vertex id
-    int32_t kept = 0;
-    for (int32_t c = lane; c < m; c += 64) {
-      if (!first[c]) continue;
-      const int32_t val = cand[c];
-      int32_t pos = 0;
-      for (int32_t j = 0; j < m; ++j) pos += first[j] && cand[j] < val;
-      colbuf[6 * (int64_t)b + pos] = val;
-      ++kept;
-    }
-    // wave sum of kept
-    for (int w = 32; w > 0; w >>= 1) kept += __shfl_xor(kept, w);
-    if (lane == 0) ncol[v] = kept;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_wave_barrier();  // the LDS staging is reused by the wave's next row
   }
 }
 
@@ -316,6 +338,11 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
     }
 }
 
+// One touched row per wave: the gradient row and the energy of the hits this vertex owns
+// (each hit counted at its first vertex), summed in pair-key order, then the row's BSR blocks,
+// one lane per column.  The row's incidences and hit records pass through LDS in chunks of
+// kRowStage (one memory round trip per chunk instead of a chain of dependent loads per
+// incidence); the sums run over the incidences in order, chunk after chunk.
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__ touched, const Counters* ctr,
                                                      const int32_t* __restrict__ off,
@@ -325,45 +352,71 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
                                                      const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                      S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
                                                      double* __restrict__ epart, int32_t* status_word) {
+  __shared__ AsmRec<S> srec[kWaves][kRowStage];
+  __shared__ Incidence sinc[kWaves][kRowStage];
+  constexpr int kWords = (int)(sizeof(AsmRec<S>) / 8);
+  static_assert(sizeof(AsmRec<S>) % 8 == 0, "records are copied as 8-byte words");
   const int wave = threadIdx.x / 64, lane = __lane_id();
+  AsmRec<S>* R = srec[wave];
+  Incidence* I = sinc[wave];
+  // stages incidences [k0, k0 + cnt) of the row starting at b (every lane of the wave calls it)
+  auto stage = [&](int32_t b, int32_t k0, int32_t cnt) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the previous chunk is no longer read
+    if (lane < cnt) I[lane] = inc2[b + k0 + lane];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < cnt * kWords; j += 64) {
+      const int r = j / kWords, w = j % kWords;
+      reinterpret_cast<uint2*>(&R[r])[w] = reinterpret_cast<const uint2*>(&recs[I[r].hit])[w];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
   const uint32_t U = ctr->n_touched;
   int status = 0;
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
     const int32_t v = touched[u];
-    const int32_t b = off[v], e = off[v + 1];
-    // gradient row (lanes 0-2) and the energy of the hits this vertex owns (lane 3), in
-    // pair-key order
-    if (lane < 4) {
-      S acc = Sc<S>::c(0.0);
-      double erow = 0.0;
-      for (int32_t k = b; k < e; ++k) {
-        const Incidence in = inc2[k];
-        if (lane < 3) acc = acc + recs[in.hit].g[3 * in.slot + lane];
-        else if (in.slot == 0) erow += recs[in.hit].T;  // each hit counted at its first vertex
-      }
-      if (lane < 3) grad[3 * (int64_t)v + lane] = acc;
-      else epart[v] = erow;
+    const int32_t b = off[v], n = off[v + 1] - b;
+    // gradient row (lanes 0-2) and energy (lane 3)
+    S acc = Sc<S>::c(0.0);
+    double erow = 0.0;
+    for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
+      const int32_t cnt = min(n - k0, kRowStage);
+      stage(b, k0, cnt);
+      if (lane < 4)
+        for (int32_t k = 0; k < cnt; ++k) {
+          if (lane < 3) acc = acc + R[k].g[3 * I[k].slot + lane];
+          else if (I[k].slot == 0) erow += R[k].T;
+        }
     }
+    if (lane < 3) grad[3 * (int64_t)v + lane] = acc;
+    else if (lane == 3) epart[v] = erow;
     if (!row_ptr) continue;
+    // BSR blocks: lane q owns column q (rows with more than 64 columns take several rounds)
     const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
-    for (int32_t q = lane; q < nc; q += 64) {
-      const int32_t col = colbuf[6 * (int64_t)b + q];
+    for (int32_t q0 = 0; q0 < nc; q0 += 64) {
+      const int32_t q = q0 + lane;
+      const int32_t col = q < nc ? colbuf[6 * (int64_t)b + q] : -1;
       S B[9];
 #pragma unroll
       for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
-      for (int32_t k = b; k < e; ++k) {
-        const Incidence in = inc2[k];
-        const AsmRec<S>& r = recs[in.hit];
-        for (int l = 0; l < 6; ++l)
-          if (r.vid[l] == col) block_jmj(r, in.slot, l, B);
+      for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
+        const int32_t cnt = min(n - k0, kRowStage);
+        if (n > kRowStage || q0 > 0) stage(b, k0, cnt);  // a one-chunk row is still in LDS
+        for (int32_t k = 0; k < cnt; ++k)
+          for (int l = 0; l < 6; ++l)
+            if (R[k].vid[l] == col) block_jmj(R[k], I[k].slot, l, B);
       }
-      const int64_t pos = (int64_t)rp + q;
-      if (pos < block_cap) {
-        col_idx[pos] = col;
+      if (q < nc) {
+        const int64_t pos = (int64_t)rp + q;
+        if (pos < block_cap) {
+          col_idx[pos] = col;
 #pragma unroll
-        for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
-      } else {
-        status = STATUS_CAPACITY;
+          for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
+        } else {
+          status = STATUS_CAPACITY;
+        }
       }
     }
   }
