@@ -180,17 +180,39 @@ __global__ void __launch_bounds__(kBpBlock) k_morton(const float* __restrict__ c
     const float ext = key2f(sb[3 + c]) - lo[c];
     inv[c] = ext > 0.f ? 1023.f / ext : 0.f;
   }
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t q[3];
-    for (int c = 0; c < 3; ++c) {
-      const float f = (centre[3 * t + c] - lo[c]) * inv[c];
-      q[c] = (uint32_t)fminf(fmaxf(f, 0.f), 1023.f);
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nt; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = base + threadIdx.x;
+    const bool active = t < nt;
+    uint32_t bk = 0;
+    if (active) {
+      uint32_t q[3];
+      for (int c = 0; c < 3; ++c) {
+        const float f = (centre[3 * t + c] - lo[c]) * inv[c];
+        q[c] = (uint32_t)fminf(fmaxf(f, 0.f), 1023.f);
+      }
+      const uint32_t code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+      const uint32_t p = tri_off ? (uint32_t)problem_of(tri_off, n_prob, t) : 0u;
+      bk = (p << mbits) | (code >> (30 - mbits));
+      bucket[t] = bk;
     }
-    const uint32_t code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    const uint32_t p = tri_off ? (uint32_t)problem_of(tri_off, n_prob, t) : 0u;
-    const uint32_t bk = (p << mbits) | (code >> (30 - mbits));
-    bucket[t] = bk;
-    rank[t] = atomicAdd(&hist[bk], 1);  // the order inside a bucket is arbitrary
+    // Neighbouring triangles share buckets: group the wave's lanes by bucket (ballots only),
+    // then one lane per group reserves the group's ranks with a single atomic, all groups at
+    // once.  The order inside a bucket is arbitrary.
+    uint64_t todo = __ballot(active);
+    uint64_t group = 0;
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t b = __shfl(bk, leader);
+      const uint64_t m = __ballot(active && bk == b) & todo;
+      if ((m >> lane) & 1ull) group = m;
+      todo &= ~m;
+    }
+    const int my_leader = active ? __ffsll((unsigned long long)group) - 1 : lane;
+    int32_t gbase = 0;
+    if (active && my_leader == lane) gbase = atomicAdd(&hist[bk], (int32_t)__popcll(group));
+    gbase = __shfl(gbase, my_leader);
+    if (active) rank[t] = gbase + (int32_t)__popcll(group & ((1ull << lane) - 1ull));
   }
 }
 
