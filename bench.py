@@ -27,28 +27,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad phase, seed 0"
 
-# HBM bytes per launch of a kernel from two rocprofv3 counter passes on this workload
-# (FETCH_SIZE x 1.9998 and WRITE_SIZE x 1.0, the factors that make a 256 MiB elementwise copy
-# read and write 256 MiB).  A figure holds only for the kernel source it was taken on: when the
-# file's hash differs, the traffic is reported as null until the counters are taken again.
-MEASURED_TRAFFIC = {
-    "bp_traverse": {"bytes": 16366234, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-                    "sha256": "50d9b78f9e0b5f7f7778cfcaea7be78c6b65fe74c38ac66d0e019753be5cf794"},
+# Counter figures per launch of a kernel on this workload, valid only for the kernel source they
+# were taken on (when the file's hash differs they are reported as null until taken again):
+#   bytes       HBM bytes from two rocprofv3 passes, FETCH_SIZE x 1.9998 and WRITE_SIZE x 1.0 (the
+#               factors that make a 256 MiB elementwise copy read and write 256 MiB)
+#   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
+MEASURED = {
+    "bp_traverse": {"bytes": 16472655, "valu_wave": 14514689, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+                    "sha256": "37e27c3548f2937deaddc0eb5bfa9e47cb06b7df17a6e38a31b6c9ddd4473bf2"},
 }
+# VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def measured_traffic(stage):
+def measured(stage, what):
     import hashlib
 
-    m = MEASURED_TRAFFIC.get(stage)
+    m = MEASURED.get(stage)
     if not m:
         return None
     with open(os.path.join(ROOT, m["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
             return None
-    return m["bytes"]
-WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad phase, seed 0"
+    return m[what]
 
 
 def stage_bytes(stage, nv, nt, P, H, nnzb, prec_bytes):
@@ -316,10 +319,19 @@ def main():
         "broadphase_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if k.startswith("bp_")),
                             "tris_per_s": nt / (sum(v for k, v in per_step_stage.items() if k.startswith("bp_")) * 1e-3)},
         "roofline": {"kernel_stage": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured(dominant, "bytes"),
                      "traffic_unit": "bytes per launch",
                      "alg_bytes_per_launch": alg, "avg_launch_ms": dom_avg_ms, "launches": dom_launches},
     }
+
+    # the same kernel against the VALU issue rate (its real bound: a latency- and issue-bound
+    # tree search), from the committed instruction count and the live duration
+    vw = measured(dominant, "valu_wave")
+    if vw and dom_avg_ms > 0:
+        rate = vw * 64 / (dom_avg_ms * 1e-3)
+        rec["roofline_issue"] = {"kernel_stage": dominant, "bound": "alu", "achieved": rate, "peak": VALU_LANE_PEAK,
+                                 "unit": "VALU lane-instructions/s", "frac": rate / VALU_LANE_PEAK,
+                                 "valu_wave_instructions_per_launch": vw}
 
     if not args.no_cpu_baseline:
         import oracle
