@@ -140,6 +140,11 @@ def extra_configs(args, np, torch, ttie, workloads):
         ctx.batch_broadphase(xd, td, to, capacity=cap, out=(pairs, n))
         ctx.batch_evaluate(xd, td, vo, pairs, n, precision=ttie.MIXED, out=out)
 
+    # the launch parameters are tuned on this batch (coordinate descent over the step time),
+    # then the tuned step is captured
+    from paper_2606_06511_amd import autotune
+
+    tuned, ms_tuned, ms_default = autotune.tune(ctx, batch_step, reps=5, rounds=1)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -164,7 +169,8 @@ def extra_configs(args, np, torch, ttie, workloads):
                                   "5,664,096 tris), batched LBVH, seed 0",
                       "problems": len(probs), "pairs": P, "hits": int(out["n_hits"].item()),
                       "ms_per_step": ms_graph, "pairs_per_s": P / (ms_graph * 1e-3),
-                      "ms_per_step_eager": ms_eager, "graph_replay_matches_eager": same}
+                      "ms_per_step_eager": ms_eager, "graph_replay_matches_eager": same,
+                      "autotuned": tuned, "ms_eager_default_params": ms_default, "ms_eager_tuned_params": ms_tuned}
     del ctx, pairs, out
 
     # inexact Newton, 20 steps, on the 4,194,304-triangle sphere (Jacobi-PCG with 50 iterations)

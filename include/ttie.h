@@ -236,6 +236,22 @@ ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, cons
 ttie_status ttie_pcg_mf(ttie_ctx* ctx, int64_t n_rows, const void* b, double scale, void* x, double mu_rel,
                         int max_iter, double tol, double* info, void* stream);
 
+/* ---- launch parameters (what an autotuner varies) ------------------------------------
+ * Launch shapes and work budgets of the kernels.  Every value in range gives the same results
+ * bit for bit (the evaluation sums in pair-key order and a candidate set does not depend on
+ * the order of emission); only the speed changes.  A value of 0 restores the default. */
+enum {
+  TTIE_PARAM_SCREEN_BLOCKS = 0, /* blocks of the screening kernel: 64 .. 65536 (default 2048) */
+  TTIE_PARAM_ROW_BLOCKS = 1,    /* blocks of the row (assembly) kernels: 64 .. 65536 (default 2048) */
+  TTIE_PARAM_TRAV_BUDGET = 2,   /* nodes a traversal lane visits before a whole wave takes over its
+                                   query: 16 .. 2^20 (default 128) */
+  TTIE_PARAM_HASH_BUDGET = 3,   /* later bucket entries a hash thread tests before a whole wave takes
+                                   over the rest: 16 .. 2^20 (default 64) */
+  TTIE_PARAM_COUNT = 4
+};
+ttie_status ttie_set_param(ttie_ctx* ctx, int param, int64_t value);
+ttie_status ttie_get_param(ttie_ctx* ctx, int param, int64_t* value_host);
+
 /* out = x + alpha * d for n_verts x 3 positions: x and out float64, d in `precision`. */
 ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double* x, const void* d, double* out,
                       int precision, void* stream);

@@ -477,6 +477,23 @@ ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double
   return TTIE_OK;
 }
 
+ttie_status ttie_set_param(ttie_ctx* ctx, int param, int64_t value) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  if (param < 0 || param >= TTIE_PARAM_COUNT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown parameter");
+  static const int64_t lo[TTIE_PARAM_COUNT] = {64, 64, 16, 16};
+  static const int64_t hi[TTIE_PARAM_COUNT] = {65536, 65536, 1 << 20, 1 << 20};
+  if (value != 0 && (value < lo[param] || value > hi[param])) return fail(TTIE_ERR_INVALID_ARGUMENT, "value out of range");
+  ctx->param[param] = value;
+  return TTIE_OK;
+}
+
+ttie_status ttie_get_param(ttie_ctx* ctx, int param, int64_t* value_host) {
+  if (!ctx || !value_host) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (param < 0 || param >= TTIE_PARAM_COUNT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown parameter");
+  *value_host = ctx_param(ctx, param);
+  return TTIE_OK;
+}
+
 ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask) {
   if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
   ctx->timing_mask = stage_mask & ((1u << TTIE_STAGE_COUNT) - 1u);

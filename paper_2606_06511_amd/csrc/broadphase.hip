@@ -421,12 +421,11 @@ constexpr int kTravThreads = 2 * kBpBlock;          // a local and a global lane
 constexpr int kTravWaves = kTravThreads / 64;
 constexpr int kTopCap = 864;                        // 27 KB of top-level boxes
 
-// A lane that has visited kTravBudget nodes hands the rest of its search to k_traverse_heavy
+// A lane that has visited `budget` nodes (a launch parameter, 128 by default) hands the rest
+// of its search to k_traverse_heavy
 // (one wave per query), by saving its depth-first state: the node it is about to visit and the
 // pending siblings of every ancestor up to its starting level.  Few queries get there -- those
 // whose boxes overlap hundreds of others, as in the fan of thin triangles around a pole.
-constexpr int kTravBudget = 128;
-
 struct TravState {
   int32_t s;      // query leaf (sorted position)
   int32_t part;   // 1: global part (skips the query's own level-4 subtree)
@@ -456,7 +455,7 @@ template <bool kGlobal>
 __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t blk, int32_t s, bool active, int lt,
                                               int32_t tbase, int L, const Box32* __restrict__ boxes,
                                               const LeafRec* __restrict__ leaves, const int32_t* __restrict__ qend,
-                                              TravState* heavy, int64_t heavy_cap, WaveEmitter& em,
+                                              TravState* heavy, int64_t heavy_cap, int budget, WaveEmitter& em,
                                               const PairSink& sink, Counters* ctr, int& status) {
   const int qi = s - blk * kBpBlock;
   const bool small_tree = L <= kSubLevels;
@@ -484,7 +483,7 @@ __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t
       break;
     }
     // over budget: hand the remaining search to a wave of its own (when the list has room)
-    const bool over = active && may_defer && visits >= kTravBudget;
+    const bool over = active && may_defer && visits >= budget;
     const uint32_t hs = wave_slot(over, &ctr->n_heavy);
     if (over) may_defer = false;
     if (over && (int64_t)hs < heavy_cap) {
@@ -593,7 +592,7 @@ __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t
 __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels lv, const Box32* __restrict__ boxes,
                                                            const LeafRec* __restrict__ leaves,
                                                            const int32_t* __restrict__ qend, TravState* heavy,
-                                                           int64_t heavy_cap, int32_t* pairs, int64_t cap,
+                                                           int64_t heavy_cap, int budget, int32_t* pairs, int64_t cap,
                                                            unsigned long long* npairs, Counters* ctr) {
   __shared__ TravShared sh;
   const PairSink sink{pairs, cap, npairs, &ctr->status};
@@ -633,10 +632,10 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
   const bool small_tree = lv.L <= kSubLevels;
   if (global_part)
     traverse_part<true>(sh, n, blk, s, s < n && !small_tree, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap,
-                        em, sink, ctr, status);
+                        budget, em, sink, ctr, status);
   else
-    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, em, sink,
-                         ctr, status);
+    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, budget, em,
+                         sink, ctr, status);
   block_flush<kTravWaves>(em, sh.wcount, &sh.bbase, sink);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
@@ -982,10 +981,10 @@ __device__ __forceinline__ bool hash_test(const HashQuery& h, int64_t j, const u
   return !adj;
 }
 
-// A thread tests at most kHashBudget later entries of its bucket; the rest of a longer bucket
+// A thread tests at most `hbudget` (a launch parameter, 64 by default) later entries of its
+// bucket; the rest of a longer bucket
 // (the cells where many triangles meet, e.g. the fan around a pole) goes to k_hash_heavy, where
 // a whole wave shares it.
-constexpr int kHashBudget = 64;
 
 __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, int64_t ecap, int64_t nbuckets, int hbits,
                                                          const int32_t* __restrict__ offset,
@@ -993,7 +992,8 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
                                                          const int32_t* __restrict__ stri,
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
-                                                         int32_t* __restrict__ heavy, int32_t* pairs, int64_t cap,
+                                                         int hbudget, int32_t* __restrict__ heavy, int32_t* pairs,
+                                                         int64_t cap,
                                                          unsigned long long* npairs, Counters* out_ctr) {
   const PairSink sink{pairs, cap, npairs, &out_ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
     int64_t stop = 0;
     if (active) {
       h = hash_query(e, ne, nbuckets, hbits, offset, skey, stri, tbox, tris, g);
-      stop = min(h.end, e + 1 + kHashBudget);
+      stop = min(h.end, e + 1 + hbudget);
     }
     const bool defer = active && h.end > stop;
     const uint32_t slot = wave_slot(defer, &out_ctr->n_heavy);
@@ -1031,7 +1031,7 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
                                                          const int32_t* __restrict__ stri,
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
-                                                         const int32_t* __restrict__ heavy, int32_t* pairs,
+                                                         int hbudget, const int32_t* __restrict__ heavy, int32_t* pairs,
                                                          int64_t cap, unsigned long long* npairs, Counters* out_ctr) {
   const PairSink sink{pairs, cap, npairs, &out_ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
@@ -1045,7 +1045,7 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
   for (int64_t it = (int64_t)blockIdx.x * (kBpBlock / 64) + threadIdx.x / 64; it < nh; it += waves) {
     const int64_t e = heavy[it];
     const HashQuery h = hash_query(e, ne, nbuckets, hbits, offset, skey, stri, tbox, tris, g);
-    for (int64_t jb = e + 1 + kHashBudget; jb < h.end; jb += 64) {
+    for (int64_t jb = e + 1 + hbudget; jb < h.end; jb += 64) {
       const int64_t j = jb + __lane_id();
       int32_t other = 0;
       const bool want = j < h.end && hash_test(h, j, skey, stri, tbox, tris, g, other);
@@ -1132,9 +1132,10 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     stage_end(c, TTIE_STAGE_BP_SORT, s);
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     int32_t* heavy = wsp<int32_t>(c, L.hash_rank);  // the ranks are consumed by the scatter
+    const int hb = (int)ctx_param(c, TTIE_PARAM_HASH_BUDGET);
     k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
-                                                           m->tris, grid, heavy, pairs, capacity, npairs, ctr);
-    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, heavy,
+                                                           m->tris, grid, hb, heavy, pairs, capacity, npairs, ctr);
+    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, hb, heavy,
                                           pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
@@ -1180,7 +1181,8 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     TravState* heavy = wsp<TravState>(c, L.bvh_heavy);
     const int64_t heavy_cap = (int64_t)(L.bvh_heavy_bytes / sizeof(TravState));
     k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy, heavy_cap,
-                                                     pairs, capacity, npairs, ctr);
+                                                     (int)ctx_param(c, TTIE_PARAM_TRAV_BUDGET), pairs, capacity,
+                                                     npairs, ctr);
     k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }

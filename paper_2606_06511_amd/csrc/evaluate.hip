@@ -675,7 +675,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   const bool bsr = row_ptr != nullptr;
 
   stage_begin(c, TTIE_STAGE_SCREEN, s);
-  k_screen<<<grid_for(pair_cap, 2048), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
+  k_screen<<<grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS)), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
                                                        hits, max_hits, defer, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
@@ -690,7 +690,8 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   hipError_t err = scan_i32(c, cnt, off, nv + 1, s);
   if (err != hipSuccess) return err;
   k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, off, cur, inc);
-  const unsigned grows = (unsigned)std::min<int64_t>(2048, (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
+  const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
+                                                     (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
   k_rows_sort<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc, inc2, recs, colbuf, cstage, 36 * c->lim.max_hits,
                                           ncol, bsr ? 1 : 0);
   if (bsr) {

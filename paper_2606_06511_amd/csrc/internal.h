@@ -94,7 +94,14 @@ struct Ctx {
   int last_interval;
   int64_t last_nverts;
   int last_valid;
+  int64_t param[TTIE_PARAM_COUNT];  // launch parameters, 0 = default
 };
+
+// a launch parameter of the context (its default when unset)
+inline int64_t ctx_param(const Ctx* c, int k) {
+  static const int64_t kDefault[TTIE_PARAM_COUNT] = {2048, 2048, 128, 64};
+  return c->param[k] ? c->param[k] : kDefault[k];
+}
 
 template <class T>
 inline T* wsp(Ctx* c, size_t off) {

@@ -27,6 +27,7 @@ BROAD_BRUTE, BROAD_LBVH, BROAD_HASH = 0, 1, 2
 HVP_EXACT, HVP_PSD = 0, 1
 PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME = 0, 1, 2, 3
 MAX_PROBLEMS = 4096
+PARAM_SCREEN_BLOCKS, PARAM_ROW_BLOCKS, PARAM_TRAV_BUDGET, PARAM_HASH_BUDGET = 0, 1, 2, 3
 
 # every function the header declares, with (restype, argtypes)
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
@@ -67,6 +68,8 @@ SIGNATURES = {
                         ctypes.c_double, _i32, _vp, _vp]),
     "ttie_pcg_mf": (_i32, [_vp, _i64, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32, ctypes.c_double, _vp, _vp]),
     "ttie_axpy": (_i32, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, _i32, _vp]),
+    "ttie_set_param": (_i32, [_vp, _i32, _i64]),
+    "ttie_get_param": (_i32, [_vp, _i32, ctypes.POINTER(_i64)]),
     "ttie_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "ttie_read_timers": (_i32, [_vp, _i32, _vp, _vp]),
 }
@@ -322,6 +325,15 @@ class Context:
             out = torch.empty_like(x)
         _check(lib().ttie_axpy(self.handle, x.shape[0], float(alpha), _ptr(x), _ptr(d), _ptr(out), precision, _stream()))
         return out
+
+    def set_param(self, param, value):
+        """Sets a launch parameter (PARAM_*); 0 restores its default.  Results do not change."""
+        _check(lib().ttie_set_param(self.handle, int(param), int(value)))
+
+    def get_param(self, param):
+        v = ctypes.c_int64(0)
+        _check(lib().ttie_get_param(self.handle, int(param), ctypes.byref(v)))
+        return v.value
 
     def set_timing(self, stages=None):
         """Enables the stage timers for the named stages (None: all, []: none)."""
