@@ -95,6 +95,29 @@ def extra_configs(args, np, torch, ttie, workloads):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
+    # two icospheres, every non-adjacent pair (brute force), FP64
+    x, tris = workloads.two_icospheres(seed=0)
+    ctx = ttie.Context(0)
+    cap = 1 << 22
+    ctx.reserve(len(x), len(tris), cap, max_hits=1 << 12, max_blocks=36 << 12)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
+    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    n = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=ttie.FP64)
+
+    def ico_step():
+        ctx.broadphase(xd, td, ttie.BROAD_BRUTE, capacity=cap, out=(pairs, n))
+        ctx.evaluate(xd, td, pairs, n, precision=ttie.FP64, out=out)
+
+    ms = run(ico_step, 20)
+    ctx.check()
+    P = int(n.item())
+    res["icospheres_brute"] = {"workload": "two icospheres (642 verts / 1280 tris each), all 3,260,220 non-adjacent "
+                                           "pairs, FP64, seed 0",
+                               "pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
+                               "pairs_per_s": P / (ms * 1e-3)}
+    del ctx, pairs, out
+
     # noisy sphere, 1024 x 513 bands
     x, tris = workloads.noisy_sphere(seed=0)
     ctx = ttie.Context(0)
