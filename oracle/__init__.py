@@ -48,7 +48,7 @@ def lib():
         L.ttie_oracle_pair_hvp.restype = ctypes.c_int
         L.ttie_oracle_eig.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.ttie_oracle_eig.restype = None
-        L.ttie_oracle_pairs.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, ctypes.c_int, _lp]
+        L.ttie_oracle_pairs.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _lp]
         L.ttie_oracle_pairs.restype = ctypes.c_void_p
         L.ttie_oracle_free.argtypes = [ctypes.c_void_p]
         L.ttie_oracle_free.restype = None
@@ -60,7 +60,7 @@ def lib():
                                          ctypes.POINTER(ctypes.c_int)]
         L.ttie_oracle_newton.restype = ctypes.c_int
         L.ttie_oracle_eval.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, _ip, ctypes.c_int64,
-                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ttie_oracle_eval.restype = ctypes.c_void_p
         L.ttie_oracle_eval_sizes.argtypes = [ctypes.c_void_p, _lp, _lp]
         L.ttie_oracle_eval_sizes.restype = ctypes.c_int
@@ -70,7 +70,7 @@ def lib():
         L.ttie_oracle_eval_free.argtypes = [ctypes.c_void_p]
         L.ttie_oracle_eval_free.restype = None
         L.ttie_oracle_hvp.argtypes = [_dp, ctypes.c_int64, _ip, ctypes.c_int64, _ip, ctypes.c_int64, _dp,
-                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int]
         L.ttie_oracle_hvp.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -136,12 +136,14 @@ def eig(A):
     return w, Q
 
 
-def pairs(x, tris, method=BROAD_BOXES):
-    """Canonical sorted candidate list (P, 2) int32: i < j, no shared vertex, and for
-    BROAD_BOXES closed FP64 bounding boxes overlapping."""
+def pairs(x, tris, method=BROAD_BOXES, vertex_adjacent=False):
+    """Canonical sorted candidate list (P, 2) int32: i < j, no shared vertex (with
+    ``vertex_adjacent``: at most one shared vertex), and for BROAD_BOXES closed FP64 bounding
+    boxes overlapping."""
     x, tris = _f64(x), _i32(tris)
     n = ctypes.c_int64(0)
-    ptr = lib().ttie_oracle_pairs(_d(x), len(x), _i(tris), len(tris), method, ctypes.byref(n))
+    ptr = lib().ttie_oracle_pairs(_d(x), len(x), _i(tris), len(tris), method, 1 if vertex_adjacent else 0,
+                                  ctypes.byref(n))
     try:
         out = np.ctypeslib.as_array(ctypes.cast(ptr, _ip), shape=(max(1, 2 * n.value),))[: 2 * n.value].copy()
     finally:
@@ -176,18 +178,20 @@ def newton(x, tris, steps=20, pcg_iters=50, pcg_tol=1e-6, mu_rel=1e-3, armijo_c=
     return x, E, al, its
 
 
-def evaluate(x, tris, pair_list, interval=INTERVAL_EQ1, psd=PSD_PER_PART, hessian=True, threads=0):
+def evaluate(x, tris, pair_list, interval=INTERVAL_EQ1, psd=PSD_PER_PART, hessian=True, threads=0,
+             vertex_adjacent=False):
     """Energy, gradient and block-sparse Hessian over a candidate list.
 
     Returns a dict with per-pair ``flags`` (0 none, 1 hit, 2 adjacent, 3 hit with a
     degenerate line frame), ``t`` (P,2), ``T`` (P,), and totals ``E``, ``G`` (N_v,3), the
     hit records (``hit_pair``, ``hit_t``, ``hit_a``, ``hit_b``, ``hit_g``, ``hit_H``) and the
-    BSR Hessian ``row_ptr``, ``col_idx``, ``vals`` (nnzb,3,3).
+    BSR Hessian ``row_ptr``, ``col_idx``, ``vals`` (nnzb,3,3).  With ``vertex_adjacent`` a pair
+    sharing exactly one vertex is evaluated instead of flagged adjacent.
     """
     x, tris, pl = _f64(x), _i32(tris), _i32(pair_list).reshape(-1, 2)
     L = lib()
     h = L.ttie_oracle_eval(_d(x), len(x), _i(tris), len(tris), _i(pl), len(pl), interval, psd,
-                           1 if hessian else 0, threads)
+                           1 if hessian else 0, threads, 1 if vertex_adjacent else 0)
     try:
         nh, nb = ctypes.c_int64(0), ctypes.c_int64(0)
         err = L.ttie_oracle_eval_sizes(h, ctypes.byref(nh), ctypes.byref(nb))
@@ -217,13 +221,14 @@ def evaluate(x, tris, pair_list, interval=INTERVAL_EQ1, psd=PSD_PER_PART, hessia
     return out
 
 
-def hvp(x, tris, pair_list, v, interval=INTERVAL_EQ1, exact=True, psd=PSD_PER_PART, threads=0):
+def hvp(x, tris, pair_list, v, interval=INTERVAL_EQ1, exact=True, psd=PSD_PER_PART, threads=0,
+        vertex_adjacent=False):
     """H v summed over the candidate list: the exact Hessian (nested duals) when ``exact``,
     else the ``psd`` Hessian of Eq. 4."""
     x, tris, pl, v = _f64(x), _i32(tris), _i32(pair_list).reshape(-1, 2), _f64(v).reshape(-1, 3)
     out = np.zeros_like(x)
     lib().ttie_oracle_hvp(_d(x), len(x), _i(tris), len(tris), _i(pl), len(pl), _d(v), interval,
-                          0 if exact else 1, psd, _d(out), threads)
+                          0 if exact else 1, psd, _d(out), threads, 1 if vertex_adjacent else 0)
     return out
 
 

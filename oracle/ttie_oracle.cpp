@@ -695,11 +695,28 @@ struct Mesh {
   Tri tri(int64_t t) const {
     return {{x + 3 * (int64_t)tris[3 * t], x + 3 * (int64_t)tris[3 * t + 1], x + 3 * (int64_t)tris[3 * t + 2]}};
   }
-  bool adjacent(int64_t i, int64_t j) const {
-    for (int a = 0; a < 3; ++a)
+  // Pairs sharing a vertex index are "adjacent" (Sec. 1) and carry no energy.  With
+  // vertex_adjacent set, a pair sharing exactly one vertex is evaluated like any other (the
+  // shared vertex lies exactly on both planes); pairs sharing an edge stay adjacent.
+  bool vertex_adjacent = false;
+  int shared(int64_t i, int64_t j) const {  // distinct vertex ids of triangle i found in triangle j
+    int n = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int32_t v = tris[3 * i + a];
+      bool dup = false;
+      for (int a2 = 0; a2 < a; ++a2) dup = dup || tris[3 * i + a2] == v;
+      if (dup) continue;
       for (int b = 0; b < 3; ++b)
-        if (tris[3 * i + a] == tris[3 * j + b]) return true;
-    return false;
+        if (tris[3 * j + b] == v) {
+          ++n;
+          break;
+        }
+    }
+    return n;
+  }
+  bool adjacent(int64_t i, int64_t j) const {
+    const int n = shared(i, j);
+    return n >= 2 || (n == 1 && !vertex_adjacent);
   }
 };
 
@@ -1049,8 +1066,10 @@ void ttie_oracle_eig(int n, const double* A, double* w, double* Q) {
   jacobi_eig(n, tmp.data(), w, Q);
 }
 
-int32_t* ttie_oracle_pairs(const double* x, int64_t nv, const int32_t* tris, int64_t nt, int method, int64_t* n_out) {
+int32_t* ttie_oracle_pairs(const double* x, int64_t nv, const int32_t* tris, int64_t nt, int method,
+                           int vertex_adjacent, int64_t* n_out) {
   Mesh m{x, nv, tris, nt};
+  m.vertex_adjacent = vertex_adjacent != 0;
   std::vector<int32_t> p = method == 0 ? pairs_brute(m) : pairs_boxes(m);
   *n_out = (int64_t)(p.size() / 2);
   int32_t* out = (int32_t*)std::malloc(std::max<size_t>(1, p.size()) * sizeof(int32_t));
@@ -1082,8 +1101,10 @@ int ttie_oracle_newton(double* x, int64_t nv, const int32_t* tris, int64_t nt, i
 }
 
 void* ttie_oracle_eval(const double* x, int64_t nv, const int32_t* tris, int64_t nt, const int32_t* pairs,
-                       int64_t np, int interval_mode, int psd_mode, int want_hessian, int nthreads) {
+                       int64_t np, int interval_mode, int psd_mode, int want_hessian, int nthreads,
+                       int vertex_adjacent) {
   Mesh m{x, nv, tris, nt};
+  m.vertex_adjacent = vertex_adjacent != 0;
   return evaluate(m, pairs, np, interval_mode, psd_mode, want_hessian, nthreads);
 }
 
@@ -1126,8 +1147,9 @@ void ttie_oracle_eval_free(void* h) { delete (EvalResult*)h; }
 // mode 1: the psd_mode Hessian of the hits (dense 18x18 per pair).
 int ttie_oracle_hvp(const double* x, int64_t nv, const int32_t* tris, int64_t nt, const int32_t* pairs,
                     int64_t np, const double* v, int interval_mode, int mode, int psd_mode, double* Hv,
-                    int nthreads) {
+                    int nthreads, int vertex_adjacent) {
   Mesh m{x, nv, tris, nt};
+  m.vertex_adjacent = vertex_adjacent != 0;
   const double half = interval_mode == 1 ? 0.5 : 1.0;
   std::memset(Hv, 0, 3 * nv * sizeof(double));
   int nth = n_threads_or_default(nthreads);

@@ -315,6 +315,27 @@ def batch_problems(seed: int = 0, n_problems: int = 64, smin: float = 2e3, smax:
     return out
 
 
+def crumpled_fans(seed: int = 0, n_fans: int = 8, blades: int = 16, height: float = 0.3):
+    """An n_fans x n_fans grid of fans: each a centre vertex and a ring of ``blades`` vertices at
+    radius 0.5 with random heights N(0, height^2), triangulated around the centre, the ring
+    winding twice around it.  Blades of the two windings lie over each other and share only
+    the centre vertex: where their heights interleave they cross, giving intersecting pairs
+    that share exactly one vertex."""
+    rng = np.random.default_rng(seed)
+    xs, ts = [], []
+    off = 0
+    for gx in range(n_fans):
+        for gy in range(n_fans):
+            c = np.array([gx * 1.2, gy * 1.2, 0.0])
+            th = 4 * np.pi * np.arange(blades) / blades
+            ring = np.stack([c[0] + 0.5 * np.cos(th), c[1] + 0.5 * np.sin(th), rng.normal(0.0, height, blades)], 1)
+            xs.append(np.vstack([c, ring]))
+            k = np.arange(blades)
+            ts.append(np.stack([np.zeros(blades, np.int64), 1 + k, 1 + (k + 1) % blades], 1) + off)
+            off += blades + 1
+    return _finish(np.concatenate(xs), np.concatenate(ts))
+
+
 def concat_problems(problems):
     """One batched mesh from independent problems ``(x, tris, ...)``: the vertices and
     triangles concatenated (triangle indices re-based to global vertex ids) and the offsets

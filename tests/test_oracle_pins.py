@@ -485,3 +485,86 @@ def test_newton_matches_dense_newton():
     assert E_ref[0] > 0
     np.testing.assert_allclose(E_or, E_ref, rtol=1e-7)
     assert list(al_or) == al_ref
+
+
+# ---------------------------------------------------------------------------------------
+# Pairs sharing exactly one vertex (an option; the paper excludes every adjacent pair).
+# T_a in z = 0 and T_b = (0,0,0), (1,.5,1), (1,.5,-1) in the plane y = x/2 share the origin.
+# D = n_a x n_b = (0,0,4) x (-1,2,0) = (-8,-4,0), so t = -(2x + y)/sqrt(5).  T_a meets the
+# plane from the origin to (4/3, 2/3, 0) (edge u1u2), T_b meets z = 0 from the origin to
+# (1, 1/2, 0) (edge v1v2): I_a = [-10/3, 0]/sqrt(5), I_b = [-5/2, 0]/sqrt(5), and Eq. 1 gives
+# t_c = [-10/3, 5/2]/sqrt(5): T = ((10/3)(5/2)/5)^2 = 25/9.  Mirroring T_b through the origin
+# makes the two cuts leave the shared vertex in opposite directions: they only touch, T = 0.
+# ---------------------------------------------------------------------------------------
+VA = np.array([[0, 0, 0], [2, 0, 0], [0, 2, 0], [0, 0, 0], [1, .5, 1], [1, .5, -1]], float)
+
+
+def test_vertex_adjacent_closed_form():
+    r = oracle.pair(VA)
+    assert r["status"] == oracle.ST_HIT
+    assert r["t0"] == pytest.approx(-10 / 3 / np.sqrt(5), rel=1e-14)
+    assert r["t1"] == pytest.approx(5 / 2 / np.sqrt(5), rel=1e-14)
+    assert r["T"] == pytest.approx(25 / 9, rel=1e-14)
+    mirror = VA.copy()
+    mirror[4:] *= [-1, -1, 1]
+    assert oracle.pair(mirror)["status"] == oracle.ST_NONE
+    # at the mesh level the shared index makes the pair adjacent unless vertex_adjacent is set
+    x = VA[[0, 1, 2, 4, 5]]
+    tris = np.array([[0, 1, 2], [0, 3, 4]], np.int32)
+    assert len(oracle.pairs(x, tris)) == 0
+    pl = oracle.pairs(x, tris, vertex_adjacent=True)
+    np.testing.assert_array_equal(pl, [[0, 1]])
+    assert oracle.evaluate(x, tris, pl)["E"] == 0.0
+    r = oracle.evaluate(x, tris, pl, vertex_adjacent=True)
+    assert r["E"] == pytest.approx(25 / 9, rel=1e-14)
+    # pairs sharing an edge stay adjacent
+    tris_e = np.array([[0, 1, 2], [0, 1, 3]], np.int32)
+    assert len(oracle.pairs(x, tris_e, oracle.BROAD_BRUTE, vertex_adjacent=True)) == 0
+
+
+def test_vertex_adjacent_flags_vs_exact():
+    rng = np.random.default_rng(11)
+    n_hit = 0
+    for _ in range(1500):
+        P = rng.integers(-3, 4, size=(5, 3)).astype(float)
+        tris = np.array([[0, 1, 2], [0, 3, 4]], np.int32)
+        r = oracle.evaluate(P, tris, np.array([[0, 1]], np.int32), hessian=False, vertex_adjacent=True)
+        e = exact_moller.pair(P[[0, 1, 2]], P[[0, 3, 4]])
+        if r["flags"][0] == 3:  # degenerate line frame: T = 0 either way
+            continue
+        assert (r["flags"][0] == 1) == bool(e["flag"])
+        n_hit += r["flags"][0] == 1
+    assert n_hit > 100
+
+
+def test_vertex_adjacent_gradient_fd():
+    # the shared vertex is one vertex: its gradient collects both slots
+    from paper_2606_06511_amd import workloads
+
+    x, tris = workloads.crumpled_fans(3, n_fans=2, blades=12)
+    pl = oracle.pairs(x, tris, vertex_adjacent=True)
+    r = oracle.evaluate(x, tris, pl, hessian=False, vertex_adjacent=True)
+    assert len(r["hit_pair"]) > 5
+    h = 1e-6
+    fd = np.zeros_like(x)
+    for v in range(len(x)):
+        for c in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[v, c] += h
+            xm[v, c] -= h
+            fd[v, c] = (oracle.evaluate(xp, tris, pl, hessian=False, vertex_adjacent=True)["E"] -
+                        oracle.evaluate(xm, tris, pl, hessian=False, vertex_adjacent=True)["E"]) / (2 * h)
+    assert np.abs(fd - r["G"]).max() <= 1e-6 * max(1.0, np.abs(r["G"]).max())
+    assert np.abs(r["G"][0]).max() > 0  # the centre vertex of the first fan feels the crossings
+
+
+def test_vertex_adjacent_pairs_definition():
+    from paper_2606_06511_amd import workloads
+
+    x, tris = workloads.crumpled_fans(2, n_fans=3, blades=10)
+    got = oracle.pairs(x, tris, vertex_adjacent=True)
+    lo, hi = x[tris].min(1), x[tris].max(1)
+    ov = np.all((lo[:, None, :] <= hi[None, :, :]) & (lo[None, :, :] <= hi[:, None, :]), axis=2)
+    shared = (tris[:, None, :, None] == tris[None, :, None, :]).any(axis=3).sum(axis=2)
+    i, j = np.nonzero(np.triu(ov & (shared <= 1), 1))
+    np.testing.assert_array_equal(got, np.stack([i, j], 1).astype(got.dtype))
