@@ -73,6 +73,16 @@ enum { TTIE_FP64 = 0, TTIE_MIXED = 1 };
 enum { TTIE_PSD_PER_PART = 0, TTIE_PSD_NEAREST = 1, TTIE_PSD_PAPER_LITERAL = 2, TTIE_PSD_RAW_EQ4 = 3 };
 enum { TTIE_INTERVAL_EQ1 = 0, TTIE_INTERVAL_APPENDIX_HALF = 1 };
 enum { TTIE_BROAD_BRUTE = 0, TTIE_BROAD_LBVH = 1, TTIE_BROAD_HASH = 2 };
+/* Pairs sharing a vertex index are adjacent (Sec. 1): the broad phase never lists them and the
+ * evaluation gives them T = 0.  The paper leaves aside triangles that share a vertex and still
+ * cross each other beyond it (a fan folded over itself).  With these bits -- OR'ed into the
+ * broad phase's method, set in ttie_options.flags -- a pair sharing exactly one vertex is
+ * listed and evaluated like any other pair: the shared vertex lies exactly on both planes
+ * (an on-plane endpoint of both segments), so two triangles that only touch there have
+ * intervals meeting in a point and T = 0, while triangles that cross beyond it get T > 0.
+ * Pairs sharing two vertices (an edge) stay adjacent. */
+enum { TTIE_BROAD_VERTEX_ADJACENT = 0x100 };
+enum { TTIE_EVAL_VERTEX_ADJACENT = 1 };
 enum { TTIE_HVP_EXACT = 0, TTIE_HVP_PSD = 1 };
 /* per-pair flag codes written by ttie_eval */
 enum { TTIE_PAIR_NONE = 0, TTIE_PAIR_HIT = 1, TTIE_PAIR_ADJACENT = 2, TTIE_PAIR_DEGENERATE_FRAME = 3 };
@@ -92,7 +102,7 @@ typedef struct ttie_options {
                         and Hessian in float32 on pair-local coordinates */
   int32_t psd_mode;  /* TTIE_PSD_* */
   int32_t interval;  /* TTIE_INTERVAL_* */
-  int32_t reserved;  /* must be 0 */
+  int32_t flags;     /* TTIE_EVAL_* bits (0: the paper's definition) */
 } ttie_options;
 
 /* Upper bounds that size the workspace.  max_pairs bounds the candidate list of

@@ -272,14 +272,15 @@ static ttie_status broadphase_impl(ttie_ctx* ctx, const ttie_mesh* mesh, int met
                                    void* stream, const char* who) {
   if (ttie_status st = need_ws(ctx)) return st;
   if (ttie_status st = check_mesh(ctx, mesh)) return st;
-  if (method != TTIE_BROAD_BRUTE && method != TTIE_BROAD_LBVH && method != TTIE_BROAD_HASH)
+  const int base_method = method & ~TTIE_BROAD_VERTEX_ADJACENT;
+  if (base_method != TTIE_BROAD_BRUTE && base_method != TTIE_BROAD_LBVH && base_method != TTIE_BROAD_HASH)
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad method");
   if (!n_pairs || (capacity > 0 && !pairs) || capacity < 0)
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad pair output");
   if (capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "capacity exceeds limits.max_pairs");
   if (((uintptr_t)pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "pairs must be 8-byte aligned");
   if (((uintptr_t)n_pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "n_pairs must be 8-byte aligned");
-  if (method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
+  if (base_method == TTIE_BROAD_BRUTE && mesh->n_tris * (mesh->n_tris - 1) / 2 >= (1ll << 32))
     return fail(TTIE_ERR_UNSUPPORTED, "brute force beyond 2^32 pairs");
   DeviceGuard g(ctx->device);
   hipError_t e = launch_broadphase(ctx, mesh, method, x_end, n_prob, tri_off, pairs, capacity, n_pairs,
@@ -315,7 +316,7 @@ static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_
   if (opts->psd_mode < 0 || opts->psd_mode > 3) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad psd_mode");
   if (opts->interval != TTIE_INTERVAL_EQ1 && opts->interval != TTIE_INTERVAL_APPENDIX_HALF)
     return fail(TTIE_ERR_INVALID_ARGUMENT, "bad interval");
-  if (opts->reserved != 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "reserved must be 0");
+  if (opts->flags & ~TTIE_EVAL_VERTEX_ADJACENT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown option flags");
   if ((!pairs && pair_capacity > 0) || !n_pairs || !energy || (!grad && mesh->n_verts > 0))
     return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL required argument");
   if (pair_capacity < 0 || pair_capacity > ctx->lim.max_pairs)

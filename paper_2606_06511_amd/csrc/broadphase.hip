@@ -455,7 +455,7 @@ template <bool kGlobal>
 __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t blk, int32_t s, bool active, int lt,
                                               int32_t tbase, int L, const Box32* __restrict__ boxes,
                                               const LeafRec* __restrict__ leaves, const int32_t* __restrict__ qend,
-                                              TravState* heavy, int64_t heavy_cap, int budget, WaveEmitter& em,
+                                              TravState* heavy, int64_t heavy_cap, int budget, bool va, WaveEmitter& em,
                                               const PairSink& sink, Counters* ctr, int& status) {
   const int qi = s - blk * kBpBlock;
   const bool small_tree = L <= kSubLevels;
@@ -550,12 +550,7 @@ __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t
         bool ex = (mask >> i) & 1u;
 #pragma unroll
         for (int c = 0; c < 3; ++c) ex = ex & (me.lo[c] <= o[i].hi[c]) & (o[i].lo[c] <= me.hi[c]);
-        bool adj = false;
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-          for (int b2 = 0; b2 < 3; ++b2) adj = adj | (me.v[a2] == o[i].v[b2]);
-        want |= (uint32_t)(ex & !adj) << i;
+        want |= (uint32_t)(ex & !is_adjacent(me.v, o[i].v, va)) << i;
         other[i] = o[i].tri;
       }
     }
@@ -589,10 +584,14 @@ __device__ __forceinline__ void traverse_part(TravShared& sh, int32_t n, int32_t
   }
 }
 
+// kVA: pairs sharing exactly one vertex are candidates (a template argument, so the default
+// keeps the plain shared-vertex test in its leaf loop)
+template <bool kVA>
 __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels lv, const Box32* __restrict__ boxes,
                                                            const LeafRec* __restrict__ leaves,
                                                            const int32_t* __restrict__ qend, TravState* heavy,
-                                                           int64_t heavy_cap, int budget, int32_t* pairs, int64_t cap,
+                                                           int64_t heavy_cap, int budget, int32_t* pairs,
+                                                           int64_t cap,
                                                            unsigned long long* npairs, Counters* ctr) {
   __shared__ TravShared sh;
   const PairSink sink{pairs, cap, npairs, &ctr->status};
@@ -632,10 +631,10 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
   const bool small_tree = lv.L <= kSubLevels;
   if (global_part)
     traverse_part<true>(sh, n, blk, s, s < n && !small_tree, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap,
-                        budget, em, sink, ctr, status);
+                        budget, kVA, em, sink, ctr, status);
   else
-    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, budget, em,
-                         sink, ctr, status);
+    traverse_part<false>(sh, n, blk, s, s < n, lt, tbase, lv.L, boxes, leaves, qend, heavy, heavy_cap, budget, kVA,
+                         em, sink, ctr, status);
   block_flush<kTravWaves>(em, sh.wcount, &sh.bbase, sink);
   if (status) atomicCAS(&ctr->status, 0, status);
 }
@@ -648,7 +647,7 @@ constexpr int kHeavyStack = 4096;
 
 __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* __restrict__ boxes,
                                                        const LeafRec* __restrict__ leaves,
-                                                       const TravState* __restrict__ heavy, int64_t heavy_cap,
+                                                       const TravState* __restrict__ heavy, int64_t heavy_cap, int va,
                                                        int32_t* pairs, int64_t cap, unsigned long long* npairs,
                                                        Counters* ctr) {
   const PairSink sink{pairs, cap, npairs, &ctr->status};
@@ -723,10 +722,7 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
         for (int i = 0; i < 4; ++i) {
           bool exact = (mask >> i) & 1u;
           for (int c = 0; c < 3; ++c) exact = exact && me.lo[c] <= o[i].hi[c] && o[i].lo[c] <= me.hi[c];
-          bool adj = false;
-          for (int a2 = 0; a2 < 3; ++a2)
-            for (int b2 = 0; b2 < 3; ++b2) adj |= me.v[a2] == o[i].v[b2];
-          want[i] = exact && !adj;
+          want[i] = exact && !is_adjacent(me.v, o[i].v, va);
           other[i] = o[i].tri;
         }
       }
@@ -757,7 +753,7 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
 }
 
 __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ tris, int64_t nt, int32_t* pairs,
-                                                    int64_t cap, unsigned long long* npairs, Counters* ctr) {
+                                                    int64_t cap, unsigned long long* npairs, int va, Counters* ctr) {
   const PairSink sink{pairs, cap, npairs, &ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
   WaveEmitter em{stage[threadIdx.x / 64], 0};
@@ -768,12 +764,8 @@ __global__ void __launch_bounds__(kBpBlock) k_brute(const int32_t* __restrict__ 
       const int64_t j = jb + threadIdx.x;
       bool want = false;
       if (j > i && j < nt) {
-        bool adj = false;
-        for (int k = 0; k < 3; ++k) {
-          const int32_t w = tris[3 * j + k];
-          adj |= w == vi[0] || w == vi[1] || w == vi[2];
-        }
-        want = !adj;
+        const int32_t vj[3] = {tris[3 * j], tris[3 * j + 1], tris[3 * j + 2]};
+        want = !is_adjacent(vi, vj, va);
       }
       em.push(want, (int32_t)i, (int32_t)j, sink);
     }
@@ -961,7 +953,8 @@ __device__ __forceinline__ HashQuery hash_query(int64_t e, int64_t ne, int64_t n
 // overlap, this cell is the pair's reference cell, and no vertex is shared
 __device__ __forceinline__ bool hash_test(const HashQuery& h, int64_t j, const uint64_t* __restrict__ skey,
                                           const int32_t* __restrict__ stri, const double* __restrict__ tbox,
-                                          const int32_t* __restrict__ tris, const HashGrid& g, int32_t& other) {
+                                          const int32_t* __restrict__ tris, const HashGrid& g, bool va,
+                                          int32_t& other) {
   if (skey[j] != h.key) return false;
   other = stri[j];
   bool hit = true;
@@ -973,12 +966,8 @@ __device__ __forceinline__ bool hash_test(const HashQuery& h, int64_t j, const u
     ref[c] = h.cell[c] > bc ? h.cell[c] : bc;
   }
   if (!hit || cell_key(ref[0], ref[1], ref[2]) != h.key) return false;
-  bool adj = false;
-  for (int k = 0; k < 3; ++k) {
-    const int32_t w = tris[3 * (int64_t)other + k];
-    adj |= w == h.v[0] || w == h.v[1] || w == h.v[2];
-  }
-  return !adj;
+  const int32_t vo[3] = {tris[3 * (int64_t)other], tris[3 * (int64_t)other + 1], tris[3 * (int64_t)other + 2]};
+  return !is_adjacent(h.v, vo, va);
 }
 
 // A thread tests at most `hbudget` (a launch parameter, 64 by default) later entries of its
@@ -992,7 +981,8 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
                                                          const int32_t* __restrict__ stri,
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
-                                                         int hbudget, int32_t* __restrict__ heavy, int32_t* pairs,
+                                                         int hbudget, int va, int32_t* __restrict__ heavy,
+                                                         int32_t* pairs,
                                                          int64_t cap,
                                                          unsigned long long* npairs, Counters* out_ctr) {
   const PairSink sink{pairs, cap, npairs, &out_ctr->status};
@@ -1017,7 +1007,7 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_pairs(const Counters* ctr, in
     // the loop runs while any lane has work, so the emitter always sees the whole wave
     for (int64_t j = e + 1; __ballot(active && j < stop); ++j) {
       int32_t other = 0;
-      const bool want = active && j < stop && hash_test(h, j, skey, stri, tbox, tris, g, other);
+      const bool want = active && j < stop && hash_test(h, j, skey, stri, tbox, tris, g, va, other);
       em.push(want, h.tri, other, sink);
     }
   }
@@ -1031,7 +1021,8 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
                                                          const int32_t* __restrict__ stri,
                                                          const double* __restrict__ tbox,
                                                          const int32_t* __restrict__ tris, const HashGrid* grid,
-                                                         int hbudget, const int32_t* __restrict__ heavy, int32_t* pairs,
+                                                         int hbudget, int va, const int32_t* __restrict__ heavy,
+                                                         int32_t* pairs,
                                                          int64_t cap, unsigned long long* npairs, Counters* out_ctr) {
   const PairSink sink{pairs, cap, npairs, &out_ctr->status};
   __shared__ int2 stage[kBpBlock / 64][kEmitCap];
@@ -1048,7 +1039,7 @@ __global__ void __launch_bounds__(kBpBlock) k_hash_heavy(const Counters* ctr, in
     for (int64_t jb = e + 1 + hbudget; jb < h.end; jb += 64) {
       const int64_t j = jb + __lane_id();
       int32_t other = 0;
-      const bool want = j < h.end && hash_test(h, j, skey, stri, tbox, tris, g, other);
+      const bool want = j < h.end && hash_test(h, j, skey, stri, tbox, tris, g, va, other);
       em.push(want, h.tri, other, sink);
     }
   }
@@ -1097,11 +1088,13 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
   Counters* ctr = wsp<Counters>(c, L.counters);
   const int64_t nt = m->n_tris;
   unsigned long long* npairs = reinterpret_cast<unsigned long long*>(n_pairs);
+  const int va = (method & TTIE_BROAD_VERTEX_ADJACENT) ? 1 : 0;
+  method &= 0xff;
   if (method == TTIE_BROAD_BRUTE || nt < 2) k_bp_init<<<1, 64, 0, s>>>(ctr, npairs);
   if (method == TTIE_BROAD_BRUTE) {
     dim3 grid(bp_grid(nt, 64), (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192));
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
-    k_brute<<<grid, kBpBlock, 0, s>>>(m->tris, nt, pairs, capacity, npairs, ctr);
+    k_brute<<<grid, kBpBlock, 0, s>>>(m->tris, nt, pairs, capacity, npairs, va, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_HASH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
@@ -1134,8 +1127,9 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     int32_t* heavy = wsp<int32_t>(c, L.hash_rank);  // the ranks are consumed by the scatter
     const int hb = (int)ctx_param(c, TTIE_PARAM_HASH_BUDGET);
     k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
-                                                           m->tris, grid, hb, heavy, pairs, capacity, npairs, ctr);
-    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, hb, heavy,
+                                                           m->tris, grid, hb, va, heavy, pairs, capacity, npairs, ctr);
+    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, hb, va,
+                                          heavy,
                                           pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
@@ -1180,10 +1174,14 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     const int64_t nb = ((nt + kBpBlock - 1) / kBpBlock + 7) / 8 * 8;
     TravState* heavy = wsp<TravState>(c, L.bvh_heavy);
     const int64_t heavy_cap = (int64_t)(L.bvh_heavy_bytes / sizeof(TravState));
-    k_traverse<<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy, heavy_cap,
-                                                     (int)ctx_param(c, TTIE_PARAM_TRAV_BUDGET), pairs, capacity,
-                                                     npairs, ctr);
-    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, pairs, capacity, npairs, ctr);
+    const int budget = (int)ctx_param(c, TTIE_PARAM_TRAV_BUDGET);
+    if (va)
+      k_traverse<true><<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy,
+                                                             heavy_cap, budget, pairs, capacity, npairs, ctr);
+    else
+      k_traverse<false><<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy,
+                                                              heavy_cap, budget, pairs, capacity, npairs, ctr);
+    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, va, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
   }
   return hipGetLastError();

@@ -55,10 +55,10 @@ __device__ __forceinline__ bool load_tri(const double* x, int64_t nv, const int3
 template <bool kExact>
 __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__ x, int64_t nv,
                                            const int32_t* __restrict__ tris, int64_t nt,
-                                           const int32_t* __restrict__ pairs, double half, HitGeom* __restrict__ hits,
-                                           uint32_t max_hits, int32_t* __restrict__ defer, int64_t max_defer,
-                                           Counters* ctr, uint8_t* __restrict__ flags, double* __restrict__ pair_T,
-                                           int& status) {
+                                           const int32_t* __restrict__ pairs, double half, bool va,
+                                           HitGeom* __restrict__ hits, uint32_t max_hits, int32_t* __restrict__ defer,
+                                           int64_t max_defer, Counters* ctr, uint8_t* __restrict__ flags,
+                                           double* __restrict__ pair_T, int& status) {
   int kind = PAIR_NONE;
   Screen sc;
   sc.t0 = sc.t1 = 0.0;
@@ -73,12 +73,7 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
         !load_tri(x, nv, tris, j, vj, B)) {
       status = STATUS_INDEX;
     } else {
-      bool adj = false;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) adj |= vi[a] == vj[b];
-      if (adj) {
+      if (is_adjacent(vi, vj, va)) {
         kind = PAIR_ADJACENT;
       } else {
         sc = screen_pair<kExact>(A, B, half, status);
@@ -126,15 +121,15 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
 __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
                                                    const int32_t* __restrict__ tris, int64_t nt,
                                                    const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
-                                                   int64_t max_pairs, double half, HitGeom* __restrict__ hits,
+                                                   int64_t max_pairs, double half, int va, HitGeom* __restrict__ hits,
                                                    uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
                                                    uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
   const int64_t np = min(*n_pairs_dev, max_pairs);
   int status = 0;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = base + threadIdx.x;
-    screen_one<false>(p < np ? p : -1, x, nv, tris, nt, pairs, half, hits, max_hits, defer, max_pairs, ctr, flags,
-                      pair_T, status);
+    screen_one<false>(p < np ? p : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr,
+                      flags, pair_T, status);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -143,15 +138,16 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
 __global__ void __launch_bounds__(kBlock) k_screen_exact(const double* __restrict__ x, int64_t nv,
                                                          const int32_t* __restrict__ tris, int64_t nt,
                                                          const int32_t* __restrict__ pairs, int64_t max_pairs,
-                                                         double half, HitGeom* __restrict__ hits, uint32_t max_hits,
+                                                         double half, int va, HitGeom* __restrict__ hits,
+                                                         uint32_t max_hits,
                                                          const int32_t* __restrict__ defer, Counters* ctr,
                                                          uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
   const int64_t nd = min((int64_t)ctr->n_defer, max_pairs);
   int status = 0;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nd; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = base + threadIdx.x;
-    screen_one<true>(q < nd ? (int64_t)defer[q] : -1, x, nv, tris, nt, pairs, half, hits, max_hits, nullptr, 0, ctr,
-                     flags, pair_T, status);
+    screen_one<true>(q < nd ? (int64_t)defer[q] : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, nullptr,
+                     0, ctr, flags, pair_T, status);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -259,8 +255,9 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
     const int32_t v = touched[u];
     const int32_t b = off[v], n = off[v + 1] - b;
-    // rank sort of the row's incidences by (pair key, position): the ranks are a permutation
-    // even if a caller repeats a pair.  Rows of up to 64 (wave-uniform test) rank from LDS.
+    // rank sort of the row's incidences by (pair key, slot, position): deterministic even when
+    // a hit holds the vertex twice (a pair sharing one vertex), and a permutation even if a
+    // caller repeats a pair.  Rows of up to 64 (wave-uniform test) rank from LDS.
     if (n <= 64) {
       Incidence me{};
       if (lane < n) sinc[wave][lane] = me = inc[b + lane];
@@ -269,8 +266,9 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
       if (lane < n) {
         int32_t rank = 0;
         for (int32_t j = 0; j < n; ++j) {
-          const int64_t kj = sinc[wave][j].key;
-          rank += (kj < me.key) | ((kj == me.key) & (j < lane));
+          const Incidence o = sinc[wave][j];
+          rank += (o.key < me.key) |
+                  ((o.key == me.key) & ((o.slot < me.slot) | ((o.slot == me.slot) & (j < lane))));
         }
         inc2[b + rank] = me;
       }
@@ -279,8 +277,8 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
         const Incidence me = inc[b + i];
         int32_t rank = 0;
         for (int32_t j = 0; j < n; ++j) {
-          const int64_t kj = inc[b + j].key;
-          rank += kj < me.key || (kj == me.key && j < i);
+          const Incidence o = inc[b + j];
+          rank += o.key < me.key || (o.key == me.key && (o.slot < me.slot || (o.slot == me.slot && j < i)));
         }
         inc2[b + rank] = me;
       }
@@ -671,16 +669,17 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   int32_t* defer = wsp<int32_t>(c, L.defer);
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
+  const int va = (o->flags & TTIE_EVAL_VERTEX_ADJACENT) ? 1 : 0;
   const int64_t nv = m->n_verts;
   const bool bsr = row_ptr != nullptr;
 
   stage_begin(c, TTIE_STAGE_SCREEN, s);
   k_screen<<<grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS)), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
-                                                       hits, max_hits, defer, ctr, flags, pair_T);
+                                                       va, hits, max_hits, defer, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
-  k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, hits,
-                                                            max_hits, defer, ctr, flags, pair_T);
+  k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,
+                                                            hits, max_hits, defer, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN_EXACT, s);
   stage_begin(c, TTIE_STAGE_DERIVS, s);
   k_derivs<S><<<grid_for(c->lim.max_hits, 1024), kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode,

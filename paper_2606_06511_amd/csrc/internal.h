@@ -50,6 +50,32 @@ struct Counters {
   uint32_t pad_;
 };
 
+// Number of distinct vertex ids of triangle a that also belong to triangle b.
+__device__ __forceinline__ int shared_vertices(const int32_t* a, const int32_t* b) {
+  int n = 0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    const bool in = (a[x] == b[0]) | (a[x] == b[1]) | (a[x] == b[2]);
+    const bool dup = (x > 0 && a[x] == a[0]) | (x > 1 && a[x] == a[1]);
+    n += in & !dup;
+  }
+  return n;
+}
+
+// Pairs sharing a vertex are adjacent (Sec. 1) and carry no energy; with the vertex-adjacent
+// option only pairs sharing two or more vertices are, and a pair sharing exactly one vertex is
+// evaluated like any other.  The option is a kernel argument, so the branch is uniform and the
+// default keeps the nine plain comparisons.
+__device__ __forceinline__ bool is_adjacent(const int32_t* a, const int32_t* b, bool vertex_adjacent) {
+  if (!vertex_adjacent) {
+    bool any = false;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) any |= (a[x] == b[0]) | (a[x] == b[1]) | (a[x] == b[2]);
+    return any;
+  }
+  return shared_vertices(a, b) >= 2;
+}
+
 // wave-aggregated append to a counter-indexed list: one atomic per wave; every lane of the wave
 // must call it
 __device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {

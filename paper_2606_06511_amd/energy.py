@@ -16,16 +16,20 @@ class TTIE:
     """Evaluator for one triangle topology (``tris``) on one GPU.
 
     Positions are passed per call (float64, ``(n_verts, 3)``, on the GPU).  The broad phase
-    is rerun for every evaluation unless a candidate list is given.
+    is rerun for every evaluation unless a candidate list is given.  With ``vertex_adjacent``,
+    pairs sharing exactly one vertex are listed and evaluated (only pairs sharing an edge are
+    skipped as adjacent).
     """
 
     def __init__(self, tris: torch.Tensor, n_verts: int, *, device: int = 0, max_pairs: int = 1 << 22,
                  max_hits: int = 1 << 18, max_blocks: int | None = None, precision: int = ttie.FP64,
-                 psd: int = ttie.PSD_PER_PART, interval: int = ttie.INTERVAL_EQ1, broadphase: int = ttie.BROAD_LBVH):
+                 psd: int = ttie.PSD_PER_PART, interval: int = ttie.INTERVAL_EQ1, broadphase: int = ttie.BROAD_LBVH,
+                 vertex_adjacent: bool = False):
         self.device = torch.device("cuda", device)
         self.tris = tris.to(self.device, torch.int32).contiguous()
         self.n_verts = int(n_verts)
         self.precision, self.psd, self.interval, self.method = precision, psd, interval, broadphase
+        self.vertex_adjacent = bool(vertex_adjacent)
         self.ctx = ttie.Context(device)
         self.ctx.reserve(self.n_verts, self.tris.shape[0], max_pairs, max_hits=max_hits,
                          max_blocks=max_blocks if max_blocks is not None else 36 * max_hits)
@@ -42,7 +46,7 @@ class TTIE:
         """Candidate pairs at x (or swept from x to x_end) into the evaluator's pair buffer;
         raises when the buffer overflowed (unless ``check`` is False: then the caller checks)."""
         self.ctx.broadphase(x, self.tris, self.method, capacity=self.pairs.shape[0], out=(self.pairs, self.n_pairs),
-                            x_end=x_end)
+                            x_end=x_end, vertex_adjacent=self.vertex_adjacent)
         if check:
             self.ctx.check()
         return self.pairs, self.n_pairs
@@ -54,7 +58,8 @@ class TTIE:
             pairs, n_pairs = self.candidates(x, check=False)
         key = (hessian, flags, pairs.shape[0])
         out = self.ctx.evaluate(x, self.tris, pairs, n_pairs, precision=self.precision, psd=self.psd,
-                                interval=self.interval, hessian=hessian, flags=flags, out=self._outs.get(key))
+                                interval=self.interval, hessian=hessian, flags=flags, out=self._outs.get(key),
+                                vertex_adjacent=self.vertex_adjacent)
         self._outs[key] = out
         self.generation += 1
         self.ctx.check()

@@ -24,6 +24,8 @@ FP64, MIXED = 0, 1
 PSD_PER_PART, PSD_NEAREST, PSD_PAPER_LITERAL, PSD_RAW_EQ4 = 0, 1, 2, 3
 INTERVAL_EQ1, INTERVAL_APPENDIX_HALF = 0, 1
 BROAD_BRUTE, BROAD_LBVH, BROAD_HASH = 0, 1, 2
+BROAD_VERTEX_ADJACENT = 0x100  # OR'ed into a broad-phase method: list pairs sharing one vertex
+EVAL_VERTEX_ADJACENT = 1       # Options.flags bit: evaluate pairs sharing one vertex
 HVP_EXACT, HVP_PSD = 0, 1
 PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME = 0, 1, 2, 3
 MAX_PROBLEMS = 4096
@@ -44,7 +46,7 @@ class Mesh(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("psd_mode", ctypes.c_int32), ("interval", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -169,9 +171,12 @@ class Context:
         if st != TTIE_OK:
             raise TTIEError(st, "reported by a kernel")
 
-    def broadphase(self, x, tris, method=BROAD_LBVH, capacity=None, out=None, x_end=None):
+    def broadphase(self, x, tris, method=BROAD_LBVH, capacity=None, out=None, x_end=None, vertex_adjacent=False):
         """Candidate pairs: returns (pairs (capacity, 2) int32, n_pairs (1,) int64), both on the GPU.
-        With x_end, boxes cover the triangles at x and at x_end (swept candidates)."""
+        With x_end, boxes cover the triangles at x and at x_end (swept candidates).  With
+        vertex_adjacent, pairs sharing exactly one vertex are candidates too."""
+        if vertex_adjacent:
+            method |= BROAD_VERTEX_ADJACENT
         if capacity is None:
             capacity = self.limits[2]
         m = self._mesh(x, tris)
@@ -205,7 +210,8 @@ class Context:
         return pairs, n
 
     def batch_evaluate(self, x, tris, vert_off, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART,
-                       interval=INTERVAL_EQ1, hessian=True, flags=False, pair_T=False, out=None):
+                       interval=INTERVAL_EQ1, hessian=True, flags=False, pair_T=False, out=None,
+                       vertex_adjacent=False):
         """``evaluate`` over a batch (vert_off: (n_problems + 1,) int64 on the GPU), adding
         ``energies`` (n_problems,) f64: the energy of every problem."""
         assert vert_off.dtype == torch.int64 and vert_off.is_contiguous() and vert_off.device == self.device
@@ -216,7 +222,7 @@ class Context:
         m = self._mesh(x, tris)
         if n_pairs is None:
             n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=self.device)
-        opts = Options(precision, psd, interval, 0)
+        opts = Options(precision, psd, interval, EVAL_VERTEX_ADJACENT if vertex_adjacent else 0)
         cap = out["col_idx"].shape[0] if hessian else 0
         _check(lib().ttie_batch_eval(self.handle, ctypes.byref(m), n_prob, _ptr(vert_off), _ptr(pairs), _ptr(n_pairs),
                                      pairs.shape[0], ctypes.byref(opts), _ptr(out["energies"]),
@@ -248,16 +254,17 @@ class Context:
         return out
 
     def evaluate(self, x, tris, pairs, n_pairs=None, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1,
-                 hessian=True, flags=False, pair_T=False, out=None):
+                 hessian=True, flags=False, pair_T=False, out=None, vertex_adjacent=False):
         """Energy, gradient and (optionally) the BSR Hessian.  Returns a dict of GPU tensors:
         energy (1,) f64, grad (N,3), and when hessian: row_ptr, col_idx, vals, n_blocks;
-        n_hits; flags (P,) u8 and pair_T (P,) f64 when asked."""
+        n_hits; flags (P,) u8 and pair_T (P,) f64 when asked.  With vertex_adjacent, pairs
+        sharing exactly one vertex are evaluated instead of being skipped as adjacent."""
         m = self._mesh(x, tris)
         dev = self.device
         if n_pairs is None:
             n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=dev)
         out = self._eval_outputs(x, pairs, precision, hessian, flags, pair_T, out)
-        opts = Options(precision, psd, interval, 0)
+        opts = Options(precision, psd, interval, EVAL_VERTEX_ADJACENT if vertex_adjacent else 0)
         cap = out["col_idx"].shape[0] if hessian else 0
         _check(lib().ttie_eval(self.handle, ctypes.byref(m), _ptr(pairs), _ptr(n_pairs), pairs.shape[0],
                                ctypes.byref(opts),
