@@ -21,7 +21,7 @@ from . import build_oracle
 
 INTERVAL_EQ1, INTERVAL_APPENDIX_HALF = 0, 1
 PSD_PER_PART, PSD_NEAREST, PSD_PAPER_LITERAL, PSD_RAW_EQ4 = 0, 1, 2, 3
-ST_NONE, ST_HIT, ST_ADJACENT, ST_BAD_FRAME = 0, 1, 2, 3
+ST_NONE, ST_HIT, ST_ADJACENT, ST_BAD_FRAME, ST_COPLANAR = 0, 1, 2, 3, 4
 BROAD_BRUTE, BROAD_BOXES = 0, 1
 
 _lib = None
@@ -183,7 +183,7 @@ def evaluate(x, tris, pair_list, interval=INTERVAL_EQ1, psd=PSD_PER_PART, hessia
     """Energy, gradient and block-sparse Hessian over a candidate list.
 
     Returns a dict with per-pair ``flags`` (0 none, 1 hit, 2 adjacent, 3 hit with a
-    degenerate line frame), ``t`` (P,2), ``T`` (P,), and totals ``E``, ``G`` (N_v,3), the
+    degenerate line frame, 4 coplanar with overlapping interiors, T = 0), ``t`` (P,2), ``T`` (P,), and totals ``E``, ``G`` (N_v,3), the
     hit records (``hit_pair``, ``hit_t``, ``hit_a``, ``hit_b``, ``hit_g``, ``hit_H``) and the
     BSR Hessian ``row_ptr``, ``col_idx``, ``vals`` (nnzb,3,3).  With ``vertex_adjacent`` a pair
     sharing exactly one vertex is evaluated instead of flagged adjacent.

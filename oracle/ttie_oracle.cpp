@@ -31,7 +31,10 @@
 //   - the intersection flag is the exact open-interval test on the exact endpoints;
 //   - min/max ties keep the first argument;
 //   - pairs sharing a vertex index are "adjacent" and carry no energy;
-//   - a hit whose FP64 line direction has zero length is reported with status 3 and T = 0.
+//   - a hit whose FP64 line direction has zero length is reported with status 3 and T = 0;
+//   - two triangles lying in one plane have no segment and no line, so T = 0 (the paper sets
+//     coplanar pairs aside); when their interiors overlap the pair is reported with status 4,
+//     still with T = 0, so that a caller can see where the energy is blind.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -513,7 +516,7 @@ bool interval_ends(const V3<S> U[3], const V3<S> V[3], const Tri& ta, const Tri&
 // ============================================================================================
 // Per-pair evaluation
 // ============================================================================================
-enum { ST_NONE = 0, ST_HIT = 1, ST_ADJACENT = 2, ST_BAD_FRAME = 3 };
+enum { ST_NONE = 0, ST_HIT = 1, ST_ADJACENT = 2, ST_BAD_FRAME = 3, ST_COPLANAR = 4 };
 enum { PSD_PER_PART = 0, PSD_NEAREST = 1, PSD_PAPER_LITERAL = 2, PSD_RAW_EQ4 = 3 };
 
 struct Classified {
@@ -521,11 +524,50 @@ struct Classified {
   Cut ca, cb;
 };
 
+// ============================================================================================
+// Coplanar overlap.  When every vertex of T_a lies on the plane of T_b (and T_b has area) the
+// two triangles share one plane; Moeller's reduction yields no segment and the energy is 0.
+// Their interiors overlap exactly when no edge line separates them: for two convex polygons
+// with disjoint interiors some line through an edge of one of them leaves the other in its
+// closed outer half-plane.  Decided in exact arithmetic after dropping a coordinate that
+// keeps the triangles' area (the exact normal of T_a has a non-zero component there).
+// ============================================================================================
+// 2D orientation of (a, b, c) with coordinate k dropped, exactly
+int orient2_exact(const double* a, const double* b, const double* c, int k) {
+  const int u = (k + 1) % 3, v = (k + 2) % 3;
+  const Dyadic r = (dy(b[u]) - dy(a[u])) * (dy(c[v]) - dy(a[v])) - (dy(b[v]) - dy(a[v])) * (dy(c[u]) - dy(a[u]));
+  return sgn(r);
+}
+
+bool coplanar_overlap(const Tri& ta, const Tri& tb) {
+  int k = 0, sa = 0;
+  while (k < 3 && (sa = orient2_exact(ta.p[0], ta.p[1], ta.p[2], k)) == 0) ++k;
+  if (sa == 0) return false;  // T_a has no area
+  const int sb = orient2_exact(tb.p[0], tb.p[1], tb.p[2], k);
+  if (sb == 0) return false;  // T_b has no area
+  for (int side = 0; side < 2; ++side) {
+    const Tri& P = side == 0 ? ta : tb;
+    const Tri& Q = side == 0 ? tb : ta;
+    const int sp = side == 0 ? sa : sb;  // P's interior lies where the edge orientation has sign sp
+    for (int e = 0; e < 3; ++e) {
+      bool separates = true;
+      for (int j = 0; j < 3; ++j)
+        if (sp * orient2_exact(P.p[e], P.p[(e + 1) % 3], Q.p[j], k) > 0) separates = false;
+      if (separates) return false;
+    }
+  }
+  return true;
+}
+
 // exact classification: straddle tests for both cuts, then the exact interval-overlap flag
 Classified classify_pair(const Tri& ta, const Tri& tb) {
   Classified r;
   int s[3];
   for (int k = 0; k < 3; ++k) s[k] = side(tb.p[0], tb.p[1], tb.p[2], ta.p[k]).sign;
+  if (s[0] == 0 && s[1] == 0 && s[2] == 0) {
+    if (coplanar_overlap(ta, tb)) r.status = ST_COPLANAR;
+    return r;
+  }
   r.ca = classify(s);
   if (!r.ca.straddle) return r;
   for (int k = 0; k < 3; ++k) s[k] = side(ta.p[0], ta.p[1], ta.p[2], tb.p[k]).sign;

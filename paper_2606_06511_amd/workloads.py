@@ -336,6 +336,31 @@ def crumpled_fans(seed: int = 0, n_fans: int = 8, blades: int = 16, height: floa
     return _finish(np.concatenate(xs), np.concatenate(ts))
 
 
+# integer frames (origin, two spanning vectors) of the planes of ``coplanar_soup``: every point
+# origin + u e1 + v e2 with small integers u, v is exactly representable, so triangles on one
+# plane are exactly coplanar; the planes lean on different coordinate axes
+_SOUP_PLANES = (
+    ((0, 0, 0), (1, 0, 0), (0, 1, 0)),     # z = 0
+    ((0, 0, -4), (1, 0, 1), (0, 1, 0)),    # x - z = 4
+    ((0, -3, 0), (1, 2, 0), (0, 1, 3)),
+    ((2, 0, 1), (0, 1, 2), (3, 0, -1)),
+)
+
+
+def coplanar_soup(seed: int = 0, n_tris: int = 4000, grid: int = 8, planes: int = 4):
+    """Separate triangles (three vertices each) with integer (u, v) corners in [0, grid]^2 on a
+    few exactly representable planes that cross each other.  Triangles on one plane are
+    exactly coplanar and often overlap, touch along edges or at vertices, or have no area;
+    triangles on different planes cross."""
+    rng = np.random.default_rng(seed)
+    pl = rng.integers(0, planes, n_tris)
+    uv = rng.integers(0, grid + 1, (n_tris, 3, 2))
+    frames = np.asarray(_SOUP_PLANES[:planes], np.float64)  # (planes, 3 rows, 3)
+    o, e1, e2 = frames[pl, 0], frames[pl, 1], frames[pl, 2]
+    x = o[:, None, :] + uv[..., :1] * e1[:, None, :] + uv[..., 1:] * e2[:, None, :]
+    return _finish(x.reshape(-1, 3), np.arange(3 * n_tris).reshape(-1, 3))
+
+
 def concat_problems(problems):
     """One batched mesh from independent problems ``(x, tris, ...)``: the vertices and
     triangles concatenated (triangle indices re-based to global vertex ids) and the offsets
