@@ -84,8 +84,12 @@ enum { TTIE_BROAD_BRUTE = 0, TTIE_BROAD_LBVH = 1, TTIE_BROAD_HASH = 2 };
 enum { TTIE_BROAD_VERTEX_ADJACENT = 0x100 };
 enum { TTIE_EVAL_VERTEX_ADJACENT = 1 };
 enum { TTIE_HVP_EXACT = 0, TTIE_HVP_PSD = 1 };
-/* per-pair flag codes written by ttie_eval */
-enum { TTIE_PAIR_NONE = 0, TTIE_PAIR_HIT = 1, TTIE_PAIR_ADJACENT = 2, TTIE_PAIR_DEGENERATE_FRAME = 3 };
+/* per-pair flag codes written by ttie_eval.  TTIE_PAIR_COPLANAR: the two triangles lie in one
+ * plane and their interiors overlap (decided exactly).  Such a pair has no intersection
+ * segment, so T = 0 as for every non-crossing pair (the paper sets coplanar pairs aside); the
+ * flag tells the caller where the energy cannot see an overlap. */
+enum { TTIE_PAIR_NONE = 0, TTIE_PAIR_HIT = 1, TTIE_PAIR_ADJACENT = 2, TTIE_PAIR_DEGENERATE_FRAME = 3,
+       TTIE_PAIR_COPLANAR = 4 };
 
 typedef struct ttie_ctx ttie_ctx;
 

@@ -32,7 +32,7 @@
 
 namespace ttie {
 
-enum { PAIR_NONE = 0, PAIR_HIT = 1, PAIR_ADJACENT = 2, PAIR_BAD_FRAME = 3, PAIR_DEFER = 4 };
+enum { PAIR_NONE = 0, PAIR_HIT = 1, PAIR_ADJACENT = 2, PAIR_BAD_FRAME = 3, PAIR_COPLANAR = 4, PAIR_DEFER = 5 };
 enum { STATUS_OK = 0, STATUS_INVALID = 1, STATUS_INDEX = 2, STATUS_NONFINITE = 3, STATUS_CAPACITY = 4, STATUS_UNSUPPORTED = 7 };
 
 // Geometry of a screened pair: kept for every intersecting pair.
@@ -153,6 +153,56 @@ __device__ __forceinline__ int orient_sign(const V3<double>& p, const V3<double>
   return o.sign;
 }
 
+// Sign of the 2D orientation of (a, b, c) with coordinate k dropped; 2 when only the exact path
+// could tell and kExact is off.  It is orient((a', 0), (b', 0), (c', 0), (0, 0, 1)) on the
+// dropped points, whose determinant is exactly the 2D one, so the filter and the exact path
+// of the 3D predicate decide it.
+template <bool kExact>
+__device__ __forceinline__ int orient2_sign(const V3<double>& a, const V3<double>& b, const V3<double>& c, int k,
+                                            int& status) {
+  const auto drop = [k](const V3<double>& p) {
+    return k == 0 ? V3<double>{p.y, p.z, 0.0} : (k == 1 ? V3<double>{p.z, p.x, 0.0} : V3<double>{p.x, p.y, 0.0});
+  };
+  return orient_sign<kExact>(drop(a), drop(b), drop(c), V3<double>{0.0, 0.0, 1.0}, status);
+}
+
+// Two triangles in one plane: the paper's reduction gives no segment and T = 0.  Their
+// interiors overlap exactly when no edge line separates them (for convex polygons with
+// disjoint interiors, the line through some edge of one leaves the other in its closed outer
+// half-plane).  Decided with exact 2D orientations after dropping the coordinate A's FP64
+// normal leans on most (or, if A has no area there, the next coordinate where it has some).
+// Returns PAIR_COPLANAR or PAIR_NONE.  Only the exact pass calls it: the fast pass defers
+// every pair whose sides are all zero (rare), so its kernel carries none of this code.
+__device__ __forceinline__ int coplanar_kind(const Tri64& A, const Tri64& B, int& status) {
+  const V3<double> a[3] = {selv(A, 0), selv(A, 1), selv(A, 2)};
+  const V3<double> b[3] = {selv(B, 0), selv(B, 1), selv(B, 2)};
+  const V3<double> n = cross(a[1] - a[0], a[2] - a[0]);
+  const double nx = fabs(n.x), ny = fabs(n.y), nz = fabs(n.z);
+  const int k0 = nx >= ny && nx >= nz ? 0 : (ny >= nz ? 1 : 2);
+  int k = k0, sa = 0;
+  for (int t = 0; t < 3; ++t) {
+    k = (k0 + t) % 3;
+    sa = orient2_sign<true>(a[0], a[1], a[2], k, status);
+    if (sa != 0) break;
+  }
+  if (sa == 0) return PAIR_NONE;  // A has no area
+  const int sb = orient2_sign<true>(b[0], b[1], b[2], k, status);
+  if (sb == 0) return PAIR_NONE;  // B has no area
+  for (int side = 0; side < 2; ++side) {
+    const V3<double>* P = side == 0 ? a : b;
+    const V3<double>* Q = side == 0 ? b : a;
+    const int sp = side == 0 ? sa : sb;  // P's interior: edge orientations of sign sp
+    for (int e = 0; e < 3; ++e) {
+      bool separates = true;
+      for (int j = 0; j < 3; ++j) {
+        separates &= orient2_sign<true>(P[e], P[(e + 1) % 3], Q[j], k, status) * sp <= 0;
+      }
+      if (separates) return PAIR_NONE;
+    }
+  }
+  return PAIR_COPLANAR;
+}
+
 struct Screen {
   int kind;  // PAIR_*
   uint32_t desc;
@@ -172,6 +222,10 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
   // T_a cut by the plane of T_b first, as the appendix does
   if (!plane_sides<kExact>(B, A, sa, out.da, status)) {
     out.kind = PAIR_DEFER;
+    return out;
+  }
+  if ((sa[0] | sa[1] | sa[2]) == 0) {  // A lies in B's plane (or B has no area)
+    out.kind = kExact ? coplanar_kind(A, B, status) : PAIR_DEFER;
     return out;
   }
   const Cut ca = make_cut(sa[0], sa[1], sa[2]);

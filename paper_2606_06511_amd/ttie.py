@@ -27,7 +27,7 @@ BROAD_BRUTE, BROAD_LBVH, BROAD_HASH = 0, 1, 2
 BROAD_VERTEX_ADJACENT = 0x100  # OR'ed into a broad-phase method: list pairs sharing one vertex
 EVAL_VERTEX_ADJACENT = 1       # Options.flags bit: evaluate pairs sharing one vertex
 HVP_EXACT, HVP_PSD = 0, 1
-PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME = 0, 1, 2, 3
+PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME, PAIR_COPLANAR = 0, 1, 2, 3, 4
 MAX_PROBLEMS = 4096
 PARAM_SCREEN_BLOCKS, PARAM_ROW_BLOCKS, PARAM_TRAV_BUDGET, PARAM_HASH_BUDGET = 0, 1, 2, 3
 

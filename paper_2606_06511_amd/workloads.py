@@ -347,14 +347,16 @@ _SOUP_PLANES = (
 )
 
 
-def coplanar_soup(seed: int = 0, n_tris: int = 4000, grid: int = 8, planes: int = 4):
-    """Separate triangles (three vertices each) with integer (u, v) corners in [0, grid]^2 on a
-    few exactly representable planes that cross each other.  Triangles on one plane are
-    exactly coplanar and often overlap, touch along edges or at vertices, or have no area;
-    triangles on different planes cross."""
+def coplanar_soup(seed: int = 0, n_tris: int = 4000, grid: int = 64, span: int = 3, planes: int = 4):
+    """Separate triangles (three vertices each) on a few exactly representable planes that
+    cross each other.  A triangle's (u, v) corners are a base point in [0, grid - span]^2 plus
+    integer offsets in [0, span]^2, so triangles on one plane are exactly coplanar and often
+    overlap, touch along edges or at vertices, or have no area; triangles on different planes
+    cross."""
     rng = np.random.default_rng(seed)
     pl = rng.integers(0, planes, n_tris)
-    uv = rng.integers(0, grid + 1, (n_tris, 3, 2))
+    base = rng.integers(0, grid - span + 1, (n_tris, 1, 2))
+    uv = base + rng.integers(0, span + 1, (n_tris, 3, 2))
     frames = np.asarray(_SOUP_PLANES[:planes], np.float64)  # (planes, 3 rows, 3)
     o, e1, e2 = frames[pl, 0], frames[pl, 1], frames[pl, 2]
     x = o[:, None, :] + uv[..., :1] * e1[:, None, :] + uv[..., 1:] * e2[:, None, :]
