@@ -1,0 +1,170 @@
+"""Pins of the oracle's quasi-static coupling (springs + energy + proximal term) against
+closed forms, finite differences, dense assemblies written out here, and a dense-solve
+version of the Newton step."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import quasistatic as qs
+from paper_2606_06511_amd import workloads
+
+
+def test_edge_count_euler():
+    x, tris = workloads.grid_mesh(9)  # a disk: E = V + F - 1
+    assert len(qs.spring_edges(tris)) == len(x) + len(tris) - 1
+    x, tris = workloads.icosphere(2)  # a sphere: E = V + F - 2
+    e = qs.spring_edges(tris)
+    assert len(e) == len(x) + len(tris) - 2
+    assert np.all(e[:, 0] < e[:, 1])
+
+
+def test_single_spring_closed_forms():
+    rest = np.array([[0.0, 0, 0], [1, 0, 0]])
+    edges = np.array([[0, 1]])
+    k = 3.0
+    # stretched to twice its length along x
+    E, G, He = qs.springs(np.array([[0.0, 0, 0], [2, 0, 0]]), rest, edges, k)
+    assert E == 1.5
+    np.testing.assert_array_equal(G, [[-3.0, 0, 0], [3.0, 0, 0]])
+    np.testing.assert_allclose(He[0], np.diag([3.0, 1.5, 1.5]), rtol=0, atol=1e-15)
+    # compressed to half: the exact transverse eigenvalue 3 (1 - 2) = -3 is clamped to 0
+    E, G, He = qs.springs(np.array([[0.0, 0, 0], [0, 0.5, 0]]), rest, edges, k)
+    assert E == pytest.approx(0.375)
+    np.testing.assert_allclose(G, [[0, 1.5, 0], [0, -1.5, 0]], atol=1e-15)
+    np.testing.assert_allclose(He[0], np.diag([0.0, 3.0, 0.0]), atol=1e-15)
+    # zero length: no direction, gradient 0 and block k I
+    E, G, He = qs.springs(np.array([[0.5, 0, 0], [0.5, 0, 0]]), rest, edges, k)
+    assert E == 1.5 and not G.any()
+    np.testing.assert_array_equal(He[0], 3.0 * np.eye(3))
+
+
+def _stretched(seed=0, n=5):
+    x, tris = workloads.grid_mesh(n)
+    rng = np.random.default_rng(seed)
+    rest = x + 0.02 * rng.normal(size=x.shape)
+    return 1.6 * rest + 0.01 * rng.normal(size=x.shape), rest, tris
+
+
+def test_spring_gradient_and_hessian_fd():
+    # every edge stretched (l > L): the PSD blocks equal the exact Hessian
+    x, rest, tris = _stretched()
+    edges = qs.spring_edges(tris)
+    k, m = 2.0, 0.5
+    E, G, He = qs.springs(x, rest, edges, k)
+    l = np.linalg.norm(x[edges[:, 0]] - x[edges[:, 1]], axis=1)
+    L = np.linalg.norm(rest[edges[:, 0]] - rest[edges[:, 1]], axis=1)
+    assert np.all(l > L)
+    h = 1e-6
+    n = x.size
+    fd_g = np.zeros(n)
+    fd_H = np.zeros((n, n))
+    for i in range(n):
+        xp, xm = x.copy().ravel(), x.copy().ravel()
+        xp[i] += h
+        xm[i] -= h
+        ep, gp, _ = qs.springs(xp.reshape(-1, 3), rest, edges, k)
+        em, gm, _ = qs.springs(xm.reshape(-1, 3), rest, edges, k)
+        fd_g[i] = (ep - em) / (2 * h)
+        fd_H[:, i] = (gp - gm).ravel() / (2 * h)
+    np.testing.assert_allclose(G.ravel(), fd_g, rtol=1e-6, atol=1e-8)
+    K = oracle.bsr_to_dense(*qs.stiffness_bsr(len(x), edges, He, m), len(x))
+    np.testing.assert_allclose(K - m * np.eye(n), fd_H, rtol=1e-5, atol=1e-6)
+
+
+def test_stiffness_against_dense_loop_and_psd():
+    x, tris = workloads.folded_cloth(1, n=6)
+    rng = np.random.default_rng(2)
+    xx = x + 0.05 * rng.normal(size=x.shape)  # a mix of stretched and compressed edges
+    edges = qs.spring_edges(tris)
+    k, m = 1.5, 0.25
+    _, _, He = qs.springs(xx, x, edges, k)
+    rp, ci, va = qs.stiffness_bsr(len(x), edges, He, m)
+    # pattern: v and its neighbours, sorted
+    for v in range(len(x)):
+        nb = set(edges[edges[:, 0] == v, 1]) | set(edges[edges[:, 1] == v, 0]) | {v}
+        assert list(ci[rp[v]:rp[v + 1]]) == sorted(nb)
+    D = m * np.eye(3 * len(x))
+    for (i, j), B in zip(edges, He):
+        for a, b, s in ((i, i, 1), (j, j, 1), (i, j, -1), (j, i, -1)):
+            D[3 * a:3 * a + 3, 3 * b:3 * b + 3] += s * B
+    np.testing.assert_allclose(oracle.bsr_to_dense(rp, ci, va, len(x)), D, rtol=0, atol=1e-13)
+    assert np.linalg.eigvalsh(D).min() >= m - 1e-10
+    l = np.linalg.norm(xx[edges[:, 0]] - xx[edges[:, 1]], axis=1)
+    L = np.linalg.norm(x[edges[:, 0]] - x[edges[:, 1]], axis=1)
+    assert np.any(l < L) and np.any(l > L)
+
+
+def test_rigid_motions_at_rest():
+    x, tris = workloads.icosphere(1)
+    c, s = np.cos(0.7), np.sin(0.7)
+    R = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+    y = x @ R.T + np.array([0.3, -1.0, 2.0])
+    edges = qs.spring_edges(tris)
+    E, G, He = qs.springs(y, x, edges, 4.0)
+    assert E < 1e-25 and np.abs(G).max() < 1e-12
+    K = oracle.bsr_to_dense(*qs.stiffness_bsr(len(x), edges, He, 0.0), len(x))
+    for v in (np.tile([1.0, 0, 0], len(x)), np.cross(np.array([0.2, -0.5, 1.0]), y).ravel()):
+        assert np.abs(K @ v).max() < 1e-12 * np.abs(K).max()
+
+
+@pytest.fixture(scope="module")
+def small_fold():
+    x, tris = workloads.folded_cloth(0, n=12)
+    r = oracle.evaluate(x, tris, oracle.pairs(x, tris), hessian=False)
+    assert len(r["hit_pair"]) > 0
+    return x, tris
+
+
+def test_objective_gradient_fd(small_fold):
+    x, tris = small_fold
+    rng = np.random.default_rng(4)
+    rest = x + 0.01 * rng.normal(size=x.shape)
+    x_prev = x + 0.01 * rng.normal(size=x.shape)
+    edges = qs.spring_edges(tris)
+    k, m, w = 1.0, 2.0, 1e3
+    pl = oracle.pairs(x, tris)
+    phi, g, _, r = qs.objective(x, rest, x_prev, tris, edges, pl, k, m, w, hessian=False)
+    Es, _, _ = qs.springs(x, rest, edges, k)
+    assert phi == pytest.approx(Es + w * r["E"] + 0.5 * m * np.sum((x - x_prev) ** 2), rel=1e-14)
+    assert r["E"] > 0
+    h = 1e-7
+    idx = rng.choice(x.size, 40, replace=False)
+    for i in idx:
+        xp, xm = x.copy().ravel(), x.copy().ravel()
+        xp[i] += h
+        xm[i] -= h
+        fp = qs.objective(xp.reshape(-1, 3), rest, x_prev, tris, edges, pl, k, m, w, hessian=False)[0]
+        fm = qs.objective(xm.reshape(-1, 3), rest, x_prev, tris, edges, pl, k, m, w, hessian=False)[0]
+        assert (fp - fm) / (2 * h) == pytest.approx(g.ravel()[i], rel=1e-5, abs=1e-7)
+
+
+def _dense_solve(K, H, w, b):
+    n = len(K[0]) - 1
+    A = oracle.bsr_to_dense(*K, n) + w * oracle.bsr_to_dense(*H, n)
+    return np.linalg.solve(A, b.ravel())
+
+
+def test_step_pcg_matches_dense_solve(small_fold):
+    x, tris = small_fold
+    kw = dict(k=1.0, m=1.0, w=1e4, newton_iters=3)
+    x1, recs = qs.qs_step(x, x, tris, pcg_iters=5000, pcg_tol=1e-14, **kw)
+    x2, recs2 = qs.qs_step(x, x, tris, solve=_dense_solve, **kw)
+    assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x2 - x).max()
+    for a, b in zip(recs, recs2):
+        assert a["alpha"] == b["alpha"]
+        assert a["phi"] == pytest.approx(b["phi"], rel=1e-10)
+        assert a["phi_new"] <= a["phi"]  # Armijo
+    # the first iteration starts at x_prev = rest: Phi = w E
+    E0 = oracle.evaluate(x, tris, oracle.pairs(x, tris), hessian=False)["E"]
+    assert recs[0]["phi"] == pytest.approx(1e4 * E0, rel=1e-12)
+    assert recs[-1]["phi_new"] < recs[0]["phi"]
+
+
+def test_quasi_static_runs_decrease_phi(small_fold):
+    x, tris = small_fold
+    xf, hist = qs.quasi_static(x, x, tris, 3, 1.0, 1.0, 1e4, newton_iters=3, pcg_iters=20)
+    assert len(hist) == 4
+    for h in hist[:-1]:
+        assert all(r["phi_new"] <= r["phi"] for r in h["newton"])
+    assert hist[-1]["E"] < hist[0]["E"]
