@@ -219,6 +219,30 @@ def extra_configs(args, np, torch, ttie, workloads):
         "pairs_per_s": sum(h["pairs"] for h in steps) / (sum(h["ms"] for h in steps) * 1e-3)}
     del model
 
+    # quasi-static coupling on the folded cloth: springs on the edges (rest = the folded state),
+    # proximal weight m, energy weight w scaled with the inverse squared edge length
+    from paper_2606_06511_amd.quasistatic import QuasiStatic
+
+    x, tris = workloads.folded_cloth(seed=0)
+    model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 22, max_hits=1 << 16)
+    xd = torch.from_numpy(x).to(dev)
+    sim = QuasiStatic(model, xd, k=1.0, m=1.0, w=1e6)
+    sim.step(xd, newton_iters=1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist = sim.run(xd, 5, newton_iters=4, pcg_iters=50)
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    its = [r for h in hist for r in h["newton"]]
+    res["quasistatic_cloth"] = {
+        "workload": "folded cloth 256x256 grid (130,050 tris), 5 quasi-static steps x 4 Newton iterations, springs "
+                    "k = 1 on the edges, proximal m = 1, energy weight w = 1e6, FP64, coupled Jacobi-PCG (50)",
+        "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist],
+        "phi": [[r["phi"] for r in h["newton"]] for h in hist[:-1]],
+        "alpha": [[r["alpha"] for r in h["newton"]] for h in hist[:-1]],
+        "ms_per_newton_iter": sum(r["ms"] for r in its) / max(len(its), 1), "total_ms": total_ms}
+    del model, sim
+
     return res
 
 

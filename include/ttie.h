@@ -250,6 +250,48 @@ ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, cons
 ttie_status ttie_pcg_mf(ttie_ctx* ctx, int64_t n_rows, const void* b, double scale, void* x, double mu_rel,
                         int max_iter, double tol, double* info, void* stream);
 
+/* ---- quasi-static coupling with a synthetic elastic model -----------------------------
+ * The paper's quasi-static simulation (Fig. 2) drives an intersecting state to an
+ * intersection-free one with the energy paired with an elastic model it does not give.  The
+ * stand-in: springs on the mesh's edges, and the objective of one quasi-static step
+ *   Phi(x) = sum over edges (k/2)(|x_i - x_j| - |r_i - r_j|)^2 + w E(x) + (m/2)|x - x_prev|^2
+ * (r: rest positions, x_prev: positions at the step's start), minimised by inexact Newton with
+ * A = K + w H, K the springs' Hessian with each edge block projected to PSD plus m I, H the PSD
+ * Hessian of the energy applied from the hit records (ttie_pcg_coupled).
+ *
+ * ttie_springs_pattern: the 3x3-block CSR pattern of K, row v holding v and its neighbours in
+ * the mesh's edge graph in increasing order.  row_ptr: n_verts + 1 int32; col_idx: up to
+ * block_capacity int32; *n_blocks (device int64) receives the block count, and a count above
+ * block_capacity latches TTIE_ERR_CAPACITY (rows that fit are still written).  Vertex indices
+ * outside [0, n_verts) latch TTIE_ERR_INDEX_OUT_OF_RANGE.  Uses the evaluation's incidence
+ * buffers, so the last evaluation is no longer available to ttie_hvp / ttie_pcg_mf. */
+ttie_status ttie_springs_pattern(ttie_ctx* ctx, const ttie_mesh* mesh, int32_t* row_ptr, int32_t* col_idx,
+                                 int64_t block_capacity, int64_t* n_blocks, void* stream);
+
+/* ttie_qs_eval: Phi, its gradient and K at x (all device float64; n_verts x 3 arrays).
+ *  row_ptr, col_idx  the pattern from ttie_springs_pattern
+ *  x, rest, x_prev   positions, rest positions, positions at the step's start
+ *  k, m, w           spring stiffness (>= 0), proximal weight (>= 0), weight of the energy (>= 0)
+ *  e_ttie, g_ttie    E (device scalar) and its gradient (n_verts x 3, float64) from a
+ *                    TTIE_FP64 ttie_eval at x; both NULL when w = 0
+ *  phi               device scalar: Phi(x)
+ *  grad, vals        optional (NULL skips): grad Phi, and K's blocks in the pattern's order
+ * Per edge with d = x_i - x_j, l = |d|, u = d / l, L = |r_i - r_j|: the PSD block is
+ * k [u u^T + max(0, 1 - L/l)(I - u u^T)], or k I for a zero-length edge (whose gradient is 0).
+ * Deterministic: rows are summed in column order, Phi in a fixed order. */
+ttie_status ttie_qs_eval(ttie_ctx* ctx, int64_t n_verts, const int32_t* row_ptr, const int32_t* col_idx,
+                         const double* x, const double* rest, const double* x_prev, double k, double m, double w,
+                         const double* e_ttie, const double* g_ttie, double* phi, double* grad, double* vals,
+                         void* stream);
+
+/* ttie_pcg_coupled: Jacobi-PCG (the iteration of ttie_pcg) on (K + w H + mu I) x = scale * b,
+ * with K a PSD 3x3-block CSR matrix in float64 (columns sorted per row, e.g. from
+ * ttie_qs_eval) and H the PSD Hessian of the last ttie_eval, which must be TTIE_FP64 and
+ * have n_verts = n_rows.  mu >= 0 is absolute.  info as for ttie_pcg (info[2] = mu). */
+ttie_status ttie_pcg_coupled(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* vals, double w, const double* b, double scale, double* x, double mu,
+                             int max_iter, double tol, double* info, void* stream);
+
 /* ---- launch parameters (what an autotuner varies) ------------------------------------
  * Launch shapes and work budgets of the kernels.  Every value in range gives the same results
  * bit for bit (the evaluation sums in pair-key order and a candidate set does not depend on
@@ -286,7 +328,8 @@ enum {
   TTIE_STAGE_ASSEMBLY = 7,    /* incidence lists, BSR pattern, rows of gradient and Hessian */
   TTIE_STAGE_HVP = 8,         /* Hessian-vector products */
   TTIE_STAGE_PCG = 9,         /* the preconditioned conjugate-gradient solve */
-  TTIE_STAGE_COUNT = 10
+  TTIE_STAGE_ELASTIC = 10,    /* the quasi-static objective (springs, proximal term) */
+  TTIE_STAGE_COUNT = 11
 };
 ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask);
 ttie_status ttie_read_timers(ttie_ctx* ctx, int n_stages, int64_t* launches_host, double* total_ms_host);

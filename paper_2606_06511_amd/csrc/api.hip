@@ -1,5 +1,6 @@
 // C ABI of libttie.so: context, workspace carve-up, argument checks, status handling.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -464,6 +465,57 @@ ttie_status ttie_pcg_mf(ttie_ctx* ctx, int64_t n_rows, const void* b, double sca
   DeviceGuard g(ctx->device);
   hipError_t e = launch_pcg_mf(ctx, n_rows, b, scale, x, mu_rel, max_iter, tol, info, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ttie_pcg_mf");
+  return TTIE_OK;
+}
+
+ttie_status ttie_springs_pattern(ttie_ctx* ctx, const ttie_mesh* mesh, int32_t* row_ptr, int32_t* col_idx,
+                                 int64_t block_capacity, int64_t* n_blocks, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+  if (!row_ptr || !n_blocks || (block_capacity > 0 && !col_idx) || block_capacity < 0)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad output arrays");
+  if (mesh->n_verts + 1 >= (1ll << 31)) return fail(TTIE_ERR_UNSUPPORTED, "too many vertices for int32 offsets");
+  if (6 * mesh->n_tris + 2 * mesh->n_verts >= (1ll << 31))
+    return fail(TTIE_ERR_UNSUPPORTED, "too many edges for int32 offsets");
+  DeviceGuard g(ctx->device);
+  ctx->last_valid = 0;  // the incidence buffers are reused
+  hipError_t e = launch_springs_pattern(ctx, mesh, row_ptr, col_idx, block_capacity, n_blocks, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_springs_pattern");
+  return TTIE_OK;
+}
+
+ttie_status ttie_qs_eval(ttie_ctx* ctx, int64_t n_verts, const int32_t* row_ptr, const int32_t* col_idx,
+                         const double* x, const double* rest, const double* x_prev, double k, double m, double w,
+                         const double* e_ttie, const double* g_ttie, double* phi, double* grad, double* vals,
+                         void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (n_verts < 0 || n_verts > ctx->lim.max_verts) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad n_verts");
+  if (!row_ptr || !phi || (n_verts > 0 && (!col_idx || !x || !rest || !x_prev)))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL array");
+  if (!(k >= 0.0) || !(m >= 0.0) || !(w >= 0.0) || !std::isfinite(k) || !std::isfinite(m) || !std::isfinite(w))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "k, m and w must be finite and >= 0");
+  if ((e_ttie == nullptr) != (g_ttie == nullptr)) return fail(TTIE_ERR_INVALID_ARGUMENT, "give both E and its gradient");
+  if (w > 0.0 && !e_ttie) return fail(TTIE_ERR_INVALID_ARGUMENT, "w > 0 needs E and its gradient");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_qs_eval(ctx, n_verts, row_ptr, col_idx, x, rest, x_prev, k, m, w, e_ttie, g_ttie, phi, grad,
+                                vals, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_qs_eval");
+  return TTIE_OK;
+}
+
+ttie_status ttie_pcg_coupled(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* vals, double w, const double* b, double scale, double* x, double mu,
+                             int max_iter, double tol, double* info, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation to take the Hessian from");
+  if (ctx->last_precision != TTIE_FP64) return fail(TTIE_ERR_UNSUPPORTED, "the last evaluation must be TTIE_FP64");
+  if (n_rows != ctx->last_nverts) return fail(TTIE_ERR_INVALID_ARGUMENT, "n_rows differs from the last evaluation");
+  if (n_rows > 0 && (!b || !x || !row_ptr || !col_idx || !vals)) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL array");
+  if (max_iter < 0 || !(tol >= 0.0) || !(mu >= 0.0) || !(w >= 0.0)) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad parameters");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_pcg_coupled(ctx, n_rows, row_ptr, col_idx, vals, w, b, scale, x, mu, max_iter, tol, info,
+                                    (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_pcg_coupled");
   return TTIE_OK;
 }
 

@@ -147,6 +147,15 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
 hipError_t launch_pcg(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                       const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
                       double* info, hipStream_t s);
+hipError_t launch_pcg_coupled(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                              double w, const double* b, double scale, double* x, double mu, int max_iter, double tol,
+                              double* info, hipStream_t s);
+hipError_t launch_springs_pattern(Ctx* c, const ttie_mesh* m, int32_t* row_ptr, int32_t* col_idx, int64_t cap,
+                                  int64_t* n_blocks, hipStream_t s);
+hipError_t launch_qs_eval(Ctx* c, int64_t nv, const int32_t* row_ptr, const int32_t* col_idx, const double* x,
+                          const double* rest, const double* x_prev, double ks, double m, double w,
+                          const double* e_ttie, const double* g_ttie, double* phi, double* grad, double* vals,
+                          hipStream_t s);
 hipError_t launch_pcg_mf(Ctx* c, int64_t n, const void* b, double scale, void* x, double mu_rel, int max_iter,
                          double tol, double* info, hipStream_t s);
 hipError_t launch_axpy(int64_t n_verts, double alpha, const double* x, const void* d, double* out, int precision,

@@ -315,6 +315,82 @@ __global__ void __launch_bounds__(kPB) k_pcg_rows_mf(int64_t n, const int32_t* _
   block_partials(pq, 0.0, pq_part, red);
 }
 
+// ---- coupled variant: A = K + w H + mu I, K a caller's PSD BSR matrix (FP64) --------------
+// (the quasi-static objective's elastic Hessian), H applied from the hit records as above.
+// Jacobi diagonal: K's diagonal entries + w times H's + mu.
+__global__ void __launch_bounds__(kPB) k_pcg_setup_cp(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col_idx,
+                                                      const double* __restrict__ vals, double w, double mu,
+                                                      const double* __restrict__ b, double scale,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      double* __restrict__ z, double* __restrict__ p,
+                                                      double* __restrict__ dinv, double* __restrict__ pout,
+                                                      PcgState* st) {
+  __shared__ double red[kPB];
+  double rz = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+    const int64_t d = diag_block(row_ptr, col_idx, i);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double dg = (d >= 0 ? vals[9 * d + 4 * c] : 0.0) + w * dinv[3 * i + c] + mu;
+      const double di = dg > 0.0 ? 1.0 / dg : 1.0;
+      const double ri = scale * b[3 * i + c];
+      const double zi = di * ri;
+      dinv[3 * i + c] = di;
+      x[3 * i + c] = 0.0;
+      r[3 * i + c] = ri;
+      z[3 * i + c] = zi;
+      p[3 * i + c] = zi;
+      rz += ri * zi;
+      bb += ri * ri;
+    }
+  }
+  block_partials(rz, bb, pout, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->mu = mu;
+    st->done = 0;
+    st->iters = 0;
+  }
+}
+
+// q = (K + w H + mu I) p: K's row times p, plus w times the hit products gathered in pair-key
+// order; partials of p.q
+__global__ void __launch_bounds__(kPB) k_pcg_rows_cp(int64_t n, const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc, const double* __restrict__ hv,
+                                                     const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx,
+                                                     const double* __restrict__ vals, double w,
+                                                     const double* __restrict__ p, double* __restrict__ q,
+                                                     double* __restrict__ pq_part, const PcgState* st) {
+  if (st->done) return;
+  __shared__ double red[kPB];
+  const double mu = st->mu;
+  double pq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+    double hs[3] = {0.0, 0.0, 0.0};
+    for (int32_t k = off[i]; k < off[i + 1]; ++k) {
+      const Incidence in = inc[k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) hs[c] += hv[18 * (int64_t)in.hit + 3 * in.slot + c];
+    }
+    double acc[3] = {mu * p[3 * i] + w * hs[0], mu * p[3 * i + 1] + w * hs[1], mu * p[3 * i + 2] + w * hs[2]};
+    for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int64_t c = col_idx[k];
+      const double p0 = p[3 * c], p1 = p[3 * c + 1], p2 = p[3 * c + 2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        acc[a] += vals[9 * (int64_t)k + 3 * a] * p0 + vals[9 * (int64_t)k + 3 * a + 1] * p1 +
+                  vals[9 * (int64_t)k + 3 * a + 2] * p2;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      q[3 * i + a] = acc[a];
+      pq += p[3 * i + a] * acc[a];
+    }
+  }
+  block_partials(pq, 0.0, pq_part, red);
+}
+
 template <class S>
 __global__ void __launch_bounds__(kPB) k_pcg_xb(int64_t n, const S* __restrict__ x, const S* __restrict__ b,
                                                 double scale, double* __restrict__ part) {
@@ -404,6 +480,43 @@ static hipError_t pcg_mf_impl(Ctx* c, int64_t n, const S* b, double scale, S* x,
   }
   if (info) {
     k_pcg_xb<S><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
+    k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
+  }
+  stage_end(c, TTIE_STAGE_PCG, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_coupled(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                              double w, const double* b, double scale, double* x, double mu, int max_iter, double tol,
+                              double* info, hipStream_t s) {
+  const Layout& L = c->L;
+  double* base = wsp<double>(c, L.pcg_vec);
+  const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
+  double *r = base, *z = base + m3, *p = base + 2 * m3, *q = base + 3 * m3, *dinv = base + 4 * m3;
+  double* part = wsp<double>(c, L.pcg_part);
+  double *pdiag = part, *pset = part + 4 * kPB, *pq = part + 8 * kPB, *pA = part + 12 * kPB, *pB = part + 16 * kPB;
+  PcgState* st = wsp<PcgState>(c, L.pcg_state);
+  const AsmRec<double>* recs = wsp<AsmRec<double>>(c, L.recs);
+  const int32_t* off = wsp<int32_t>(c, L.off);
+  const Incidence* inc = wsp<Incidence>(c, L.inc2);
+  double* hv = wsp<double>(c, L.hvbuf);
+  const Counters* ctr = wsp<Counters>(c, L.counters);
+  const uint32_t max_hits = (uint32_t)c->lim.max_hits;
+  const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (c->lim.max_hits + kPB - 1) / kPB));
+  stage_begin(c, TTIE_STAGE_PCG, s);
+  k_pcg_diag_mf<double><<<kPB, kPB, 0, s>>>(n, off, inc, recs, dinv, pdiag);  // raw diagonal of H into dinv
+  k_pcg_setup_cp<<<kPB, kPB, 0, s>>>(n, row_ptr, col_idx, vals, w, mu, b, scale, x, r, z, p, dinv, pset, st);
+  const double* rz_old = pset;
+  for (int it = 0; it < max_iter; ++it) {
+    double* rz_new = (it % 2 == 0) ? pA : pB;
+    k_pcg_hits_mf<double><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, p, hv, st);
+    k_pcg_rows_cp<<<kPB, kPB, 0, s>>>(n, off, inc, hv, row_ptr, col_idx, vals, w, p, q, pq, st);
+    k_pcg_update<double><<<kPB, kPB, 0, s>>>(n, x, r, z, p, q, dinv, rz_old, pq, rz_new, st);
+    k_pcg_dir<double><<<kPB, kPB, 0, s>>>(n, p, z, rz_old, rz_new, pset, tol, it, st);
+    rz_old = rz_new;
+  }
+  if (info) {
+    k_pcg_xb<double><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
     k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
   }
   stage_end(c, TTIE_STAGE_PCG, s);

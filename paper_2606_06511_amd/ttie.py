@@ -70,6 +70,11 @@ SIGNATURES = {
                         ctypes.c_double, _i32, _vp, _vp]),
     "ttie_pcg_mf": (_i32, [_vp, _i64, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32, ctypes.c_double, _vp, _vp]),
     "ttie_axpy": (_i32, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, _i32, _vp]),
+    "ttie_springs_pattern": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, _vp, _vp]),
+    "ttie_qs_eval": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ttie_pcg_coupled": (_i32, [_vp, _i64, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp,
+                                ctypes.c_double, _i32, ctypes.c_double, _vp, _vp]),
     "ttie_set_param": (_i32, [_vp, _i32, _i64]),
     "ttie_get_param": (_i32, [_vp, _i32, ctypes.POINTER(_i64)]),
     "ttie_set_timing": (_i32, [_vp, ctypes.c_uint32]),
@@ -77,7 +82,7 @@ SIGNATURES = {
 }
 
 STAGES = ["bp_boxes", "bp_sort", "bp_build", "bp_traverse", "screen", "screen_exact", "derivs", "assembly", "hvp",
-          "pcg"]
+          "pcg", "elastic"]
 
 _lib = None
 
@@ -323,6 +328,53 @@ class Context:
             info = torch.zeros(4, dtype=torch.float64, device=b.device)
         _check(lib().ttie_pcg_mf(self.handle, b.shape[0], _ptr(b), float(scale), _ptr(out), float(mu_rel),
                                  int(max_iter), float(tol), _ptr(info), _stream()))
+        return out, info
+
+    def springs_pattern(self, tris, n_verts, capacity=None):
+        """The 3x3-block CSR pattern of the springs' Hessian on the mesh's edge graph: returns
+        (row_ptr (n_verts + 1,) int32, col_idx (n_blocks,) int32) on the GPU (synchronizes to size
+        col_idx).  Invalidates the last evaluation."""
+        dev = self.device
+        x_dummy = torch.zeros((n_verts, 3), dtype=torch.float64, device=dev)
+        m = self._mesh(x_dummy, tris)
+        if capacity is None:
+            capacity = 6 * tris.shape[0] + n_verts
+        row_ptr = torch.empty(n_verts + 1, dtype=torch.int32, device=dev)
+        col_idx = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        nb = torch.zeros(1, dtype=torch.int64, device=dev)
+        _check(lib().ttie_springs_pattern(self.handle, ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), capacity,
+                                          _ptr(nb), _stream()))
+        self.check()
+        return row_ptr, col_idx[: int(nb.item())]
+
+    def qs_eval(self, row_ptr, col_idx, x, rest, x_prev, k, m, w, e_ttie=None, g_ttie=None, grad=True, vals=True,
+                out=None):
+        """Objective of a quasi-static step (springs + w E + proximal term): returns a dict with
+        ``phi`` (1,) f64 and, when asked, ``grad`` (N, 3) and ``vals`` (n_blocks, 3, 3), all f64."""
+        dev = self.device
+        n = x.shape[0]
+        if out is None:
+            out = {"phi": torch.zeros(1, dtype=torch.float64, device=dev)}
+            if grad:
+                out["grad"] = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            if vals:
+                out["vals"] = torch.empty((col_idx.shape[0], 3, 3), dtype=torch.float64, device=dev)
+        _check(lib().ttie_qs_eval(self.handle, n, _ptr(row_ptr), _ptr(col_idx), _ptr(x), _ptr(rest), _ptr(x_prev),
+                                  float(k), float(m), float(w), _ptr(e_ttie), _ptr(g_ttie), _ptr(out["phi"]),
+                                  _ptr(out.get("grad")) if grad else None, _ptr(out.get("vals")) if vals else None,
+                                  _stream()))
+        return out
+
+    def pcg_coupled(self, row_ptr, col_idx, vals, w, b, scale=1.0, mu=0.0, max_iter=50, tol=1e-6, out=None, info=None):
+        """Jacobi-PCG on (K + w H + mu I) x = scale * b, K in BSR (f64), H the PSD Hessian of the
+        last (FP64) evaluation.  Returns (x, info) like ``pcg``."""
+        if out is None:
+            out = torch.empty_like(b)
+        if info is None:
+            info = torch.zeros(4, dtype=torch.float64, device=b.device)
+        _check(lib().ttie_pcg_coupled(self.handle, b.shape[0], _ptr(row_ptr), _ptr(col_idx), _ptr(vals), float(w),
+                                      _ptr(b), float(scale), _ptr(out), float(mu), int(max_iter), float(tol),
+                                      _ptr(info), _stream()))
         return out, info
 
     def axpy(self, x, alpha, d, out=None):
