@@ -308,7 +308,10 @@ enum {
 ttie_status ttie_set_param(ttie_ctx* ctx, int param, int64_t value);
 ttie_status ttie_get_param(ttie_ctx* ctx, int param, int64_t* value_host);
 
-/* out = x + alpha * d for n_verts x 3 positions: x and out float64, d in `precision`. */
+/* out = x + alpha * d for n_verts x 3 positions: x and out float64, d in `precision`.  A result
+ * of magnitude below 2^-200 is set to 0, so positions stay in the coordinate domain of the exact
+ * predicates (0, or magnitude in [2^-200, 2^200]); a truncated solve can leave vanishing
+ * components at far vertices. */
 ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double* x, const void* d, double* out,
                       int precision, void* stream);
 

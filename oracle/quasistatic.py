@@ -149,6 +149,13 @@ def pcg(apply, b, diag, max_iter, tol):
     return d, it
 
 
+def flush_tiny(x):
+    """Coordinates of magnitude below 2^-200 set to 0: trial positions stay in the exact
+    predicates' coordinate domain (0, or magnitude in [2^-200, 2^200]), as in the Newton loop."""
+    x = np.asarray(x, np.float64)
+    return np.where(np.abs(x) < 2.0 ** -200, 0.0, x)
+
+
 def qs_step(x_prev, rest, tris, k, m, w, newton_iters=4, pcg_iters=50, pcg_tol=1e-6, armijo_c=1e-4, beta=0.5,
             max_halvings=30, solve=None):
     """One quasi-static step: ``newton_iters`` inexact Newton iterations on Phi from x_prev.
@@ -173,10 +180,10 @@ def qs_step(x_prev, rest, tris, k, m, w, newton_iters=4, pcg_iters=50, pcg_tol=1
             d, its = pcg(apply, -g.ravel(), diag, pcg_iters, pcg_tol)
         d = d.reshape(-1, 3)
         gd = float(np.sum(g * d))
-        sw = pairs_swept(x, x + d, tris)
+        sw = pairs_swept(x, flush_tiny(x + d), tris)
         alpha = 1.0
         for h in range(max_halvings):
-            xt = x + alpha * d
+            xt = flush_tiny(x + alpha * d)
             phit = objective(xt, rest, x_prev, tris, edges, sw, k, m, w, hessian=False)[0]
             if phit <= phi + armijo_c * alpha * gd:
                 break

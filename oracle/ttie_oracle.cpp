@@ -975,6 +975,11 @@ double dotv(const std::vector<double>& a, const std::vector<double>& b) {
   return s;
 }
 
+// Positions stay in the coordinate domain of the exact predicates (0, or magnitude in
+// [2^-200, 2^200]): a trial coordinate of smaller magnitude (a far vertex reached by a
+// truncated solve with a vanishing component) is set to 0.
+double flush_tiny(double v) { return std::fabs(v) < 0x1p-200 ? 0.0 : v; }
+
 int newton(double* x, int64_t nv, const int32_t* tris, int64_t nt, const NewtonParams& P, double* energies,
            double* alphas, int* pcg_iters_out) {
   int done = 0;
@@ -1040,11 +1045,11 @@ int newton(double* x, int64_t nv, const int32_t* tris, int64_t nt, const NewtonP
     delete R;
     // Armijo backtracking with candidates swept from x to x + d
     std::vector<double> xe(3 * nv);
-    for (int64_t i = 0; i < 3 * nv; ++i) xe[i] = x[i] + d[i];
+    for (int64_t i = 0; i < 3 * nv; ++i) xe[i] = flush_tiny(x[i] + d[i]);
     std::vector<int32_t> sw = pairs_boxes(m, xe.data());
     double alpha = 1.0;
     for (int h = 0; h < P.max_halvings; ++h) {
-      for (int64_t i = 0; i < 3 * nv; ++i) xt[i] = x[i] + alpha * d[i];
+      for (int64_t i = 0; i < 3 * nv; ++i) xt[i] = flush_tiny(x[i] + alpha * d[i]);
       Mesh mt{xt.data(), nv, tris, nt};
       EvalResult* Rt = evaluate(mt, sw.data(), (int64_t)sw.size() / 2, P.interval_mode, P.psd_mode, 0, P.nthreads);
       const double Et = Rt->E;

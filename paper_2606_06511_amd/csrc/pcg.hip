@@ -415,8 +415,10 @@ __global__ void __launch_bounds__(kPB) k_pcg_info(const double* __restrict__ par
 template <class S>
 __global__ void __launch_bounds__(kPB) k_axpy(int64_t n, double alpha, const double* __restrict__ x,
                                               const S* __restrict__ d, double* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB)
-    out[i] = x[i] + alpha * (double)d[i];
+  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+    const double v = x[i] + alpha * (double)d[i];
+    out[i] = fabs(v) < 0x1p-200 ? 0.0 : v;  // stay in the predicates' coordinate domain
+  }
 }
 
 template <class S>

@@ -159,3 +159,15 @@ def test_quasi_static_trajectory_matches_oracle():
             assert a["alpha"] == b["alpha"]
             assert a["phi"] == pytest.approx(b["phi"], rel=1e-6)
             assert a["phi_new"] <= a["phi"]
+
+
+def test_axpy_keeps_positions_in_the_predicate_domain():
+    from paper_2606_06511_amd import ttie
+
+    c = ttie.Context(0)
+    c.reserve(16, 16, 16)
+    x = torch.tensor([[0.0, 1.0, 0.0], [0.0, 0.0, 3.0]], dtype=torch.float64, device="cuda")
+    d = torch.tensor([[1e-250, 0.5, 2.0 ** -200], [-(2.0 ** -201), -1e-300, 1.0]], dtype=torch.float64,
+                     device="cuda")
+    out = c.axpy(x, 1.0, d).cpu().numpy()
+    np.testing.assert_array_equal(out, [[0.0, 1.5, 2.0 ** -200], [0.0, 0.0, 4.0]])
