@@ -213,12 +213,28 @@ __global__ void __launch_bounds__(kBlock) k_derivs(const double* __restrict__ x,
 #pragma unroll
       for (int k = 0; k < 6; ++k) vid[k] = r.vid[k];
     }
-    // count the six incidences; a vertex whose count leaves 0 joins the touched list
+    // count the six incidences (all six atomics in flight at once); a vertex whose count
+    // leaves 0 joins the touched list, the wave reserving its slots with one atomic
+    int32_t old[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) old[k] = active ? atomicAdd(&cnt[vid[k]], 1) : 1;
+    uint64_t fm[6];
+    uint32_t total = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const bool first = active && atomicAdd(&cnt[vid[k]], 1) == 0;
-      const uint32_t slot = wave_slot(first, &ctr->n_touched);
-      if (first) touched[slot] = vid[k];
+      fm[k] = __ballot(old[k] == 0);
+      total += (uint32_t)__popcll(fm[k]);
+    }
+    if (total) {
+      uint32_t wbase = 0;
+      if (__lane_id() == 0) wbase = atomicAdd(&ctr->n_touched, total);
+      wbase = __builtin_amdgcn_readfirstlane(wbase);
+      const uint64_t below = (1ull << __lane_id()) - 1ull;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (old[k] == 0) touched[wbase + (uint32_t)__popcll(fm[k] & below)] = vid[k];
+        wbase += (uint32_t)__popcll(fm[k]);
+      }
     }
   }
 }

@@ -171,8 +171,9 @@ __device__ __forceinline__ int orient2_sign(const V3<double>& a, const V3<double
 // disjoint interiors, the line through some edge of one leaves the other in its closed outer
 // half-plane).  Decided with exact 2D orientations after dropping the coordinate A's FP64
 // normal leans on most (or, if A has no area there, the next coordinate where it has some).
-// Returns PAIR_COPLANAR or PAIR_NONE.  Only the exact pass calls it: the fast pass defers
-// every pair whose sides are all zero (rare), so its kernel carries none of this code.
+// Returns PAIR_COPLANAR, PAIR_NONE, or PAIR_DEFER when kExact is off and a sign needs the
+// exact path.
+template <bool kExact>
 __device__ __forceinline__ int coplanar_kind(const Tri64& A, const Tri64& B, int& status) {
   const V3<double> a[3] = {selv(A, 0), selv(A, 1), selv(A, 2)};
   const V3<double> b[3] = {selv(B, 0), selv(B, 1), selv(B, 2)};
@@ -180,22 +181,31 @@ __device__ __forceinline__ int coplanar_kind(const Tri64& A, const Tri64& B, int
   const double nx = fabs(n.x), ny = fabs(n.y), nz = fabs(n.z);
   const int k0 = nx >= ny && nx >= nz ? 0 : (ny >= nz ? 1 : 2);
   int k = k0, sa = 0;
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
     k = (k0 + t) % 3;
-    sa = orient2_sign<true>(a[0], a[1], a[2], k, status);
+    sa = orient2_sign<kExact>(a[0], a[1], a[2], k, status);
     if (sa != 0) break;
   }
+  if (sa == 2) return PAIR_DEFER;
   if (sa == 0) return PAIR_NONE;  // A has no area
-  const int sb = orient2_sign<true>(b[0], b[1], b[2], k, status);
+  const int sb = orient2_sign<kExact>(b[0], b[1], b[2], k, status);
+  if (sb == 2) return PAIR_DEFER;
   if (sb == 0) return PAIR_NONE;  // B has no area
+  // (fully unrolled, so every vertex index is a constant and nothing lives in scratch)
+#pragma unroll
   for (int side = 0; side < 2; ++side) {
     const V3<double>* P = side == 0 ? a : b;
     const V3<double>* Q = side == 0 ? b : a;
     const int sp = side == 0 ? sa : sb;  // P's interior: edge orientations of sign sp
+#pragma unroll
     for (int e = 0; e < 3; ++e) {
       bool separates = true;
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
-        separates &= orient2_sign<true>(P[e], P[(e + 1) % 3], Q[j], k, status) * sp <= 0;
+        const int o = orient2_sign<kExact>(P[e], P[(e + 1) % 3], Q[j], k, status);
+        if (o == 2) return PAIR_DEFER;
+        separates &= o * sp <= 0;
       }
       if (separates) return PAIR_NONE;
     }
@@ -225,7 +235,7 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
     return out;
   }
   if ((sa[0] | sa[1] | sa[2]) == 0) {  // A lies in B's plane (or B has no area)
-    out.kind = kExact ? coplanar_kind(A, B, status) : PAIR_DEFER;
+    out.kind = coplanar_kind<kExact>(A, B, status);
     return out;
   }
   const Cut ca = make_cut(sa[0], sa[1], sa[2]);
