@@ -321,10 +321,10 @@ ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double
  * recorded events and returns, for stages 0..n_stages-1, the number of timed launches and
  * their summed duration in milliseconds since the previous read, then resets them. */
 enum {
-  TTIE_STAGE_BP_BOXES = 0,    /* triangle boxes, scene bounds, Morton codes */
-  TTIE_STAGE_BP_SORT = 1,     /* radix sort of the Morton codes */
-  TTIE_STAGE_BP_BUILD = 2,    /* radix-tree build and bottom-up refit */
-  TTIE_STAGE_BP_TRAVERSE = 3, /* tree self-traversal / brute-force enumeration, pair emission */
+  TTIE_STAGE_BP_BOXES = 0,    /* triangle boxes, scene bounds, Morton bucket ranks (spatial hash: cells) */
+  TTIE_STAGE_BP_SORT = 1,     /* counting sort by Morton bucket (spatial hash: by cell hash) */
+  TTIE_STAGE_BP_BUILD = 2,    /* leaf records and the implicit 4-ary tree's boxes, bottom up */
+  TTIE_STAGE_BP_TRAVERSE = 3, /* tree self-traversal / hash buckets / brute force, pair emission */
   TTIE_STAGE_SCREEN = 4,      /* per-candidate screening with FP64 filters */
   TTIE_STAGE_SCREEN_EXACT = 5,/* re-screening of the deferred candidates with exact predicates */
   TTIE_STAGE_DERIVS = 6,      /* per-hit interval gradients, energy, gradient, Hessian core */
