@@ -18,6 +18,11 @@
  *    (ttie_workspace_size / ttie_set_workspace).
  *  - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls enqueue work
  *    on it and return without waiting, except where a call says it synchronizes.
+ *  - A context's workspace carries state from call to call (the last evaluation's hits, the
+ *    broad phase's tree, counters kept zero between calls), so the calls on one context must
+ *    be ordered: one stream, or streams ordered by events.  Unordered calls on one context
+ *    race; work that runs concurrently takes one context each.  The library keeps no
+ *    global state, so separate contexts are independent (also on one device).
  *  - Positions x: n_verts x 3 float64, row-major (x0,y0,z0,x1,...).  Triangles: n_tris x 3
  *    int32 vertex indices.  Pairs: n_pairs x 2 int32 triangle indices (i, j), i != j; the
  *    degrees of freedom of a pair are ordered (u0,u1,u2,v0,v1,v2) with u = tris[i] (T_a)
