@@ -217,6 +217,17 @@ def extra_configs(args, np, torch, ttie, workloads):
         "alpha": [h["alpha"] for h in steps], "ms_per_newton_step": [round(h["ms"], 3) for h in steps],
         "total_ms": total_ms, "E_final_over_E0": hist[-1]["E"] / hist[0]["E"] if hist[0]["E"] else None,
         "pairs_per_s": sum(h["pairs"] for h in steps) / (sum(h["ms"] for h in steps) * 1e-3)}
+    # the same 20 steps matrix-free: the solve applies the PSD Hessian from the hit records
+    newton(model, xd, steps=1, matrix_free=True)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist_mf = newton(model, xd, steps=20, matrix_free=True)
+    torch.cuda.synchronize()
+    steps_mf = [h for h in hist_mf if "alpha" in h]
+    res["newton_4m"]["matrix_free"] = {
+        "E": [h["E"] for h in hist_mf], "total_ms": (time.perf_counter() - t0) * 1e3,
+        "ms_per_newton_step": [round(h["ms"], 3) for h in steps_mf],
+        "E_final_over_E0": hist_mf[-1]["E"] / hist_mf[0]["E"] if hist_mf[0]["E"] else None}
     del model
 
     # quasi-static coupling on the folded cloth: springs on the edges (rest = the folded state),
