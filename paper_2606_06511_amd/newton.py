@@ -2,9 +2,12 @@
 
 Per step: evaluate energy, gradient and PSD BSR Hessian at x; solve (H + mu I) d = -g with
 the library's device-resident Jacobi-PCG; take candidates with boxes swept from x to x + d
-(so every trial point is covered); Armijo backtracking on E along d.  The paper gives no
-parameters: mu = mu_rel * mean diagonal entry, 50 PCG iterations or relative residual 1e-6,
-c = 1e-4, halving up to 30 times.  All arithmetic runs in library kernels; this module only
+(so every trial point is covered); Armijo backtracking on E along d.  The accepted point lies
+on the swept segment, so the next step evaluates over the same swept list instead of running
+the broad phase again: its extra pairs have disjoint boxes (T = 0), and the assembly sums the
+hits in pair-key order, so the results are bit-identical to those over the exact list.  The
+paper gives no parameters: mu = mu_rel * mean diagonal entry, 50 PCG iterations or relative
+residual 1e-6, c = 1e-4, halving up to 30 times.  All arithmetic runs in library kernels; this module only
 sequences the calls and reads the scalars the line search needs.
 """
 
@@ -27,9 +30,13 @@ def newton(model: TTIE, x: torch.Tensor, steps: int = 20, pcg_iters: int = 50, p
     ctx = model.ctx
     x = x.detach().clone().contiguous()
     hist = []
+    swept = None  # the last step's swept candidates: they cover the accepted point
     for _ in range(steps):
         t0 = time.perf_counter()
-        out = model.evaluate(x, hessian=not matrix_free)
+        if swept is None:
+            out = model.evaluate(x, hessian=not matrix_free)
+        else:
+            out = model.evaluate(x, hessian=not matrix_free, pairs=swept[0], n_pairs=swept[1])
         E = out["energy"].item()
         rec = {"E": E, "pairs": int(model.n_pairs.item()), "hits": int(out["n_hits"].item())}
         if E == 0.0:
@@ -51,6 +58,7 @@ def newton(model: TTIE, x: torch.Tensor, steps: int = 20, pcg_iters: int = 50, p
                 break
             alpha *= beta
         x = xt
+        swept = (pairs, n)
         torch.cuda.synchronize()
         rec.update(alpha=alpha, pcg_iters=int(inf[0]), pcg_resid=inf[1], mu=inf[2],
                    ms=(time.perf_counter() - t0) * 1e3)

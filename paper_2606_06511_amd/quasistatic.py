@@ -9,8 +9,11 @@ with ``newton_iters`` Newton iterations: evaluate E and its gradient at x (FP64,
 from the broad phase), Phi, grad Phi and the springs' PSD Hessian K (with m I) in
 ``ttie_qs_eval``; solve (K + w H) d = -grad Phi by Jacobi-PCG with H applied from the hit
 records (``ttie_pcg_coupled``); take candidates from boxes swept from x to x + d; backtrack on
-Phi (Armijo).  Steps repeat until one starts intersection-free (E = 0).  All arithmetic runs in
-library kernels; this module sequences the calls and reads the scalars the line search needs.
+Phi (Armijo).  Steps repeat until one starts intersection-free (E = 0).  As in the Newton
+loop, an iterate evaluates over the swept candidates of the line search that produced it (a
+superset of its own candidates with bit-identical results), so the broad phase runs once per
+iteration.  All arithmetic runs in library kernels; this module sequences the calls and reads
+the scalars the line search needs.
 """
 
 from __future__ import annotations
@@ -44,15 +47,21 @@ class QuasiStatic:
             self._out = out
         return out
 
-    def step(self, x_prev, newton_iters=4, pcg_iters=50, pcg_tol=1e-6, armijo_c=1e-4, beta=0.5, max_halvings=30):
-        """One quasi-static step from x_prev; returns the new positions and per-iteration records."""
+    def step(self, x_prev, newton_iters=4, pcg_iters=50, pcg_tol=1e-6, armijo_c=1e-4, beta=0.5, max_halvings=30,
+             cand=None):
+        """One quasi-static step from x_prev; returns the new positions, per-iteration records
+        and the candidates that cover the new positions.  ``cand`` (pairs, n_pairs) may give
+        candidates covering x_prev (e.g. the previous step's); otherwise the broad phase runs."""
         model, ctx = self.model, self.ctx
         x_prev = x_prev.detach().contiguous()
         x = x_prev.clone()
         recs = []
         for _ in range(newton_iters):
             t0 = time.perf_counter()
-            out_t = model.evaluate(x, hessian=False)
+            if cand is None:
+                out_t = model.evaluate(x, hessian=False)
+            else:
+                out_t = model.evaluate(x, hessian=False, pairs=cand[0], n_pairs=cand[1])
             o = self.objective(x, x_prev, out_t)
             phi = o["phi"].item()
             d, info = ctx.pcg_coupled(self.row_ptr, self.col_idx, o["vals"], self.w, o["grad"], scale=-1.0, mu=0.0,
@@ -72,24 +81,29 @@ class QuasiStatic:
                 if h + 1 < max_halvings:
                     alpha *= beta
             x = xt
+            cand = (pairs, n)
             torch.cuda.synchronize()
             rec.update(alpha=alpha, phi_new=phit, ms=(time.perf_counter() - t0) * 1e3)
             recs.append(rec)
-        return x, recs
+        return x, recs, cand
 
     def run(self, x0, steps, **kw):
         """Steps from x0 until one starts with E = 0 or ``steps`` ran.  Returns the final
         positions and per-step records {E, hits, newton}."""
         x = x0.detach().clone().contiguous()
         hist = []
+        cand = None
         for _ in range(steps):
-            o = self.model.evaluate(x, hessian=False)
+            if cand is None:
+                o = self.model.evaluate(x, hessian=False)
+            else:
+                o = self.model.evaluate(x, hessian=False, pairs=cand[0], n_pairs=cand[1])
             E = o["energy"].item()
             if E == 0.0:
                 hist.append({"E": 0.0, "hits": 0, "newton": []})
                 return x, hist
             hits = int(o["n_hits"].item())
-            x, recs = self.step(x, **kw)
+            x, recs, cand = self.step(x, cand=cand, **kw)
             hist.append({"E": E, "hits": hits, "newton": recs})
         o = self.model.evaluate(x, hessian=False)
         hist.append({"E": o["energy"].item(), "hits": int(o["n_hits"].item()), "newton": []})
