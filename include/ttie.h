@@ -242,12 +242,17 @@ ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, c
  * preconditioner is the diagonal of H + mu I, x starts at 0, and the iteration stops after
  * max_iter steps or when |r| <= tol |scale b|.  b and x are n_rows x 3 in the precision of
  * vals; reductions accumulate in float64 in a fixed order.  info (device, 4 float64, may be
- * NULL) receives {iterations, |r| / |b|, mu, x . (scale b)}. */
+ * NULL) receives {iterations, |r| / |b|, mu, x . (scale b)}.
+ * The iteration runs over the rows that hold blocks: elsewhere H + mu I is mu I, and b must be
+ * 0 there (a gradient from ttie_eval is), so the solution is 0 there too; a non-zero b on such
+ * a row latches TTIE_ERR_INVALID_ARGUMENT.  Each iteration thus costs in proportion to the rows
+ * the hits touch, not to n_rows. */
 ttie_status ttie_pcg(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                      const void* b, double scale, void* x, double mu_rel, int max_iter, double tol, int precision,
                      double* info, void* stream);
 
-/* Matrix-free variant of ttie_pcg (the same iteration, mu and preconditioner): H is the PSD
+/* Matrix-free variant of ttie_pcg (the same iteration, mu and preconditioner, over the rows
+ * the last evaluation's hits touch; b must be 0 on the others): H is the PSD
  * Hessian of the last ttie_eval, applied from its per-hit records as the sum over hits of
  * J^T M J (J = [a^T; b^T], Eq. 4 with the evaluation's PSD core) without assembling the BSR
  * matrix; its diagonal comes from the same records.  n_rows must equal the last evaluation's
@@ -289,7 +294,8 @@ ttie_status ttie_qs_eval(ttie_ctx* ctx, int64_t n_verts, const int32_t* row_ptr,
                          const double* e_ttie, const double* g_ttie, double* phi, double* grad, double* vals,
                          void* stream);
 
-/* ttie_pcg_coupled: Jacobi-PCG (the iteration of ttie_pcg) on (K + w H + mu I) x = scale * b,
+/* ttie_pcg_coupled: Jacobi-PCG (the iteration of ttie_pcg, over the rows where K holds blocks
+ * or the hits touch; b must be 0 on the others) on (K + w H + mu I) x = scale * b,
  * with K a PSD 3x3-block CSR matrix in float64 (columns sorted per row, e.g. from
  * ttie_qs_eval) and H the PSD Hessian of the last ttie_eval, which must be TTIE_FP64 and
  * have n_verts = n_rows.  mu >= 0 is absolute.  info as for ttie_pcg (info[2] = mu). */

@@ -67,6 +67,9 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.touched = take(6 * H * 4);
   L.inc2 = take(6 * H * sizeof(Incidence));
   L.pcg_vec = take(5 * 3 * (size_t)lim.max_verts * 8);
+  L.pcg_flag = take(V * 4);  // active-row flags, their scan and the active-row list
+  L.pcg_pos = take(V * 4);
+  L.pcg_act = take(V * 4);
   L.pcg_part = take(5 * 256 * 4 * 8);
   L.pcg_state = take(64);
   L.total = o;

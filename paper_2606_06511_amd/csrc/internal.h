@@ -93,7 +93,7 @@ struct Layout {
   size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
       scan_tmp_bytes;
   size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
-      bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state;
+      bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state, pcg_flag, pcg_pos, pcg_act;
   size_t total;
 };
 

@@ -7,6 +7,13 @@
 //   k_pcg_matvec  q = (H + mu I) p, partials of p.q
 //   k_pcg_update  alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials r.z, r.r
 //   k_pcg_dir     beta = r.z(new) / r.z(old); p = z + beta p; convergence test
+//
+// Active rows.  H is zero outside the rows that hold blocks (those the hits touch), so there
+// (H + mu I) is mu I; with b = 0 on those rows the residual, the search direction and the
+// solution stay exactly 0 on them for the whole iteration.  The solve therefore runs over the
+// list of active rows only (built once per solve, in row order, so the sums keep a fixed
+// order), and b must vanish elsewhere: a Newton gradient does.  On a mesh of millions of
+// vertices with tens of thousands touched this makes each iteration a few microseconds.
 #include "internal.h"
 
 namespace ttie {
@@ -62,13 +69,75 @@ __device__ __forceinline__ int64_t diag_block(const int32_t* row_ptr, const int3
   return -1;
 }
 
+
+// ---- the active rows ------------------------------------------------------------------------
+// flag[v] = row v holds blocks (row_ptr) or incidences (off); x, p = 0 on every row; a non-zero
+// b on an inactive row latches STATUS_INVALID.  Row n's flag is 0 (the scan's total).
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_diag(int64_t n, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kPB) k_pcg_flags(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ off, const S* __restrict__ b,
+                                                   S* __restrict__ x, S* __restrict__ p, int32_t* __restrict__ flag,
+                                                   Counters* ctr) {
+  for (int64_t v = (int64_t)blockIdx.x * kPB + threadIdx.x; v <= n; v += (int64_t)gridDim.x * kPB) {
+    if (v == n) {
+      flag[n] = 0;
+      continue;
+    }
+    const bool act = (row_ptr && row_ptr[v + 1] > row_ptr[v]) || (off && off[v + 1] > off[v]);
+    flag[v] = act ? 1 : 0;
+    bool nz = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[3 * v + c] = (S)0.0;
+      p[3 * v + c] = (S)0.0;
+      nz |= (double)b[3 * v + c] != 0.0;
+    }
+    if (!act && nz) atomicCAS(&ctr->status, 0, STATUS_INVALID);
+  }
+}
+
+__global__ void __launch_bounds__(kPB) k_pcg_compact(int64_t n, const int32_t* __restrict__ flag,
+                                                     const int32_t* __restrict__ pos, int32_t* __restrict__ act) {
+  for (int64_t v = (int64_t)blockIdx.x * kPB + threadIdx.x; v < n; v += (int64_t)gridDim.x * kPB)
+    if (flag[v]) act[pos[v]] = (int32_t)v;
+}
+
+// the list of active rows and its device count (pos[n])
+struct Active {
+  const int32_t* rows;
+  const int32_t* count;
+};
+
+template <class S>
+static hipError_t pcg_active(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* off, const S* b, S* x, S* p,
+                             Active& a, hipStream_t s) {
+  const Layout& L = c->L;
+  int32_t* flag = wsp<int32_t>(c, L.pcg_flag);
+  int32_t* pos = wsp<int32_t>(c, L.pcg_pos);
+  int32_t* act = wsp<int32_t>(c, L.pcg_act);
+  Counters* ctr = wsp<Counters>(c, L.counters);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 1 + kPB - 1) / kPB));
+  k_pcg_flags<S><<<g, kPB, 0, s>>>(n, row_ptr, off, b, x, p, flag, ctr);
+  hipError_t e = launch_scan_i32(c, flag, pos, n + 1, s);
+  if (e != hipSuccess) return e;
+  k_pcg_compact<<<g, kPB, 0, s>>>(n, flag, pos, act);
+  a.rows = act;
+  a.count = pos + n;
+  return hipGetLastError();
+}
+
+#define PCG_ROWS(j, i, a)                                                                          \
+  const int64_t na_ = *(a).count;                                                                  \
+  for (int64_t j = (int64_t)blockIdx.x * kPB + threadIdx.x; j < na_; j += (int64_t)gridDim.x * kPB)
+
+template <class S>
+__global__ void __launch_bounds__(kPB) k_pcg_diag(Active a, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_idx, const S* __restrict__ vals,
                                                   double* __restrict__ part) {
   __shared__ double red[kPB];
   double sum = 0.0, cnt = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * kPB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t r = a.rows[j];
     const int64_t d = diag_block(row_ptr, col_idx, r);
     if (d >= 0) {
       sum += (double)vals[9 * d] + (double)vals[9 * d + 4] + (double)vals[9 * d + 8];
@@ -79,18 +148,19 @@ __global__ void __launch_bounds__(kPB) k_pcg_diag(int64_t n, const int32_t* __re
 }
 
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_setup(int64_t n, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kPB) k_pcg_setup(Active a, const int32_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col_idx, const S* __restrict__ vals,
-                                                   const S* __restrict__ b, double scale, S* __restrict__ x,
-                                                   S* __restrict__ r, S* __restrict__ z, S* __restrict__ p,
-                                                   S* __restrict__ dinv, double mu_rel, const double* __restrict__ pdiag,
+                                                   const S* __restrict__ b, double scale, S* __restrict__ r,
+                                                   S* __restrict__ z, S* __restrict__ p, S* __restrict__ dinv,
+                                                   double mu_rel, const double* __restrict__ pdiag,
                                                    double* __restrict__ pout, PcgState* st) {
   __shared__ double red[kPB];
   const double dsum = grid_sum(pdiag, 0, red), dcnt = grid_sum(pdiag, 1, red);
   // mu relative to the mean diagonal entry of the rows holding blocks (1 for an empty matrix)
   const double mu = mu_rel * (dcnt > 0.0 ? dsum / dcnt : 1.0);
   double rz = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     const int64_t d = diag_block(row_ptr, col_idx, i);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -99,7 +169,6 @@ __global__ void __launch_bounds__(kPB) k_pcg_setup(int64_t n, const int32_t* __r
       const double ri = scale * (double)b[3 * i + c];
       const double zi = di * ri;
       dinv[3 * i + c] = (S)di;
-      x[3 * i + c] = (S)0.0;
       r[3 * i + c] = (S)ri;
       z[3 * i + c] = (S)zi;
       p[3 * i + c] = (S)zi;
@@ -116,7 +185,7 @@ __global__ void __launch_bounds__(kPB) k_pcg_setup(int64_t n, const int32_t* __r
 }
 
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_matvec(int64_t n, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kPB) k_pcg_matvec(Active a, const int32_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col_idx, const S* __restrict__ vals,
                                                     const S* __restrict__ p, S* __restrict__ q,
                                                     double* __restrict__ pq_part, const PcgState* st) {
@@ -124,27 +193,28 @@ __global__ void __launch_bounds__(kPB) k_pcg_matvec(int64_t n, const int32_t* __
   __shared__ double red[kPB];
   const double mu = st->mu;
   double pq = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     double acc[3] = {mu * (double)p[3 * i], mu * (double)p[3 * i + 1], mu * (double)p[3 * i + 2]};
     for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
       const int64_t c = col_idx[k];
       const double p0 = p[3 * c], p1 = p[3 * c + 1], p2 = p[3 * c + 2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        acc[a] += (double)vals[9 * (int64_t)k + 3 * a] * p0 + (double)vals[9 * (int64_t)k + 3 * a + 1] * p1 +
-                  (double)vals[9 * (int64_t)k + 3 * a + 2] * p2;
+      for (int e = 0; e < 3; ++e)
+        acc[e] += (double)vals[9 * (int64_t)k + 3 * e] * p0 + (double)vals[9 * (int64_t)k + 3 * e + 1] * p1 +
+                  (double)vals[9 * (int64_t)k + 3 * e + 2] * p2;
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      q[3 * i + a] = (S)acc[a];
-      pq += (double)p[3 * i + a] * acc[a];
+    for (int e = 0; e < 3; ++e) {
+      q[3 * i + e] = (S)acc[e];
+      pq += (double)p[3 * i + e] * acc[e];
     }
   }
   block_partials(pq, 0.0, pq_part, red);
 }
 
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_update(int64_t n, S* __restrict__ x, S* __restrict__ r,
+__global__ void __launch_bounds__(kPB) k_pcg_update(Active a, S* __restrict__ x, S* __restrict__ r,
                                                     S* __restrict__ z, const S* __restrict__ p,
                                                     const S* __restrict__ q, const S* __restrict__ dinv,
                                                     const double* __restrict__ rz_part, const double* __restrict__ pq_part,
@@ -158,20 +228,25 @@ __global__ void __launch_bounds__(kPB) k_pcg_update(int64_t n, S* __restrict__ x
   }
   const double alpha = rz / pq;
   double rzn = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * kPB) {
-    x[i] = (S)((double)x[i] + alpha * (double)p[i]);
-    const double ri = (double)r[i] - alpha * (double)q[i];
-    const double zi = (double)dinv[i] * ri;
-    r[i] = (S)ri;
-    z[i] = (S)zi;
-    rzn += ri * zi;
-    rr += ri * ri;
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t k = 3 * i + c;
+      x[k] = (S)((double)x[k] + alpha * (double)p[k]);
+      const double ri = (double)r[k] - alpha * (double)q[k];
+      const double zi = (double)dinv[k] * ri;
+      r[k] = (S)ri;
+      z[k] = (S)zi;
+      rzn += ri * zi;
+      rr += ri * ri;
+    }
   }
   block_partials(rzn, rr, out_part, red);
 }
 
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_dir(int64_t n, S* __restrict__ p, const S* __restrict__ z,
+__global__ void __launch_bounds__(kPB) k_pcg_dir(Active a, S* __restrict__ p, const S* __restrict__ z,
                                                  const double* __restrict__ rz_old_part,
                                                  const double* __restrict__ rz_new_part,
                                                  const double* __restrict__ setup_part, double tol, int iter,
@@ -189,8 +264,11 @@ __global__ void __launch_bounds__(kPB) k_pcg_dir(int64_t n, S* __restrict__ p, c
   }
   if (conv) return;
   const double beta = rzo > 0.0 ? rzn / rzo : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * kPB)
-    p[i] = (S)((double)z[i] + beta * (double)p[i]);
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[3 * i + c] = (S)((double)z[3 * i + c] + beta * (double)p[3 * i + c]);
+  }
 }
 
 // ---- matrix-free variant: H applied from the last evaluation's per-hit records -------------
@@ -198,16 +276,17 @@ __global__ void __launch_bounds__(kPB) k_pcg_dir(int64_t n, S* __restrict__ p, c
 // evaluation.  Rows gather their incidences in pair-key order (the sorted lists the
 // evaluation leaves behind), so the products are deterministic.
 
-// raw diagonal of H per dof into dg (0 for untouched rows), partials of (sum, count) over the
-// rows holding hits, as the BSR variant takes them over the rows holding blocks
+// raw diagonal of H per dof into dg, partials of (sum, count) over the active rows, as the BSR
+// variant takes them over the rows holding blocks
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_diag_mf(int64_t n, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kPB) k_pcg_diag_mf(Active a, const int32_t* __restrict__ off,
                                                      const Incidence* __restrict__ inc,
                                                      const AsmRec<S>* __restrict__ recs, S* __restrict__ dg,
                                                      double* __restrict__ part) {
   __shared__ double red[kPB];
   double sum = 0.0, cnt = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     const int32_t b = off[i], e = off[i + 1];
     double d[3] = {0.0, 0.0, 0.0};
     for (int32_t k = b; k < e; ++k) {
@@ -235,7 +314,7 @@ __global__ void __launch_bounds__(kPB) k_pcg_diag_mf(int64_t n, const int32_t* _
 
 // as k_pcg_setup, with the diagonal from dinv (holding the raw diagonal on entry)
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_setup_mf(int64_t n, const S* __restrict__ b, double scale, S* __restrict__ x,
+__global__ void __launch_bounds__(kPB) k_pcg_setup_mf(Active a, const S* __restrict__ b, double scale,
                                                       S* __restrict__ r, S* __restrict__ z, S* __restrict__ p,
                                                       S* __restrict__ dinv, double mu_rel,
                                                       const double* __restrict__ pdiag, double* __restrict__ pout,
@@ -244,18 +323,22 @@ __global__ void __launch_bounds__(kPB) k_pcg_setup_mf(int64_t n, const S* __rest
   const double dsum = grid_sum(pdiag, 0, red), dcnt = grid_sum(pdiag, 1, red);
   const double mu = mu_rel * (dcnt > 0.0 ? dsum / dcnt : 1.0);
   double rz = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * kPB) {
-    const double dg = (double)dinv[i] + mu;
-    const double di = dg > 0.0 ? 1.0 / dg : 1.0;
-    const double ri = scale * (double)b[i];
-    const double zi = di * ri;
-    dinv[i] = (S)di;
-    x[i] = (S)0.0;
-    r[i] = (S)ri;
-    z[i] = (S)zi;
-    p[i] = (S)zi;
-    rz += ri * zi;
-    bb += ri * ri;
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t k = 3 * i + c;
+      const double dg = (double)dinv[k] + mu;
+      const double di = dg > 0.0 ? 1.0 / dg : 1.0;
+      const double ri = scale * (double)b[k];
+      const double zi = di * ri;
+      dinv[k] = (S)di;
+      r[k] = (S)ri;
+      z[k] = (S)zi;
+      p[k] = (S)zi;
+      rz += ri * zi;
+      bb += ri * ri;
+    }
   }
   block_partials(rz, bb, pout, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -291,7 +374,7 @@ __global__ void __launch_bounds__(kPB) k_pcg_hits_mf(const AsmRec<S>* __restrict
 
 // q = (H + mu I) p from the per-hit products, row by row in pair-key order; partials of p.q
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_rows_mf(int64_t n, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kPB) k_pcg_rows_mf(Active a, const int32_t* __restrict__ off,
                                                      const Incidence* __restrict__ inc, const S* __restrict__ hv,
                                                      const S* __restrict__ p, S* __restrict__ q,
                                                      double* __restrict__ pq_part, const PcgState* st) {
@@ -299,7 +382,8 @@ __global__ void __launch_bounds__(kPB) k_pcg_rows_mf(int64_t n, const int32_t* _
   __shared__ double red[kPB];
   const double mu = st->mu;
   double pq = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     double acc[3] = {mu * (double)p[3 * i], mu * (double)p[3 * i + 1], mu * (double)p[3 * i + 2]};
     for (int32_t k = off[i]; k < off[i + 1]; ++k) {
       const Incidence in = inc[k];
@@ -318,17 +402,17 @@ __global__ void __launch_bounds__(kPB) k_pcg_rows_mf(int64_t n, const int32_t* _
 // ---- coupled variant: A = K + w H + mu I, K a caller's PSD BSR matrix (FP64) --------------
 // (the quasi-static objective's elastic Hessian), H applied from the hit records as above.
 // Jacobi diagonal: K's diagonal entries + w times H's + mu.
-__global__ void __launch_bounds__(kPB) k_pcg_setup_cp(int64_t n, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kPB) k_pcg_setup_cp(Active a, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col_idx,
                                                       const double* __restrict__ vals, double w, double mu,
                                                       const double* __restrict__ b, double scale,
-                                                      double* __restrict__ x, double* __restrict__ r,
-                                                      double* __restrict__ z, double* __restrict__ p,
-                                                      double* __restrict__ dinv, double* __restrict__ pout,
-                                                      PcgState* st) {
+                                                      double* __restrict__ r, double* __restrict__ z,
+                                                      double* __restrict__ p, double* __restrict__ dinv,
+                                                      double* __restrict__ pout, PcgState* st) {
   __shared__ double red[kPB];
   double rz = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     const int64_t d = diag_block(row_ptr, col_idx, i);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -337,7 +421,6 @@ __global__ void __launch_bounds__(kPB) k_pcg_setup_cp(int64_t n, const int32_t* 
       const double ri = scale * b[3 * i + c];
       const double zi = di * ri;
       dinv[3 * i + c] = di;
-      x[3 * i + c] = 0.0;
       r[3 * i + c] = ri;
       z[3 * i + c] = zi;
       p[3 * i + c] = zi;
@@ -355,7 +438,7 @@ __global__ void __launch_bounds__(kPB) k_pcg_setup_cp(int64_t n, const int32_t* 
 
 // q = (K + w H + mu I) p: K's row times p, plus w times the hit products gathered in pair-key
 // order; partials of p.q
-__global__ void __launch_bounds__(kPB) k_pcg_rows_cp(int64_t n, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kPB) k_pcg_rows_cp(Active a, const int32_t* __restrict__ off,
                                                      const Incidence* __restrict__ inc, const double* __restrict__ hv,
                                                      const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col_idx,
@@ -366,7 +449,8 @@ __global__ void __launch_bounds__(kPB) k_pcg_rows_cp(int64_t n, const int32_t* _
   __shared__ double red[kPB];
   const double mu = st->mu;
   double pq = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPB) {
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
     double hs[3] = {0.0, 0.0, 0.0};
     for (int32_t k = off[i]; k < off[i + 1]; ++k) {
       const Incidence in = inc[k];
@@ -378,26 +462,29 @@ __global__ void __launch_bounds__(kPB) k_pcg_rows_cp(int64_t n, const int32_t* _
       const int64_t c = col_idx[k];
       const double p0 = p[3 * c], p1 = p[3 * c + 1], p2 = p[3 * c + 2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        acc[a] += vals[9 * (int64_t)k + 3 * a] * p0 + vals[9 * (int64_t)k + 3 * a + 1] * p1 +
-                  vals[9 * (int64_t)k + 3 * a + 2] * p2;
+      for (int e = 0; e < 3; ++e)
+        acc[e] += vals[9 * (int64_t)k + 3 * e] * p0 + vals[9 * (int64_t)k + 3 * e + 1] * p1 +
+                  vals[9 * (int64_t)k + 3 * e + 2] * p2;
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      q[3 * i + a] = acc[a];
-      pq += p[3 * i + a] * acc[a];
+    for (int e = 0; e < 3; ++e) {
+      q[3 * i + e] = acc[e];
+      pq += p[3 * i + e] * acc[e];
     }
   }
   block_partials(pq, 0.0, pq_part, red);
 }
 
 template <class S>
-__global__ void __launch_bounds__(kPB) k_pcg_xb(int64_t n, const S* __restrict__ x, const S* __restrict__ b,
+__global__ void __launch_bounds__(kPB) k_pcg_xb(Active a, const S* __restrict__ x, const S* __restrict__ b,
                                                 double scale, double* __restrict__ part) {
   __shared__ double red[kPB];
   double xb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * kPB)
-    xb += (double)x[i] * scale * (double)b[i];
+  PCG_ROWS(j, i, a) {
+    const int64_t i = a.rows[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xb += (double)x[3 * i + c] * scale * (double)b[3 * i + c];
+  }
   block_partials(xb, 0.0, part, red);
 }
 
@@ -421,32 +508,62 @@ __global__ void __launch_bounds__(kPB) k_axpy(int64_t n, double alpha, const dou
   }
 }
 
+
+// the vectors and partials of a solve, carved from the workspace
+template <class S>
+struct PcgBufs {
+  S *r, *z, *p, *q, *dinv;
+  double *pdiag, *pset, *pq, *pA, *pB;
+  PcgState* st;
+  PcgBufs(Ctx* c) {
+    const Layout& L = c->L;
+    S* base = wsp<S>(c, L.pcg_vec);
+    const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
+    r = base;
+    z = base + m3;
+    p = base + 2 * m3;
+    q = base + 3 * m3;
+    dinv = base + 4 * m3;
+    double* part = wsp<double>(c, L.pcg_part);  // 5 partial arrays of kPB x 4
+    pdiag = part;
+    pset = part + 4 * kPB;
+    pq = part + 8 * kPB;
+    pA = part + 12 * kPB;
+    pB = part + 16 * kPB;
+    st = wsp<PcgState>(c, L.pcg_state);
+  }
+};
+
+template <class S>
+static void pcg_finish(Ctx* c, const Active& a, const PcgBufs<S>& B, const S* x, const S* b, double scale,
+                       double* info, hipStream_t s) {
+  if (info) {
+    k_pcg_xb<S><<<kPB, kPB, 0, s>>>(a, x, b, scale, B.pq);
+    k_pcg_info<<<1, kPB, 0, s>>>(B.pq, B.st, info);
+  }
+}
+
 template <class S>
 static hipError_t pcg_impl(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const S* vals,
                            const S* b, double scale, S* x, double mu_rel, int max_iter, double tol, double* info,
                            hipStream_t s) {
-  const Layout& L = c->L;
-  S* base = wsp<S>(c, L.pcg_vec);
-  const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
-  S *r = base, *z = base + m3, *p = base + 2 * m3, *q = base + 3 * m3, *dinv = base + 4 * m3;
-  double* part = wsp<double>(c, L.pcg_part);  // 5 partial arrays of kPB x 4
-  double *pdiag = part, *pset = part + 4 * kPB, *pq = part + 8 * kPB, *pA = part + 12 * kPB, *pB = part + 16 * kPB;
-  PcgState* st = wsp<PcgState>(c, L.pcg_state);
+  PcgBufs<S> B(c);
   stage_begin(c, TTIE_STAGE_PCG, s);
-  k_pcg_diag<S><<<kPB, kPB, 0, s>>>(n, row_ptr, col_idx, vals, pdiag);
-  k_pcg_setup<S><<<kPB, kPB, 0, s>>>(n, row_ptr, col_idx, vals, b, scale, x, r, z, p, dinv, mu_rel, pdiag, pset, st);
-  const double* rz_old = pset;
+  Active a;
+  hipError_t e = pcg_active<S>(c, n, row_ptr, nullptr, b, x, B.p, a, s);
+  if (e != hipSuccess) return e;
+  k_pcg_diag<S><<<kPB, kPB, 0, s>>>(a, row_ptr, col_idx, vals, B.pdiag);
+  k_pcg_setup<S><<<kPB, kPB, 0, s>>>(a, row_ptr, col_idx, vals, b, scale, B.r, B.z, B.p, B.dinv, mu_rel, B.pdiag,
+                                     B.pset, B.st);
+  const double* rz_old = B.pset;
   for (int it = 0; it < max_iter; ++it) {
-    double* rz_new = (it % 2 == 0) ? pA : pB;
-    k_pcg_matvec<S><<<kPB, kPB, 0, s>>>(n, row_ptr, col_idx, vals, p, q, pq, st);
-    k_pcg_update<S><<<kPB, kPB, 0, s>>>(n, x, r, z, p, q, dinv, rz_old, pq, rz_new, st);
-    k_pcg_dir<S><<<kPB, kPB, 0, s>>>(n, p, z, rz_old, rz_new, pset, tol, it, st);
+    double* rz_new = (it % 2 == 0) ? B.pA : B.pB;
+    k_pcg_matvec<S><<<kPB, kPB, 0, s>>>(a, row_ptr, col_idx, vals, B.p, B.q, B.pq, B.st);
+    k_pcg_update<S><<<kPB, kPB, 0, s>>>(a, x, B.r, B.z, B.p, B.q, B.dinv, rz_old, B.pq, rz_new, B.st);
+    k_pcg_dir<S><<<kPB, kPB, 0, s>>>(a, B.p, B.z, rz_old, rz_new, B.pset, tol, it, B.st);
     rz_old = rz_new;
   }
-  if (info) {
-    k_pcg_xb<S><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
-    k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
-  }
+  pcg_finish<S>(c, a, B, x, b, scale, info, s);
   stage_end(c, TTIE_STAGE_PCG, s);
   return hipGetLastError();
 }
@@ -455,12 +572,7 @@ template <class S>
 static hipError_t pcg_mf_impl(Ctx* c, int64_t n, const S* b, double scale, S* x, double mu_rel, int max_iter, double tol,
                               double* info, hipStream_t s) {
   const Layout& L = c->L;
-  S* base = wsp<S>(c, L.pcg_vec);
-  const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
-  S *r = base, *z = base + m3, *p = base + 2 * m3, *q = base + 3 * m3, *dinv = base + 4 * m3;
-  double* part = wsp<double>(c, L.pcg_part);
-  double *pdiag = part, *pset = part + 4 * kPB, *pq = part + 8 * kPB, *pA = part + 12 * kPB, *pB = part + 16 * kPB;
-  PcgState* st = wsp<PcgState>(c, L.pcg_state);
+  PcgBufs<S> B(c);
   const AsmRec<S>* recs = wsp<AsmRec<S>>(c, L.recs);
   const int32_t* off = wsp<int32_t>(c, L.off);
   const Incidence* inc = wsp<Incidence>(c, L.inc2);
@@ -469,21 +581,21 @@ static hipError_t pcg_mf_impl(Ctx* c, int64_t n, const S* b, double scale, S* x,
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (c->lim.max_hits + kPB - 1) / kPB));
   stage_begin(c, TTIE_STAGE_PCG, s);
-  k_pcg_diag_mf<S><<<kPB, kPB, 0, s>>>(n, off, inc, recs, dinv, pdiag);
-  k_pcg_setup_mf<S><<<kPB, kPB, 0, s>>>(n, b, scale, x, r, z, p, dinv, mu_rel, pdiag, pset, st);
-  const double* rz_old = pset;
+  Active a;
+  hipError_t e = pcg_active<S>(c, n, nullptr, off, b, x, B.p, a, s);
+  if (e != hipSuccess) return e;
+  k_pcg_diag_mf<S><<<kPB, kPB, 0, s>>>(a, off, inc, recs, B.dinv, B.pdiag);
+  k_pcg_setup_mf<S><<<kPB, kPB, 0, s>>>(a, b, scale, B.r, B.z, B.p, B.dinv, mu_rel, B.pdiag, B.pset, B.st);
+  const double* rz_old = B.pset;
   for (int it = 0; it < max_iter; ++it) {
-    double* rz_new = (it % 2 == 0) ? pA : pB;
-    k_pcg_hits_mf<S><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, p, hv, st);
-    k_pcg_rows_mf<S><<<kPB, kPB, 0, s>>>(n, off, inc, hv, p, q, pq, st);
-    k_pcg_update<S><<<kPB, kPB, 0, s>>>(n, x, r, z, p, q, dinv, rz_old, pq, rz_new, st);
-    k_pcg_dir<S><<<kPB, kPB, 0, s>>>(n, p, z, rz_old, rz_new, pset, tol, it, st);
+    double* rz_new = (it % 2 == 0) ? B.pA : B.pB;
+    k_pcg_hits_mf<S><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, B.p, hv, B.st);
+    k_pcg_rows_mf<S><<<kPB, kPB, 0, s>>>(a, off, inc, hv, B.p, B.q, B.pq, B.st);
+    k_pcg_update<S><<<kPB, kPB, 0, s>>>(a, x, B.r, B.z, B.p, B.q, B.dinv, rz_old, B.pq, rz_new, B.st);
+    k_pcg_dir<S><<<kPB, kPB, 0, s>>>(a, B.p, B.z, rz_old, rz_new, B.pset, tol, it, B.st);
     rz_old = rz_new;
   }
-  if (info) {
-    k_pcg_xb<S><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
-    k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
-  }
+  pcg_finish<S>(c, a, B, x, b, scale, info, s);
   stage_end(c, TTIE_STAGE_PCG, s);
   return hipGetLastError();
 }
@@ -492,12 +604,7 @@ hipError_t launch_pcg_coupled(Ctx* c, int64_t n, const int32_t* row_ptr, const i
                               double w, const double* b, double scale, double* x, double mu, int max_iter, double tol,
                               double* info, hipStream_t s) {
   const Layout& L = c->L;
-  double* base = wsp<double>(c, L.pcg_vec);
-  const int64_t m3 = 3 * (int64_t)c->lim.max_verts;
-  double *r = base, *z = base + m3, *p = base + 2 * m3, *q = base + 3 * m3, *dinv = base + 4 * m3;
-  double* part = wsp<double>(c, L.pcg_part);
-  double *pdiag = part, *pset = part + 4 * kPB, *pq = part + 8 * kPB, *pA = part + 12 * kPB, *pB = part + 16 * kPB;
-  PcgState* st = wsp<PcgState>(c, L.pcg_state);
+  PcgBufs<double> B(c);
   const AsmRec<double>* recs = wsp<AsmRec<double>>(c, L.recs);
   const int32_t* off = wsp<int32_t>(c, L.off);
   const Incidence* inc = wsp<Incidence>(c, L.inc2);
@@ -506,21 +613,21 @@ hipError_t launch_pcg_coupled(Ctx* c, int64_t n, const int32_t* row_ptr, const i
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (c->lim.max_hits + kPB - 1) / kPB));
   stage_begin(c, TTIE_STAGE_PCG, s);
-  k_pcg_diag_mf<double><<<kPB, kPB, 0, s>>>(n, off, inc, recs, dinv, pdiag);  // raw diagonal of H into dinv
-  k_pcg_setup_cp<<<kPB, kPB, 0, s>>>(n, row_ptr, col_idx, vals, w, mu, b, scale, x, r, z, p, dinv, pset, st);
-  const double* rz_old = pset;
+  Active a;
+  hipError_t e = pcg_active<double>(c, n, row_ptr, off, b, x, B.p, a, s);
+  if (e != hipSuccess) return e;
+  k_pcg_diag_mf<double><<<kPB, kPB, 0, s>>>(a, off, inc, recs, B.dinv, B.pdiag);  // raw diagonal of H into dinv
+  k_pcg_setup_cp<<<kPB, kPB, 0, s>>>(a, row_ptr, col_idx, vals, w, mu, b, scale, B.r, B.z, B.p, B.dinv, B.pset, B.st);
+  const double* rz_old = B.pset;
   for (int it = 0; it < max_iter; ++it) {
-    double* rz_new = (it % 2 == 0) ? pA : pB;
-    k_pcg_hits_mf<double><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, p, hv, st);
-    k_pcg_rows_cp<<<kPB, kPB, 0, s>>>(n, off, inc, hv, row_ptr, col_idx, vals, w, p, q, pq, st);
-    k_pcg_update<double><<<kPB, kPB, 0, s>>>(n, x, r, z, p, q, dinv, rz_old, pq, rz_new, st);
-    k_pcg_dir<double><<<kPB, kPB, 0, s>>>(n, p, z, rz_old, rz_new, pset, tol, it, st);
+    double* rz_new = (it % 2 == 0) ? B.pA : B.pB;
+    k_pcg_hits_mf<double><<<gh, kPB, 0, s>>>(recs, ctr, max_hits, B.p, hv, B.st);
+    k_pcg_rows_cp<<<kPB, kPB, 0, s>>>(a, off, inc, hv, row_ptr, col_idx, vals, w, B.p, B.q, B.pq, B.st);
+    k_pcg_update<double><<<kPB, kPB, 0, s>>>(a, x, B.r, B.z, B.p, B.q, B.dinv, rz_old, B.pq, rz_new, B.st);
+    k_pcg_dir<double><<<kPB, kPB, 0, s>>>(a, B.p, B.z, rz_old, rz_new, B.pset, tol, it, B.st);
     rz_old = rz_new;
   }
-  if (info) {
-    k_pcg_xb<double><<<kPB, kPB, 0, s>>>(n, x, b, scale, pq);
-    k_pcg_info<<<1, kPB, 0, s>>>(pq, st, info);
-  }
+  pcg_finish<double>(c, a, B, x, b, scale, info, s);
   stage_end(c, TTIE_STAGE_PCG, s);
   return hipGetLastError();
 }

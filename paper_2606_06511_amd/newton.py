@@ -6,7 +6,8 @@ the library's device-resident Jacobi-PCG; take candidates with boxes swept from 
 on the swept segment, so the next step evaluates over the same swept list instead of running
 the broad phase again: its extra pairs have disjoint boxes (T = 0), and the assembly sums the
 hits in pair-key order, so the results are bit-identical to those over the exact list.  The
-paper gives no parameters: mu = mu_rel * mean diagonal entry, 50 PCG iterations or relative
+line search evaluates every trial point with the Hessian, and the accepted one (always the last
+evaluated) is the next step's evaluation.  The paper gives no parameters: mu = mu_rel * mean diagonal entry, 50 PCG iterations or relative
 residual 1e-6, c = 1e-4, halving up to 30 times.  All arithmetic runs in library kernels; this module only
 sequences the calls and reads the scalars the line search needs.
 """
@@ -30,13 +31,11 @@ def newton(model: TTIE, x: torch.Tensor, steps: int = 20, pcg_iters: int = 50, p
     ctx = model.ctx
     x = x.detach().clone().contiguous()
     hist = []
-    swept = None  # the last step's swept candidates: they cover the accepted point
+    out = None  # the evaluation at x: the first step's, then the accepted trial point's
     for _ in range(steps):
         t0 = time.perf_counter()
-        if swept is None:
+        if out is None:
             out = model.evaluate(x, hessian=not matrix_free)
-        else:
-            out = model.evaluate(x, hessian=not matrix_free, pairs=swept[0], n_pairs=swept[1])
         E = out["energy"].item()
         rec = {"E": E, "pairs": int(model.n_pairs.item()), "hits": int(out["n_hits"].item())}
         if E == 0.0:
@@ -53,12 +52,12 @@ def newton(model: TTIE, x: torch.Tensor, steps: int = 20, pcg_iters: int = 50, p
         alpha = 1.0
         for h in range(max_halvings):
             xt = ctx.axpy(x, alpha, d)
-            Et = model.evaluate(xt, hessian=False, pairs=pairs, n_pairs=n)["energy"].item()
+            out = model.evaluate(xt, hessian=not matrix_free, pairs=pairs, n_pairs=n)
+            Et = out["energy"].item()
             if Et <= E + armijo_c * alpha * gd or h + 1 == max_halvings:
                 break
             alpha *= beta
         x = xt
-        swept = (pairs, n)
         torch.cuda.synchronize()
         rec.update(alpha=alpha, pcg_iters=int(inf[0]), pcg_resid=inf[1], mu=inf[2],
                    ms=(time.perf_counter() - t0) * 1e3)

@@ -12,7 +12,7 @@ records (``ttie_pcg_coupled``); take candidates from boxes swept from x to x + d
 Phi (Armijo).  Steps repeat until one starts intersection-free (E = 0).  As in the Newton
 loop, an iterate evaluates over the swept candidates of the line search that produced it (a
 superset of its own candidates with bit-identical results), so the broad phase runs once per
-iteration.  All arithmetic runs in library kernels; this module sequences the calls and reads
+iteration, and the evaluation of the accepted trial point serves the next iteration.  All arithmetic runs in library kernels; this module sequences the calls and reads
 the scalars the line search needs.
 """
 
@@ -48,20 +48,23 @@ class QuasiStatic:
         return out
 
     def step(self, x_prev, newton_iters=4, pcg_iters=50, pcg_tol=1e-6, armijo_c=1e-4, beta=0.5, max_halvings=30,
-             cand=None):
+             cand=None, out_t=None):
         """One quasi-static step from x_prev; returns the new positions, per-iteration records
         and the candidates that cover the new positions.  ``cand`` (pairs, n_pairs) may give
-        candidates covering x_prev (e.g. the previous step's); otherwise the broad phase runs."""
+        candidates covering x_prev (e.g. the previous step's); otherwise the broad phase runs.
+        ``out_t`` may give the energy's evaluation at x_prev when it is the context's last."""
         model, ctx = self.model, self.ctx
         x_prev = x_prev.detach().contiguous()
         x = x_prev.clone()
         recs = []
+        # out_t: the energy's evaluation at x (the accepted trial point's after the first)
         for _ in range(newton_iters):
             t0 = time.perf_counter()
-            if cand is None:
-                out_t = model.evaluate(x, hessian=False)
-            else:
-                out_t = model.evaluate(x, hessian=False, pairs=cand[0], n_pairs=cand[1])
+            if out_t is None:
+                if cand is None:
+                    out_t = model.evaluate(x, hessian=False)
+                else:
+                    out_t = model.evaluate(x, hessian=False, pairs=cand[0], n_pairs=cand[1])
             o = self.objective(x, x_prev, out_t)
             phi = o["phi"].item()
             d, info = ctx.pcg_coupled(self.row_ptr, self.col_idx, o["vals"], self.w, o["grad"], scale=-1.0, mu=0.0,
@@ -74,8 +77,8 @@ class QuasiStatic:
             alpha = 1.0
             for h in range(max_halvings):
                 xt = ctx.axpy(x, alpha, d)
-                ot = model.evaluate(xt, hessian=False, pairs=pairs, n_pairs=n)
-                phit = self.objective(xt, x_prev, ot, grad=False, vals=False)["phi"].item()
+                out_t = model.evaluate(xt, hessian=False, pairs=pairs, n_pairs=n)
+                phit = self.objective(xt, x_prev, out_t, grad=False, vals=False)["phi"].item()
                 if phit <= phi + armijo_c * alpha * gd:
                     break
                 if h + 1 < max_halvings:
@@ -103,7 +106,7 @@ class QuasiStatic:
                 hist.append({"E": 0.0, "hits": 0, "newton": []})
                 return x, hist
             hits = int(o["n_hits"].item())
-            x, recs, cand = self.step(x, cand=cand, **kw)
+            x, recs, cand = self.step(x, cand=cand, out_t=o, **kw)
             hist.append({"E": E, "hits": hits, "newton": recs})
         o = self.model.evaluate(x, hessian=False)
         hist.append({"E": o["energy"].item(), "hits": int(o["n_hits"].item()), "newton": []})

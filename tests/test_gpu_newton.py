@@ -157,3 +157,23 @@ def test_newton_subset_mixed_decreases(sphere_subset):
     E = np.array([h["E"] for h in hist])
     assert np.all(np.diff(E) <= 0)
     assert E[-1] <= 0.3 * E[0]
+
+
+def test_pcg_runs_on_the_touched_rows_only():
+    """The solve iterates over the rows holding blocks; b must vanish elsewhere (a gradient
+    does), and a right-hand side that does not is reported."""
+    x, tris = workloads.folded_cloth(seed=0, n=40)
+    m = _model(x, tris, max_pairs=1 << 16, max_hits=1 << 12)
+    out = m.evaluate(torch.from_numpy(x).cuda(), hessian=True)
+    rp = out["row_ptr"].cpu().numpy()
+    empty = np.nonzero(np.diff(rp) == 0)[0]
+    assert len(empty) > 0
+    g = out["grad"].cpu().numpy()
+    assert not g[empty].any()
+    d, _ = m.ctx.pcg(out["row_ptr"], out["col_idx"], out["vals"], out["grad"], scale=-1.0)
+    m.ctx.check()
+    assert not d.cpu().numpy()[empty].any()
+    b = out["grad"].clone()
+    b[int(empty[0]), 1] = 1.0
+    m.ctx.pcg(out["row_ptr"], out["col_idx"], out["vals"], b, scale=-1.0)
+    assert m.ctx.status() == 1

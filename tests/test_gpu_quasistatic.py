@@ -138,27 +138,38 @@ def test_pcg_coupled_needs_fp64_evaluation():
         m.ctx.pcg_coupled(rp, ci, vals, 1.0, b)
 
 
-def test_quasi_static_trajectory_matches_oracle():
+def test_quasi_static_steps_match_oracle():
+    """Newton iterations of the quasi-static objective from the same states on both sides.
+
+    Whole trajectories are not comparable: on this input a perturbation of 1e-15 in x changes
+    the oracle's own step lengths after one step (the Armijo decisions and the set of hits
+    switch), with truncated and with converged solves alike.  So the states come from a GPU
+    run, and from each of them one iteration with a converged solve is compared: objective,
+    energy, hits, step length and displacement."""
     from paper_2606_06511_amd.quasistatic import QuasiStatic
 
     x, tris = workloads.folded_cloth(0, n=24)
     k, mm, w = 1.0, 1.0, 1e4
-    # 20 PCG iterations: the truncated solve is insensitive to the summation order at this
-    # cap, so both runs take the same step lengths and agree closely
-    _, hist_ref = qs.quasi_static(x, x, tris, 3, k, mm, w, newton_iters=3, pcg_iters=20)
     m = _model(x, tris, max_pairs=1 << 16, max_hits=1 << 12)
     xd = _dev(x)
     sim = QuasiStatic(m, xd, k, mm, w)
-    _, hist = sim.run(xd, 3, newton_iters=3, pcg_iters=20)
-    assert len(hist) == len(hist_ref)
-    assert hist[0]["E"] == pytest.approx(hist_ref[0]["E"], rel=1e-10)
-    for h, r in zip(hist, hist_ref):
-        assert h["E"] == pytest.approx(r["E"], rel=1e-6)
-        assert h["hits"] == r["hits"]
-        for a, b in zip(h["newton"], r["newton"]):
-            assert a["alpha"] == b["alpha"]
-            assert a["phi"] == pytest.approx(b["phi"], rel=1e-6)
-            assert a["phi_new"] <= a["phi"]
+    states = [xd]
+    cur, cand = xd, None
+    for _ in range(2):
+        cur, recs, cand = sim.step(cur, newton_iters=2, pcg_iters=20, cand=cand)
+        assert all(r["phi_new"] <= r["phi"] for r in recs)
+        states.append(cur)
+    for xk in states:
+        xk_np = xk.cpu().numpy()
+        x1, rg, _ = sim.step(xk, newton_iters=1, pcg_iters=3000, pcg_tol=1e-13)
+        x1_ref, ro = qs.qs_step(xk_np, x, tris, k, mm, w, newton_iters=1, pcg_iters=3000, pcg_tol=1e-13)
+        a, b = rg[0], ro[0]
+        assert a["phi"] == pytest.approx(b["phi"], rel=1e-12)
+        assert a["E"] == pytest.approx(b["E"], rel=1e-10)
+        assert a["hits"] == b["hits"] > 0
+        assert a["alpha"] == b["alpha"]
+        assert a["phi_new"] <= a["phi"] and b["phi_new"] <= b["phi"]
+        assert _rel(x1.cpu().numpy() - xk_np, x1_ref - xk_np) <= 1e-7
 
 
 def test_axpy_keeps_positions_in_the_predicate_domain():
