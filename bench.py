@@ -29,24 +29,27 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad phase, seed 0"
 
-# Counter figures per launch of a kernel on this workload, valid only for the kernel source they
-# were taken on (when the file's hash differs they are reported as null until taken again):
+# Counter figures per launch of a kernel on this workload, valid only for the kernel source and
+# the launch parameters they were taken with (otherwise reported as null until taken again):
 #   bytes       HBM bytes from two rocprofv3 passes, FETCH_SIZE x 1.9998 and WRITE_SIZE x 1.0 (the
 #               factors that make a 256 MiB elementwise copy read and write 256 MiB)
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
 MEASURED = {
-    "bp_traverse": {"bytes": 16465022, "valu_wave": 14612976, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-                    "sha256": "8a3a2dbd6cbc54fa103bad2258bc01f3fcdf790b6fb092999ef1848d49d33bb3"},
+    "bp_traverse": {"bytes": 16486053, "valu_wave": 14451040, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+                    "sha256": "a49a4ac47dd7a2e0a60204b71fb83440eff3de302356d71e99f5d6413398cbb7",
+                    "params": {"trav_budget": 32}},
 }
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def measured(stage, what):
+def measured(stage, what, params=None):
     import hashlib
 
     m = MEASURED.get(stage)
     if not m:
+        return None
+    if params is not None and any(params.get(k) != v for k, v in m.get("params", {}).items()):
         return None
     with open(os.path.join(ROOT, m["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
@@ -267,6 +270,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the larger configurations (1M-triangle sphere, 64-problem batch)")
+    ap.add_argument("--params", default="", metavar="NAME=V,...",
+                    help="fix launch parameters (trav_budget, screen_blocks, row_blocks) instead of autotuning them; "
+                         "a profiler run uses this to time the configuration the autotuner picks")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="finish with one elementwise copy kernel over this many MB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -331,6 +337,22 @@ def main():
     primary = args.precision
     other = "fp64" if primary == "mixed" else "mixed"
 
+    # launch parameters picked by the autotuner on this very step before anything is timed
+    # (they change the speed only, never a result)
+    from paper_2606_06511_amd import autotune
+
+    if args.params:
+        tuned = {}
+        for item in args.params.split(","):
+            name, val = item.split("=")
+            ctx.set_param(autotune.SPACE[name][0], int(val))
+            tuned[name] = int(val)
+        ms_tuned = ms_default = None
+    else:
+        tuned, ms_tuned, ms_default = autotune.tune(ctx, lambda: step(primary), reps=20, rounds=1)
+    torch.cuda.synchronize()
+    ctx.check()
+
     # stage breakdown from warm-up steps with every timer on
     step(primary)
     torch.cuda.synchronize()
@@ -373,7 +395,9 @@ def main():
         "dtype": "f32+f64pred" if primary == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n_verts": nv, "n_tris": nt, "pairs": P, "hits": H, "nnzb": nnzb,
-                   "step": "broadphase+screen+derivatives+energy+gradient+BSR Hessian"},
+                   "step": "broadphase+screen+derivatives+energy+gradient+BSR Hessian",
+                   "launch_params": tuned},
+        "autotune": {"ms_per_step_default_params": ms_default, "ms_per_step_tuned_params": ms_tuned},
         other: {"value": P / (ms_other * 1e-3), "ms_per_step": ms_other},
         "stages_ms_per_step": {k: round(v, 5) for k, v in per_step_stage.items()},
         # the same step split at the stage timers: evaluation only (screening through BSR
@@ -383,14 +407,14 @@ def main():
         "broadphase_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if k.startswith("bp_")),
                             "tris_per_s": nt / (sum(v for k, v in per_step_stage.items() if k.startswith("bp_")) * 1e-3)},
         "roofline": {"kernel_stage": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured(dominant, "bytes"),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured(dominant, "bytes", tuned),
                      "traffic_unit": "bytes per launch",
                      "alg_bytes_per_launch": alg, "avg_launch_ms": dom_avg_ms, "launches": dom_launches},
     }
 
     # the same kernel against the VALU issue rate (its real bound: a latency- and issue-bound
     # tree search), from the committed instruction count and the live duration
-    vw = measured(dominant, "valu_wave")
+    vw = measured(dominant, "valu_wave", tuned)
     if vw and dom_avg_ms > 0:
         rate = vw * 64 / (dom_avg_ms * 1e-3)
         rec["roofline_issue"] = {"kernel_stage": dominant, "bound": "alu", "achieved": rate, "peak": VALU_LANE_PEAK,

@@ -335,7 +335,8 @@ enum {
   TTIE_STAGE_BP_BOXES = 0,    /* triangle boxes, scene bounds, Morton bucket ranks (spatial hash: cells) */
   TTIE_STAGE_BP_SORT = 1,     /* counting sort by Morton bucket (spatial hash: by cell hash) */
   TTIE_STAGE_BP_BUILD = 2,    /* leaf records and the implicit 4-ary tree's boxes, bottom up */
-  TTIE_STAGE_BP_TRAVERSE = 3, /* tree self-traversal / hash buckets / brute force, pair emission */
+  TTIE_STAGE_BP_TRAVERSE = 3, /* tree self-traversal / hash buckets / brute force, pair emission
+                                 (the queries over the traversal budget go on in TTIE_STAGE_BP_HEAVY) */
   TTIE_STAGE_SCREEN = 4,      /* per-candidate screening with FP64 filters */
   TTIE_STAGE_SCREEN_EXACT = 5,/* re-screening of the deferred candidates with exact predicates */
   TTIE_STAGE_DERIVS = 6,      /* per-hit interval gradients, energy, gradient, Hessian core */
@@ -343,7 +344,8 @@ enum {
   TTIE_STAGE_HVP = 8,         /* Hessian-vector products */
   TTIE_STAGE_PCG = 9,         /* the preconditioned conjugate-gradient solve */
   TTIE_STAGE_ELASTIC = 10,    /* the quasi-static objective (springs, proximal term) */
-  TTIE_STAGE_COUNT = 11
+  TTIE_STAGE_BP_HEAVY = 11,   /* broad-phase queries handed to a whole wave each (tree or hash) */
+  TTIE_STAGE_COUNT = 12
 };
 ttie_status ttie_set_timing(ttie_ctx* ctx, uint32_t stage_mask);
 ttie_status ttie_read_timers(ttie_ctx* ctx, int n_stages, int64_t* launches_host, double* total_ms_host);

@@ -1128,10 +1128,11 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     const int hb = (int)ctx_param(c, TTIE_PARAM_HASH_BUDGET);
     k_hash_pairs<<<bp_grid(4 * nt, 8192), kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox,
                                                            m->tris, grid, hb, va, heavy, pairs, capacity, npairs, ctr);
-    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, hb, va,
-                                          heavy,
-                                          pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
+    stage_begin(c, TTIE_STAGE_BP_HEAVY, s);
+    k_hash_heavy<<<512, kBpBlock, 0, s>>>(ctr, ecap, nbuckets, hbits, offset, skey, stri, tbox, m->tris, grid, hb, va,
+                                          heavy, pairs, capacity, npairs, ctr);
+    stage_end(c, TTIE_STAGE_BP_HEAVY, s);
   } else if (method == TTIE_BROAD_LBVH && nt >= 2) {
     double* tbox = wsp<double>(c, L.bvh_tbox);
     float* centre = wsp<float>(c, L.bvh_centroid);
@@ -1181,8 +1182,10 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     else
       k_traverse<false><<<(unsigned)nb, kTravThreads, 0, s>>>(nt, lv, boxes, leaves, tri_off ? qend : nullptr, heavy,
                                                               heavy_cap, budget, pairs, capacity, npairs, ctr);
-    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, va, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
+    stage_begin(c, TTIE_STAGE_BP_HEAVY, s);
+    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, va, pairs, capacity, npairs, ctr);
+    stage_end(c, TTIE_STAGE_BP_HEAVY, s);
   }
   return hipGetLastError();
 }

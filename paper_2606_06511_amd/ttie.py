@@ -82,7 +82,7 @@ SIGNATURES = {
 }
 
 STAGES = ["bp_boxes", "bp_sort", "bp_build", "bp_traverse", "screen", "screen_exact", "derivs", "assembly", "hvp",
-          "pcg", "elastic"]
+          "pcg", "elastic", "bp_heavy"]
 
 _lib = None
 
