@@ -18,7 +18,7 @@ from fractions import Fraction
 
 
 def _vec(p):
-    return tuple(Fraction(float(c)) for c in p)
+    return tuple(c if isinstance(c, Fraction) else Fraction(float(c)) for c in p)
 
 
 def _sub(a, b):

@@ -29,7 +29,11 @@
 //     det[p1-p0, p2-p0, x-p0]; an FP64 distance whose sign disagrees with the exact sign is
 //     replaced by the exact value (rounded), so lerp weights stay in [0,1];
 //   - the intersection flag is the exact open-interval test on the exact endpoints;
-//   - min/max ties keep the first argument;
+//   - the two ends of each segment are ordered along D exactly (the min/max of the interval
+//     ends): with the segment's endpoints E0 on edge (k, k1) (or E0 = the on-plane vertex k and
+//     E1 on the opposite edge (k1, k2)), t(E1) - t(E0) has the sign of the orientation of
+//     (k, k1, k2) in the triangle times the side of k1 (negated for T_b, whose cut lies on the
+//     plane of T_a and D = n_a x n_b), so two different endpoints never tie;
 //   - pairs sharing a vertex index are "adjacent" and carry no energy;
 //   - a hit whose FP64 line direction has zero length is reported with status 3 and T = 0;
 //   - two triangles lying in one plane have no segment and no line, so T = 0 (the paper sets
@@ -488,8 +492,18 @@ void intersects(const V3<S> P[3], const V3<S> C[3], const Tri& tp, const Tri& tc
   seg[1] = seg_point(cut, 1, C, d);
 }
 
-template <class S> const S& min_first(const S& x, const S& y) { return val(y) < val(x) ? y : x; }
-template <class S> const S& max_first(const S& x, const S& y) { return val(y) > val(x) ? y : x; }
+// sign of t(endpoint 1) - t(endpoint 0) of a cut along D = n_a x n_b, from the exact sides.
+// For T_a cut by the plane of T_b, write E1 - E0 = mu D; within the plane of T_a the 2D cross
+// product with the edge e1 = k1 - k gives mu (n_a.(e1 x D)) = lambda n_a.(e1 x e2) with
+// lambda > 0, and n_a.(e1 x D) = |n_a|^2 (n_b.e1), whose sign is the side of k1 (k lies on the
+// other side or on the plane).  For T_b the same steps give the opposite sign.
+int seg_order(const Cut& c, bool cut_of_b) {
+  const int k = c.p[0];
+  const int k1 = c.q[0] >= 0 ? c.q[0] : c.p[1];
+  const int orientation = ((k1 - k + 3) % 3 == 1) ? 1 : -1;  // (k, k1, k2) cyclic in the triangle
+  const int o = orientation * c.s[k1];
+  return cut_of_b ? -o : o;
+}
 
 template <class S>
 bool interval_ends(const V3<S> U[3], const V3<S> V[3], const Tri& ta, const Tri& tb, const Cut& ca,
@@ -506,8 +520,10 @@ bool interval_ends(const V3<S> U[3], const V3<S> V[3], const Tri& ta, const Tri&
   V3<S> A = scale(0.25, Sa[0] + Sa[1] + Sb[0] + Sb[1]);
   S t00 = dot(D, Sa[0] - A), t01 = dot(D, Sa[1] - A);
   S t10 = dot(D, Sb[0] - A), t11 = dot(D, Sb[1] - A);
-  S ta0 = min_first(t00, t01), ta1 = max_first(t00, t01);
-  S tb0 = min_first(t10, t11), tb1 = max_first(t10, t11);
+  const bool a_up = seg_order(ca, false) > 0;  // t(Sa[1]) > t(Sa[0])
+  const bool b_up = seg_order(cb, true) > 0;
+  S ta0 = a_up ? t00 : t01, ta1 = a_up ? t01 : t00;
+  S tb0 = b_up ? t10 : t11, tb1 = b_up ? t11 : t10;
   tc0 = half * (ta0 - tb1);
   tc1 = half * (ta1 - tb0);
   return true;

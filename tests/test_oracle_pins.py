@@ -246,6 +246,55 @@ def test_gradient_and_interval_derivatives_fd():
     assert checked > 400
 
 
+def _exact_t_derivative(X, v):
+    """Directional derivatives of the exact (t_c^0, t_c^1) along v: exact rational difference
+    quotients of tc and |D|^2 over a step of 2^-120 (far below any kink of these inputs, so
+    the truncation error is O(2^-120)), then t = tc / |D|."""
+    from fractions import Fraction
+
+    h = Fraction(1, 2 ** 120)
+    Xq = [[Fraction(float(c)) for c in row] for row in X]
+    Xh = [[Xq[i][c] + h * Fraction(float(v[3 * i + c])) for c in range(3)] for i in range(6)]
+    e0, e1 = exact_moller.pair(Xq[:3], Xq[3:]), exact_moller.pair(Xh[:3], Xh[3:])
+    assert e0["flag"] and e1["flag"]
+    DD, dDD = float(e0["DD"]), float((e1["DD"] - e0["DD"]) / h)
+    out = []
+    for key in ("tc0", "tc1"):
+        tc, dtc = float(e0[key]), float((e1[key] - e0[key]) / h)
+        out.append(dtc / np.sqrt(DD) - tc * dDD / (2 * DD ** 1.5))
+    return out
+
+
+def test_interval_derivatives_at_near_tied_ends():
+    """A vertex within 2^-60..2^-48 of the other triangle's plane makes its two crossing
+    points (one segment's ends) nearly coincide: their t values differ by less than their
+    rounding error, and picking the wrong one as the minimum swaps the derivatives of two
+    different edge crossings.  The oracle's dt_c^0/dX and dt_c^1/dX must be those of the
+    exact interval; both triangles take the near vertex in every position."""
+    rng = np.random.default_rng(21)
+    checked = 0
+    for trial in range(48):
+        # T_b in the plane y = 0, T_a with a lone vertex just above it and two below
+        tb = np.array([[-1.0, 0.0, -1.0], [2.0, 0.0, -1.0], [0.5, 0.0, 2.0]])
+        tb[:, [0, 2]] += rng.normal(0, 0.05, size=(3, 2))
+        near = np.array([0.4 + 0.2 * rng.random(), 2.0 ** -rng.uniform(48, 60), 0.1 + 0.2 * rng.random()])
+        far = np.array([[rng.uniform(-0.2, 0.3), -1 - rng.random(), rng.uniform(0.3, 0.9)],
+                        [rng.uniform(0.8, 1.3), -1 - rng.random(), rng.uniform(-0.6, 0.0)]])
+        ta = np.concatenate([near[None], far])[np.roll(np.arange(3), trial % 3)]
+        if trial % 6 >= 3:
+            ta = ta[[0, 2, 1]]  # the other orientation
+        X = np.concatenate([ta, tb]) if trial % 2 == 0 else np.concatenate([tb, ta])
+        r = oracle.pair(X)
+        assert r["status"] == oracle.ST_HIT
+        v = rng.normal(size=18)
+        da, db = _exact_t_derivative(X, v)
+        scale = max(1.0, np.abs(r["a"]).max(), np.abs(r["b"]).max()) * np.linalg.norm(v)
+        assert abs(r["a"] @ v - da) <= 1e-9 * scale, (trial, r["a"] @ v, da)
+        assert abs(r["b"] @ v - db) <= 1e-9 * scale, (trial, r["b"] @ v, db)
+        checked += 1
+    assert checked == 48
+
+
 def test_exact_hvp_fd():
     h = 1e-6
     rng = np.random.default_rng(2)
