@@ -86,6 +86,19 @@ __device__ __forceinline__ Cut make_cut(int s0, int s1, int s2) {
   return c;
 }
 
+// Sign of t(end 1) - t(end 0) for the cut of A by the plane of B, with D = n_A x n_B (the
+// cut of B by the plane of A has the opposite sign).  Both ends lie on the line, so
+// end 1 - end 0 = mu D; crossing it with the first edge e1 = (k, k1) within A's plane gives
+// mu |n_A|^2 (n_B . e1) = lambda n_A . (e1 x e2) with lambda > 0.  n_B . e1 has the sign of
+// the side of k1 (k is on the other side or on the plane), and n_A . (e1 x e2) is +|n_A|^2
+// when (k, k1, k2) runs in the triangle's own order.
+__device__ __forceinline__ int seg_order(const Cut& c) {
+  const int k = c.p[0];
+  const int k1 = c.q[0] != 3 ? c.q[0] : c.p[1];
+  const int s1 = k1 == 0 ? c.s[0] : (k1 == 1 ? c.s[1] : c.s[2]);
+  return (k1 == (k == 2 ? 0 : k + 1)) ? s1 : -s1;
+}
+
 struct Tri64 {
   double p[3][3];
 };
@@ -291,9 +304,10 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
     }
     tb[k] = dot(D, Q);
   }
-  // min/max keep the first argument on ties
-  const int amin = ta[1] < ta[0] ? 1 : 0, amax = ta[1] > ta[0] ? 1 : 0;
-  const int bmin = tb[1] < tb[0] ? 1 : 0, bmax = tb[1] > tb[0] ? 1 : 0;
+  // which end of each segment comes first along D, decided exactly (never from the rounded
+  // t values, which can misorder two ends closer than their rounding error)
+  const int amin = seg_order(ca) < 0 ? 1 : 0, amax = 1 - amin;
+  const int bmin = seg_order(cb) > 0 ? 1 : 0, bmax = 1 - bmin;
   uint32_t desc = 0;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
