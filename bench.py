@@ -35,8 +35,8 @@ WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad p
 #               factors that make a 256 MiB elementwise copy read and write 256 MiB)
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
 MEASURED = {
-    "bp_traverse": {"bytes": 16486053, "valu_wave": 14451040, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-                    "sha256": "a49a4ac47dd7a2e0a60204b71fb83440eff3de302356d71e99f5d6413398cbb7",
+    "bp_traverse": {"bytes": 16494118, "valu_wave": 14477079, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+                    "sha256": "b60eb6a25bcfaea5967463a928a452e8025a740351beb2a77969843a698776df",
                     "params": {"trav_budget": 32}},
 }
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)

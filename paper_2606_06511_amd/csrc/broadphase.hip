@@ -11,8 +11,9 @@
 //   scan, scatter  counting sort of the triangles by bucket (order inside a bucket arbitrary)
 //   k_levels       an implicit complete 4-ary tree over the sorted leaves: node (l, k) covers
 //                  leaves [k 4^l, (k+1) 4^l); boxes are reduced level by level in LDS, four
-//                  levels per launch, so building needs no atomics and no fences.  The first
-//                  launch also writes the sorted leaf records (FP64 box, vertex ids).
+//                  levels per launch from the leaves, five per launch above, so building needs
+//                  no atomics and no fences.  The first launch also writes the sorted leaf
+//                  records (FP64 box, vertex ids).
 //   k_traverse     two lanes per leaf s (its own 256-leaf subtree, staged in LDS, and the rest
 //                  of the tree), depth first over the subtrees holding leaves after s,
 //                  four child boxes per visit and a 64-bit mask stack, descending where the
@@ -262,18 +263,20 @@ __device__ __forceinline__ Box32 box_union(const Box32& a, const Box32& b) {
   return r;
 }
 
-// Reduces levels l0+1 .. l0+4 from the boxes of level l0 (l0 = 0: made from the sorted
-// leaves, which are written too).  Block b owns level-l0 nodes [256 b, 256 b + 256).
+// Reduces levels l0+1 .. l0+4 (256 threads) or l0+1 .. l0+5 (1024 threads) from the boxes of
+// level l0 (l0 = 0: made from the sorted leaves, which are written too).  Block b owns level-l0
+// nodes [kThreads b, kThreads (b + 1)).
 // For a batch (tri_off != NULL) the leaf pass also writes qend[k]: the end of the sorted range of
 // the problem owning leaf k (problem p + 1 starts at the offset of its first bucket).
-__global__ void __launch_bounds__(kBpBlock) k_levels(int l0, Levels lv, const double* __restrict__ tbox,
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_levels(int l0, Levels lv, const double* __restrict__ tbox,
                                                      const int32_t* __restrict__ ids,
                                                      const int32_t* __restrict__ tris, Box32* __restrict__ boxes,
                                                      LeafRec* __restrict__ leaves, const int64_t* __restrict__ tri_off,
                                                      int n_prob, int mbits, const int32_t* __restrict__ offset,
                                                      int32_t* __restrict__ qend) {
-  __shared__ Box32 sh[kBpBlock];
-  const int64_t k = (int64_t)blockIdx.x * kBpBlock + threadIdx.x;
+  __shared__ Box32 sh[kThreads];
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   Box32 bx;
   for (int c = 0; c < 4; ++c) {
     bx.lo[c] = 3.0e38f;
@@ -303,8 +306,10 @@ __global__ void __launch_bounds__(kBpBlock) k_levels(int l0, Levels lv, const do
   }
   sh[threadIdx.x] = bx;
   __syncthreads();
-  for (int j = 1; j <= 4 && l0 + j <= lv.L; ++j) {
-    const int cnt = kBpBlock >> (2 * j);
+  constexpr int kLevels = kThreads == 256 ? 4 : 5;
+  static_assert(kThreads == 1 << (2 * kLevels), "a block reduces kThreads nodes to one");
+  for (int j = 1; j <= kLevels && l0 + j <= lv.L; ++j) {
+    const int cnt = kThreads >> (2 * j);
     Box32 r;
     const bool act = threadIdx.x < cnt;
     if (act) r = box_union(box_union(sh[4 * threadIdx.x], sh[4 * threadIdx.x + 1]),
@@ -1166,9 +1171,16 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
     k_scatter<<<bp_grid(std::max<int64_t>(nt, nbuckets)), kBpBlock, 0, s>>>(nt, nbuckets, k1, v1, offset, v2, hist);
     stage_end(c, TTIE_STAGE_BP_SORT, s);
     stage_begin(c, TTIE_STAGE_BP_BUILD, s);
-    for (int l0 = 0; l0 < lv.L; l0 += 4)
-      k_levels<<<(unsigned)((lv.m[l0] + kBpBlock - 1) / kBpBlock), kBpBlock, 0, s>>>(
-          l0, lv, tbox, v2, m->tris, boxes, leaves, tri_off, n_prob, mbits, offset, qend);
+    // leaves to level 4 in blocks of 256, then five levels per launch in blocks of 1024 (a
+    // tree of up to 4^9 leaves takes two launches)
+    for (int l0 = 0; l0 < lv.L; l0 += l0 == 0 ? 4 : 5) {
+      if (l0 == 0)
+        k_levels<256><<<(unsigned)((lv.m[0] + 255) / 256), 256, 0, s>>>(0, lv, tbox, v2, m->tris, boxes, leaves,
+                                                                         tri_off, n_prob, mbits, offset, qend);
+      else
+        k_levels<1024><<<(unsigned)((lv.m[l0] + 1023) / 1024), 1024, 0, s>>>(l0, lv, tbox, v2, m->tris, boxes, leaves,
+                                                                             tri_off, n_prob, mbits, offset, qend);
+    }
     stage_end(c, TTIE_STAGE_BP_BUILD, s);
     stage_begin(c, TTIE_STAGE_BP_TRAVERSE, s);
     // one lane per leaf, block count rounded up to a multiple of the 8 XCDs

@@ -418,9 +418,18 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
       for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
         const int32_t cnt = min(n - k0, kRowStage);
         if (n > kRowStage || q0 > 0) stage(b, k0, cnt);  // a one-chunk row is still in LDS
-        for (int32_t k = 0; k < cnt; ++k)
-          for (int l = 0; l < 6; ++l)
-            if (R[k].vid[l] == col) block_jmj(R[k], I[k].slot, l, B);
+        for (int32_t k = 0; k < cnt; ++k) {
+          // the hit's slots holding this lane's column, in slot order: the lanes hold distinct
+          // columns, so one pass of block_jmj serves every lane that matches a slot of the hit
+          // (instead of one pass per slot, most with a single lane active)
+          uint32_t match = 0;
+#pragma unroll
+          for (int l = 0; l < 6; ++l) match |= (uint32_t)(R[k].vid[l] == col) << l;
+          while (match) {
+            block_jmj(R[k], I[k].slot, __builtin_ctz(match), B);
+            match &= match - 1;
+          }
+        }
       }
       if (q < nc) {
         const int64_t pos = (int64_t)rp + q;
