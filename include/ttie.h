@@ -63,7 +63,8 @@ typedef enum ttie_status {
   TTIE_ERR_CAPACITY = 4,           /* an output or the workspace is too small */
   TTIE_ERR_HIP = 5,                /* a HIP runtime call failed */
   TTIE_ERR_NO_DEVICE = 6,          /* no usable GPU */
-  TTIE_ERR_UNSUPPORTED = 7         /* coordinate outside the exact-predicate domain */
+  TTIE_ERR_UNSUPPORTED = 7,        /* coordinate outside the exact-predicate domain */
+  TTIE_ERR_INTERNAL = 8            /* a bounded device-side wait ran out (a library fault) */
 } ttie_status;
 
 /* precision policy */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttie.so")
-SOURCES = ["api.hip", "evaluate.hip", "broadphase.hip", "pcg.hip", "springs.hip"]
+SOURCES = ["api.hip", "evaluate.hip", "broadphase.hip", "scan.hip", "pcg.hip", "springs.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

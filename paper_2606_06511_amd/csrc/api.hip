@@ -251,6 +251,8 @@ ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* d
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cur), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.ncol), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.bvh_hist), kMaxBuckets, s);
+  // the scan's counters and tile words (each scan leaves them zero again)
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.scan_tmp), (int64_t)(L.scan_tmp_bytes / 4), s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.epart_v), 2 * (limits->max_verts + 1), s);
   if (e != hipSuccess) return hip_fail(e, "ttie_set_workspace");
   return TTIE_OK;

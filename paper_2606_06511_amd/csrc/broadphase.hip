@@ -22,7 +22,6 @@
 //                  shared-vertex test; pairs are staged per wave in LDS (ballot + mbcnt) and
 //                  flushed with one atomic per full buffer
 //   k_brute        all i < j without a shared vertex (no box test)
-#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 

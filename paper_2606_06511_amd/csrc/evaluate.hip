@@ -20,7 +20,6 @@
 //   k_eval_finish    block partials summed in block order; scalar outputs; counters reset
 #include <algorithm>
 
-#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 
@@ -650,20 +649,6 @@ static unsigned grid_for(int64_t n, unsigned cap = 4096) {
 hipError_t launch_fill_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
   k_fill_zero_i32<<<grid_for(n), kBlock, 0, s>>>(p, n);
   return hipGetLastError();
-}
-
-size_t scan_temp_bytes(int64_t n) {
-  size_t bytes = 0;
-  int32_t* dummy = nullptr;
-  if (rocprim::exclusive_scan(nullptr, bytes, dummy, dummy, 0, (size_t)n, rocprim::plus<int32_t>()) != hipSuccess)
-    return 0;
-  return bytes;
-}
-
-hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  size_t bytes = c->L.scan_tmp_bytes;
-  return rocprim::exclusive_scan(c->ws + c->L.scan_tmp, bytes, in, out, 0, (size_t)n, rocprim::plus<int32_t>(), s);
 }
 
 static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {

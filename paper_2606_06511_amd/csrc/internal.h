@@ -50,6 +50,12 @@ struct Counters {
   uint32_t pad_;
 };
 
+// Counters of the one-launch scan (tiles taken, tiles done); both are zero between scans.
+struct ScanState {
+  uint32_t next_tile;
+  uint32_t done;
+};
+
 // Number of distinct vertex ids of triangle a that also belong to triangle b.
 __device__ __forceinline__ int shared_vertices(const int32_t* a, const int32_t* b) {
   int n = 0;

@@ -33,7 +33,8 @@
 namespace ttie {
 
 enum { PAIR_NONE = 0, PAIR_HIT = 1, PAIR_ADJACENT = 2, PAIR_BAD_FRAME = 3, PAIR_COPLANAR = 4, PAIR_DEFER = 5 };
-enum { STATUS_OK = 0, STATUS_INVALID = 1, STATUS_INDEX = 2, STATUS_NONFINITE = 3, STATUS_CAPACITY = 4, STATUS_UNSUPPORTED = 7 };
+enum { STATUS_OK = 0, STATUS_INVALID = 1, STATUS_INDEX = 2, STATUS_NONFINITE = 3, STATUS_CAPACITY = 4, STATUS_UNSUPPORTED = 7,
+       STATUS_INTERNAL = 8 };
 
 // Geometry of a screened pair: kept for every intersecting pair.
 struct HitGeom {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libttie.so")
 TTIE_OK = 0
 STATUS_NAMES = {
     0: "OK", 1: "INVALID_ARGUMENT", 2: "INDEX_OUT_OF_RANGE", 3: "NONFINITE_INPUT", 4: "CAPACITY",
-    5: "HIP", 6: "NO_DEVICE", 7: "UNSUPPORTED",
+    5: "HIP", 6: "NO_DEVICE", 7: "UNSUPPORTED", 8: "INTERNAL",
 }
 FP64, MIXED = 0, 1
 PSD_PER_PART, PSD_NEAREST, PSD_PAPER_LITERAL, PSD_RAW_EQ4 = 0, 1, 2, 3
