@@ -175,7 +175,7 @@ hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* 
                          const void* x, void* y, int precision, hipStream_t s);
 hipError_t launch_init_counters(Ctx* c, hipStream_t s);
 size_t scan_temp_bytes(int64_t n);
-// exclusive scan of n int32 (rocPRIM)
+// exclusive scan of n int32 in one launch (csrc/scan.hip); scan_temp_bytes sizes its state
 hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 
 }  // namespace ttie

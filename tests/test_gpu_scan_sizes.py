@@ -1,0 +1,65 @@
+"""Counts at the tile edges of the one-launch scan (2048 entries per tile).  The evaluation
+scans N_v + 1 incidence counts and N_v + 1 column counts (the second is the BSR row pointer
+itself), so a small folded cloth is spread over N_v vertex slots, the rest unused, with N_v + 1
+just below, at and just above tile edges and past 64 tiles (the look-back window).  Candidates,
+flags, energy, gradient and the BSR matrix against the oracle; the row pointers bit-exact."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_06511_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TILE = 2048
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_06511_amd import ttie
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = ttie.Context(0)
+    c.reserve(70 * TILE, 4096, 1 << 18, max_hits=1 << 14, max_blocks=1 << 19)
+    return c
+
+
+def spread_cloth(nv, seed):
+    """The 40 x 40 folded cloth with its vertices at random slots of [0, nv); the unused
+    slots hold points far from it, so they touch nothing."""
+    x0, tris0 = workloads.folded_cloth(seed=seed, n=40)
+    rng = np.random.default_rng(seed)
+    slot = np.sort(rng.choice(nv, size=len(x0), replace=False))
+    x = 10.0 + rng.random((nv, 3))
+    x[slot] = x0
+    return x, slot[tris0].astype(np.int32)
+
+
+@pytest.mark.parametrize("nv", [TILE - 2, TILE - 1, TILE, 2 * TILE - 1, 64 * TILE - 1, 64 * TILE, 65 * TILE + 5])
+def test_scan_tile_edges(ctx, nv):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = spread_cloth(nv, seed=nv % 7)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(tris).cuda()
+    pairs, n = ctx.broadphase(xd, td, ttie.BROAD_LBVH)
+    ctx.check()
+    got = pairs[: int(n.item())].cpu().numpy()
+    got = got[np.lexsort((got[:, 1], got[:, 0]))]
+    ref_pairs = oracle.pairs(x, tris)
+    np.testing.assert_array_equal(got, ref_pairs)
+    ref = oracle.evaluate(x, tris, ref_pairs)
+    assert len(ref["hit_pair"]) > 0
+    out = ctx.evaluate(xd, td, torch.from_numpy(ref_pairs).cuda(), precision=ttie.FP64, flags=True)
+    ctx.check()
+    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
+    assert abs(out["energy"].item() - ref["E"]) <= 1e-10 * ref["E"]
+    g, G = out["grad"].cpu().numpy(), ref["G"]
+    assert np.linalg.norm(g - G) <= 1e-10 * np.linalg.norm(G)
+    nb = int(out["n_blocks"].item())
+    np.testing.assert_array_equal(out["row_ptr"].cpu().numpy(), ref["row_ptr"])
+    np.testing.assert_array_equal(out["col_idx"][:nb].cpu().numpy(), ref["col_idx"])
+    v, V = out["vals"][:nb].cpu().numpy(), ref["vals"]
+    assert np.linalg.norm(v - V) <= 1e-10 * np.linalg.norm(V)
