@@ -18,7 +18,7 @@ from . import ttie
 SPACE = {
     "screen_blocks": (ttie.PARAM_SCREEN_BLOCKS, (512, 1024, 2048, 4096, 8192)),
     "row_blocks": (ttie.PARAM_ROW_BLOCKS, (256, 512, 1024, 2048, 4096)),
-    "trav_budget": (ttie.PARAM_TRAV_BUDGET, (32, 64, 128, 256, 1024)),
+    "trav_budget": (ttie.PARAM_TRAV_BUDGET, (16, 24, 32, 64, 128, 256, 1024)),
 }
 
 

@@ -643,50 +643,86 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
   if (status) atomicCAS(&ctr->status, 0, status);
 }
 
-// One wave per saved query: the remaining nodes form a stack in LDS; every step each lane
-// takes one node, tests its four children, and pushes the overlapping inner children (or tests
-// the leaves), so a query that overlaps hundreds of leaves needs tens of steps instead of
-// hundreds of serial visits.  Everything is read from global memory.
+// One wave per batch of saved queries (one query while the list is no longer than the grid,
+// at most kHeavyQ): the remaining nodes of all of them form
+// one stack in LDS, each entry tagged with its query's slot; every step each lane takes one
+// node, tests its four children against that query's box, and pushes the overlapping inner
+// children (or tests the leaves).  A query that overlaps hundreds of leaves needs tens of steps
+// instead of hundreds of serial visits, and queries with a few visits left share the wave's
+// lanes instead of holding a whole wave each.  Everything but the stack is read from global
+// memory.
+//
+// Stack bound: a query saved at level l brings at most 1 + 3 (L - l) entries, and a step
+// replaces at most 64 entries by at most 256 children one level down, so the stack holds at
+// most Q (1 + 3 L) + 3 * 64 * L + 64 entries; the host picks Q so that this fits kHeavyStack.
 constexpr int kHeavyStack = 4096;
+constexpr int kHeavyQ = 8;
+
+inline int heavy_batch(int L) {
+  const int q = (kHeavyStack - 64 - 3 * 64 * L) / (1 + 3 * L);
+  return q < 1 ? 1 : (q > kHeavyQ ? kHeavyQ : q);
+}
 
 __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* __restrict__ boxes,
                                                        const LeafRec* __restrict__ leaves,
                                                        const TravState* __restrict__ heavy, int64_t heavy_cap, int va,
-                                                       int32_t* pairs, int64_t cap, unsigned long long* npairs,
-                                                       Counters* ctr) {
+                                                       int nq_max, int32_t* pairs, int64_t cap,
+                                                       unsigned long long* npairs, Counters* ctr) {
   const PairSink sink{pairs, cap, npairs, &ctr->status};
-  __shared__ int2 stack[kHeavyStack];
+  __shared__ int2 stack[kHeavyStack];  // (level | slot << 8, node)
   __shared__ int2 stage[kEmitCap];
   __shared__ int wcount[1];
   __shared__ int64_t bbase;
+  __shared__ float sq[kHeavyQ][6];      // per slot: the query's FP32 box
+  __shared__ LeafRec sme[kHeavyQ];      // its leaf record
+  __shared__ int32_t ss[kHeavyQ], slast[kHeavyQ], spart[kHeavyQ];
   WaveEmitter em{stage, 0};
   const int lane = __lane_id();
   int status = 0;
   const int64_t nh = min((int64_t)ctr->n_heavy, heavy_cap);
-  for (int64_t it = blockIdx.x; it < nh; it += gridDim.x) {
-    const TravState t = heavy[it];
-    const int64_t s = t.s, blk = s / kBpBlock, last = t.last;
-    const bool global_part = t.part != 0;
-    const Box32 qb = boxes[lv.off[0] + s];
-    float q[6];
-    for (int c = 0; c < 3; ++c) {
-      q[c] = qb.lo[c];
-      q[3 + c] = qb.hi[c];
+  // one query per wave while the list is no longer than the grid, then batches just large
+  // enough to cover it in one pass (at most nq_max)
+  const int per = (int)min((int64_t)nq_max, max((int64_t)1, (nh + gridDim.x - 1) / gridDim.x));
+  for (int64_t it0 = (int64_t)blockIdx.x * per; it0 < nh; it0 += (int64_t)gridDim.x * per) {
+    const int nq = (int)min((int64_t)per, nh - it0);
+    // lane j < nq loads query j and lists its remaining search: the node it was about to
+    // visit and the pending siblings of its ancestors (slot j of pend: siblings at level j)
+    TravState t{};
+    int cnt = 0;
+    if (lane < nq) {
+      t = heavy[it0 + lane];
+      const Box32 qb = boxes[lv.off[0] + t.s];
+      for (int c = 0; c < 3; ++c) {
+        sq[lane][c] = qb.lo[c];
+        sq[lane][3 + c] = qb.hi[c];
+      }
+      sme[lane] = leaves[t.s];
+      ss[lane] = t.s;
+      slast[lane] = t.last;
+      spart[lane] = t.part;
+      cnt = 1;
+      for (int j = t.l; j < t.top; ++j) cnt += __popc((uint32_t)(t.pend >> (4 * j)) & 15u);
     }
-    const LeafRec me = leaves[s];
-    // the remaining search: the node about to be visited and the pending siblings of its
-    // ancestors (slot j of pend: siblings at level j)
-    int sp = 0;
-    if (lane == 0) {
-      stack[sp++] = make_int2(t.l, t.k);
+    int incl = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    int sp = __shfl(incl, 63);
+    if (sp > kHeavyStack) {  // excluded by the host's choice of nq_max; never silent
+      status = STATUS_CAPACITY;
+      break;
+    }
+    if (lane < nq) {
+      int pos = incl - cnt;
+      stack[pos++] = make_int2(t.l | lane << 8, t.k);
       for (int j = t.l; j < t.top; ++j) {
         const uint32_t pm = (uint32_t)(t.pend >> (4 * j)) & 15u;
         const int32_t anc = t.k >> (2 * (j - t.l));
         for (int i = 0; i < 4; ++i)
-          if (pm & (1u << i)) stack[sp++] = make_int2(j, (anc & ~3) + i);
+          if (pm & (1u << i)) stack[pos++] = make_int2(j | lane << 8, (anc & ~3) + i);
       }
     }
-    sp = __shfl(sp, 0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     while (sp > 0) {
@@ -697,13 +733,17 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
       sp -= take;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      uint32_t mask = 0;
-      const int lc = node.x - 1;
+      const int slot = node.x >> 8;
+      const int lc = (node.x & 255) - 1;
       const int64_t c0 = 4 * (int64_t)node.y;
+      const int64_t s = ss[slot];
+      uint32_t mask = 0;
       if (act) {
+        float q[6];
+        for (int c = 0; c < 6; ++c) q[c] = sq[slot][c];
         int64_t first = lc > 0 ? (s >> (2 * lc)) : s + 1;
-        if (global_part && lc == kSubLevels) first = blk + 1;
-        const int64_t lastc = (last - 1) >> (2 * lc);
+        if (spart[slot] != 0 && lc == kSubLevels) first = s / kBpBlock + 1;
+        const int64_t lastc = ((int64_t)slast[slot] - 1) >> (2 * lc);
         const int64_t mcount = lv.m[lc];
         const Box32* g = boxes + lv.off[lc] + c0;
         Box32 cb[4];
@@ -718,7 +758,10 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
       // leaves: exact tests and emission
       bool want[4] = {false, false, false, false};
       int32_t other[4] = {0, 0, 0, 0};
+      int32_t mine = 0;
       if (act && lc == 0 && mask) {
+        const LeafRec me = sme[slot];
+        mine = me.tri;
         LeafRec o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] = leaves[c0 + i];
@@ -731,26 +774,29 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
         }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) em.push(want[i], me.tri, other[i], sink);
-      // inner children: onto the stack (wave prefix sum of the counts)
-      const int cnt = act && lc > 0 ? __popc(mask) : 0;
-      int incl = cnt;
+      for (int i = 0; i < 4; ++i) em.push(want[i], mine, other[i], sink);
+      // inner children: onto the stack (wave prefix sum of the counts), with the slot tag
+      const int ccnt = act && lc > 0 ? __popc(mask) : 0;
+      int cincl = ccnt;
       for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d);
-        if (lane >= d) incl += y;
+        const int y = __shfl_up(cincl, d);
+        if (lane >= d) cincl += y;
       }
-      const int total = __shfl(incl, 63);
+      const int total = __shfl(cincl, 63);
       if (sp + total > kHeavyStack) {
-        status = STATUS_CAPACITY;  // cannot happen for trees of at most 24 levels; never silent
+        status = STATUS_CAPACITY;  // excluded by the bound above; never silent
         break;
       }
-      int pos = sp + incl - cnt;
+      int pos = sp + cincl - ccnt;
       for (int i = 0; i < 4; ++i)
-        if (cnt && (mask & (1u << i))) stack[pos++] = make_int2(lc, (int32_t)(c0 + i));
+        if (ccnt && (mask & (1u << i))) stack[pos++] = make_int2(lc | slot << 8, (int32_t)(c0 + i));
       sp += total;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
+    if (status) break;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the slot arrays are refilled by the next batch
   }
   block_flush<1>(em, wcount, &bbase, sink);
   if (status) atomicCAS(&ctr->status, 0, status);
@@ -1195,7 +1241,8 @@ hipError_t launch_broadphase(Ctx* c, const ttie_mesh* m, int method, const doubl
                                                               heavy_cap, budget, pairs, capacity, npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_TRAVERSE, s);
     stage_begin(c, TTIE_STAGE_BP_HEAVY, s);
-    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, va, pairs, capacity, npairs, ctr);
+    k_traverse_heavy<<<1024, 64, 0, s>>>(lv, boxes, leaves, heavy, heavy_cap, va, heavy_batch(lv.L), pairs, capacity,
+                                         npairs, ctr);
     stage_end(c, TTIE_STAGE_BP_HEAVY, s);
   }
   return hipGetLastError();

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +70,22 @@ def test_results_do_not_depend_on_params(which):
             ref = res
             assert res[0] == res[1]  # both broad phases give the same set
         assert res == ref, st
+
+
+@pytest.mark.parametrize("budget", [16, 24])
+def test_low_budgets_full_cloth(budget):
+    """At low traversal budgets most deferred work is many short searches, which the
+    wave-cooperative kernel takes in batches of up to 8 queries per wave (budget 16 defers
+    about 24,000 queries on the full cloth: three passes of the 1024-wave grid)."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0)
+    c = _ctx(len(x), len(tris))
+    c.set_param(ttie.PARAM_TRAV_BUDGET, budget)
+    pairs, n = c.broadphase(torch.from_numpy(x).cuda(), torch.from_numpy(tris).cuda(), ttie.BROAD_LBVH)
+    c.check()
+    got = pairs[: int(n.item())].cpu().numpy()
+    np.testing.assert_array_equal(got[np.lexsort((got[:, 1], got[:, 0]))], oracle.pairs(x, tris))
 
 
 def test_autotune_picks_valid_values():
