@@ -36,10 +36,10 @@ WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad p
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
 MEASURED = {
     "bp_traverse": [
-        {"bytes": 16643753, "valu_wave": 13793334, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "219aeedc0824de661cb64afef1b1a614a3e571170f6f8b1f9ccd7d4d932ed0a5", "params": {"trav_budget": 24}},
-        {"bytes": 16493665, "valu_wave": 14439390, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "219aeedc0824de661cb64afef1b1a614a3e571170f6f8b1f9ccd7d4d932ed0a5", "params": {"trav_budget": 32}},
+        {"bytes": 16645320, "valu_wave": 13830845, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+         "sha256": "daf8614b8b3d448e2ffaceeb2b271c6c6677c65393da828ed7715686a91ca9b3", "params": {"trav_budget": 24}},
+        {"bytes": 16495279, "valu_wave": 14487182, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+         "sha256": "daf8614b8b3d448e2ffaceeb2b271c6c6677c65393da828ed7715686a91ca9b3", "params": {"trav_budget": 32}},
     ],
 }
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)

@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
 // replaces at most 64 entries by at most 256 children one level down, so the stack holds at
 // most Q (1 + 3 L) + 3 * 64 * L + 64 entries; the host picks Q so that this fits kHeavyStack.
 constexpr int kHeavyStack = 4096;
-constexpr int kHeavyQ = 8;
+constexpr int kHeavyQ = 32;
 
 inline int heavy_batch(int L) {
   const int q = (kHeavyStack - 64 - 3 * 64 * L) / (1 + 3 * L);

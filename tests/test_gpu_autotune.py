@@ -75,8 +75,8 @@ def test_results_do_not_depend_on_params(which):
 @pytest.mark.parametrize("budget", [16, 24])
 def test_low_budgets_full_cloth(budget):
     """At low traversal budgets most deferred work is many short searches, which the
-    wave-cooperative kernel takes in batches of up to 8 queries per wave (budget 16 defers
-    about 24,000 queries on the full cloth: three passes of the 1024-wave grid)."""
+    wave-cooperative kernel takes in batches of up to 32 queries per wave (budget 16 defers
+    about 24,000 queries on the full cloth: about 24 per wave)."""
     from paper_2606_06511_amd import ttie
 
     x, tris = workloads.folded_cloth(0)
