@@ -9,10 +9,17 @@ the timed region; nothing is allocated inside it.
 
 Prints one JSON line.  Besides the contract fields it carries:
   fp64          the same step on the all-FP64 path
+  hits_per_s    intersecting pairs found per second of the step
+  eval_only, broadphase_only
+                the step split at the stage timers (candidate pairs/s of the evaluation,
+                triangles/s of the broad phase)
   err           relative errors of both paths against the FP64 CPU oracle
   stages        per-stage kernel time from the library's stage timers (warm-up steps)
   roofline      the dominant kernel's algorithmic bytes / its measured duration vs HBM peak
+  roofline_issue  the same kernel's VALU issue rate vs the VALU issue peak
   cpu_baseline  the CPU oracle timed on this host on the same workload
+  extra         the larger workloads (brute-force icospheres, 1M-triangle sphere, batch of 64,
+                Newton on the 4M-triangle sphere, quasi-static cloth)
 """
 
 from __future__ import annotations
@@ -399,6 +406,7 @@ def main():
         "config": {"workload": WORKLOAD, "n_verts": nv, "n_tris": nt, "pairs": P, "hits": H, "nnzb": nnzb,
                    "step": "broadphase+screen+derivatives+energy+gradient+BSR Hessian",
                    "launch_params": tuned},
+        "hits_per_s": H / (ms * 1e-3),  # intersecting pairs found per second of the whole step
         "autotune": {"ms_per_step_default_params": ms_default, "ms_per_step_tuned_params": ms_tuned},
         other: {"value": P / (ms_other * 1e-3), "ms_per_step": ms_other},
         "stages_ms_per_step": {k: round(v, 5) for k, v in per_step_stage.items()},
