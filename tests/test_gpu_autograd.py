@@ -127,3 +127,54 @@ def test_big_sphere_fp32_against_fp64_oracle(big_sphere):
         scale = max(np.abs(r["a"]).max(), np.abs(r["b"]).max())
         assert np.abs(h["a"][k] - r["a"]).max() <= 1e-3 * scale
         assert np.abs(h["b"][k] - r["b"]).max() <= 1e-3 * scale
+
+
+def test_big_sphere_per_pair_fd(big_sphere):
+    """Full 18-dof central differences of T (FP64) on 1,000 sampled hit pairs of the
+    1,048,576-triangle sphere, against the GPU's per-pair gradient (Eq. 3).  All perturbed
+    copies go to the GPU in one evaluation: a soup of disjoint triangle pairs, the sampled pairs
+    themselves and each one shifted by +-h along one dof.  A copy's vertices belong to its pair
+    only, so the base copies' gradient rows are the per-pair gradients.  Each pair is moved so
+    its first vertex is the origin (T does not change), and its step is 1e-5 of its shorter
+    interval end |t| (some hits overlap by less than 1e-6 along the line, and T has a kink where
+    an end reaches 0); the quotient divides by the step as represented.  A dof whose one-sided
+    slopes disagree by more than 1e-2 of the pair's largest gradient entry (a sign or an end
+    order changing within the step) would be skipped; at least 99% must be checked."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris, pairs, ref = big_sphere
+    hp = pairs[ref["hit_pair"]]
+    rng = np.random.default_rng(3)
+    idx = rng.choice(len(hp), size=1000, replace=False)
+    sel = hp[idx]
+    hk = 1e-5 * np.abs(ref["hit_t"][idx]).min(axis=1)
+    X0 = np.concatenate([x[tris[sel[:, 0]]], x[tris[sel[:, 1]]]], axis=1)  # (1000, 6, 3)
+    X0 = X0 - X0[:, :1, :]
+    copies, steps = [X0], []
+    for d in range(18):
+        Xp, Xm = X0.copy(), X0.copy()
+        Xp[:, d // 3, d % 3] += hk
+        Xm[:, d // 3, d % 3] -= hk
+        copies += [Xp, Xm]
+        steps.append(Xp[:, d // 3, d % 3] - Xm[:, d // 3, d % 3])
+    xs = np.ascontiguousarray(np.stack(copies).reshape(-1, 3))  # (37 x 1000 x 6, 3)
+    ts = np.arange(len(xs), dtype=np.int32).reshape(-1, 3)
+    pl = np.arange(len(ts), dtype=np.int32).reshape(-1, 2)
+    ctx = ttie.Context(0)
+    ctx.reserve(len(xs), len(ts), len(pl), max_hits=1 << 16, max_blocks=1 << 21)
+    out = ctx.evaluate(torch.from_numpy(xs).cuda(), torch.from_numpy(ts).cuda(), torch.from_numpy(pl).cuda(),
+                       precision=ttie.FP64, pair_T=True)
+    ctx.check()
+    T = out["pair_T"].cpu().numpy().reshape(37, 1000)
+    g = out["grad"].cpu().numpy().reshape(37, 1000, 18)[0]  # the base copies
+    assert np.all(T > 0)
+    scale = np.abs(g).max(axis=1)
+    checked = 0
+    for d in range(18):
+        Tp, Tm, st = T[1 + 2 * d], T[2 + 2 * d], steps[d]
+        fd = (Tp - Tm) / st
+        fwd, bwd = (Tp - T[0]) / (st / 2), (T[0] - Tm) / (st / 2)
+        smooth = np.abs(fwd - bwd) <= 1e-2 * scale
+        assert np.all(np.abs(fd - g[:, d])[smooth] <= 1e-4 * scale[smooth]), d
+        checked += int(smooth.sum())
+    assert checked >= 0.99 * 18 * 1000
