@@ -444,10 +444,22 @@ def main():
             if time.perf_counter() - t0 >= args.cpu_seconds:
                 break
         el = time.perf_counter() - t0
+        # the same on one thread (the box broad phase is single-threaded either way)
+        reps1 = 0
+        t1 = time.perf_counter()
+        while True:
+            p1 = oracle.pairs(x, tris, oracle.BROAD_BOXES)
+            oracle.evaluate(x, tris, p1, psd=oracle.PSD_PER_PART, hessian=True, threads=1)
+            reps1 += 1
+            if time.perf_counter() - t1 >= args.cpu_seconds / 2:
+                break
+        el1 = time.perf_counter() - t1
         rec["cpu_baseline"] = {"value": len(ref_pairs) * reps / el, "unit": "pairs/s", "cores": oracle.threads(),
                                "kind": "oracle",
                                "sample": f"the full workload (box broad phase + evaluation + BSR assembly), "
-                                         f"{reps} repetitions in {el:.1f} s"}
+                                         f"{reps} repetitions in {el:.1f} s",
+                               "value_1thread": len(p1) * reps1 / el1,
+                               "sample_1thread": f"the same on one thread, {reps1} repetitions in {el1:.1f} s"}
 
         def rel(a, b):
             a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
