@@ -44,9 +44,9 @@ WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad p
 MEASURED = {
     "bp_traverse": [
         {"bytes": 16645320, "valu_wave": 13830845, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "daf8614b8b3d448e2ffaceeb2b271c6c6677c65393da828ed7715686a91ca9b3", "params": {"trav_budget": 24}},
+         "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 24}},
         {"bytes": 16495279, "valu_wave": 14487182, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "daf8614b8b3d448e2ffaceeb2b271c6c6677c65393da828ed7715686a91ca9b3", "params": {"trav_budget": 32}},
+         "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 32}},
     ],
 }
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)

@@ -426,10 +426,11 @@ constexpr int kTravWaves = kTravThreads / 64;
 constexpr int kTopCap = 864;                        // 27 KB of top-level boxes
 
 // A lane that has visited `budget` nodes (a launch parameter, 128 by default) hands the rest
-// of its search to k_traverse_heavy
-// (one wave per query), by saving its depth-first state: the node it is about to visit and the
-// pending siblings of every ancestor up to its starting level.  Few queries get there -- those
-// whose boxes overlap hundreds of others, as in the fan of thin triangles around a pole.
+// of its search to k_traverse_heavy (a wave per query, or per batch of queries when many are
+// deferred), by saving its depth-first state: the node it is about to visit and the pending
+// siblings of every ancestor up to its starting level.  At the default budget few queries get
+// there -- those whose boxes overlap hundreds of others, as in the fan of thin triangles around
+// a pole; a low budget defers many short searches instead.
 struct TravState {
   int32_t s;      // query leaf (sorted position)
   int32_t part;   // 1: global part (skips the query's own level-4 subtree)
