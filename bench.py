@@ -90,12 +90,15 @@ def stage_bytes(stage, nv, nt, P, H, nnzb, prec_bytes):
     return table.get(stage, 0)
 
 
-def extra_configs(args, np, torch, ttie, workloads):
-    """The larger workloads, mixed precision, BSR Hessian on: the 1,048,576-triangle noisy
-    sphere (eager steps, stage breakdown) and the batch of 64 two-mesh problems (one step =
-    batched broad phase + batched evaluation, captured once in a HIP graph and replayed)."""
+def extra_configs(args, np, torch, ttie, workloads, only=None):
+    """The larger workloads: the two icospheres by brute force (FP64), the 1,048,576-triangle
+    noisy sphere (mixed, BSR on; eager steps, stage breakdown), the batch of 64 two-mesh problems
+    (one step = batched broad phase + batched evaluation, captured once in a HIP graph and
+    replayed), 20 Newton steps on the 4,194,304-triangle sphere (BSR and matrix-free) and the
+    quasi-static cloth.  ``only`` (a set of names) restricts the run to those workloads."""
     dev = torch.device("cuda", 0)
     res = {}
+    want = (lambda name: only is None or name in only)
 
     def run(step, steps):
         for _ in range(3):
@@ -107,164 +110,172 @@ def extra_configs(args, np, torch, ttie, workloads):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    # two icospheres, every non-adjacent pair (brute force), FP64
-    x, tris = workloads.two_icospheres(seed=0)
-    ctx = ttie.Context(0)
-    cap = 1 << 22
-    ctx.reserve(len(x), len(tris), cap, max_hits=1 << 12, max_blocks=36 << 12)
-    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
-    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-    n = torch.zeros(1, dtype=torch.int64, device=dev)
-    out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=ttie.FP64)
+    if want("icospheres_brute"):
+        # two icospheres, every non-adjacent pair (brute force), FP64
+        x, tris = workloads.two_icospheres(seed=0)
+        ctx = ttie.Context(0)
+        cap = 1 << 22
+        ctx.reserve(len(x), len(tris), cap, max_hits=1 << 12, max_blocks=36 << 12)
+        xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        n = torch.zeros(1, dtype=torch.int64, device=dev)
+        out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=ttie.FP64)
 
-    def ico_step():
-        ctx.broadphase(xd, td, ttie.BROAD_BRUTE, capacity=cap, out=(pairs, n))
-        ctx.evaluate(xd, td, pairs, n, precision=ttie.FP64, out=out)
+        def ico_step():
+            ctx.broadphase(xd, td, ttie.BROAD_BRUTE, capacity=cap, out=(pairs, n))
+            ctx.evaluate(xd, td, pairs, n, precision=ttie.FP64, out=out)
 
-    ms = run(ico_step, 20)
-    ctx.check()
-    P = int(n.item())
-    res["icospheres_brute"] = {"workload": "two icospheres (642 verts / 1280 tris each), all 3,260,220 non-adjacent "
-                                           "pairs, FP64, seed 0",
-                               "pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
-                               "pairs_per_s": P / (ms * 1e-3)}
-    del ctx, pairs, out
+        ms = run(ico_step, 20)
+        ctx.check()
+        P = int(n.item())
+        res["icospheres_brute"] = {"workload": "two icospheres (642 verts / 1280 tris each), all 3,260,220 non-adjacent "
+                                               "pairs, FP64, seed 0",
+                                   "pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
+                                   "pairs_per_s": P / (ms * 1e-3)}
+        del ctx, pairs, out
 
-    # noisy sphere, 1024 x 513 bands
-    x, tris = workloads.noisy_sphere(seed=0)
-    ctx = ttie.Context(0)
-    cap, hcap = 1 << 23, 1 << 17
-    ctx.reserve(len(x), len(tris), cap, max_hits=hcap, max_blocks=36 * hcap)
-    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
-    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-    n = torch.zeros(1, dtype=torch.int64, device=dev)
-    out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=ttie.MIXED)
+    if want("sphere_1m"):
+        # noisy sphere, 1024 x 513 bands
+        x, tris = workloads.noisy_sphere(seed=0)
+        ctx = ttie.Context(0)
+        cap, hcap = 1 << 23, 1 << 17
+        ctx.reserve(len(x), len(tris), cap, max_hits=hcap, max_blocks=36 * hcap)
+        xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        n = torch.zeros(1, dtype=torch.int64, device=dev)
+        out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=ttie.MIXED)
 
-    def sphere_step():
-        ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=cap, out=(pairs, n))
-        ctx.evaluate(xd, td, pairs, n, precision=ttie.MIXED, out=out)
+        def sphere_step():
+            ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=cap, out=(pairs, n))
+            ctx.evaluate(xd, td, pairs, n, precision=ttie.MIXED, out=out)
 
-    ms = run(sphere_step, 20)
-    ctx.check()
-    ctx.set_timing(None)
-    for _ in range(5):
-        sphere_step()
-    torch.cuda.synchronize()
-    st = ctx.read_timers()
-    ctx.set_timing([])
-    P = int(n.item())
-    bp_ms = sum(v[1] for k, v in st.items() if k.startswith("bp_")) / 5
-    res["sphere_1m"] = {"workload": "noisy UV sphere 1024x513 bands (524,290 verts, 1,048,576 tris), LBVH, seed 0",
-                        "pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
-                        "pairs_per_s": P / (ms * 1e-3), "broadphase_tris_per_s": len(tris) / (bp_ms * 1e-3),
-                        "stages_ms_per_step": {k: round(v[1] / 5, 5) for k, v in st.items()}}
-    del ctx, pairs, out
+        ms = run(sphere_step, 20)
+        ctx.check()
+        ctx.set_timing(None)
+        for _ in range(5):
+            sphere_step()
+        torch.cuda.synchronize()
+        st = ctx.read_timers()
+        ctx.set_timing([])
+        P = int(n.item())
+        bp_ms = sum(v[1] for k, v in st.items() if k.startswith("bp_")) / 5
+        res["sphere_1m"] = {"workload": "noisy UV sphere 1024x513 bands (524,290 verts, 1,048,576 tris), LBVH, seed 0",
+                            "pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
+                            "pairs_per_s": P / (ms * 1e-3), "broadphase_tris_per_s": len(tris) / (bp_ms * 1e-3),
+                            "stages_ms_per_step": {k: round(v[1] / 5, 5) for k, v in st.items()}}
+        del ctx, pairs, out
 
-    # 64 two-mesh problems in one batch
-    probs = workloads.batch_problems(seed=0)
-    x, tris, vert_off, tri_off = workloads.concat_problems(probs)
-    ctx = ttie.Context(0)
-    ctx.reserve(len(x), len(tris), cap, max_hits=hcap, max_blocks=36 * hcap)
-    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
-    vo, to = torch.from_numpy(vert_off).to(dev), torch.from_numpy(tri_off).to(dev)
-    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-    out = ctx.batch_evaluate(xd, td, vo, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev),
-                             precision=ttie.MIXED)
+    if want("batch64"):
+        # 64 two-mesh problems in one batch
+        probs = workloads.batch_problems(seed=0)
+        x, tris, vert_off, tri_off = workloads.concat_problems(probs)
+        ctx = ttie.Context(0)
+        cap, hcap = 1 << 23, 1 << 17
+        ctx.reserve(len(x), len(tris), cap, max_hits=hcap, max_blocks=36 * hcap)
+        n = torch.zeros(1, dtype=torch.int64, device=dev)
+        xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
+        vo, to = torch.from_numpy(vert_off).to(dev), torch.from_numpy(tri_off).to(dev)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        out = ctx.batch_evaluate(xd, td, vo, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev),
+                                 precision=ttie.MIXED)
 
-    def batch_step():
-        ctx.batch_broadphase(xd, td, to, capacity=cap, out=(pairs, n))
-        ctx.batch_evaluate(xd, td, vo, pairs, n, precision=ttie.MIXED, out=out)
+        def batch_step():
+            ctx.batch_broadphase(xd, td, to, capacity=cap, out=(pairs, n))
+            ctx.batch_evaluate(xd, td, vo, pairs, n, precision=ttie.MIXED, out=out)
 
-    # the launch parameters are tuned on this batch (coordinate descent over the step time),
-    # then the tuned step is captured
-    from paper_2606_06511_amd import autotune
+        # the launch parameters are tuned on this batch (coordinate descent over the step time),
+        # then the tuned step is captured
+        from paper_2606_06511_amd import autotune
 
-    tuned, ms_tuned, ms_default = autotune.tune(ctx, batch_step, reps=5, rounds=1)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        batch_step()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    ctx.check()
-    eager_E = out["energies"].cpu().numpy().copy()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, capture_error_mode="relaxed"):
-        batch_step()
-    out["energies"].zero_()
-    g.replay()
-    torch.cuda.synchronize()
-    ctx.check()
-    same = bool(np.array_equal(out["energies"].cpu().numpy(), eager_E))
-    ms_graph = run(g.replay, 20)
-    ms_eager = run(batch_step, 10)
-    ctx.check()
-    P = int(n.item())
-    res["batch64"] = {"workload": "64 two-mesh problems (icospheres, tori, bump grids; 2,842,166 verts, "
-                                  "5,664,096 tris), batched LBVH, seed 0",
-                      "problems": len(probs), "pairs": P, "hits": int(out["n_hits"].item()),
-                      "ms_per_step": ms_graph, "pairs_per_s": P / (ms_graph * 1e-3),
-                      "ms_per_step_eager": ms_eager, "graph_replay_matches_eager": same,
-                      "autotuned": tuned, "ms_eager_default_params": ms_default, "ms_eager_tuned_params": ms_tuned}
-    del ctx, pairs, out
+        tuned, ms_tuned, ms_default = autotune.tune(ctx, batch_step, reps=5, rounds=1)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            batch_step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        ctx.check()
+        eager_E = out["energies"].cpu().numpy().copy()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, capture_error_mode="relaxed"):
+            batch_step()
+        out["energies"].zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        ctx.check()
+        same = bool(np.array_equal(out["energies"].cpu().numpy(), eager_E))
+        ms_graph = run(g.replay, 20)
+        ms_eager = run(batch_step, 10)
+        ctx.check()
+        P = int(n.item())
+        res["batch64"] = {"workload": "64 two-mesh problems (icospheres, tori, bump grids; 2,842,166 verts, "
+                                      "5,664,096 tris), batched LBVH, seed 0",
+                          "problems": len(probs), "pairs": P, "hits": int(out["n_hits"].item()),
+                          "ms_per_step": ms_graph, "pairs_per_s": P / (ms_graph * 1e-3),
+                          "ms_per_step_eager": ms_eager, "graph_replay_matches_eager": same,
+                          "autotuned": tuned, "ms_eager_default_params": ms_default, "ms_eager_tuned_params": ms_tuned}
+        del ctx, pairs, out
 
-    # inexact Newton, 20 steps, on the 4,194,304-triangle sphere (Jacobi-PCG with 50 iterations)
-    from paper_2606_06511_amd.energy import TTIE
-    from paper_2606_06511_amd.newton import newton
+    if want("newton_4m"):
+        # inexact Newton, 20 steps, on the 4,194,304-triangle sphere (Jacobi-PCG with 50 iterations)
+        from paper_2606_06511_amd.energy import TTIE
+        from paper_2606_06511_amd.newton import newton
 
-    x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
-    model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 25, max_hits=1 << 17, precision=ttie.MIXED)
-    xd = torch.from_numpy(x).to(dev)
-    newton(model, xd, steps=1)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, hist = newton(model, xd, steps=20)
-    torch.cuda.synchronize()
-    total_ms = (time.perf_counter() - t0) * 1e3
-    steps = [h for h in hist if "alpha" in h]
-    res["newton_4m"] = {
-        "workload": "noisy UV sphere 2048x1025 bands (2,097,154 verts, 4,194,304 tris), 20 inexact Newton steps, "
-                    "BSR Hessian + Jacobi-PCG (50), Armijo, swept LBVH candidates",
-        "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist], "pairs": [h["pairs"] for h in hist],
-        "alpha": [h["alpha"] for h in steps], "ms_per_newton_step": [round(h["ms"], 3) for h in steps],
-        "total_ms": total_ms, "E_final_over_E0": hist[-1]["E"] / hist[0]["E"] if hist[0]["E"] else None,
-        "pairs_per_s": sum(h["pairs"] for h in steps) / (sum(h["ms"] for h in steps) * 1e-3)}
-    # the same 20 steps matrix-free: the solve applies the PSD Hessian from the hit records
-    newton(model, xd, steps=1, matrix_free=True)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, hist_mf = newton(model, xd, steps=20, matrix_free=True)
-    torch.cuda.synchronize()
-    steps_mf = [h for h in hist_mf if "alpha" in h]
-    res["newton_4m"]["matrix_free"] = {
-        "E": [h["E"] for h in hist_mf], "total_ms": (time.perf_counter() - t0) * 1e3,
-        "ms_per_newton_step": [round(h["ms"], 3) for h in steps_mf],
-        "E_final_over_E0": hist_mf[-1]["E"] / hist_mf[0]["E"] if hist_mf[0]["E"] else None}
-    del model
+        x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
+        model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 25, max_hits=1 << 17, precision=ttie.MIXED)
+        xd = torch.from_numpy(x).to(dev)
+        newton(model, xd, steps=1)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hist = newton(model, xd, steps=20)
+        torch.cuda.synchronize()
+        total_ms = (time.perf_counter() - t0) * 1e3
+        steps = [h for h in hist if "alpha" in h]
+        res["newton_4m"] = {
+            "workload": "noisy UV sphere 2048x1025 bands (2,097,154 verts, 4,194,304 tris), 20 inexact Newton steps, "
+                        "BSR Hessian + Jacobi-PCG (50), Armijo, swept LBVH candidates",
+            "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist], "pairs": [h["pairs"] for h in hist],
+            "alpha": [h["alpha"] for h in steps], "ms_per_newton_step": [round(h["ms"], 3) for h in steps],
+            "total_ms": total_ms, "E_final_over_E0": hist[-1]["E"] / hist[0]["E"] if hist[0]["E"] else None,
+            "pairs_per_s": sum(h["pairs"] for h in steps) / (sum(h["ms"] for h in steps) * 1e-3)}
+        # the same 20 steps matrix-free: the solve applies the PSD Hessian from the hit records
+        newton(model, xd, steps=1, matrix_free=True)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hist_mf = newton(model, xd, steps=20, matrix_free=True)
+        torch.cuda.synchronize()
+        steps_mf = [h for h in hist_mf if "alpha" in h]
+        res["newton_4m"]["matrix_free"] = {
+            "E": [h["E"] for h in hist_mf], "total_ms": (time.perf_counter() - t0) * 1e3,
+            "ms_per_newton_step": [round(h["ms"], 3) for h in steps_mf],
+            "E_final_over_E0": hist_mf[-1]["E"] / hist_mf[0]["E"] if hist_mf[0]["E"] else None}
+        del model
 
-    # quasi-static coupling on the folded cloth: springs on the edges (rest = the folded state),
-    # proximal weight m, energy weight w scaled with the inverse squared edge length
-    from paper_2606_06511_amd.quasistatic import QuasiStatic
+    if want("quasistatic_cloth"):
+        # quasi-static coupling on the folded cloth: springs on the edges (rest = the folded state),
+        # proximal weight m, energy weight w scaled with the inverse squared edge length
+        from paper_2606_06511_amd.energy import TTIE
+        from paper_2606_06511_amd.quasistatic import QuasiStatic
 
-    x, tris = workloads.folded_cloth(seed=0)
-    model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 22, max_hits=1 << 16)
-    xd = torch.from_numpy(x).to(dev)
-    sim = QuasiStatic(model, xd, k=1.0, m=1.0, w=1e6)
-    sim.step(xd, newton_iters=1)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, hist = sim.run(xd, 5, newton_iters=4, pcg_iters=50)
-    torch.cuda.synchronize()
-    total_ms = (time.perf_counter() - t0) * 1e3
-    its = [r for h in hist for r in h["newton"]]
-    res["quasistatic_cloth"] = {
-        "workload": "folded cloth 256x256 grid (130,050 tris), 5 quasi-static steps x 4 Newton iterations, springs "
-                    "k = 1 on the edges, proximal m = 1, energy weight w = 1e6, FP64, coupled Jacobi-PCG (50)",
-        "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist],
-        "phi": [[r["phi"] for r in h["newton"]] for h in hist[:-1]],
-        "alpha": [[r["alpha"] for r in h["newton"]] for h in hist[:-1]],
-        "ms_per_newton_iter": sum(r["ms"] for r in its) / max(len(its), 1), "total_ms": total_ms}
-    del model, sim
+        x, tris = workloads.folded_cloth(seed=0)
+        model = TTIE(torch.from_numpy(tris), len(x), max_pairs=1 << 22, max_hits=1 << 16)
+        xd = torch.from_numpy(x).to(dev)
+        sim = QuasiStatic(model, xd, k=1.0, m=1.0, w=1e6)
+        sim.step(xd, newton_iters=1)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hist = sim.run(xd, 5, newton_iters=4, pcg_iters=50)
+        torch.cuda.synchronize()
+        total_ms = (time.perf_counter() - t0) * 1e3
+        its = [r for h in hist for r in h["newton"]]
+        res["quasistatic_cloth"] = {
+            "workload": "folded cloth 256x256 grid (130,050 tris), 5 quasi-static steps x 4 Newton iterations, springs "
+                        "k = 1 on the edges, proximal m = 1, energy weight w = 1e6, FP64, coupled Jacobi-PCG (50)",
+            "E": [h["E"] for h in hist], "hits": [h["hits"] for h in hist],
+            "phi": [[r["phi"] for r in h["newton"]] for h in hist[:-1]],
+            "alpha": [[r["alpha"] for r in h["newton"]] for h in hist[:-1]],
+            "ms_per_newton_iter": sum(r["ms"] for r in its) / max(len(its), 1), "total_ms": total_ms}
+        del model, sim
 
     return res
 
@@ -282,6 +293,10 @@ def main():
     ap.add_argument("--params", default="", metavar="NAME=V,...",
                     help="fix launch parameters (trav_budget, screen_blocks, row_blocks) instead of autotuning them; "
                          "a profiler run uses this to time the configuration the autotuner picks")
+    ap.add_argument("--extra-only", default="", metavar="NAME,...",
+                    help="run only these larger workloads (icospheres_brute, sphere_1m, batch64, newton_4m, "
+                         "quasistatic_cloth) and print their records: for profiling one workload alone, "
+                         "not a benchmark line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="finish with one elementwise copy kernel over this many MB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -295,6 +310,11 @@ def main():
     import torch
 
     from paper_2606_06511_amd import ttie, workloads
+
+    if args.extra_only:
+        only = set(args.extra_only.split(","))
+        print(json.dumps({"extra": extra_configs(args, np, torch, ttie, workloads, only=only)}), flush=True)
+        return
 
     x, tris = workloads.folded_cloth(seed=0, n=256)
     nv, nt = len(x), len(tris)

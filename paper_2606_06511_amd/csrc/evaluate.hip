@@ -314,9 +314,11 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
       __builtin_amdgcn_wave_barrier();
       for (int32_t c = lane; c < m; c += 64) {
         const int32_t val = cand[c];
-        bool f = true;
-        for (int32_t j = 0; j < c && f; ++j) f = cand[j] != val;
-        first[c] = f ? 1 : 0;
+        // no early exit: the loads are independent, so they pipeline instead of each waiting
+        // for the previous compare
+        uint32_t dup = 0;
+        for (int32_t j = 0; j < c; ++j) dup |= (uint32_t)(cand[j] == val);
+        first[c] = dup ? 0 : 1;
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
