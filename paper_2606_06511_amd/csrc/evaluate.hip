@@ -255,6 +255,44 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kCandCap = 256;  // column candidates staged in LDS per wave
 constexpr int kRowStage = 16;  // incidences (and their hit records) a wave stages in LDS per row
 
+// The distinct columns of one row, in increasing vertex order, written to out: the six vertex
+// ids of every incident hit go to cand with a first-occurrence flag each, and a kept candidate
+// goes to the number of kept candidates with a smaller id.  Returns the count (every lane).
+template <class S>
+__device__ __forceinline__ int32_t row_columns(int32_t* cand, uint8_t* first, int32_t m, bool staged,
+                                               const Incidence* sinc, const Incidence* __restrict__ rinc,
+                                               const AsmRec<S>* __restrict__ recs, int32_t* __restrict__ out,
+                                               int lane) {
+  if (staged) {
+    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[sinc[c / 6].hit].vid[c % 6];
+  } else {
+    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[rinc[c / 6].hit].vid[c % 6];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int32_t c = lane; c < m; c += 64) {
+    const int32_t val = cand[c];
+    // no early exit: the loads are independent, so they pipeline instead of each waiting for
+    // the previous compare
+    uint32_t dup = 0;
+    for (int32_t j = 0; j < c; ++j) dup |= (uint32_t)(cand[j] == val);
+    first[c] = dup ? 0 : 1;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  int32_t kept = 0;
+  for (int32_t c = lane; c < m; c += 64) {
+    if (!first[c]) continue;
+    const int32_t val = cand[c];
+    int32_t pos = 0;
+    for (int32_t j = 0; j < m; ++j) pos += (int32_t)(first[j] != 0 && cand[j] < val);
+    out[pos] = val;
+    ++kept;
+  }
+  for (int w = 32; w > 0; w >>= 1) kept += __shfl_xor(kept, w);
+  return kept;
+}
+
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict__ touched, const Counters* ctr,
                                                       const int32_t* __restrict__ off,
@@ -300,40 +338,17 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
     }
     if (want_bsr) {
       // candidate columns: the six vertices of every incident hit, staged in LDS (or, for very
-      // large rows, in the workspace) with a first-occurrence flag each
+      // large rows, in the workspace) with a first-occurrence flag each.  The two cases are
+      // separate calls so that the LDS one reads LDS directly (a pointer that may point to
+      // either memory would compile to slower generic loads).
       const int32_t m = 6 * n;
-      const bool in_lds = m <= kCandCap;
-      int32_t* cand = in_lds ? lcand[wave] : cstage + 6 * (int64_t)b;
-      uint8_t* first = in_lds ? lflag[wave] : reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b;
-      if (n <= 64) {
-        for (int32_t c = lane; c < m; c += 64) cand[c] = recs[sinc[wave][c / 6].hit].vid[c % 6];
-      } else {
-        for (int32_t c = lane; c < m; c += 64) cand[c] = recs[inc[b + c / 6].hit].vid[c % 6];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int32_t c = lane; c < m; c += 64) {
-        const int32_t val = cand[c];
-        // no early exit: the loads are independent, so they pipeline instead of each waiting
-        // for the previous compare
-        uint32_t dup = 0;
-        for (int32_t j = 0; j < c; ++j) dup |= (uint32_t)(cand[j] == val);
-        first[c] = dup ? 0 : 1;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      // a kept candidate goes to the number of kept candidates with a smaller vertex id
-      int32_t kept = 0;
-      for (int32_t c = lane; c < m; c += 64) {
-        if (!first[c]) continue;
-        const int32_t val = cand[c];
-        int32_t pos = 0;
-        for (int32_t j = 0; j < m; ++j) pos += first[j] && cand[j] < val;
-        colbuf[6 * (int64_t)b + pos] = val;
-        ++kept;
-      }
-      // wave sum of kept
-      for (int w = 32; w > 0; w >>= 1) kept += __shfl_xor(kept, w);
+      int32_t kept;
+      if (m <= kCandCap)
+        kept = row_columns(lcand[wave], lflag[wave], m, n <= 64, sinc[wave], inc + b, recs, colbuf + 6 * (int64_t)b,
+                           lane);
+      else
+        kept = row_columns(cstage + 6 * (int64_t)b, reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
+                           m, false, sinc[wave], inc + b, recs, colbuf + 6 * (int64_t)b, lane);
       if (lane == 0) ncol[v] = kept;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
