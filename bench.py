@@ -43,9 +43,9 @@ WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad p
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
 MEASURED = {
     "bp_traverse": [
-        {"bytes": 16645320, "valu_wave": 13830845, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+        {"bytes": 16645751, "valu_wave": 13846425, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
          "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 24}},
-        {"bytes": 16495279, "valu_wave": 14487182, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
+        {"bytes": 16494401, "valu_wave": 14476783, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
          "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 32}},
     ],
 }
