@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the TTIE hot path on one MI355X.
 
-One step = the whole hot path over the folded-cloth workload (256 x 256 vertex grid,
-130,050 triangles, seed 0): LBVH broad phase -> screening of every candidate pair ->
-per-hit interval gradients -> energy, gradient and PSD block-sparse Hessian assembly.
-The metric is candidate pairs per second of that step.  Inputs are resident in HBM before
-the timed region; nothing is allocated inside it.
+Workload: the noisy UV sphere of 2048 x 1025 bands (2,097,154 vertices, 4,194,304 triangles,
+seed 0) -- the largest single-GPU configuration -- with its LBVH candidate list (16.3 M pairs)
+built once, before anything is timed.  One step = one evaluation of the whole candidate list:
+screening of every pair (plane sides, exact flag, interval ends) -> per-hit interval gradients
+-> energy, gradient and PSD block-sparse Hessian (pattern and values).  The metric is candidate
+pairs per second of that step.  The headline runs the all-FP64 path; the mixed path (float32
+per-hit algebra, float64 decisions) runs beside it.
+
+Timing: every rep is preceded by a 1 GiB write that evicts the L2s and the 256 MB Infinity
+Cache, and is bracketed by HIP events on the library's stream; the reported time is the median
+of the K reps.  Inputs are resident in HBM before the timed region and nothing is allocated in
+it.
 
 Prints one JSON line.  Besides the contract fields it carries:
-  fp64          the same step on the all-FP64 path
+  mixed         the same step on the mixed path (and its ratio to the FP64 one)
+  end_to_end    broad phase + evaluation per step (pairs/s), same flush and median
+  broadphase_only  the LBVH broad phase alone (triangles/s)
   hits_per_s    intersecting pairs found per second of the step
-  eval_only, broadphase_only
-                the step split at the stage timers (candidate pairs/s of the evaluation,
-                triangles/s of the broad phase)
-  err           relative errors of both paths against the FP64 CPU oracle
-  stages        per-stage kernel time from the library's stage timers (warm-up steps)
-  roofline      the dominant kernel's algorithmic bytes / its measured duration vs HBM peak
-  roofline_issue  the same kernel's VALU issue rate vs the VALU issue peak
-  cpu_baseline  the CPU oracle timed on this host on the same workload
-  extra         the larger workloads (brute-force icospheres, 1M-triangle sphere, batch of 64,
-                Newton on the 4M-triangle sphere, quasi-static cloth)
+  stages_ms_per_step   per-stage kernel time from the library's stage timers
+  roofline      the dominant kernel: its algorithmic bytes / its measured launch duration
+  roofline_path the whole step: the path's algorithmic bytes / the step's median time
+  err           element-wise errors of both paths against the FP64 CPU oracle on the full list
+  cpu_baseline  the CPU oracle timed on this host on the same candidate list
+  extra         the other workloads (folded cloth step, brute-force icospheres, 1M-triangle
+                sphere, batch of 64, Newton on the 4M-triangle sphere, quasi-static cloth)
 """
 
 from __future__ import annotations
@@ -34,21 +40,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad phase, seed 0"
+WORKLOAD = ("noisy UV sphere 2048x1025 bands (2,097,154 verts, 4,194,304 tris), LBVH candidates built once, "
+            "seed 0")
+FLUSH_BYTES = 1 << 30
 
-# Counter figures per launch of a kernel on this workload, valid only for the kernel source and
-# the launch parameters they were taken with (otherwise reported as null until taken again):
-#   bytes       HBM bytes from two rocprofv3 passes, FETCH_SIZE x 1.9998 and WRITE_SIZE x 1.0 (the
-#               factors that make a 256 MiB elementwise copy read and write 256 MiB)
+# Counter figures per launch of a kernel on the headline workload, valid only for the kernel
+# source and the launch parameters they were taken with (otherwise reported as null until taken
+# again):
+#   bytes       HBM bytes from two rocprofv3 passes, FETCH_SIZE x fetch_scale and WRITE_SIZE x
+#               write_scale (the factors that make a 256 MiB elementwise copy read and write
+#               256 MiB)
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
-MEASURED = {
-    "bp_traverse": [
-        {"bytes": 16645751, "valu_wave": 13846425, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 24}},
-        {"bytes": 16494401, "valu_wave": 14476783, "source": "paper_2606_06511_amd/csrc/broadphase.hip",
-         "sha256": "5efb9b997f8b387f40d5c27da6cb45273ad84ac11c0ce1cb456614f836aff4f7", "params": {"trav_budget": 32}},
-    ],
-}
+MEASURED = {}
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
 
@@ -59,11 +62,27 @@ def measured(stage, what, params=None):
     for m in MEASURED.get(stage, []):
         if params is not None and any(params.get(k) != v for k, v in m.get("params", {}).items()):
             continue
-        with open(os.path.join(ROOT, m["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
-                continue
-        return m[what]
+        ok = True
+        for src, sha in m["sources"].items():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                ok &= hashlib.sha256(f.read()).hexdigest() == sha
+        if ok:
+            return m[what]
     return None
+
+
+def path_bytes(nv, nt, P, H, nnzb, prec_bytes, flags=False):
+    """Algorithmic HBM bytes of one evaluation (screening through BSR assembly): each input read
+    once, each output written once, each hit record written once and read once."""
+    s = prec_bytes
+    return (8 * P                      # pair ids (int32 x 2)
+            + 12 * nt + 24 * nv        # triangle indices, float64 positions
+            + (P if flags else 0)      # per-pair flags
+            + 2 * (41 * s + 24) * H    # hit record: a, b, M, t0, t1, T (41 scalars) + 6 vertex ids
+            + 3 * s * nv               # gradient
+            + (9 * s + 4) * nnzb       # BSR values and column indices
+            + 4 * (nv + 1)             # BSR row pointers
+            + 8)                       # energy
 
 
 def stage_bytes(stage, nv, nt, P, H, nnzb, prec_bytes):
@@ -91,7 +110,8 @@ def stage_bytes(stage, nv, nt, P, H, nnzb, prec_bytes):
 
 
 def extra_configs(args, np, torch, ttie, workloads, only=None):
-    """The larger workloads: the two icospheres by brute force (FP64), the 1,048,576-triangle
+    """The other workloads: the folded cloth (broad phase + evaluation per step), the two
+    icospheres by brute force (FP64), the 1,048,576-triangle
     noisy sphere (mixed, BSR on; eager steps, stage breakdown), the batch of 64 two-mesh problems
     (one step = batched broad phase + batched evaluation, captured once in a HIP graph and
     replayed), 20 Newton steps on the 4,194,304-triangle sphere (BSR and matrix-free) and the
@@ -109,6 +129,32 @@ def extra_configs(args, np, torch, ttie, workloads, only=None):
             step()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
+
+    if want("cloth_step"):
+        # the folded cloth, one step = LBVH broad phase + evaluation with BSR (both precisions)
+        x, tris = workloads.folded_cloth(seed=0, n=256)
+        ctx = ttie.Context(0)
+        cap, hcap = 1 << 21, 1 << 16
+        ctx.reserve(len(x), len(tris), cap, max_hits=hcap, max_blocks=36 * hcap)
+        xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tris).to(dev)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        n = torch.zeros(1, dtype=torch.int64, device=dev)
+        rec = {"workload": "folded cloth 256x256 grid (65,536 verts, 130,050 tris), LBVH broad phase + evaluation, "
+                           "seed 0"}
+        for name, prec in (("fp64", ttie.FP64), ("mixed", ttie.MIXED)):
+            out = ctx.evaluate(xd, td, pairs[:1], torch.zeros(1, dtype=torch.int64, device=dev), precision=prec)
+
+            def cloth_step():
+                ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=cap, out=(pairs, n))
+                ctx.evaluate(xd, td, pairs, n, precision=prec, out=out)
+
+            ms = run(cloth_step, 50)
+            ctx.check()
+            P = int(n.item())
+            rec[name] = {"pairs": P, "hits": int(out["n_hits"].item()), "ms_per_step": ms,
+                         "pairs_per_s": P / (ms * 1e-3)}
+        res["cloth_step"] = rec
+        del ctx, pairs, out
 
     if want("icospheres_brute"):
         # two icospheres, every non-adjacent pair (brute force), FP64
@@ -280,21 +326,25 @@ def extra_configs(args, np, torch, ttie, workloads, only=None):
     return res
 
 
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return 0.5 * (v[(n - 1) // 2] + v[n // 2])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU oracle sample length")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="skip the larger configurations (1M-triangle sphere, 64-problem batch)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--params", default="", metavar="NAME=V,...",
-                    help="fix launch parameters (trav_budget, screen_blocks, row_blocks) instead of autotuning them; "
-                         "a profiler run uses this to time the configuration the autotuner picks")
+                    help="fix launch parameters (screen_blocks, row_blocks, trav_budget) instead of autotuning "
+                         "them; a profiler run uses this to time the configuration the autotuner picks")
     ap.add_argument("--extra-only", default="", metavar="NAME,...",
-                    help="run only these larger workloads (icospheres_brute, sphere_1m, batch64, newton_4m, "
+                    help="run only these other workloads (cloth_step, icospheres_brute, sphere_1m, batch64, newton_4m, "
                          "quasistatic_cloth) and print their records: for profiling one workload alone, "
                          "not a benchmark line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
@@ -316,16 +366,24 @@ def main():
         print(json.dumps({"extra": extra_configs(args, np, torch, ttie, workloads, only=only)}), flush=True)
         return
 
-    x, tris = workloads.folded_cloth(seed=0, n=256)
+    x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
     nv, nt = len(x), len(tris)
     dev = torch.device("cuda", 0)
     ctx = ttie.Context(0)
-    max_pairs, max_hits = 1 << 21, 1 << 16
+    max_pairs, max_hits = 1 << 25, 1 << 17
     ctx.reserve(nv, nt, max_pairs, max_hits=max_hits, max_blocks=36 * max_hits)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(tris).to(dev)
     pairs = torch.empty((max_pairs, 2), dtype=torch.int32, device=dev)
     npairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=max_pairs, out=(pairs, npairs))
+    torch.cuda.synchronize()
+    ctx.check()
+    P = int(npairs.item())
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+
+    def flush():
+        flush_buf.fill_(1.0)  # 1 GiB written: evicts the L2s and the Infinity Cache
 
     def outputs(dt):
         return {"energy": torch.zeros(1, dtype=torch.float64, device=dev),
@@ -336,40 +394,55 @@ def main():
                 "vals": torch.empty((36 * max_hits, 3, 3), dtype=dt, device=dev),
                 "n_blocks": torch.zeros(1, dtype=torch.int64, device=dev)}
 
-    precs = {"mixed": ttie.MIXED, "fp64": ttie.FP64}
-    outs = {"mixed": outputs(torch.float32), "fp64": outputs(torch.float64)}
+    precs = {"fp64": ttie.FP64, "mixed": ttie.MIXED}
+    outs = {"fp64": outputs(torch.float64), "mixed": outputs(torch.float32)}
+    bp_pairs = torch.empty_like(pairs)
+    bp_n = torch.zeros(1, dtype=torch.int64, device=dev)
 
     def step(name):
-        ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=max_pairs, out=(pairs, npairs))
         ctx.evaluate(xd, td, pairs, npairs, precision=precs[name], hessian=True, out=outs[name])
 
-    def timed(name, steps, warmup, stage=None):
+    def bp_step():
+        ctx.broadphase(xd, td, ttie.BROAD_LBVH, capacity=max_pairs, out=(bp_pairs, bp_n))
+
+    def e2e_step(name):
+        bp_step()
+        ctx.evaluate(xd, td, bp_pairs, bp_n, precision=precs[name], hessian=True, out=outs[name])
+
+    def timed(fn, steps, warmup, stage=None):
+        """Median over `steps` reps of fn's device time (HIP events on the current stream, the
+        stream the library launches on), each rep after a cache flush; with `stage`, that stage's
+        timers are on during the timed reps."""
         ctx.set_timing([])
         for _ in range(warmup):
-            step(name)
+            flush()
+            fn()
         torch.cuda.synchronize()
         ctx.check()
         ctx.read_timers()
         if stage:
             ctx.set_timing([stage])
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            step(name)
+        for e0, e1 in ev:
+            flush()
+            e0.record()
+            fn()
+            e1.record()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        wall = time.perf_counter() - t0
         tim = ctx.read_timers()
         ctx.set_timing([])
         ctx.check()
-        return (t1 - t0) * 1e3 / steps, tim
-
-    primary = args.precision
-    other = "fp64" if primary == "mixed" else "mixed"
+        ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        return median(ms), ms, wall, tim
 
     # launch parameters picked by the autotuner on this very step before anything is timed
     # (they change the speed only, never a result)
     from paper_2606_06511_amd import autotune
 
+    space = {k: v for k, v in autotune.SPACE.items() if k != "trav_budget"}
     if args.params:
         tuned = {}
         for item in args.params.split(","):
@@ -377,38 +450,45 @@ def main():
             ctx.set_param(autotune.SPACE[name][0], int(val))
             tuned[name] = int(val)
         ms_tuned = ms_default = None
+    elif args.no_tune:
+        tuned, ms_tuned, ms_default = {}, None, None
     else:
-        tuned, ms_tuned, ms_default = autotune.tune(ctx, lambda: step(primary), reps=20, rounds=1)
+        tuned, ms_tuned, ms_default = autotune.tune(ctx, lambda: step("fp64"), space=space, reps=5, rounds=1)
     torch.cuda.synchronize()
     ctx.check()
 
-    # stage breakdown from warm-up steps with every timer on
-    step(primary)
-    torch.cuda.synchronize()
-    ctx.read_timers()
-    ctx.set_timing(None)
-    for _ in range(max(5, args.warmup // 2)):
-        step(primary)
-    torch.cuda.synchronize()
-    stages = ctx.read_timers()
-    ctx.set_timing([])
-    nsteps_b = max(5, args.warmup // 2)
-    stage_avg = {k: v[1] / v[0] for k, v in stages.items()}
-    per_step_stage = {k: v[1] / nsteps_b for k, v in stages.items()}
-    dominant = max(per_step_stage, key=per_step_stage.get)
+    # stage breakdown from extra reps with every timer on (cache flushed before each)
+    nst = max(5, args.warmup)
+    per_step_stage = {}
+    for name in ("fp64", "mixed"):
+        ctx.set_timing(None)
+        for _ in range(nst):
+            flush()
+            step(name)
+        torch.cuda.synchronize()
+        st = ctx.read_timers()
+        ctx.set_timing([])
+        per_step_stage[name] = {k: v[1] / nst for k, v in st.items()}
+    dominant = max(per_step_stage["fp64"], key=per_step_stage["fp64"].get)
 
-    ms, tim = timed(primary, args.steps, args.warmup, stage=dominant)
-    ms_other, _ = timed(other, args.steps, args.warmup)
+    ms, ms_all, wall, tim = timed(lambda: step("fp64"), args.steps, args.warmup, stage=dominant)
+    ms_mixed, _, _, tim_mixed = timed(lambda: step("mixed"), args.steps, args.warmup, stage=dominant)
+    ms_e2e, _, _, _ = timed(lambda: e2e_step("fp64"), args.steps, args.warmup)
+    ms_e2e_mixed, _, _, _ = timed(lambda: e2e_step("mixed"), args.steps, args.warmup)
+    ms_bp, _, _, _ = timed(bp_step, args.steps, args.warmup)
+    ctx.check()
+    assert int(bp_n.item()) == P
 
-    P = int(npairs.item())
-    H = int(outs[primary]["n_hits"].item())
-    nnzb = int(outs[primary]["n_blocks"].item())
+    H = int(outs["fp64"]["n_hits"].item())
+    nnzb = int(outs["fp64"]["n_blocks"].item())
     value = P / (ms * 1e-3)
     dom_launches, dom_ms = tim.get(dominant, (0, 0.0))
     dom_avg_ms = dom_ms / max(dom_launches, 1)
-    prec_bytes = 4 if primary == "mixed" else 8
-    alg = stage_bytes(dominant, nv, nt, P, H, nnzb, prec_bytes)
+    alg = stage_bytes(dominant, nv, nt, P, H, nnzb, 8)
     achieved = alg / (dom_avg_ms * 1e-3) / 1e9 if dom_avg_ms > 0 else 0.0
+    b_path = path_bytes(nv, nt, P, H, nnzb, 8)
+    b_path_mixed = path_bytes(nv, nt, P, H, nnzb, 4)
+    traffic = measured(dominant, "bytes", tuned)
 
     rec = {
         "metric": "triangle pairs/s (energy+grad+PSD Hessian assembled), FP32 vs FP64 at stated err",
@@ -421,29 +501,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64pred" if primary == "mixed" else "f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n_verts": nv, "n_tris": nt, "pairs": P, "hits": H, "nnzb": nnzb,
-                   "step": "broadphase+screen+derivatives+energy+gradient+BSR Hessian",
+                   "step": "evaluation of the candidate list: screening + interval gradients + energy + gradient + "
+                           "BSR Hessian (pattern and values); candidates built before the timed region",
+                   "timing": "median of the reps, HIP events around each rep, 1 GiB cache flush before each",
                    "launch_params": tuned},
-        "hits_per_s": H / (ms * 1e-3),  # intersecting pairs found per second of the whole step
+        "ms_per_step_mean": sum(ms_all) / len(ms_all),
+        "timed_wall_s": wall,
+        "hits_per_s": H / (ms * 1e-3),
+        "mixed": {"value": P / (ms_mixed * 1e-3), "ms_per_step": ms_mixed, "dtype": "f32 per-hit algebra, f64 "
+                  "decisions, interval ends and energy", "speedup_vs_fp64": ms / ms_mixed},
+        "end_to_end": {"fp64": {"pairs_per_s": P / (ms_e2e * 1e-3), "ms_per_step": ms_e2e},
+                       "mixed": {"pairs_per_s": P / (ms_e2e_mixed * 1e-3), "ms_per_step": ms_e2e_mixed}},
+        "broadphase_only": {"ms_per_step": ms_bp, "tris_per_s": nt / (ms_bp * 1e-3)},
         "autotune": {"ms_per_step_default_params": ms_default, "ms_per_step_tuned_params": ms_tuned},
-        other: {"value": P / (ms_other * 1e-3), "ms_per_step": ms_other},
-        "stages_ms_per_step": {k: round(v, 5) for k, v in per_step_stage.items()},
-        # the same step split at the stage timers: evaluation only (screening through BSR
-        # assembly, candidate pairs per second of it) and the broad phase (triangles per second)
-        "eval_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if not k.startswith("bp_")),
-                      "pairs_per_s": P / (sum(v for k, v in per_step_stage.items() if not k.startswith("bp_")) * 1e-3)},
-        "broadphase_only": {"ms_per_step": sum(v for k, v in per_step_stage.items() if k.startswith("bp_")),
-                            "tris_per_s": nt / (sum(v for k, v in per_step_stage.items() if k.startswith("bp_")) * 1e-3)},
+        "stages_ms_per_step": {k: {s: round(v, 5) for s, v in d.items()} for k, d in per_step_stage.items()},
         "roofline": {"kernel_stage": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured(dominant, "bytes", tuned),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch",
                      "alg_bytes_per_launch": alg, "avg_launch_ms": dom_avg_ms, "launches": dom_launches},
+        "roofline_path": {"bound": "hbm", "alg_bytes_per_step": b_path,
+                          "achieved": b_path / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b_path / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "mixed": {"alg_bytes_per_step": b_path_mixed,
+                                    "frac": b_path_mixed / (ms_mixed * 1e-3) / 1e9 / HBM_PEAK_GBS}},
     }
-
-    # the same kernel against the VALU issue rate (its real bound: a latency- and issue-bound
-    # tree search), from the committed instruction count and the live duration
     vw = measured(dominant, "valu_wave", tuned)
     if vw and dom_avg_ms > 0:
         rate = vw * 64 / (dom_avg_ms * 1e-3)
@@ -454,45 +538,42 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        res = None
-        reps = 0
+        # the oracle on the same candidate list (sorted), all host threads, then on one thread
+        # over a slice of it
+        pl = pairs[:P].cpu().numpy()
+        pl = pl[np.lexsort((pl[:, 1], pl[:, 0]))]
         t0 = time.perf_counter()
-        while True:
-            ref_pairs = oracle.pairs(x, tris, oracle.BROAD_BOXES)
-            res = oracle.evaluate(x, tris, ref_pairs, psd=oracle.PSD_PER_PART, hessian=True)
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
+        ref = oracle.evaluate(x, tris, pl, psd=oracle.PSD_PER_PART, hessian=True)
         el = time.perf_counter() - t0
-        # the same on one thread (the box broad phase is single-threaded either way)
-        reps1 = 0
+        n1 = 400_000
         t1 = time.perf_counter()
-        while True:
-            p1 = oracle.pairs(x, tris, oracle.BROAD_BOXES)
-            oracle.evaluate(x, tris, p1, psd=oracle.PSD_PER_PART, hessian=True, threads=1)
-            reps1 += 1
-            if time.perf_counter() - t1 >= args.cpu_seconds / 2:
-                break
+        oracle.evaluate(x, tris, pl[:n1], psd=oracle.PSD_PER_PART, hessian=True, threads=1)
         el1 = time.perf_counter() - t1
-        rec["cpu_baseline"] = {"value": len(ref_pairs) * reps / el, "unit": "pairs/s", "cores": oracle.threads(),
-                               "kind": "oracle",
-                               "sample": f"the full workload (box broad phase + evaluation + BSR assembly), "
-                                         f"{reps} repetitions in {el:.1f} s",
-                               "value_1thread": len(p1) * reps1 / el1,
-                               "sample_1thread": f"the same on one thread, {reps1} repetitions in {el1:.1f} s"}
-
-        def rel(a, b):
-            a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
+        rec["cpu_baseline"] = {"value": P / el, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"the whole workload: all {P:,} candidates (evaluation + BSR assembly, "
+                                         f"no broad phase), once, in {el:.1f} s",
+                               "value_1thread": n1 / el1,
+                               "sample_1thread": f"the first {n1:,} candidates in canonical order on one thread, "
+                                                 f"{el1:.1f} s"}
         err = {}
-        for name in ("mixed", "fp64"):
+        for name in ("fp64", "mixed"):
             o = outs[name]
+            e = {"energy_rel": abs(o["energy"].item() - ref["E"]) / abs(ref["E"])}
+            g = o["grad"].cpu().numpy().astype(np.float64)
+            e["grad_rel_norm"] = float(np.linalg.norm(g - ref["G"]) / np.linalg.norm(ref["G"]))
             nb = int(o["n_blocks"].item())
-            err[name] = {"energy_rel": abs(o["energy"].item() - res["E"]) / abs(res["E"]),
-                         "grad_rel": rel(o["grad"].cpu().numpy(), res["G"]),
-                         "hess_rel": rel(o["vals"][:nb].cpu().numpy(), res["vals"])
-                         if nb == len(res["vals"]) else None}
+            if nb == len(ref["vals"]):
+                rp = o["row_ptr"].cpu().numpy()
+                same = bool(np.array_equal(rp, ref["row_ptr"]) and
+                            np.array_equal(o["col_idx"][:nb].cpu().numpy(), ref["col_idx"]))
+                v = o["vals"][:nb].cpu().numpy().astype(np.float64)
+                # per block, relative to the largest entry of its block row
+                row = np.repeat(np.arange(nv), np.diff(ref["row_ptr"]))
+                rmax = np.zeros(nv)
+                np.maximum.at(rmax, row, np.abs(ref["vals"]).reshape(nb, 9).max(1))
+                e["bsr_pattern_identical"] = same
+                e["bsr_max_rel_to_row"] = float((np.abs(v - ref["vals"]).reshape(nb, 9).max(1) / rmax[row]).max())
+            err[name] = e
         rec["err"] = err
     if not args.no_extra:
         rec["extra"] = extra_configs(args, np, torch, ttie, workloads)

@@ -217,12 +217,42 @@ ttie_status ttie_batch_eval(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems
                             int64_t* n_blocks, int64_t* n_hits, void* stream);
 
 /* Copies the last evaluation's intersecting pairs, sorted by (i, j), to HOST buffers of
- * `capacity` entries: pair indices (i, j) int32 x 2, t_c (float64 x 2), T (float64) and the
- * interval gradients a = dt_c^0, b = dt_c^1 (float64 x 18 each, converted from the
- * evaluation's precision).  Synchronizes `stream`; *count_host receives the hit count
- * (TTIE_ERR_CAPACITY if it exceeds capacity).  Any output pointer may be NULL. */
+ * `capacity` entries: pair indices (i, j) int32 x 2, t_c (float64 x 2, Eq. 1), T (float64,
+ * Eq. 2), the interval gradients a = dt_c^0, b = dt_c^1 and the pair's energy gradient
+ * g = 2 t0 t1^2 a + 2 t0^2 t1 b (Eq. 3) (float64 x 18 each, converted from the evaluation's
+ * precision), and the 2x2 core M of the pair's Hessian J^T M J (float64 x 3: M00, M01, M11;
+ * Eq. 4 as projected by the evaluation's PSD mode).  Synchronizes `stream`; *count_host
+ * receives the hit count (TTIE_ERR_CAPACITY if it exceeds capacity).  Any output pointer may be
+ * NULL.  A diagnostic call (host copies): it is in no timed path. */
 ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij_host, double* tc_host, double* T_host,
-                          double* a_host, double* b_host, int64_t* count_host, void* stream);
+                          double* a_host, double* b_host, double* g_host, double* M_host, int64_t* count_host,
+                          void* stream);
+
+/* ---- the Hessian as two calls: pattern, then values --------------------------------------
+ * The BSR Hessian of the last ttie_eval (Eq. 4 per pair as projected by its PSD mode, summed
+ * over the intersecting pairs; Sec. 1.2 records each pair's derivatives to build the global
+ * matrix), split so that a caller can size the pattern before taking the values and refresh the
+ * values on a pattern it keeps.  Both read the hit records and incidence lists that ttie_eval
+ * leaves in the workspace (valid until the next ttie_eval or ttie_springs_pattern); the ttie_eval
+ * call itself may have skipped its own BSR output.
+ *
+ * ttie_bsr_symbolic: the pattern -- the union over intersecting pairs of their 6 x 6 vertex
+ * blocks, full symmetric storage, columns sorted per row.  row_ptr: n_verts + 1 int32 (every
+ * entry written); col_idx: up to `capacity` int32; *n_blocks (device int64, 8-byte aligned)
+ * receives nnzb.  When nnzb exceeds capacity only the columns that fit are written and
+ * TTIE_ERR_CAPACITY is latched (row_ptr and *n_blocks are still complete, so the caller can
+ * size col_idx from them and call again). */
+ttie_status ttie_bsr_symbolic(ttie_ctx* ctx, int32_t* row_ptr, int32_t* col_idx, int64_t capacity,
+                              int64_t* n_blocks, void* stream);
+
+/* ttie_bsr_numeric: the values on a caller's pattern (row_ptr, col_idx with sorted columns, over
+ * the last evaluation's n_verts rows), e.g. one from ttie_bsr_symbolic of an earlier evaluation.
+ * vals: row_ptr[n_verts] x 3 x 3 in the last evaluation's precision, every block written: the
+ * blocks the hits give, summed in the order of ttie_eval's own assembly (identical values on
+ * the same pattern), and 0 elsewhere.  A pattern that misses a block the hits need latches
+ * TTIE_ERR_INVALID_ARGUMENT (the values are then incomplete). */
+ttie_status ttie_bsr_numeric(ttie_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx, void* vals,
+                             void* stream);
 
 /* Hessian-vector product of the energy at the positions of the last ttie_eval (same mesh
  * and x): Hv = H v, v and Hv n_verts x 3 in the evaluation's precision.  mode

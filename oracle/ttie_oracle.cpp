@@ -35,7 +35,10 @@
 //     (k, k1, k2) in the triangle times the side of k1 (negated for T_b, whose cut lies on the
 //     plane of T_a and D = n_a x n_b), so two different endpoints never tie;
 //   - pairs sharing a vertex index are "adjacent" and carry no energy;
-//   - a hit whose FP64 line direction has zero length is reported with status 3 and T = 0;
+//   - a hit whose FP64 line direction D = n_a x n_b (normals and D rounded as written, no fused
+//     operations) is exactly (0, 0, 0) is reported with status 3 and T = 0: the exact D of a
+//     hit is never zero (both triangles straddle the other's plane), so this happens only
+//     when the rounded normals come out parallel;
 //   - two triangles lying in one plane have no segment and no line, so T = 0 (the paper sets
 //     coplanar pairs aside); when their interiors overlap the pair is reported with status 4,
 //     still with T = 0, so that a caller can see where the energy is blind.
@@ -514,8 +517,16 @@ bool interval_ends(const V3<S> U[3], const V3<S> V[3], const Tri& ta, const Tri&
   V3<S> un = cross(U[1] - U[0], U[2] - U[0]);
   V3<S> vn = cross(V[1] - V[0], V[2] - V[0]);
   V3<S> D = cross(un, vn);
+  // The line frame is undefined only when the FP64 direction is exactly (0, 0, 0).  Otherwise
+  // D is first multiplied by 2^-e, e the exponent of its largest component: an exact scaling
+  // (in two factors, so that neither over- nor underflows) that leaves D/|D| unchanged and
+  // keeps |D|^2 finite and non-zero over the whole coordinate domain.
+  const double m = std::max(std::fabs(val(D.x)), std::max(std::fabs(val(D.y)), std::fabs(val(D.z))));
+  if (!(m > 0.0)) return false;
+  const int e = std::ilogb(m);
+  D = scale(std::ldexp(1.0, -(e / 2)), D);
+  D = scale(std::ldexp(1.0, -(e - e / 2)), D);
   S len = dsqrt(dot(D, D));
-  if (!(val(len) > 0.0)) return false;
   D = div(D, len);
   V3<S> A = scale(0.25, Sa[0] + Sa[1] + Sb[0] + Sb[1]);
   S t00 = dot(D, Sa[0] - A), t01 = dot(D, Sa[1] - A);

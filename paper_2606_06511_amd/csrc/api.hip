@@ -365,11 +365,11 @@ ttie_status ttie_batch_eval(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems
 }
 
 ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij, double* tc, double* T, double* a, double* b,
-                          int64_t* count_host, void* stream) {
+                          double* g, double* M, int64_t* count_host, void* stream) {
   if (ttie_status st = need_ws(ctx)) return st;
   if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation yet");
   if (!count_host || capacity < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad argument");
-  DeviceGuard g(ctx->device);
+  DeviceGuard guard(ctx->device);
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   Counters ctr;
   if (e == hipSuccess) e = hipMemcpy(&ctr, ctx->ws + ctx->L.counters, sizeof(ctr), hipMemcpyDeviceToHost);
@@ -401,22 +401,51 @@ ttie_status ttie_get_hits(ttie_ctx* ctx, int64_t capacity, int32_t* ij, double* 
       tc[2 * q + 1] = h.t1;
     }
     for (int z = 0; z < 18; ++z) {
-      double av, bv;
+      double av, bv, gv, mv = 0.0;
       if (fp64) {
         const auto* r = reinterpret_cast<const AsmRec<double>*>(rec.data() + k * rs);
         av = r->a[z];
         bv = r->b[z];
+        gv = r->g[z];
+        if (z < 3) mv = r->M[z];
         if (T && z == 0) T[q] = r->T;
       } else {
         const auto* r = reinterpret_cast<const AsmRec<float>*>(rec.data() + k * rs);
         av = r->a[z];
         bv = r->b[z];
+        gv = r->g[z];
+        if (z < 3) mv = r->M[z];
         if (T && z == 0) T[q] = r->T;
       }
       if (a) a[18 * q + z] = av;
       if (b) b[18 * q + z] = bv;
+      if (g) g[18 * q + z] = gv;
+      if (M && z < 3) M[3 * q + z] = mv;
     }
   }
+  return TTIE_OK;
+}
+
+ttie_status ttie_bsr_symbolic(ttie_ctx* ctx, int32_t* row_ptr, int32_t* col_idx, int64_t capacity, int64_t* n_blocks,
+                              void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation yet");
+  if (!row_ptr || !n_blocks || capacity < 0 || (capacity > 0 && !col_idx))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "bad output arrays");
+  if (((uintptr_t)n_blocks) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "n_blocks must be 8-byte aligned");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_bsr_symbolic(ctx, row_ptr, col_idx, capacity, n_blocks, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_bsr_symbolic");
+  return TTIE_OK;
+}
+
+ttie_status ttie_bsr_numeric(ttie_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx, void* vals, void* stream) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (!ctx->last_valid) return fail(TTIE_ERR_INVALID_ARGUMENT, "no evaluation yet");
+  if (!row_ptr || !col_idx || !vals) return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL array");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_bsr_numeric(ctx, row_ptr, col_idx, vals, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ttie_bsr_numeric");
   return TTIE_OK;
 }
 

@@ -403,13 +403,6 @@ __device__ __forceinline__ void block_flush(WaveEmitter& em, int* wcount, int64_
   }
 }
 
-// Blocks are dealt to the XCDs round-robin; renumbering them so that each XCD runs a
-// contiguous range of logical blocks keeps each XCD's L2 on one region of the Morton order.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-  const int64_t per = nblocks / 8;
-  return (b % 8) * per + b / 8;
-}
-
 // Two lanes per leaf s, depth-first over the subtrees holding leaves after s.  A visited node
 // tests its four children at once (one contiguous load); the pending children of every level
 // on the current path are kept as 4-bit masks in one 64-bit word, so no stack is needed.

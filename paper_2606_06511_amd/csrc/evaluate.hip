@@ -26,6 +26,7 @@
 namespace ttie {
 
 constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ void latch(int32_t* status, int code) { atomicCAS(status, 0, code); }
 
@@ -116,19 +117,149 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
   }
 }
 
-// fast pass over every candidate: FP64 filters only, uncertain pairs deferred
+// ---- the fast pass: FP64 filters only, uncertain pairs deferred --------------------------
+// The screening of Sec. 1 is a cascade whose stages let fewer and fewer pairs through: on the
+// noisy spheres about 35% of the candidates have a vertex of T_a on each side of T_b's plane,
+// about 19% also the converse, and 0.2% intersect.  One lane per candidate all the way down
+// would make every wave execute every stage (some lane nearly always goes on).  Instead each
+// wave runs a stage on 64 candidates at once and queues the survivors in LDS; the next stage
+// runs when 64 are queued.  The last stage is the full screening of screen_one, so every
+// decision and value is exactly the one-pass result.
+constexpr int kQueue = 128;  // queue slots per wave and stage (at most 63 waiting + 64 arriving)
+
+enum { STEP_SETTLED = 0, STEP_DEFER = 1, STEP_NEXT = 2, STEP_FULL = 3 };
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Appends the lanes that want it to a wave's LDS queue; n is wave-uniform.
+__device__ __forceinline__ void queue_push(uint32_t* q, int& n, bool want, int64_t p) {
+  const uint64_t mask = __ballot(want);
+  if (want) q[n + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = (uint32_t)p;
+  n += __popcll(mask);
+  wave_sync_lds();
+}
+
+__device__ __forceinline__ void defer_append(bool want, int64_t p, int32_t* defer, int64_t max_defer, Counters* ctr,
+                                             int& status) {
+  const uint32_t ds = wave_slot(want, &ctr->n_defer);
+  if (want) {
+    if ((int64_t)ds < max_defer) defer[ds] = (int32_t)p;
+    else status = STATUS_CAPACITY;
+  }
+}
+
+__device__ __forceinline__ void settle(int64_t p, int kind, uint8_t* flags, double* pair_T) {
+  if (flags) flags[p] = (uint8_t)kind;
+  if (pair_T) pair_T[p] = 0.0;
+}
+
+__device__ __forceinline__ bool load_pair(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
+                                          const int32_t* pairs, int32_t vi[3], int32_t vj[3], Tri64& A, Tri64& B) {
+  const int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+  if (i < 0 || j < 0 || i >= nt || j >= nt || i == j) return false;
+  return load_tri(x, nv, tris, i, vi, A) && load_tri(x, nv, tris, j, vj, B);
+}
+
+// Stage 1 (every candidate): indices, adjacency, T_a's sides against T_b's plane.
+__device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
+                                             const int32_t* pairs, bool va, uint8_t* flags, double* pair_T,
+                                             int& status) {
+  int32_t vi[3], vj[3];
+  Tri64 A, B;
+  if (!load_pair(p, x, nv, tris, nt, pairs, vi, vj, A, B)) {
+    status = STATUS_INDEX;
+    settle(p, PAIR_NONE, flags, pair_T);
+    return STEP_SETTLED;
+  }
+  if (is_adjacent(vi, vj, va)) {
+    settle(p, PAIR_ADJACENT, flags, pair_T);
+    return STEP_SETTLED;
+  }
+  int sa[3];
+  double da[3];
+  if (!plane_sides<false>(B, A, sa, da, status)) return STEP_DEFER;
+  if ((sa[0] | sa[1] | sa[2]) == 0) return STEP_FULL;  // T_a in T_b's plane: the coplanar test
+  if (!make_cut(sa[0], sa[1], sa[2]).straddle) {
+    settle(p, PAIR_NONE, flags, pair_T);
+    return STEP_SETTLED;
+  }
+  return STEP_NEXT;
+}
+
+// Stage 2 (T_a straddles T_b's plane): T_b's sides against T_a's plane.
+__device__ __forceinline__ int screen_stage2(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
+                                             const int32_t* pairs, uint8_t* flags, double* pair_T, int& status) {
+  int32_t vi[3], vj[3];
+  Tri64 A, B;
+  load_pair(p, x, nv, tris, nt, pairs, vi, vj, A, B);  // checked in stage 1
+  int sb[3];
+  double db[3];
+  if (!plane_sides<false>(A, B, sb, db, status)) return STEP_DEFER;
+  if (!make_cut(sb[0], sb[1], sb[2]).straddle) {
+    settle(p, PAIR_NONE, flags, pair_T);
+    return STEP_SETTLED;
+  }
+  return STEP_NEXT;
+}
+
 __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
                                                    const int32_t* __restrict__ tris, int64_t nt,
                                                    const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
                                                    int64_t max_pairs, double half, int va, HitGeom* __restrict__ hits,
                                                    uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
                                                    uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
+  __shared__ uint32_t q1s[kWaves][kQueue], q2s[kWaves][kQueue];
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  uint32_t* q1 = q1s[wave];
+  uint32_t* q2 = q2s[wave];
   const int64_t np = min(*n_pairs_dev, max_pairs);
-  int status = 0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = base + threadIdx.x;
-    screen_one<false>(p < np ? p : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr,
-                      flags, pair_T, status);
+  // each wave screens one contiguous chunk of the list; blocks are renumbered so that each XCD
+  // runs a contiguous range of chunks (its L2 then sees one region of the mesh)
+  const int64_t G = gridDim.x;
+  const int64_t lb = (G % 8 == 0) ? xcd_block(blockIdx.x, G) : (int64_t)blockIdx.x;
+  const int64_t nw = G * kWaves;
+  const int64_t chunk = ((np + nw - 1) / nw + 63) / 64 * 64;
+  const int64_t beg = (lb * kWaves + wave) * chunk, end = min(np, beg + chunk);
+  int n1 = 0, n2 = 0, status = 0;
+  int64_t base = beg;
+  // One stage per round, chosen wave-uniformly: the last stage as soon as 64 candidates wait for
+  // it, then the middle one, then a new batch; at the end of the chunk the queues drain.  Each
+  // stage runs from one place in the code, so only one of them is live in registers at a time.
+  // Stage 1 runs only with both queues below 64 and stage 2 only with the last one below 64, so
+  // no queue ever holds more than 127.
+  while (true) {
+    const bool more = base < end;
+    int st = STEP_SETTLED;
+    int64_t p = -1;
+    if (n2 >= 64 || (!more && n1 == 0 && n2 > 0)) {
+      const int take = min(n2, 64);
+      p = lane < take ? (int64_t)q2[n2 - take + lane] : -1;
+      wave_sync_lds();
+      n2 -= take;
+      screen_one<false>(p, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags,
+                        pair_T, status);
+      continue;
+    }
+    if (n1 >= 64 || (!more && n1 > 0)) {
+      const int take = min(n1, 64);
+      p = lane < take ? (int64_t)q1[n1 - take + lane] : -1;
+      wave_sync_lds();
+      n1 -= take;
+      if (p >= 0) st = screen_stage2(p, x, nv, tris, nt, pairs, flags, pair_T, status);
+      defer_append(st == STEP_DEFER, p, defer, max_pairs, ctr, status);
+      queue_push(q2, n2, st == STEP_NEXT, p);
+      continue;
+    }
+    if (!more) break;
+    p = base + lane < end ? base + lane : -1;
+    base += 64;
+    if (p >= 0) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, status);
+    defer_append(st == STEP_DEFER, p, defer, max_pairs, ctr, status);
+    queue_push(q2, n2, st == STEP_FULL, p);
+    queue_push(q1, n1, st == STEP_NEXT, p);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -151,15 +282,28 @@ __global__ void __launch_bounds__(kBlock) k_screen_exact(const double* __restric
   if (status) latch(&ctr->status, status);
 }
 
-// pair-local coordinates (origin u0) of a hit, in scalar S
+// Pair-local coordinates of a hit in scalar S: relative to u0 (formed in float64) and multiplied
+// by 2^-e, e the exponent of the largest of them (returned), so that the largest lies in [1, 2).
+// Scaling by a power of two is exact and changes no relative rounding; it only keeps a tiny or
+// huge pair's products inside float32's range.
 template <class S>
-__device__ __forceinline__ void local_coords(const double* x, const int32_t vid[6], V3<S> X[6]) {
+__device__ __forceinline__ int local_coords(const double* x, const int32_t vid[6], V3<S> X[6]) {
   const double o0 = x[3 * (int64_t)vid[0]], o1 = x[3 * (int64_t)vid[0] + 1], o2 = x[3 * (int64_t)vid[0] + 2];
+  double d[6][3];
+  double m = 0.0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const double* p = x + 3 * (int64_t)vid[k];
-    X[k] = V3<S>{Sc<S>::c(p[0] - o0), Sc<S>::c(p[1] - o1), Sc<S>::c(p[2] - o2)};
+    d[k][0] = p[0] - o0;
+    d[k][1] = p[1] - o1;
+    d[k][2] = p[2] - o2;
+    m = fmax(m, fmax(fabs(d[k][0]), fmax(fabs(d[k][1]), fabs(d[k][2]))));
   }
+  const int e = m > 0.0 ? ilogb(m) : 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    X[k] = V3<S>{Sc<S>::c(ldexp(d[k][0], -e)), Sc<S>::c(ldexp(d[k][1], -e)), Sc<S>::c(ldexp(d[k][2], -e))};
+  return e;
 }
 
 __device__ __forceinline__ void hit_vids(const int32_t* tris, int64_t key, int32_t vid[6]) {
@@ -188,8 +332,8 @@ __global__ void __launch_bounds__(kBlock) k_derivs(const double* __restrict__ x,
       r.pad = 0;
       r.key = g.key;
       V3<S> X[6];
-      local_coords<S>(x, r.vid, X);
-      interval_grads<S>(X, g.da, g.db, g.desc, half, r.a, r.b);
+      const int e = local_coords<S>(x, r.vid, X);
+      interval_grads<S>(X, g.da, g.db, e, g.desc, half, r.a, r.b);
       const double t0 = g.t0, t1 = g.t1;
       const double pr = t0 * t1;
       r.T = pr * pr;
@@ -251,7 +395,6 @@ __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ r
   }
 }
 
-constexpr int kWaves = kBlock / 64;
 constexpr int kCandCap = 256;  // column candidates staged in LDS per wave
 constexpr int kRowStage = 16;  // incidences (and their hit records) a wave stages in LDS per row
 
@@ -553,9 +696,135 @@ __global__ void __launch_bounds__(kBlock) k_eval_finish(int nblocks, const doubl
     if (nb > block_cap) latch(&ctr->status, STATUS_CAPACITY);
   }
   ctr->last_hits = min(H, max_hits);
+  ctr->last_touched = ctr->n_touched;
   ctr->n_hits = 0;
   ctr->n_defer = 0;
   ctr->n_touched = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// The BSR Hessian of the last evaluation as two calls: the pattern (symbolic) and the values
+// on a caller's pattern (numeric), from the hit records and the sorted incidence lists the
+// evaluation leaves in the workspace.
+// ------------------------------------------------------------------------------------------
+// Symbolic, first pass: the distinct columns of every touched row (as in k_rows_sort) and
+// their count.
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_sym_cols(const int32_t* __restrict__ touched, const Counters* ctr,
+                                                     const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc2,
+                                                     const AsmRec<S>* __restrict__ recs, int32_t* __restrict__ colbuf,
+                                                     int32_t* __restrict__ cstage, int64_t cstage_len,
+                                                     int32_t* __restrict__ ncol) {
+  __shared__ int32_t lcand[kWaves][kCandCap];
+  __shared__ uint8_t lflag[kWaves][kCandCap];
+  __shared__ Incidence sinc[kWaves][64];
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  const uint32_t U = ctr->last_touched;
+  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
+    const int32_t v = touched[u];
+    const int32_t b = off[v], n = off[v + 1] - b;
+    const int32_t m = 6 * n;
+    int32_t kept;
+    if (m <= kCandCap)
+      kept = row_columns(lcand[wave], lflag[wave], m, false, sinc[wave], inc2 + b, recs, colbuf + 6 * (int64_t)b,
+                         lane);
+    else
+      kept = row_columns(cstage + 6 * (int64_t)b, reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
+                         m, false, sinc[wave], inc2 + b, recs, colbuf + 6 * (int64_t)b, lane);
+    if (lane == 0) ncol[v] = kept;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Symbolic, second pass (after the row pointers): column indices of every touched row, the
+// column counts cleared for the next call, the block count.
+__global__ void __launch_bounds__(kBlock) k_sym_write(const int32_t* __restrict__ touched, Counters* ctr,
+                                                      const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ colbuf,
+                                                      const int32_t* __restrict__ row_ptr, int64_t nv,
+                                                      int32_t* __restrict__ col_idx, int64_t cap,
+                                                      int32_t* __restrict__ ncol, int64_t* n_blocks) {
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  const uint32_t U = ctr->last_touched;
+  int status = 0;
+  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
+    const int32_t v = touched[u];
+    const int32_t b = off[v], rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
+    for (int32_t q = lane; q < nc; q += 64) {
+      if ((int64_t)rp + q < cap) col_idx[rp + q] = colbuf[6 * (int64_t)b + q];
+      else status = STATUS_CAPACITY;
+    }
+    if (lane == 0) ncol[v] = 0;
+  }
+  if (status) latch(&ctr->status, status);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t nb = row_ptr[nv];
+    *n_blocks = nb;
+    if (nb > cap) latch(&ctr->status, STATUS_CAPACITY);
+  }
+}
+
+template <class S>
+__global__ void k_zero_blocks(const int32_t* __restrict__ row_ptr, int64_t nv, S* __restrict__ vals) {
+  const int64_t n = 9 * (int64_t)row_ptr[nv];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    vals[i] = S(0);
+}
+
+// Numeric: the blocks J_k^T M J_l of every touched row, summed in pair-key order (the order of
+// the one-call assembly, so the values are the same bit for bit) into the caller's columns.  A
+// hit vertex missing from its row's columns latches TTIE_ERR_INVALID_ARGUMENT.
+template <class S>
+__global__ void __launch_bounds__(kBlock) k_num_rows(const int32_t* __restrict__ touched, Counters* ctr,
+                                                     const int32_t* __restrict__ off,
+                                                     const Incidence* __restrict__ inc2,
+                                                     const AsmRec<S>* __restrict__ recs,
+                                                     const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx, S* __restrict__ vals) {
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  const uint32_t U = ctr->last_touched;
+  int status = 0;
+  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
+    const int32_t v = touched[u];
+    const int32_t b = off[v], n = off[v + 1] - b;
+    const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
+    // coverage: every vertex of every incident hit is a column of the row (binary search)
+    for (int32_t t = lane; t < 6 * n; t += 64) {
+      const int32_t want = recs[inc2[b + t / 6].hit].vid[t % 6];
+      int32_t lo = 0, hi = nc;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col_idx[rp + mid] < want) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= nc || col_idx[rp + lo] != want) status = STATUS_INVALID;
+    }
+    for (int32_t q0 = 0; q0 < nc; q0 += 64) {
+      const int32_t q = q0 + lane;
+      const int32_t col = q < nc ? col_idx[rp + q] : -1;
+      S B[9];
+#pragma unroll
+      for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
+      for (int32_t k = 0; k < n; ++k) {
+        const Incidence in = inc2[b + k];
+        const AsmRec<S>& r = recs[in.hit];
+        uint32_t match = 0;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) match |= (uint32_t)(r.vid[l] == col) << l;
+        while (match) {
+          block_jmj(r, in.slot, __builtin_ctz(match), B);
+          match &= match - 1;
+        }
+      }
+      if (q < nc) {
+#pragma unroll
+        for (int z = 0; z < 9; ++z) vals[9 * ((int64_t)rp + q) + z] = B[z];
+      }
+    }
+  }
+  if (status) latch(&ctr->status, status);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -572,17 +841,20 @@ __global__ void __launch_bounds__(kBlock) k_hvp_exact(const double* __restrict__
     const HitGeom g = hits[h];
     const AsmRec<S>& r = recs[h];
     V3<S> Xv[6];
-    local_coords<S>(x, r.vid, Xv);
+    const int e = local_coords<S>(x, r.vid, Xv);
     V3<DS> X[6];
     S vv[18];
+    // the coordinates are scaled by 2^-e, so their tangents along v are too; the tangents of a
+    // and b (degree 0) then come out in the original units
+    const S sv = Sc<S>::c(ldexp(1.0, -e));
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) vv[3 * k + c] = v[3 * (int64_t)r.vid[k] + c];
-      X[k] = V3<DS>{DS{Xv[k].x, vv[3 * k]}, DS{Xv[k].y, vv[3 * k + 1]}, DS{Xv[k].z, vv[3 * k + 2]}};
+      X[k] = V3<DS>{DS{Xv[k].x, sv * vv[3 * k]}, DS{Xv[k].y, sv * vv[3 * k + 1]}, DS{Xv[k].z, sv * vv[3 * k + 2]}};
     }
     DS a[18], b[18];
-    interval_grads<DS>(X, g.da, g.db, g.desc, half, a, b);
+    interval_grads<DS>(X, g.da, g.db, e, g.desc, half, a, b);
     // first-order tangents of t_c^0, t_c^1 along v
     S t0d = S(0), t1d = S(0);
 #pragma unroll
@@ -743,6 +1015,55 @@ hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const i
                              (double*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
   return eval_impl<float>(c, m, pairs, n_pairs, pair_capacity, o, energy, (float*)grad, flags, pair_T, row_ptr, col_idx,
                           (float*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
+}
+
+template <class S>
+static hipError_t bsr_symbolic_impl(Ctx* c, int32_t* row_ptr, int32_t* col_idx, int64_t cap, int64_t* n_blocks,
+                                    hipStream_t s) {
+  const Layout& L = c->L;
+  Counters* ctr = wsp<Counters>(c, L.counters);
+  const int64_t nv = c->last_nverts;
+  const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
+                                                     (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
+  stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
+  k_sym_cols<S><<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
+                                         wsp<Incidence>(c, L.inc2), wsp<AsmRec<S>>(c, L.recs),
+                                         wsp<int32_t>(c, L.colbuf), wsp<int32_t>(c, L.cstage),
+                                         36 * c->lim.max_hits, wsp<int32_t>(c, L.ncol));
+  hipError_t err = scan_i32(c, wsp<int32_t>(c, L.ncol), row_ptr, nv + 1, s);
+  if (err != hipSuccess) return err;
+  k_sym_write<<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
+                                       wsp<int32_t>(c, L.colbuf), row_ptr, nv, col_idx, cap, wsp<int32_t>(c, L.ncol),
+                                       n_blocks);
+  stage_end(c, TTIE_STAGE_ASSEMBLY, s);
+  return hipGetLastError();
+}
+
+template <class S>
+static hipError_t bsr_numeric_impl(Ctx* c, const int32_t* row_ptr, const int32_t* col_idx, S* vals, hipStream_t s) {
+  const Layout& L = c->L;
+  Counters* ctr = wsp<Counters>(c, L.counters);
+  const int64_t nv = c->last_nverts;
+  const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
+                                                     (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
+  stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
+  k_zero_blocks<S><<<grid_for(9 * c->lim.max_blocks, 2048), kBlock, 0, s>>>(row_ptr, nv, vals);
+  k_num_rows<S><<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
+                                         wsp<Incidence>(c, L.inc2), wsp<AsmRec<S>>(c, L.recs), row_ptr, col_idx,
+                                         vals);
+  stage_end(c, TTIE_STAGE_ASSEMBLY, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bsr_symbolic(Ctx* c, int32_t* row_ptr, int32_t* col_idx, int64_t capacity, int64_t* n_blocks,
+                               hipStream_t s) {
+  if (c->last_precision == TTIE_FP64) return bsr_symbolic_impl<double>(c, row_ptr, col_idx, capacity, n_blocks, s);
+  return bsr_symbolic_impl<float>(c, row_ptr, col_idx, capacity, n_blocks, s);
+}
+
+hipError_t launch_bsr_numeric(Ctx* c, const int32_t* row_ptr, const int32_t* col_idx, void* vals, hipStream_t s) {
+  if (c->last_precision == TTIE_FP64) return bsr_numeric_impl<double>(c, row_ptr, col_idx, (double*)vals, s);
+  return bsr_numeric_impl<float>(c, row_ptr, col_idx, (float*)vals, s);
 }
 
 template <class S>

@@ -41,7 +41,7 @@ struct Incidence {
 struct Counters {
   int32_t status;          // latched TTIE status (first error wins)
   uint32_t n_hits;         // intersecting pairs found by the last screening
-  uint32_t spare;          // (unused)
+  uint32_t last_touched;   // vertices touched by the hits of the last completed evaluation
   uint32_t n_defer;        // candidates whose signs need the exact fallback
   uint32_t n_touched;      // vertices touched by the hits of the current evaluation
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
@@ -80,6 +80,14 @@ __device__ __forceinline__ bool is_adjacent(const int32_t* a, const int32_t* b, 
     return any;
   }
   return shared_vertices(a, b) >= 2;
+}
+
+// Blocks are dealt to the XCDs round-robin; renumbering them so that each XCD runs a
+// contiguous range of logical blocks keeps each XCD's L2 on one region of the data (nblocks a
+// multiple of 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t per = nblocks / 8;
+  return (b % 8) * per + b / 8;
 }
 
 // wave-aggregated append to a counter-indexed list: one atomic per wave; every lane of the wave
@@ -171,6 +179,10 @@ hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const i
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
                        int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, hipStream_t s);
 hipError_t launch_hvp(Ctx* c, const ttie_mesh* m, const void* v, void* Hv, int mode, hipStream_t s);
+// BSR pattern and values of the last evaluation's PSD Hessian, as two calls
+hipError_t launch_bsr_symbolic(Ctx* c, int32_t* row_ptr, int32_t* col_idx, int64_t capacity, int64_t* n_blocks,
+                               hipStream_t s);
+hipError_t launch_bsr_numeric(Ctx* c, const int32_t* row_ptr, const int32_t* col_idx, void* vals, hipStream_t s);
 hipError_t launch_bsr_mv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                          const void* x, void* y, int precision, hipStream_t s);
 hipError_t launch_init_counters(Ctx* c, hipStream_t s);

@@ -227,6 +227,33 @@ __device__ __forceinline__ int coplanar_kind(const Tri64& A, const Tri64& B, int
   return PAIR_COPLANAR;
 }
 
+// Line direction D = n_a x n_b of a pair (Sec. 1: the intersection line of the two planes).
+// The normals and D are rounded exactly as written, with no fused multiply-adds, so that the
+// one discrete decision taken on rounded values -- D exactly (0, 0, 0), a degenerate frame --
+// is the same wherever the definition is evaluated in float64.  (The exact D of a hit is never
+// zero: both triangles straddle the other's plane.  Only rounded normals that come out parallel
+// give a zero.)  A non-zero D is then multiplied by 2^-e, e the exponent of its largest
+// component: exact, D/|D| unchanged, and |D|^2 stays finite and non-zero over the whole
+// coordinate domain (components of order 2^-600 would underflow when squared).
+__device__ __forceinline__ bool line_direction(const Tri64& A, const Tri64& B, V3<double>& D) {
+#pragma clang fp contract(off)
+  const double a1x = A.p[1][0] - A.p[0][0], a1y = A.p[1][1] - A.p[0][1], a1z = A.p[1][2] - A.p[0][2];
+  const double a2x = A.p[2][0] - A.p[0][0], a2y = A.p[2][1] - A.p[0][1], a2z = A.p[2][2] - A.p[0][2];
+  const double b1x = B.p[1][0] - B.p[0][0], b1y = B.p[1][1] - B.p[0][1], b1z = B.p[1][2] - B.p[0][2];
+  const double b2x = B.p[2][0] - B.p[0][0], b2y = B.p[2][1] - B.p[0][1], b2z = B.p[2][2] - B.p[0][2];
+  const double nax = a1y * a2z - a1z * a2y, nay = a1z * a2x - a1x * a2z, naz = a1x * a2y - a1y * a2x;
+  const double nbx = b1y * b2z - b1z * b2y, nby = b1z * b2x - b1x * b2z, nbz = b1x * b2y - b1y * b2x;
+  const double dx = nay * nbz - naz * nby, dy = naz * nbx - nax * nbz, dz = nax * nby - nay * nbx;
+  const double m = fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
+  if (!(m > 0.0)) {
+    D = V3<double>{0.0, 0.0, 0.0};
+    return false;
+  }
+  const int e = ilogb(m);
+  D = V3<double>{ldexp(dx, -e), ldexp(dy, -e), ldexp(dz, -e)};
+  return true;
+}
+
 struct Screen {
   int kind;  // PAIR_*
   uint32_t desc;
@@ -285,9 +312,8 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
 
   // FP64 interval ends on pair-local coordinates (origin u0)
   const V3<double> o = selv(A, 0);
-  const V3<double> na = cross(selv(A, 1) - o, selv(A, 2) - o);
-  const V3<double> nb = cross(selv(B, 1) - selv(B, 0), selv(B, 2) - selv(B, 0));
-  const V3<double> D = cross(na, nb);
+  V3<double> D;
+  const bool frame = line_direction(A, B, D);
   const double len = sqrt(dot(D, D));
   double ta[2], tb[2];
 #pragma unroll
@@ -317,7 +343,7 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
   }
   desc |= (uint32_t)amin << 16 | (uint32_t)amax << 17 | (uint32_t)bmin << 18 | (uint32_t)bmax << 19;
   out.desc = desc;
-  if (!(len > 0.0)) {
+  if (!frame) {
     out.kind = PAIR_BAD_FRAME;
     return out;
   }
@@ -369,10 +395,14 @@ __device__ __forceinline__ void add_endpoint(V3<S> (&out)[6], S sgn, int p, int 
   out[ps + 0] = out[ps + 0] - sgn * ((w * den) * n + g1 + g2);
 }
 
+// X: the pair's coordinates relative to u0 and multiplied by 2^-e (see local_coords); a and b
+// are homogeneous of degree 0 in the coordinates, so the scaling changes nothing but the range
+// of the intermediate values, which then neither under- nor overflows in float32.  The plane
+// sides are of degree 3, so the stored ones are scaled by 2^-3e to match.
 template <class S>
 __device__ __forceinline__ void interval_grads(const V3<S> (&X)[6], const double dstored_a[3],
-                                               const double dstored_b[3], uint32_t desc, double half, S a[18],
-                                               S b[18]) {
+                                               const double dstored_b[3], int e, uint32_t desc, double half,
+                                               S a[18], S b[18]) {
   const V3<S> U[3] = {X[0], X[1], X[2]};
   const V3<S> V[3] = {X[3], X[4], X[5]};
   const V3<S> na = cross(U[1] - U[0], U[2] - U[0]);
@@ -384,8 +414,8 @@ __device__ __forceinline__ void interval_grads(const V3<S> (&X)[6], const double
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     // the screening's values (exact where the filter failed); tangents from the formula
-    da[k] = Sc<S>::with_value(dot(nb, U[k] - V[0]), dstored_a[k]);
-    db[k] = Sc<S>::with_value(dot(na, V[k] - U[0]), dstored_b[k]);
+    da[k] = Sc<S>::with_value(dot(nb, U[k] - V[0]), ldexp(dstored_a[k], -3 * e));
+    db[k] = Sc<S>::with_value(dot(na, V[k] - U[0]), ldexp(dstored_b[k], -3 * e));
   }
   V3<S> ga[6], gb[6];
   const S zero = Sc<S>::c(0.0);

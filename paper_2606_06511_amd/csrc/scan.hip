@@ -4,8 +4,9 @@
 // on belongs to a block that is already running), scans it in registers and LDS, publishes
 // its aggregate, walks back over its predecessors' published words until it meets an
 // inclusive prefix, and publishes its own inclusive prefix.  A published word holds the flag
-// and the value together and is written and read with device-scope atomics, so no fence is
-// needed.  The last block to finish clears the tile words and both counters, so the state is
+// and the value together and is written and read with device-scope atomics, so the look-back
+// needs no fence.  The last block to finish (counted with a release-acquire atomic, which orders
+// each block's final word before its count) clears the tile words and both counters, so the state is
 // zero before every scan without a separate initialisation launch, and a captured graph can
 // replay the scan.  A predecessor publishes its aggregate before its own look-back, so a wait
 // lasts microseconds; the waits are still bounded, and one that outlasts the bound latches
@@ -114,8 +115,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_i32(const int32_t* __rest
   for (int j = 0; j < kScanItems; ++j)
     if (base + j < n) out[base + j] = pre + v[j];
   // the last block to finish clears the tile words and the counters for the next scan (every
-  // other block has finished its look-back before counting itself done)
-  if (threadIdx.x == 0) s_last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
+  // other block has finished its look-back before counting itself done).  The count is taken
+  // with release-acquire ordering at device scope: the tile word this thread stored above is
+  // then visible before the count, so the last block's clearing comes after every block's final
+  // store and no stale word survives into the next scan.
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(&st->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   __syncthreads();
   if (!s_last) return;
   for (int64_t t = threadIdx.x; t < (int64_t)gridDim.x; t += kScanThreads) word_store(&words[t], 0);

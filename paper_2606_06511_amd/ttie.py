@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttie.so")
 
 TTIE_OK = 0
+(TTIE_ERR_INVALID_ARGUMENT, TTIE_ERR_INDEX_OUT_OF_RANGE, TTIE_ERR_NONFINITE_INPUT, TTIE_ERR_CAPACITY, TTIE_ERR_HIP,
+ TTIE_ERR_NO_DEVICE, TTIE_ERR_UNSUPPORTED, TTIE_ERR_INTERNAL) = range(1, 9)
 STATUS_NAMES = {
     0: "OK", 1: "INVALID_ARGUMENT", 2: "INDEX_OUT_OF_RANGE", 3: "NONFINITE_INPUT", 4: "CAPACITY",
     5: "HIP", 6: "NO_DEVICE", 7: "UNSUPPORTED", 8: "INTERNAL",
@@ -63,7 +65,9 @@ SIGNATURES = {
     "ttie_batch_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, _vp, _vp]),
     "ttie_batch_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(Options), _vp,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
-    "ttie_get_hits": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ttie_get_hits": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ttie_bsr_symbolic": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "ttie_bsr_numeric": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "ttie_hvp": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i32, _vp]),
     "ttie_bsr_mv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "ttie_pcg": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _i32,
@@ -280,8 +284,37 @@ class Context:
                                _ptr(out.get("n_blocks")) if hessian else None, _ptr(out["n_hits"]), _stream()))
         return out
 
+    def bsr_symbolic(self, n_verts, capacity=None):
+        """Pattern of the last evaluation's Hessian: (row_ptr (n_verts + 1,) int32, col_idx
+        (capacity,) int32, n_blocks (1,) int64), all on the GPU, no synchronization."""
+        dev = self.device
+        if capacity is None:
+            capacity = self.limits[4]
+        row_ptr = torch.empty(n_verts + 1, dtype=torch.int32, device=dev)
+        col_idx = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        nb = torch.zeros(1, dtype=torch.int64, device=dev)
+        _check(lib().ttie_bsr_symbolic(self.handle, _ptr(row_ptr), _ptr(col_idx), capacity, _ptr(nb), _stream()))
+        return row_ptr, col_idx, nb
+
+    def bsr_numeric(self, row_ptr, col_idx, dtype, out=None):
+        """Values of the last evaluation's Hessian on the pattern (row_ptr, col_idx): a
+        (len(col_idx), 3, 3) tensor of ``dtype`` (the evaluation's precision)."""
+        if out is None:
+            out = torch.empty((max(col_idx.shape[0], 1), 3, 3), dtype=dtype, device=self.device)
+        _check(lib().ttie_bsr_numeric(self.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(out), _stream()))
+        return out
+
+    @staticmethod
+    def hessian(out, n_verts):
+        """The BSR Hessian of an ``evaluate`` result as a ``torch.sparse_bsr_tensor`` of size
+        (3 n_verts, 3 n_verts) (reads the block count: synchronizes)."""
+        nb = int(out["n_blocks"].item())
+        return torch.sparse_bsr_tensor(out["row_ptr"], out["col_idx"][:nb], out["vals"][:nb],
+                                       size=(3 * n_verts, 3 * n_verts))
+
     def hits(self, capacity=None):
-        """The last evaluation's hits, sorted by (i, j), as numpy arrays (synchronizes)."""
+        """The last evaluation's hits, sorted by (i, j), as numpy arrays (synchronizes): ij, t (t_c^0,
+        t_c^1), T, a, b, g (18 each) and M (the Hessian core: M00, M01, M11)."""
         import numpy as np
 
         if capacity is None:
@@ -291,12 +324,14 @@ class Context:
         T = np.zeros(capacity)
         a = np.zeros((capacity, 18))
         b = np.zeros((capacity, 18))
+        g = np.zeros((capacity, 18))
+        M = np.zeros((capacity, 3))
         n = ctypes.c_int64(0)
         _check(lib().ttie_get_hits(self.handle, capacity, ij.ctypes.data_as(_vp), tc.ctypes.data_as(_vp),
                                    T.ctypes.data_as(_vp), a.ctypes.data_as(_vp), b.ctypes.data_as(_vp),
-                                   ctypes.byref(n), _stream()))
+                                   g.ctypes.data_as(_vp), M.ctypes.data_as(_vp), ctypes.byref(n), _stream()))
         k = n.value
-        return dict(ij=ij[:k], t=tc[:k], T=T[:k], a=a[:k], b=b[:k])
+        return dict(ij=ij[:k], t=tc[:k], T=T[:k], a=a[:k], b=b[:k], g=g[:k], M=M[:k])
 
     def hvp(self, x, tris, v, mode=HVP_EXACT, out=None):
         """H v at the last evaluation's positions (v in the evaluation's precision)."""
@@ -418,3 +453,37 @@ class Context:
         _check(lib().ttie_bsr_mv(self.handle, row_ptr.shape[0] - 1, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
                                  _ptr(xin), _ptr(out), precision, _stream()))
         return out
+
+
+# ---- module-level calls (one context per device, sized on demand) -------------------------
+_contexts = {}
+
+
+def _context(device, n_verts, n_tris, n_pairs):
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    c = _contexts.get(idx)
+    if c is None:
+        c = _contexts[idx] = Context(idx)
+    c.reserve(max(n_verts, 1), max(n_tris, 1), max(n_pairs, 1), max_hits=max(1024, min(max(n_pairs, 1), 1 << 20)))
+    return c
+
+
+def broadphase(x, tris, method=BROAD_LBVH, max_pairs=None):
+    """Candidate pairs of the mesh as an (n_pairs, 2) int32 GPU tensor (reads the count:
+    synchronizes).  ``max_pairs`` bounds the list (default 64 per triangle)."""
+    if max_pairs is None:
+        max_pairs = 64 * max(tris.shape[0], 1)
+    c = _context(x.device, x.shape[0], tris.shape[0], max_pairs)
+    pairs, n = c.broadphase(x, tris, method, capacity=max_pairs)
+    c.check()
+    return pairs[: int(n.item())]
+
+
+def evaluate(x, tris, pairs, precision=FP64, psd=PSD_PER_PART, interval=INTERVAL_EQ1):
+    """(E, G, H) over a candidate list: the energy (float64 scalar tensor), the gradient (N, 3)
+    and the PSD Hessian as a ``torch.sparse_bsr_tensor`` of size (3N, 3N) with 3 x 3 blocks
+    (synchronizes to size H and to check the status word)."""
+    c = _context(x.device, x.shape[0], tris.shape[0], pairs.shape[0])
+    out = c.evaluate(x, tris, pairs, precision=precision, psd=psd, interval=interval)
+    c.check()
+    return out["energy"][0], out["grad"], Context.hessian(out, x.shape[0])

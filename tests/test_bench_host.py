@@ -8,6 +8,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -29,35 +30,44 @@ def test_more_than_one_gpu_is_refused(n):
     assert line["n_gpus"] == n and "one GPU" in line["error"]
 
 
-def test_counter_figures_follow_source_and_params():
+def test_counter_figures_follow_source_and_params(monkeypatch):
+    import hashlib
+
     b = _bench()
-    entries = b.MEASURED["bp_traverse"]
-    assert {tuple(sorted(e["params"].items())) for e in entries} == {(("trav_budget", 24),), (("trav_budget", 32),)}
-    for e in entries:
-        # the committed source is the one the figures were taken on
-        assert b.measured("bp_traverse", "bytes", dict(e["params"], screen_blocks=1, row_blocks=1)) == e["bytes"]
-        assert b.measured("bp_traverse", "valu_wave", e["params"]) == e["valu_wave"]
-    # other launch parameters: no figure
-    assert b.measured("bp_traverse", "bytes", {"trav_budget": 64}) is None
-    # another source: no figure
-    saved = [dict(e) for e in entries]
-    try:
+    src = "paper_2606_06511_amd/csrc/evaluate.hip"
+    sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    table = {"screen": [{"bytes": 123, "valu_wave": 45, "sources": {src: sha}, "params": {"screen_blocks": 2048}},
+                        {"bytes": 456, "valu_wave": 67, "sources": {src: "0" * 64}, "params": {}}]}
+    monkeypatch.setattr(b, "MEASURED", table)
+    # the committed source and the same launch parameter: the figure
+    assert b.measured("screen", "bytes", {"screen_blocks": 2048, "row_blocks": 1}) == 123
+    assert b.measured("screen", "valu_wave", {"screen_blocks": 2048}) == 45
+    # another launch parameter, or a source that changed since: no figure
+    assert b.measured("screen", "bytes", {"screen_blocks": 4096}) is None
+    table["screen"][0]["sources"] = {src: "1" * 64}
+    assert b.measured("screen", "bytes", {"screen_blocks": 2048}) is None
+    assert b.measured("derivs", "bytes", {}) is None
+    # every committed figure names sources that exist
+    for entries in _bench().MEASURED.values():
         for e in entries:
-            e["sha256"] = "0" * 64
-        assert b.measured("bp_traverse", "bytes", {"trav_budget": 24}) is None
-    finally:
-        b.MEASURED["bp_traverse"][:] = saved
-    assert b.measured("screen", "bytes", {}) is None
+            assert all(os.path.exists(os.path.join(ROOT, f)) for f in e["sources"])
 
 
-def test_algorithmic_bytes():
+@pytest.mark.parametrize("prec", [np.float32, np.float64])
+def test_path_bytes_count_the_arrays(prec):
+    """The path's algorithmic bytes are the sizes of the arrays one evaluation must read and
+    write: the candidate list, triangles and positions in; every hit record out and back in;
+    gradient, BSR values, column indices and row pointers, and the energy out."""
     b = _bench()
-    nv, nt, P, H, nnzb = 65_536, 130_050, 172_212, 498, 6_178
-    # the traversal: every leaf record (64 B) and leaf box (32 B), the inner levels (~nt/3 boxes
-    # of 32 B) and every pair written once (8 B)
-    assert b.stage_bytes("bp_traverse", nv, nt, P, H, nnzb, 4) == 64 * nt + 32 * nt + 32 * nt // 3 + 8 * P
-    # screening reads each pair, vertex and triangle once and writes the hit records
-    assert b.stage_bytes("screen", nv, nt, P, H, nnzb, 4) == 8 * P + 24 * nv + 12 * nt + 80 * H
-    # the assembly grows with the precision of the gradient and the Hessian blocks
-    assert b.stage_bytes("assembly", nv, nt, P, H, nnzb, 8) > b.stage_bytes("assembly", nv, nt, P, H, nnzb, 4)
-    assert b.stage_bytes("unknown", nv, nt, P, H, nnzb, 4) == 0
+    nv, nt, P, H, nnzb = 1000, 1900, 5000, 37, 811
+    s = np.dtype(prec).itemsize
+    rec = np.dtype([("a", prec, 18), ("b", prec, 18), ("M", prec, 3), ("t", prec, 2), ("vid", np.int32, 6)])
+    arrays_in = [np.zeros((P, 2), np.int32), np.zeros((nt, 3), np.int32), np.zeros((nv, 3), np.float64)]
+    records = np.zeros(H, rec)
+    arrays_out = [np.zeros((nv, 3), prec), np.zeros((nnzb, 3, 3), prec), np.zeros(nnzb, np.int32),
+                  np.zeros(nv + 1, np.int32), np.zeros(1, np.float64)]
+    want = sum(a.nbytes for a in arrays_in) + 2 * records.nbytes + sum(a.nbytes for a in arrays_out)
+    assert b.path_bytes(nv, nt, P, H, nnzb, s) == want
+    assert b.path_bytes(nv, nt, P, H, nnzb, s, flags=True) == want + np.zeros(P, np.uint8).nbytes
+    # the screening stage reads the same inputs and writes the 80-byte hit geometry
+    assert b.stage_bytes("screen", nv, nt, P, H, nnzb, s) == sum(a.nbytes for a in arrays_in) + 80 * H

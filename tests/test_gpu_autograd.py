@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -31,14 +32,15 @@ def test_backward_and_double_backward_match_oracle(precision):
     E = m.energy(xd)
     pairs = oracle.pairs(x, tris)
     ref = oracle.evaluate(x, tris, pairs, hessian=False)
-    assert abs(E.item() - ref["E"]) <= 1e-10 * ref["E"]
+    pc.check_energy(E.item(), ref["E"])
     (g,) = torch.autograd.grad(E, xd, create_graph=True)
-    tol = 1e-10 if precision == 0 else 1e-4
-    assert _rel(g.detach().cpu().numpy(), ref["G"]) <= tol
+    pc.check_grad(g.detach().cpu().numpy(), ref, pairs, tris, precision)
     v = torch.randn_like(xd)
     (hv,) = torch.autograd.grad((g * v).sum(), xd)
-    ref_hv = oracle.hvp(x, tris, pairs, v.cpu().numpy(), exact=True)
-    assert _rel(hv.cpu().numpy(), ref_hv) <= (1e-9 if precision == 0 else 1e-3)
+    vn = v.cpu().numpy()
+    ref_hv = oracle.hvp(x, tris, pairs, vn, exact=True)
+    pc.check_vector(hv.cpu().numpy(), ref_hv, pc.hvp_row_scales(x, tris, pairs, vn, True, ref), precision,
+                    "double backward (exact HVP)")
 
 
 def test_gradcheck_and_gradgradcheck_fp64():
@@ -84,14 +86,16 @@ def test_big_sphere_fp64_fd_and_oracle(big_sphere):
     out = m.evaluate(xd, pairs=pd, n_pairs=nd, hessian=False, flags=True)
     np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
     E, G = out["energy"].item(), out["grad"].cpu().numpy()
-    assert abs(E - ref["E"]) <= 1e-10 * ref["E"]
-    assert _rel(G, ref["G"]) <= 1e-10
+    pc.check_energy(E, ref["E"])
+    pc.check_grad(G, ref, pairs, tris, 0)
+    pc.check_hits(m.ctx.hits(1 << 18), ref, pairs, 0, hessian=False, what="1M sphere")
     rng = np.random.default_rng(0)
     v = rng.normal(size=x.shape)
     v /= np.linalg.norm(v)
     vd = torch.from_numpy(v).cuda()
     Hv = m.hvp(xd, vd).cpu().numpy()
-    assert _rel(Hv, oracle.hvp(x, tris, pairs, v, exact=True)) <= 1e-9
+    pc.check_vector(Hv, oracle.hvp(x, tris, pairs, v, exact=True), pc.hvp_row_scales(x, tris, pairs, v, True, ref), 0,
+                    "exact HVP")
     # central differences along v with the candidate list fixed
     h = 1e-6
     op = m.evaluate(xd + h * vd, pairs=pd, n_pairs=nd, hessian=False)
@@ -111,22 +115,16 @@ def test_big_sphere_fp32_against_fp64_oracle(big_sphere):
     pd = torch.from_numpy(pairs).cuda()
     nd = torch.tensor([len(pairs)], dtype=torch.int64, device="cuda")
     out = m.evaluate(xd, pairs=pd, n_pairs=nd, hessian=False)
-    assert abs(out["energy"].item() - ref["E"]) <= 1e-10 * ref["E"]  # T is FP64 on both paths
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= 1e-4
+    pc.check_energy(out["energy"].item(), ref["E"])  # T is FP64 on both paths
+    pc.check_grad(out["grad"].cpu().numpy(), ref, pairs, tris, ttie.MIXED)
+    # every hit: interval ends, a, b and g against the oracle
+    pc.check_hits(m.ctx.hits(1 << 18), ref, pairs, ttie.MIXED, hessian=False, what="1M sphere mixed")
     rng = np.random.default_rng(1)
     v = rng.normal(size=x.shape)
     v /= np.linalg.norm(v)
     Hv = m.hvp(xd, torch.from_numpy(v).cuda()).cpu().numpy()
-    assert _rel(Hv, oracle.hvp(x, tris, pairs, v, exact=True)) <= 1e-3
-    # sampled hits: interval gradients against the oracle's per-pair evaluation
-    h = m.ctx.hits()
-    idx = rng.choice(len(h["ij"]), size=min(1000, len(h["ij"])), replace=False)
-    for k in idx:
-        i, j = h["ij"][k]
-        r = oracle.pair(np.concatenate([x[tris[i]], x[tris[j]]]))
-        scale = max(np.abs(r["a"]).max(), np.abs(r["b"]).max())
-        assert np.abs(h["a"][k] - r["a"]).max() <= 1e-3 * scale
-        assert np.abs(h["b"][k] - r["b"]).max() <= 1e-3 * scale
+    pc.check_vector(Hv, oracle.hvp(x, tris, pairs, v, exact=True), pc.hvp_row_scales(x, tris, pairs, v, True, ref),
+                    ttie.MIXED, "exact HVP (mixed)")
 
 
 def test_big_sphere_per_pair_fd(big_sphere):

@@ -1,0 +1,185 @@
+"""GPU tests of the boundary's two-call Hessian (pattern, then values), the sparse-tensor form of
+H, and the pairs at the edges of float64 (the degenerate line frame, extreme coordinate scales),
+all through the C ABI against the CPU oracle."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity_checks as pc
+from paper_2606_06511_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_06511_amd import ttie
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = ttie.Context(0)
+    c.reserve(70_000, 140_000, 400_000, max_hits=20_000, max_blocks=400_000)
+    return c
+
+
+def _dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symbolic_then_numeric(ctx, precision):
+    """Pattern first (sized from the device count), values second, on an evaluation that skipped
+    its own BSR output: identical pattern to the oracle's, values element-wise within the bar, and
+    bit-identical to the one-call assembly of ttie_eval."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=128)
+    pairs = oracle.pairs(x, tris)
+    ref = oracle.evaluate(x, tris, pairs)
+    xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
+    dt = torch.float64 if precision == 0 else torch.float32
+    one = ctx.evaluate(xd, td, pd, precision=precision, hessian=True)
+    nb1 = int(one["n_blocks"].item())
+    ctx.evaluate(xd, td, pd, precision=precision, hessian=False)
+    # a capacity that is too small: the count and the row pointers are still complete
+    rp, ci, nb = ctx.bsr_symbolic(len(x), capacity=10)
+    assert ctx.status() == ttie.TTIE_ERR_CAPACITY
+    n_blocks = int(nb.item())
+    assert n_blocks == len(ref["col_idx"]) == nb1
+    np.testing.assert_array_equal(rp.cpu().numpy(), ref["row_ptr"])
+    rp, ci, nb = ctx.bsr_symbolic(len(x), capacity=n_blocks)
+    assert ctx.status() == ttie.TTIE_OK
+    ci = ci[:n_blocks]
+    vals = ctx.bsr_numeric(rp, ci, dt)
+    assert ctx.status() == ttie.TTIE_OK
+    pc.check_bsr(rp.cpu().numpy(), ci.cpu().numpy(), vals.cpu().numpy(), ref, precision, "two-call BSR")
+    assert torch.equal(vals, one["vals"][:nb1])
+    assert torch.equal(ci, one["col_idx"][:nb1])
+
+
+def test_numeric_refresh_on_a_kept_pattern(ctx):
+    """Values refreshed on a fixed pattern after the positions move: the pattern of the first
+    evaluation holds the second's blocks (a superset from swept candidates); the refreshed values
+    match the oracle's on the blocks the second evaluation has and are 0 on the others."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(1, n=96)
+    rng = np.random.default_rng(5)
+    x2 = x + 1e-3 * rng.normal(size=x.shape)
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    x2d = _dev(x2, torch.float64)
+    # the pattern of the union of both states' hits: evaluate the swept candidates at x, then
+    # take the union pattern from the oracle
+    pairs = oracle.pairs_swept(x, x2, tris)
+    ref1 = oracle.evaluate(x, tris, pairs)
+    ref2 = oracle.evaluate(x2, tris, pairs)
+    pd = _dev(pairs, torch.int32)
+    # pattern: blocks of either state, built as a dense boolean block mask then compressed
+    nv = len(x)
+    mask = {}
+    for ref in (ref1, ref2):
+        for r in range(nv):
+            for k in range(ref["row_ptr"][r], ref["row_ptr"][r + 1]):
+                mask[(r, int(ref["col_idx"][k]))] = True
+    keys = sorted(mask)
+    row_ptr = np.zeros(nv + 1, np.int32)
+    for r, _ in keys:
+        row_ptr[r + 1] += 1
+    row_ptr = np.cumsum(row_ptr).astype(np.int32)
+    col_idx = np.array([c for _, c in keys], np.int32)
+    assert len(col_idx) > len(ref2["col_idx"])
+    ctx.evaluate(x2d, td, pd, precision=ttie.FP64, hessian=False)
+    vals = ctx.bsr_numeric(_dev(row_ptr), _dev(col_idx), torch.float64).cpu().numpy()
+    assert ctx.status() == ttie.TTIE_OK
+    want = np.zeros((len(col_idx), 3, 3))
+    pos = {k: n for n, k in enumerate(keys)}
+    for r in range(nv):
+        for k in range(ref2["row_ptr"][r], ref2["row_ptr"][r + 1]):
+            want[pos[(r, int(ref2["col_idx"][k]))]] = ref2["vals"][k]
+    row = np.repeat(np.arange(nv), np.diff(row_ptr))
+    rmax = np.zeros(nv)
+    np.maximum.at(rmax, row, np.abs(want).reshape(-1, 9).max(1))
+    err = np.abs(vals - want).reshape(-1, 9).max(1)
+    assert np.all(err <= 1e-10 * rmax[row])
+    assert np.all(vals[rmax[row] == 0] == 0)
+    # a pattern that misses blocks is reported
+    ctx.bsr_numeric(_dev(row_ptr), _dev(np.zeros_like(col_idx)), torch.float64)
+    assert ctx.status() == ttie.TTIE_ERR_INVALID_ARGUMENT
+
+
+def test_module_evaluate_returns_sparse_bsr(ctx):
+    from paper_2606_06511_amd import ttie
+
+    x, tris = workloads.folded_cloth(0, n=48)
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    pairs = ttie.broadphase(xd, td)
+    ref_pairs = oracle.pairs(x, tris)
+    got = pairs.cpu().numpy()
+    np.testing.assert_array_equal(got[np.lexsort((got[:, 1], got[:, 0]))], ref_pairs)
+    E, G, H = ttie.evaluate(xd, td, pairs)
+    assert H.layout == torch.sparse_bsr and H.shape == (3 * len(x), 3 * len(x))
+    ref = oracle.evaluate(x, tris, got)
+    pc.check_energy(E.item(), ref["E"])
+    pc.check_grad(G.cpu().numpy(), ref, got, tris, 0)
+    assert len(ref["hit_pair"]) > 10
+    Hc = H.cpu()
+    pc.check_bsr(Hc.crow_indices().numpy(), Hc.col_indices().numpy(), Hc.values().numpy(), ref, 0, "sparse H")
+    # H v by torch's sparse product equals the PSD Hessian-vector product of the oracle
+    v = np.random.default_rng(0).normal(size=x.shape)
+    hv = (Hc @ torch.from_numpy(v.reshape(-1, 1))).numpy().reshape(-1, 3)
+    want_hv = oracle.hvp(x, tris, got, v, exact=False)
+    assert np.abs(hv - want_hv).max() <= 1e-10 * np.abs(want_hv).max()
+
+
+def _pair_mesh(X):
+    return np.ascontiguousarray(X, np.float64), np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_degenerate_frame_pair(ctx, precision):
+    """The hand-built pair whose float64 line direction rounds to (0, 0, 0) although the
+    triangles intersect: both sides flag it 3 with no energy."""
+    from paper_2606_06511_amd import ttie
+
+    g = json.load(open(os.path.join(GOLDEN, "degenerate_frame.json")))
+    X = np.array([[float.fromhex(c) for c in p] for p in g["X_hex"]])
+    x, tris = _pair_mesh(X)
+    pairs = np.array([[0, 1]], np.int32)
+    ref = oracle.evaluate(x, tris, pairs)
+    assert ref["flags"][0] == ttie.PAIR_DEGENERATE_FRAME
+    out = ctx.evaluate(_dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32),
+                       precision=precision, flags=True, pair_T=True)
+    assert ctx.status() == ttie.TTIE_OK
+    assert out["flags"].cpu().numpy()[0] == ttie.PAIR_DEGENERATE_FRAME
+    assert out["energy"].item() == 0.0 and out["pair_T"].item() == 0.0
+    assert torch.count_nonzero(out["grad"]).item() == 0 and int(out["n_blocks"].item()) == 0
+
+
+@pytest.mark.parametrize("k,precision", [(-150, 0), (-60, 0), (60, 0), (150, 0), (-30, 1), (30, 1)])
+def test_worked_example_at_extreme_scale(ctx, k, precision):
+    """The worked example scaled by 2^k: t scales by 2^k, T by 2^4k, a and b are unchanged.  The
+    float64 line direction (order 2^4k) is rescaled before normalising, and the per-hit
+    derivatives run on pair-local coordinates scaled to order 1, so float32 neither under- nor
+    overflows in them.  (The mixed path's float32 outputs -- g of order 2^3k, the Hessian of
+    order 2^2k -- bound its own range: |k| = 30 keeps them inside float32.)"""
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    s = 2.0 ** k
+    x, tris = _pair_mesh(np.array(g["X"], float) * s)
+    pairs = np.array([[0, 1]], np.int32)
+    ref = oracle.evaluate(x, tris, pairs)
+    out = ctx.evaluate(_dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32),
+                       precision=precision, flags=True, pair_T=True)
+    assert ctx.status() == 0
+    pc.check_eval_outputs(out, ref, pairs, tris, precision, what=f"2^{k}")
+    h = ctx.hits()
+    pc.check_hits(h, ref, pairs, precision, what=f"2^{k}")
+    assert h["t"][0, 0] == g["t0"] * s and h["t"][0, 1] == g["t1"] * s and h["T"][0] == g["T"] * s ** 4
+    np.testing.assert_allclose(h["a"][0].reshape(6, 3), np.array(g["a"]), atol=1e-15 if precision == 0 else 1e-7)
+    np.testing.assert_allclose(h["b"][0].reshape(6, 3), np.array(g["b"]), atol=1e-15 if precision == 0 else 1e-7)

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -28,12 +29,6 @@ def ctx():
 
 def _dev(a, dtype=None):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
-
-
-def _rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
 def _sorted_pairs(pairs, n):
@@ -68,16 +63,9 @@ def test_soup_flags_and_energy(ctx, soup, precision):
     out = ctx.evaluate(_dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32),
                        precision=precision, flags=True, pair_T=True)
     ctx.check()
-    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
-    assert int(out["n_hits"].item()) == len(ref["hit_pair"])
-    assert abs(out["energy"].item() - ref["E"]) <= FP64_TOL * ref["E"]
     assert np.all(out["pair_T"].cpu().numpy()[ref["flags"] == ttie.PAIR_COPLANAR] == 0.0)
-    tol = FP64_TOL if precision == 0 else MIXED_TOL
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= tol
-    nb = int(out["n_blocks"].item())
-    np.testing.assert_array_equal(out["row_ptr"].cpu().numpy(), ref["row_ptr"])
-    np.testing.assert_array_equal(out["col_idx"][:nb].cpu().numpy(), ref["col_idx"])
-    assert _rel(out["vals"][:nb].cpu().numpy(), ref["vals"]) <= tol
+    pc.check_eval_outputs(out, ref, pairs, tris, precision, what="coplanar soup")
+    pc.check_hits(ctx.hits(1 << 18), ref, pairs, precision, what="coplanar soup")
 
 
 @pytest.mark.parametrize("plane", range(4))

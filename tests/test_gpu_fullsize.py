@@ -1,21 +1,18 @@
 """Parity at the full sizes of the larger workloads, in the launch configuration the benchmark
-times: the 4,194,304-triangle noisy sphere (candidates, flags, energy and gradient, mixed and
-FP64) and the batch of 64 two-mesh problems (5,664,096 triangles: batched candidates and the
-energy of every problem)."""
+times: the 4,194,304-triangle noisy sphere (candidates, flags, energy, gradient, every hit and
+the BSR Hessian, mixed and FP64) and the batch of 64 two-mesh problems (5,664,096 triangles:
+batched candidates, every problem's energy, the gradient, every hit and the BSR Hessian), all
+element by element (tests/parity_checks.py)."""
 
 import numpy as np
 import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _sorted(p):
@@ -28,7 +25,7 @@ def sphere4m():
     x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
     assert len(tris) == 4_194_304
     pairs = oracle.pairs(x, tris)
-    return x, tris, pairs, oracle.evaluate(x, tris, pairs, hessian=False)
+    return x, tris, pairs, oracle.evaluate(x, tris, pairs, hessian=True)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -50,9 +47,8 @@ def test_sphere_4m(sphere4m, precision):
     order = np.lexsort((got[:, 1], got[:, 0]))
     np.testing.assert_array_equal(out["flags"][: len(got)].cpu().numpy()[order], ref["flags"])
     assert int(out["n_hits"].item()) == len(ref["hit_pair"]) == 26_800
-    assert abs(out["energy"].item() - ref["E"]) <= 1e-10 * ref["E"]
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= (1e-10 if precision == 0 else 1e-4)
-    assert int(out["n_blocks"].item()) > 0
+    pc.check_eval_outputs(out, ref, ref_pairs, tris, precision, flags=False, what="4M sphere")
+    pc.check_hits(ctx.hits(1 << 17), ref, ref_pairs, precision, what="4M sphere")
 
 
 def test_batch64():
@@ -76,6 +72,14 @@ def test_batch64():
         r = oracle.evaluate(xp, tp, pp, hessian=False)
         E_ref.append(r["E"])
         hits += len(r["hit_pair"])
-    np.testing.assert_array_equal(got, np.concatenate(ref_pairs))
+    ref_pairs = np.concatenate(ref_pairs)
+    np.testing.assert_array_equal(got, ref_pairs)
     assert int(out["n_hits"].item()) == hits
-    np.testing.assert_allclose(out["energies"].cpu().numpy(), E_ref, rtol=1e-10)
+    E = out["energies"].cpu().numpy()
+    for p in range(len(E_ref)):
+        pc.check_energy(E[p], E_ref[p], f"problem {p} energy")
+    # gradient, every hit and the Hessian against the oracle on the concatenated mesh with the
+    # batch's candidates (no pair joins two problems, so that is exactly the batch's answer)
+    ref = oracle.evaluate(x, tris, ref_pairs, hessian=True)
+    pc.check_eval_outputs(out, ref, ref_pairs, tris, ttie.MIXED, flags=False, what="batch of 64")
+    pc.check_hits(ctx.hits(1 << 17), ref, ref_pairs, ttie.MIXED, what="batch of 64")

@@ -1,18 +1,18 @@
 """Randomized parity over many seeds: small meshes on an integer grid whose triangles share
 vertices at random (so adjacency, one-vertex contacts, coplanar and touching configurations,
 zero-area and repeated-vertex triangles all occur), candidate lists with repeated and reversed
-pairs, both precisions and the vertex-adjacent option, against the oracle on the same inputs."""
+pairs, both precisions and the vertex-adjacent option, against the oracle on the same inputs,
+element by element (tests/parity_checks.py)."""
 
 import numpy as np
 import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 
 pytestmark = pytest.mark.gpu
 
-FP64_TOL = 1e-10
-MIXED_TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -28,12 +28,6 @@ def ctx():
 
 def _dev(a, dtype=None):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
-
-
-def _rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
 def _sorted_pairs(pairs, n):
@@ -62,7 +56,6 @@ def test_random_shared_vertex_meshes(ctx, seed):
     x, tris = shared_vertex_mesh(seed)
     va = seed % 3 == 0
     precision = ttie.FP64 if seed % 2 == 0 else ttie.MIXED
-    tol = FP64_TOL if precision == ttie.FP64 else MIXED_TOL
     xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
     # broad phases: both give exactly the oracle's candidates
     ref_pairs = oracle.pairs(x, tris, vertex_adjacent=va)
@@ -84,12 +77,5 @@ def test_random_shared_vertex_meshes(ctx, seed):
     out = ctx.evaluate(xd, td, _dev(pl, torch.int32), precision=precision, flags=True, pair_T=True,
                        vertex_adjacent=va)
     ctx.check()
-    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
-    assert int(out["n_hits"].item()) == len(ref["hit_pair"])
-    assert abs(out["energy"].item() - ref["E"]) <= FP64_TOL * max(ref["E"], 1e-300)
-    assert _rel(out["pair_T"].cpu().numpy(), ref["T"]) <= FP64_TOL
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= tol
-    nb = int(out["n_blocks"].item())
-    np.testing.assert_array_equal(out["row_ptr"].cpu().numpy(), ref["row_ptr"])
-    np.testing.assert_array_equal(out["col_idx"][:nb].cpu().numpy(), ref["col_idx"])
-    assert _rel(out["vals"][:nb].cpu().numpy(), ref["vals"]) <= tol
+    pc.check_eval_outputs(out, ref, pl, tris, precision, what=f"seed {seed}")
+    pc.check_hits(ctx.hits(), ref, pl, precision, what=f"seed {seed}")

@@ -147,12 +147,24 @@ def test_newton_subset_matrix_free_against_oracle(sphere_subset):
     assert [h["alpha"] for h in hist[:-1]] == list(al_ref)
 
 
-def test_newton_subset_mixed_decreases(sphere_subset):
+def test_newton_subset_mixed_against_oracle(sphere_subset):
+    """The mixed path (float32 gradient, Hessian and solve) against the float64 oracle: the first
+    step element by element -- E0 to 1e-10 (float64 on both paths), the same step length, the
+    displacement of every vertex within 1e-3 of the largest one and E1 within 1e-4 (a truncated
+    solve of 20 iterations on float32 data) -- then the whole 20-step run by its properties."""
     from paper_2606_06511_amd import ttie
     from paper_2606_06511_amd.newton import newton
 
     x, tris = sphere_subset
     m = _model(x, tris, max_pairs=1 << 20, max_hits=1 << 16, precision=ttie.MIXED)
+    x1_ref, E_ref, al_ref, _ = oracle.newton(x, tris, steps=1, pcg_iters=20)
+    x1, hist = newton(m, torch.from_numpy(x).cuda(), steps=1, pcg_iters=20)
+    x1 = x1.cpu().numpy()
+    assert hist[0]["E"] == pytest.approx(E_ref[0], rel=1e-10)
+    assert hist[0]["alpha"] == al_ref[0]
+    d, d_ref = x1 - x, x1_ref - x
+    assert np.abs(d - d_ref).max() <= 1e-3 * np.abs(d_ref).max()
+    assert hist[-1]["E"] == pytest.approx(E_ref[1], rel=1e-4)
     _, hist = newton(m, torch.from_numpy(x).cuda(), steps=20)
     E = np.array([h["E"] for h in hist])
     assert np.all(np.diff(E) <= 0)

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -54,12 +55,4 @@ def test_scan_tile_edges(ctx, nv):
     assert len(ref["hit_pair"]) > 0
     out = ctx.evaluate(xd, td, torch.from_numpy(ref_pairs).cuda(), precision=ttie.FP64, flags=True)
     ctx.check()
-    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
-    assert abs(out["energy"].item() - ref["E"]) <= 1e-10 * ref["E"]
-    g, G = out["grad"].cpu().numpy(), ref["G"]
-    assert np.linalg.norm(g - G) <= 1e-10 * np.linalg.norm(G)
-    nb = int(out["n_blocks"].item())
-    np.testing.assert_array_equal(out["row_ptr"].cpu().numpy(), ref["row_ptr"])
-    np.testing.assert_array_equal(out["col_idx"][:nb].cpu().numpy(), ref["col_idx"])
-    v, V = out["vals"][:nb].cpu().numpy(), ref["vals"]
-    assert np.linalg.norm(v - V) <= 1e-10 * np.linalg.norm(V)
+    pc.check_eval_outputs(out, ref, ref_pairs, tris, ttie.FP64, what=f"n_v = {nv}")

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+import parity_checks as pc
 from paper_2606_06511_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -45,12 +46,6 @@ def _sorted_pairs(pairs, n):
     p = pairs[: int(n.item())].cpu().numpy()
     key = p[:, 0].astype(np.int64) << 32 | p[:, 1].astype(np.int64)
     return p[np.argsort(key)]
-
-
-def _rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
 def _shares_one_vertex(tris, pairs):
@@ -108,24 +103,13 @@ def test_eval_matches_oracle(ctx, fans, precision):
     from paper_2606_06511_amd import ttie
 
     x, tris, pairs = fans
-    tol = FP64_TOL if precision == ttie.FP64 else MIXED_TOL
     ref = oracle.evaluate(x, tris, pairs, vertex_adjacent=True)
     assert ref["E"] > 0 and len(ref["hit_pair"]) > 1000
     xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
     out = ctx.evaluate(xd, td, pd, precision=precision, flags=True, pair_T=True, vertex_adjacent=True)
     ctx.check()
-    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
-    assert int(out["n_hits"].item()) == len(ref["hit_pair"])
-    assert abs(out["energy"].item() - ref["E"]) <= FP64_TOL * ref["E"]
-    assert _rel(out["pair_T"].cpu().numpy(), ref["T"]) <= FP64_TOL
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= tol
-    nb = int(out["n_blocks"].item())
-    np.testing.assert_array_equal(out["row_ptr"].cpu().numpy(), ref["row_ptr"])
-    np.testing.assert_array_equal(out["col_idx"][:nb].cpu().numpy(), ref["col_idx"])
-    assert _rel(out["vals"][:nb].cpu().numpy(), ref["vals"]) <= tol
-    h = ctx.hits()
-    np.testing.assert_array_equal(h["ij"], pairs[ref["hit_pair"]])
-    assert _rel(h["t"], ref["hit_t"]) <= FP64_TOL
+    pc.check_eval_outputs(out, ref, pairs, tris, precision, what="fans")
+    pc.check_hits(ctx.hits(), ref, pairs, precision, what="fans")
     # every hit of this mesh shares the centre vertex of its fan
     assert _shares_one_vertex(tris, pairs[ref["hit_pair"]]).all()
     # the default evaluation of the same list flags them adjacent: no energy
@@ -147,9 +131,7 @@ def test_eval_grid_mesh_touching_pairs(ctx):
     xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
     out = ctx.evaluate(xd, td, pd, precision=ttie.FP64, flags=True, vertex_adjacent=True)
     ctx.check()
-    np.testing.assert_array_equal(out["flags"].cpu().numpy(), ref["flags"])
-    assert abs(out["energy"].item() - ref["E"]) <= FP64_TOL * max(ref["E"], 1e-300)
-    assert _rel(out["grad"].cpu().numpy(), ref["G"]) <= FP64_TOL
+    pc.check_eval_outputs(out, ref, pairs, tris, ttie.FP64, what="grid with touching pairs")
 
 
 def test_eval_deterministic(ctx, fans):
@@ -180,14 +162,15 @@ def test_hvp_matches_oracle(ctx, fans, precision):
     v = rng.normal(size=x.shape)
     v /= np.linalg.norm(v)
     dt = torch.float64 if precision == 0 else torch.float32
-    tol = FP64_TOL if precision == 0 else MIXED_TOL
     hv = ctx.hvp(xd, td, _dev(v, dt), ttie.HVP_EXACT).cpu().numpy()
-    assert _rel(hv, oracle.hvp(x, tris, pairs, v, exact=True, vertex_adjacent=True)) <= tol * 10
+    pc.check_vector(hv, oracle.hvp(x, tris, pairs, v, exact=True, vertex_adjacent=True),
+                    pc.hvp_row_scales(x, tris, pairs, v, True, vertex_adjacent=True), precision, "exact HVP")
     refp = oracle.hvp(x, tris, pairs, v, exact=False, vertex_adjacent=True)
+    scalep = pc.hvp_row_scales(x, tris, pairs, v, False, vertex_adjacent=True)
     hp = ctx.hvp(xd, td, _dev(v, dt), ttie.HVP_PSD).cpu().numpy()
-    assert _rel(hp, refp) <= tol
+    pc.check_vector(hp, refp, scalep, precision, "PSD HVP")
     y = ctx.bsr_mv(out["row_ptr"], out["col_idx"], out["vals"], _dev(v, dt)).cpu().numpy()
-    assert _rel(y, refp) <= tol
+    pc.check_vector(y, refp, scalep, precision, "BSR matvec")
 
 
 def test_batch_eval_with_option(ctx):

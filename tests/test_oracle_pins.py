@@ -579,8 +579,8 @@ def test_vertex_adjacent_flags_vs_exact():
         tris = np.array([[0, 1, 2], [0, 3, 4]], np.int32)
         r = oracle.evaluate(P, tris, np.array([[0, 1]], np.int32), hessian=False, vertex_adjacent=True)
         e = exact_moller.pair(P[[0, 1, 2]], P[[0, 3, 4]])
-        if r["flags"][0] == 3:  # degenerate line frame: T = 0 either way
-            continue
+        # small integers: every normal and D is exact, so a hit never has a zero line direction
+        assert r["flags"][0] != 3
         assert (r["flags"][0] == 1) == bool(e["flag"])
         n_hit += r["flags"][0] == 1
     assert n_hit > 100
@@ -617,3 +617,57 @@ def test_vertex_adjacent_pairs_definition():
     shared = (tris[:, None, :, None] == tris[None, :, None, :]).any(axis=3).sum(axis=2)
     i, j = np.nonzero(np.triu(ov & (shared <= 1), 1))
     np.testing.assert_array_equal(got, np.stack([i, j], 1).astype(got.dtype))
+
+
+# ---------------------------------------------------------------------------------------
+# The line frame at the edges of float64.  Eq. 1-2 are homogeneous: scaling every coordinate
+# by s = 2^k (exact in float64) scales t_c by s and T by s^4, and leaves a = dt_c^0/dX and
+# b = dt_c^1/dX unchanged.  At s = 2^-150 the direction D = n_a x n_b is of order 2^-600, so
+# |D|^2 would underflow to 0; at s = 2^150 it would overflow.  The oracle scales D by a power of
+# two before normalising it, so both give the worked example's values exactly.
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [-150, 150])
+def test_worked_example_at_extreme_scale(k):
+    s = 2.0 ** k
+    r = oracle.pair(WORKED * s)
+    assert r["status"] == oracle.ST_HIT
+    assert r["t0"] == GOLDEN["t0"] * s and r["t1"] == GOLDEN["t1"] * s
+    assert r["T"] == GOLDEN["T"] * s ** 4
+    np.testing.assert_allclose(r["a"].reshape(6, 3), A_WORKED, atol=1e-15)
+    np.testing.assert_allclose(r["b"].reshape(6, 3), B_WORKED, atol=1e-15)
+    np.testing.assert_allclose(r["g"].reshape(6, 3) / s ** 3, np.array(GOLDEN["g"]), atol=1e-15)
+    # every operation is a power-of-two multiple of the unscaled one: bit-identical a and b
+    u = oracle.pair(WORKED)
+    np.testing.assert_array_equal(r["a"], u["a"])
+    np.testing.assert_array_equal(r["b"], u["b"])
+    e = exact_moller.pair(WORKED[:3] * s, WORKED[3:] * s)
+    assert e["flag"]
+
+
+# ---------------------------------------------------------------------------------------
+# The degenerate line frame (status 3).  An exact hit always has a non-zero line direction:
+# both triangles straddle the other's plane, so the planes are not parallel.  Only rounding can
+# make the float64 D = n_a x n_b vanish, and tests/golden/degenerate_frame.json holds a pair
+# built by hand for that: the two products of each component of n_b round to the same double.
+# The exact-rational Moeller test finds the intersection; the oracle reports status 3, T = 0.
+# ---------------------------------------------------------------------------------------
+DEGENERATE = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "degenerate_frame.json")))
+
+
+def test_degenerate_frame_pair():
+    X = np.array([[float.fromhex(c) for c in p] for p in DEGENERATE["X_hex"]])
+    np.testing.assert_array_equal(X, np.array(DEGENERATE["X"], float))
+    e = exact_moller.pair(X[:3], X[3:])
+    assert e["straddle"] and e["flag"]
+    assert e["DD"] > 0  # the exact direction is not zero
+    r = oracle.pair(X)
+    assert r["status"] == DEGENERATE["status"] == oracle.ST_BAD_FRAME
+    assert r["T"] == 0.0 and not np.any(r["g"]) and not np.any(r["H"])
+    # the same pair inside a mesh: flag 3, no energy, no gradient, no Hessian block
+    tris = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    m = oracle.evaluate(X, tris, np.array([[0, 1]], np.int32))
+    assert m["flags"][0] == 3 and m["E"] == 0.0 and not np.any(m["G"]) and len(m["vals"]) == 0
+    # nudging the tilt so that the products no longer round together gives an ordinary hit
+    Y = X.copy()
+    Y[5, 2] += 2.0 ** -90  # v2.z - v0.z = 2^-40 (1 + 2^-51 + 2^-50), exact; n_b.x = 2^-90
+    assert oracle.pair(Y)["status"] == oracle.ST_HIT and exact_moller.pair(Y[:3], Y[3:])["flag"]
