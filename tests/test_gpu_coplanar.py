@@ -42,7 +42,7 @@ def soup():
     # 20,000 separate triangles on four crossing planes, small corners on a 64 x 64 integer grid
     x, tris = workloads.coplanar_soup(0, n_tris=20_000)
     pairs = oracle.pairs(x, tris)
-    return x, tris, pairs, oracle.evaluate(x, tris, pairs)
+    return x, tris, pairs, pc.reference(x, tris, pairs)
 
 
 @pytest.mark.parametrize("method", [1, 2])
@@ -79,7 +79,7 @@ def test_same_plane_pairs(ctx, plane):
     x = (o + uv[..., :1] * e1 + uv[..., 1:] * e2).reshape(-1, 3)
     tris = np.arange(len(x), dtype=np.int32).reshape(-1, 3)
     pairs = np.arange(len(tris), dtype=np.int32).reshape(-1, 2)
-    ref = oracle.evaluate(x, tris, pairs)
+    ref = pc.reference(x, tris, pairs)
     out = ctx.evaluate(_dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32), flags=True)
     ctx.check()
     got = out["flags"].cpu().numpy()
@@ -95,7 +95,7 @@ def test_flat_fans_with_vertex_adjacent_pairs(ctx):
 
     x, tris = workloads.crumpled_fans(0, n_fans=6, height=0.0)
     pairs = oracle.pairs(x, tris, vertex_adjacent=True)
-    ref = oracle.evaluate(x, tris, pairs, vertex_adjacent=True)
+    ref = pc.reference(x, tris, pairs, vertex_adjacent=True)
     assert np.sum(ref["flags"] == ttie.PAIR_COPLANAR) >= 36 * 8
     xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
     out = ctx.evaluate(xd, td, _dev(pairs, torch.int32), flags=True, vertex_adjacent=True)

@@ -25,7 +25,7 @@ def sphere4m():
     x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
     assert len(tris) == 4_194_304
     pairs = oracle.pairs(x, tris)
-    return x, tris, pairs, oracle.evaluate(x, tris, pairs, hessian=True)
+    return x, tris, pairs, pc.reference(x, tris, pairs, hessian=True)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -65,21 +65,21 @@ def test_batch64():
     out = ctx.batch_evaluate(xd, td, torch.from_numpy(vert_off).cuda(), pairs, n, precision=ttie.MIXED)
     ctx.check()
     got = _sorted(pairs[: int(n.item())].cpu().numpy())
-    ref_pairs, E_ref, hits = [], [], 0
+    ref_pairs, refs, hits = [], [], 0
     for p, (xp, tp, _) in enumerate(probs):
         pp = oracle.pairs(xp, tp)
         ref_pairs.append(pp + tri_off[p])
         r = oracle.evaluate(xp, tp, pp, hessian=False)
-        E_ref.append(r["E"])
+        refs.append(r)
         hits += len(r["hit_pair"])
     ref_pairs = np.concatenate(ref_pairs)
     np.testing.assert_array_equal(got, ref_pairs)
     assert int(out["n_hits"].item()) == hits
     E = out["energies"].cpu().numpy()
-    for p in range(len(E_ref)):
-        pc.check_energy(E[p], E_ref[p], f"problem {p} energy")
+    for p, r in enumerate(refs):
+        pc.check_energy(E[p], r, f"problem {p} energy")
     # gradient, every hit and the Hessian against the oracle on the concatenated mesh with the
     # batch's candidates (no pair joins two problems, so that is exactly the batch's answer)
-    ref = oracle.evaluate(x, tris, ref_pairs, hessian=True)
+    ref = pc.reference(x, tris, ref_pairs, hessian=True)
     pc.check_eval_outputs(out, ref, ref_pairs, tris, ttie.MIXED, flags=False, what="batch of 64")
     pc.check_hits(ctx.hits(1 << 17), ref, ref_pairs, ttie.MIXED, what="batch of 64")

@@ -73,7 +73,7 @@ def test_random_shared_vertex_meshes(ctx, seed):
     extra = extra[extra[:, 0] != extra[:, 1]]
     rep = pl[rng.integers(0, max(len(pl), 1), size=min(10, len(pl)))] if len(pl) else pl
     pl = np.concatenate([pl, extra, rep]).astype(np.int32)
-    ref = oracle.evaluate(x, tris, pl, vertex_adjacent=va)
+    ref = pc.reference(x, tris, pl, vertex_adjacent=va)
     out = ctx.evaluate(xd, td, _dev(pl, torch.int32), precision=precision, flags=True, pair_T=True,
                        vertex_adjacent=va)
     ctx.check()

@@ -50,7 +50,7 @@ def _run(ctx, x, tris, pairs, precision, psd=0, interval=0, flags=True):
 
 
 def _compare_eval(ctx, x, tris, pairs, precision, psd=0, interval=0):
-    ref = oracle.evaluate(x, tris, pairs, interval=interval, psd=psd)
+    ref = pc.reference(x, tris, pairs, interval=interval, psd=psd)
     out, dev = _run(ctx, x, tris, pairs, precision, psd, interval)
     pc.check_eval_outputs(out, ref, pairs, tris, precision)
     pc.check_hits(ctx.hits(), ref, pairs, precision)
@@ -191,7 +191,7 @@ def test_eval_degenerate_integer_triangles(ctx, seed):
 
     x, tris = workloads.integer_grid_triangles(seed, 60)
     pairs = np.array(list(itertools.combinations(range(len(tris)), 2)), np.int32)
-    ref = oracle.evaluate(x, tris, pairs)
+    ref = pc.reference(x, tris, pairs)
     out, _ = _run(ctx, x, tris, pairs, 0)
     pc.check_eval_outputs(out, ref, pairs, tris, 0)
     pc.check_hits(ctx.hits(), ref, pairs, 0)
@@ -208,7 +208,7 @@ def test_eval_empty_and_ragged(ctx):
         cnt = torch.tensor([n], dtype=torch.int64, device="cuda")
         out = ctx.evaluate(xd, td, pd, cnt)
         assert ctx.status() == ttie.TTIE_OK
-        ref = oracle.evaluate(x, tris, pairs[:n]) if n > 0 else None
+        ref = pc.reference(x, tris, pairs[:n]) if n > 0 else None
         if ref is None:
             assert out["energy"].item() == 0.0 and int(out["n_blocks"].item()) == 0
             assert torch.count_nonzero(out["grad"]).item() == 0

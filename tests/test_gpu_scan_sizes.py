@@ -51,7 +51,7 @@ def test_scan_tile_edges(ctx, nv):
     got = got[np.lexsort((got[:, 1], got[:, 0]))]
     ref_pairs = oracle.pairs(x, tris)
     np.testing.assert_array_equal(got, ref_pairs)
-    ref = oracle.evaluate(x, tris, ref_pairs)
+    ref = pc.reference(x, tris, ref_pairs)
     assert len(ref["hit_pair"]) > 0
     out = ctx.evaluate(xd, td, torch.from_numpy(ref_pairs).cuda(), precision=ttie.FP64, flags=True)
     ctx.check()

@@ -103,7 +103,7 @@ def test_eval_matches_oracle(ctx, fans, precision):
     from paper_2606_06511_amd import ttie
 
     x, tris, pairs = fans
-    ref = oracle.evaluate(x, tris, pairs, vertex_adjacent=True)
+    ref = pc.reference(x, tris, pairs, vertex_adjacent=True)
     assert ref["E"] > 0 and len(ref["hit_pair"]) > 1000
     xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
     out = ctx.evaluate(xd, td, pd, precision=precision, flags=True, pair_T=True, vertex_adjacent=True)
@@ -127,7 +127,7 @@ def test_eval_grid_mesh_touching_pairs(ctx):
 
     x, tris = workloads.folded_cloth(0, n=64)
     pairs = oracle.pairs(x, tris, vertex_adjacent=True)
-    ref = oracle.evaluate(x, tris, pairs, vertex_adjacent=True)
+    ref = pc.reference(x, tris, pairs, vertex_adjacent=True)
     xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
     out = ctx.evaluate(xd, td, pd, precision=ttie.FP64, flags=True, vertex_adjacent=True)
     ctx.check()
