@@ -26,11 +26,13 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
     return at;
   };
   const size_t H = (size_t)lim.max_hits, V = (size_t)lim.max_verts + 1, T = (size_t)std::max<int64_t>(lim.max_tris, 1);
+  // bitmap words over the vertices [0, max_verts] (one bit each), plus one
+  const size_t W = (size_t)lim.max_verts / 32 + 2;
   L.counters = take(sizeof(Counters));
   L.hits = take(H * sizeof(HitGeom));
   L.defer = take((size_t)lim.max_pairs * 4);
   L.recs = take(H * sizeof(AsmRec<double>));
-  L.cnt = take(V * 4);
+  L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time
   L.cur = take(V * 4);
   L.off = take(V * 4);
   L.ncol = take(V * 4);
@@ -38,8 +40,17 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.colbuf = take(36 * H * 4);
   L.cstage = take(36 * H * 4 + 36 * H);  // candidate values, then one flag byte each
   L.hvbuf = take(18 * H * 8);
-  L.epart = take(kRowBlocks * 8);
   L.epart_v = take(V * 8);
+  L.bm = take(W * 4);
+  L.wcnt = take(W * 4);
+  L.wp = take(W * 4);
+  L.wi = take(W * 4);
+  L.incpos = take(6 * H * 4);
+  L.roff = take((6 * H + 1) * 4);
+  L.coff = take((6 * H + 1) * 4);
+  L.erow = take(6 * H * 8);
+  // block totals of the word scan (two per 1024 words) and of the column scan (one per 1024 rows)
+  L.part = take(std::max<size_t>(2 * (W / 1024 + 2), 6 * H / 1024 + 2) * 4);
   L.scan_tmp_bytes = scan_bytes;
   L.scan_tmp = take(scan_bytes);
   L.bvh_keys = take(T * 4);
@@ -64,7 +75,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.hash_rank = take(E * 4);
   L.hash_skey = take(E * 8);
   L.hash_stri = take(E * 4);
-  L.touched = take(6 * H * 4);
+  L.touched = take(6 * H * 4);  // the vertex of each row
   L.inc2 = take(6 * H * sizeof(Incidence));
   L.pcg_vec = take(5 * 3 * (size_t)lim.max_verts * 8);
   L.pcg_flag = take(V * 4);  // active-row flags, their scan and the active-row list
@@ -247,7 +258,9 @@ ttie_status ttie_set_workspace(ttie_ctx* ctx, const ttie_limits* limits, void* d
   hipStream_t s = (hipStream_t)stream;
   // the counters and the per-vertex incidence counts start (and are kept) at zero
   hipError_t e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.counters), sizeof(Counters) / 4, s);
-  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cnt), limits->max_verts + 1, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cnt), 32 * (limits->max_verts / 32 + 2), s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.wcnt), limits->max_verts / 32 + 2, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.bm), limits->max_verts / 32 + 2, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.cur), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.ncol), limits->max_verts + 1, s);
   if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(ctx, L.bvh_hist), kMaxBuckets, s);

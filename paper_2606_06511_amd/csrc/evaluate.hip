@@ -2,22 +2,24 @@
 // deterministic (no floating-point atomics) assembly of energy, gradient and BSR Hessian.
 //
 // Pipeline on one stream, no host synchronization:
-//   k_screen         one lane per candidate: adjacency, FP64-filtered plane sides and flag,
-//                    FP64 interval ends; hits and filter-uncertain candidates are appended
-//                    with one atomic per wave (ballot + mbcnt)
+//   k_screen         one lane per candidate: adjacency, coordinate domain, FP64-filtered plane
+//                    sides and flag, FP64 interval ends; hits and filter-uncertain candidates
+//                    are appended with one atomic per wave (ballot + mbcnt); clears the bitmap
+//                    of touched vertices
 //   k_screen_exact   the uncertain candidates again, with the exact fallback
 //   k_derivs<S>      one lane per hit: a = dt_c^0, b = dt_c^1, T, g (Eq. 3), 2x2 Hessian core;
-//                    counts the hit's six vertices and lists the vertices touched first
-//   scan             exclusive scan of the per-vertex incidence counts
-//   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists
-//   k_rows_sort<S>   one wave per touched vertex: rank-sort its incidences by pair key (the
-//                    summation order) and list its distinct neighbour vertices (BSR columns)
-//   scan             BSR row pointers from the column counts
-//   k_rows_asm<S>    one wave per touched vertex, a lane per column: blocks J_k^T M J_l summed
-//                    in pair-key order; the gradient row and the row's energy share
-//   k_rows_final<S>  every vertex: zero gradient rows, energy summed in vertex order (fixed
-//                    tree per block), coordinate checks, per-vertex counters cleared
-//   k_eval_finish    block partials summed in block order; scalar outputs; counters reset
+//                    counts the hit's six incidences and marks its vertices in the bitmap
+//   k_rank           one block: per bitmap word, the touched vertices and the incidences below it
+//   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists; name the rows
+//   k_rows_sort<S>   one wave per touched vertex (row): rank-sort its incidences by pair key
+//                    (the summation order) and list its distinct neighbour vertices (BSR columns)
+//   k_col_scan       one block: BSR offsets of the rows from their column counts
+//   k_rows_asm<S>    one wave per row, a lane per column: blocks J_k^T M J_l summed in
+//                    pair-key order; the gradient row and the row's energy share
+//   k_dense<S>       every vertex: incidence offsets, BSR row pointers, zero gradient rows of
+//                    untouched vertices, counts cleared; block 0: energy summed in row order,
+//                    scalar outputs, counters reset
+// Everything from k_derivs to k_rows_asm scales with the hits, not with the mesh.
 #include <algorithm>
 
 
@@ -163,7 +165,25 @@ __device__ __forceinline__ bool load_pair(int64_t p, const double* x, int64_t nv
   return load_tri(x, nv, tris, i, vi, A) && load_tri(x, nv, tris, j, vj, B);
 }
 
-// Stage 1 (every candidate): indices, adjacency, T_a's sides against T_b's plane.
+// Coordinates must be finite, and 0 or of magnitude in [2^-200, 2^200]: the domain on which
+// the exact predicates are exact and overflow-free.  Decided on the bit patterns.
+__device__ __forceinline__ int coord_status(const Tri64& A, const Tri64& B) {
+  constexpr uint64_t kInf = 0x7ff0000000000000ull, kLo = 823ull << 52, kHi = 1223ull << 52;  // 2^-200, 2^200
+  bool nonfinite = false, outside = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t qa = (uint64_t)__double_as_longlong(A.p[k][c]) & 0x7fffffffffffffffull;
+      const uint64_t qb = (uint64_t)__double_as_longlong(B.p[k][c]) & 0x7fffffffffffffffull;
+      nonfinite |= (qa >= kInf) | (qb >= kInf);
+      outside |= (qa != 0 && (qa < kLo || qa > kHi)) | (qb != 0 && (qb < kLo || qb > kHi));
+    }
+  return nonfinite ? STATUS_NONFINITE : outside ? STATUS_UNSUPPORTED : 0;
+}
+
+// Stage 1 (every candidate): indices, coordinate domain, adjacency, T_a's sides against T_b's
+// plane.
 __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
                                              const int32_t* pairs, bool va, uint8_t* flags, double* pair_T,
                                              int& status) {
@@ -171,6 +191,11 @@ __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t
   Tri64 A, B;
   if (!load_pair(p, x, nv, tris, nt, pairs, vi, vj, A, B)) {
     status = STATUS_INDEX;
+    settle(p, PAIR_NONE, flags, pair_T);
+    return STEP_SETTLED;
+  }
+  if (const int cs = coord_status(A, B)) {
+    status = cs;
     settle(p, PAIR_NONE, flags, pair_T);
     return STEP_SETTLED;
   }
@@ -210,8 +235,13 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
                                                    const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
                                                    int64_t max_pairs, double half, int va, HitGeom* __restrict__ hits,
                                                    uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
-                                                   uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
+                                                   uint8_t* __restrict__ flags, double* __restrict__ pair_T,
+                                                   uint32_t* __restrict__ bm, int64_t nbm) {
   __shared__ uint32_t q1s[kWaves][kQueue], q2s[kWaves][kQueue];
+  // the touched-vertex bitmap of the previous evaluation (read by the calls after it) is
+  // cleared here, before k_derivs marks this one's
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nbm; w += (int64_t)gridDim.x * blockDim.x)
+    bm[w] = 0u;
   const int wave = threadIdx.x / 64, lane = __lane_id();
   uint32_t* q1 = q1s[wave];
   uint32_t* q2 = q2s[wave];
@@ -315,120 +345,327 @@ __device__ __forceinline__ void hit_vids(const int32_t* tris, int64_t key, int32
   }
 }
 
+// ---- rows of the touched vertices -------------------------------------------------------
+// The assembly works on the vertices the hits touch, in increasing vertex order: the compact
+// rows 0..R-1.  k_derivs marks each touched vertex in a bitmap (one bit per vertex) and counts
+// its incidences (cnt, and per bitmap word wcnt).  One scan over the words (k_rank) then gives,
+// for word w, the touched vertices below it (wp[w]) and their incidences (wi[w]), so that
+//   row of touched vertex v             = wp[v/32] + popcount(word bits below v)
+//   first incidence of vertex v's list  = wi[v/32] + sum of cnt over the vertices below v in its word
+// Everything after the screening scales with the hits, not with N_v, except the final pass
+// that writes the dense outputs (gradient rows, BSR row pointers, incidence offsets).
+// The word scan and the column scan run in blocks of kRankBlockWords entries: a first launch
+// writes each block's totals, the second adds the totals of the blocks below its own and scans
+// inside the block.  (Counting into a few shared totals with atomics instead serialises on the
+// contended addresses: measured 55 us for the 4M-triangle sphere's 27 K hits.)
+constexpr int kRankThreads = 256;
+constexpr int kRankWordsPerThread = 4;
+constexpr int kRankBlockWords = kRankThreads * kRankWordsPerThread;
+
+__device__ __forceinline__ uint32_t vrank(const uint32_t* __restrict__ bm, const uint32_t* __restrict__ wp, int64_t v) {
+  const uint64_t w = (uint64_t)v >> 5;
+  return wp[w] + (uint32_t)__popc(bm[w] & ((1u << (v & 31)) - 1u));
+}
+
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_derivs(const double* __restrict__ x, const int32_t* __restrict__ tris,
                                                    const HitGeom* __restrict__ hits, Counters* ctr, uint32_t max_hits,
                                                    int psd_mode, double half, AsmRec<S>* __restrict__ recs,
-                                                   int32_t* __restrict__ cnt, int32_t* __restrict__ touched) {
+                                                   int32_t* __restrict__ cnt, uint32_t* __restrict__ wcnt,
+                                                   uint32_t* __restrict__ bm, int32_t* __restrict__ incpos) {
   const uint32_t H = min(ctr->n_hits, max_hits);
-  for (uint32_t base = blockIdx.x * blockDim.x; base < H; base += gridDim.x * blockDim.x) {
-    const uint32_t h = base + threadIdx.x;
-    const bool active = h < H;
-    int32_t vid[6] = {0, 0, 0, 0, 0, 0};
-    if (active) {
-      const HitGeom g = hits[h];
-      AsmRec<S> r;
-      hit_vids(tris, g.key, r.vid);
-      r.pad = 0;
-      r.key = g.key;
-      V3<S> X[6];
-      const int e = local_coords<S>(x, r.vid, X);
-      interval_grads<S>(X, g.da, g.db, e, g.desc, half, r.a, r.b);
-      const double t0 = g.t0, t1 = g.t1;
-      const double pr = t0 * t1;
-      r.T = pr * pr;
-      // Eq. 3: dT = 2 t0 t1^2 a + 2 t1 t0^2 b
-      const S ca = Sc<S>::c(2.0 * pr * t1), cb = Sc<S>::c(2.0 * pr * t0);
-      double aa = 0, bb = 0, ab = 0;
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+    const HitGeom g = hits[h];
+    AsmRec<S> r;
+    hit_vids(tris, g.key, r.vid);
+    r.pad = 0;
+    r.key = g.key;
+    V3<S> X[6];
+    const int e = local_coords<S>(x, r.vid, X);
+    interval_grads<S>(X, g.da, g.db, e, g.desc, half, r.a, r.b);
+    const double t0 = g.t0, t1 = g.t1;
+    const double pr = t0 * t1;
+    r.T = pr * pr;
+    // Eq. 3: dT = 2 t0 t1^2 a + 2 t1 t0^2 b
+    const S ca = Sc<S>::c(2.0 * pr * t1), cb = Sc<S>::c(2.0 * pr * t0);
+    double aa = 0, bb = 0, ab = 0;
 #pragma unroll
-      for (int k = 0; k < 18; ++k) {
-        r.g[k] = ca * r.a[k] + cb * r.b[k];
-        aa += (double)r.a[k] * (double)r.a[k];
-        bb += (double)r.b[k] * (double)r.b[k];
-        ab += (double)r.a[k] * (double)r.b[k];
-      }
-      double M[3];
-      hessian_core(psd_mode, t0, t1, aa, bb, ab, M);
-      r.M[0] = Sc<S>::c(M[0]);
-      r.M[1] = Sc<S>::c(M[1]);
-      r.M[2] = Sc<S>::c(M[2]);
-      recs[h] = r;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) vid[k] = r.vid[k];
+    for (int k = 0; k < 18; ++k) {
+      r.g[k] = ca * r.a[k] + cb * r.b[k];
+      aa += (double)r.a[k] * (double)r.a[k];
+      bb += (double)r.b[k] * (double)r.b[k];
+      ab += (double)r.a[k] * (double)r.b[k];
     }
-    // count the six incidences (all six atomics in flight at once); a vertex whose count
-    // leaves 0 joins the touched list, the wave reserving its slots with one atomic
-    int32_t old[6];
+    double M[3];
+    hessian_core(psd_mode, t0, t1, aa, bb, ab, M);
+    r.M[0] = Sc<S>::c(M[0]);
+    r.M[1] = Sc<S>::c(M[1]);
+    r.M[2] = Sc<S>::c(M[2]);
+    recs[h] = r;
+    // the six incidences: each one's place in its vertex's list (all atomics in flight at
+    // once), the per-word count, and the vertex's bit (set by its first incidence)
+    int32_t vid[6], old[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) old[k] = active ? atomicAdd(&cnt[vid[k]], 1) : 1;
-    uint64_t fm[6];
-    uint32_t total = 0;
+    for (int k = 0; k < 6; ++k) vid[k] = r.vid[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      fm[k] = __ballot(old[k] == 0);
-      total += (uint32_t)__popcll(fm[k]);
+    for (int k = 0; k < 6; ++k) old[k] = atomicAdd(&cnt[vid[k]], 1);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) atomicAdd(&wcnt[(uint32_t)vid[k] >> 5], 1u);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (old[k] == 0) atomicOr(&bm[(uint32_t)vid[k] >> 5], 1u << (vid[k] & 31));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) incpos[6 * (int64_t)h + k] = old[k];
+  }
+}
+
+// Exclusive prefix sums of two per-thread values over a block of kRankThreads threads (in
+// thread order); the totals come back in ta, tb.
+__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t& ea, uint32_t& eb,
+                                            uint32_t& ta, uint32_t& tb) {
+  const int lane = __lane_id(), wave = threadIdx.x / 64;
+  uint32_t ia = a, ib = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t ya = __shfl_up(ia, d), yb = __shfl_up(ib, d);
+    if (lane >= d) {
+      ia += ya;
+      ib += yb;
     }
-    if (total) {
-      uint32_t wbase = 0;
-      if (__lane_id() == 0) wbase = atomicAdd(&ctr->n_touched, total);
-      wbase = __builtin_amdgcn_readfirstlane(wbase);
-      const uint64_t below = (1ull << __lane_id()) - 1ull;
+  }
+  if (lane == 63) {
+    sh[wave] = ia;
+    sh[32 + wave] = ib;
+  }
+  __syncthreads();
+  uint32_t oa = 0, ob = 0;
+  ta = 0;
+  tb = 0;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        if (old[k] == 0) touched[wbase + (uint32_t)__popcll(fm[k] & below)] = vid[k];
-        wbase += (uint32_t)__popcll(fm[k]);
-      }
+  for (int k = 0; k < kRankThreads / 64; ++k) {
+    const uint32_t sa = sh[k], sb = sh[32 + k];
+    if (k < wave) {
+      oa += sa;
+      ob += sb;
+    }
+    ta += sa;
+    tb += sb;
+  }
+  ea = oa + ia - a;
+  eb = ob + ib - b;
+}
+
+// Sum over the block of two per-thread values (every thread gets both totals).
+__device__ __forceinline__ void block_sum2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t& ta, uint32_t& tb) {
+  uint32_t ea, eb;
+  block_scan2(a, b, sh, ea, eb, ta, tb);
+}
+
+// Loads four consecutive entries of two arrays (zero past n).
+__device__ __forceinline__ void load4x2(const uint32_t* __restrict__ p, const uint32_t* __restrict__ q, int64_t i0,
+                                        int64_t n, uint32_t a[4], uint32_t b[4]) {
+  if (i0 + 4 <= n) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p + i0);
+    const uint4 y = *reinterpret_cast<const uint4*>(q + i0);
+    a[0] = x.x, a[1] = x.y, a[2] = x.z, a[3] = x.w;
+    b[0] = y.x, b[1] = y.y, b[2] = y.z, b[3] = y.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = i0 + k < n ? p[i0 + k] : 0u;
+      b[k] = i0 + k < n ? q[i0 + k] : 0u;
     }
   }
 }
 
+// Per block of kRankBlockWords bitmap words: its touched vertices and incidences.
+__global__ void __launch_bounds__(kRankThreads) k_rank_part(const uint32_t* __restrict__ bm,
+                                                            const uint32_t* __restrict__ wcnt, int64_t nw,
+                                                            uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[64];
+  uint32_t b[4], c[4];
+  load4x2(bm, wcnt, (int64_t)blockIdx.x * kRankBlockWords + 4 * threadIdx.x, nw, b, c);
+  uint32_t tb, tc;
+  block_sum2(__popc(b[0]) + __popc(b[1]) + __popc(b[2]) + __popc(b[3]), c[0] + c[1] + c[2] + c[3], sh, tb, tc);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = tb;
+    part[2 * blockIdx.x + 1] = tc;
+  }
+}
+
+// wp[w] and wi[w] for every bitmap word (nw words, plus the totals R and the incidence count
+// at index nw).  Block b scans words [b kRankBlockWords, (b + 1) kRankBlockWords), four per
+// thread, from the totals of the blocks below it.
+__global__ void __launch_bounds__(kRankThreads) k_rank(const uint32_t* __restrict__ bm,
+                                                       const uint32_t* __restrict__ wcnt, int64_t nw,
+                                                       const uint32_t* __restrict__ part, uint32_t* __restrict__ wp,
+                                                       uint32_t* __restrict__ wi) {
+  __shared__ uint32_t sh[64];
+  uint32_t pr = 0, pi = 0;
+  for (uint32_t q = threadIdx.x; q < blockIdx.x; q += kRankThreads) {
+    pr += part[2 * q];
+    pi += part[2 * q + 1];
+  }
+  uint32_t rows, incs;
+  block_sum2(pr, pi, sh, rows, incs);
+  __syncthreads();  // sh is reused
+  const int64_t w0 = (int64_t)blockIdx.x * kRankBlockWords + 4 * threadIdx.x;
+  uint32_t b[4], c[4];
+  load4x2(bm, wcnt, w0, nw, b, c);
+  uint32_t eb, ec, tb, tc;
+  block_scan2(__popc(b[0]) + __popc(b[1]) + __popc(b[2]) + __popc(b[3]), c[0] + c[1] + c[2] + c[3], sh, eb, ec, tb,
+              tc);
+  uint32_t pb = rows + eb, pc = incs + ec;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (w0 + k < nw) {
+      wp[w0 + k] = pb;
+      wi[w0 + k] = pc;
+    }
+    pb += (uint32_t)__popc(b[k]);
+    pc += c[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {  // the last block: the totals
+    wp[nw] = rows + tb;
+    wi[nw] = incs + tc;
+  }
+}
+
+// First incidence of vertex v's list: the incidences of the words below v's and of the
+// vertices below v in its word (one 128-byte line of cnt).
+__device__ __forceinline__ uint32_t list_start(const int32_t* __restrict__ cnt, const uint32_t* __restrict__ wi,
+                                               int32_t v) {
+  const uint32_t w = (uint32_t)v >> 5, j = (uint32_t)v & 31u;
+  const int4* line = reinterpret_cast<const int4*>(cnt + 32 * (int64_t)w);
+  uint32_t below = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int4 y = line[q];
+    below += (4 * q < (int)j ? (uint32_t)y.x : 0u) + (4 * q + 1 < (int)j ? (uint32_t)y.y : 0u) +
+             (4 * q + 2 < (int)j ? (uint32_t)y.z : 0u) + (4 * q + 3 < (int)j ? (uint32_t)y.w : 0u);
+  }
+  return wi[w] + below;
+}
+
+// Scatters the incidences into per-vertex lists; an incidence that came first in its vertex
+// names the vertex's row (rowv) and the row's first incidence (roff).
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ recs, const Counters* ctr,
-                                                 uint32_t max_hits, const int32_t* __restrict__ off,
-                                                 int32_t* __restrict__ cur, Incidence* __restrict__ inc) {
+                                                 uint32_t max_hits, const int32_t* __restrict__ incpos,
+                                                 const int32_t* __restrict__ cnt, const uint32_t* __restrict__ bm,
+                                                 const uint32_t* __restrict__ wp, const uint32_t* __restrict__ wi,
+                                                 int64_t nw, Incidence* __restrict__ inc, int32_t* __restrict__ rowv,
+                                                 int32_t* __restrict__ roff) {
   const uint32_t H = min(ctr->n_hits, max_hits);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 6 * H; t += gridDim.x * blockDim.x) {
-    const uint32_t h = t / 6, k = t % 6;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt == 0) roff[wp[nw]] = (int32_t)wi[nw];
+  for (int64_t t = gt; t < 6 * (int64_t)H; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h = t / 6;
+    const int k = (int)(t % 6);
     const int32_t v = recs[h].vid[k];
-    const int32_t pos = off[v] + atomicAdd(&cur[v], 1);
-    inc[pos] = Incidence{recs[h].key, (int32_t)h, (int32_t)k};
+    const int32_t pos = incpos[t];
+    const uint32_t start = list_start(cnt, wi, v);
+    inc[start + pos] = Incidence{recs[h].key, (int32_t)h, k};
+    if (pos == 0) {
+      const uint32_t r = vrank(bm, wp, v);
+      rowv[r] = v;
+      roff[r] = (int32_t)start;
+    }
   }
 }
 
-constexpr int kCandCap = 256;  // column candidates staged in LDS per wave
-constexpr int kRowStage = 16;  // incidences (and their hit records) a wave stages in LDS per row
+constexpr int kIncCap = 256;   // incidences of a row ranked from LDS
+constexpr int kColCap = 1024;  // column candidates of a row sorted in LDS
 
-// The distinct columns of one row, in increasing vertex order, written to out: the six vertex
-// ids of every incident hit go to cand with a first-occurrence flag each, and a kept candidate
-// goes to the number of kept candidates with a smaller id.  Returns the count (every lane).
+// Bitonic sort of s[0, p) (p a power of two, 64 <= p <= kColCap) by one wave in LDS.
+__device__ __forceinline__ void wave_sort_lds(int32_t* s, int p, int lane) {
+  for (int k = 2; k <= p; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < p; i += 64) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int32_t a = s[i], b = s[l];
+          if ((a > b) == ((i & k) == 0)) {
+            s[i] = b;
+            s[l] = a;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Bitonic sort of one value per lane across the wave (ascending in lane order).
+__device__ __forceinline__ int32_t wave_sort_reg(int32_t v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int32_t o = __shfl_xor(v, j);
+      const bool lower = (lane & j) == 0, up = (lane & k) == 0;
+      v = (lower == up) ? min(v, o) : max(v, o);
+    }
+  return v;
+}
+
+// The distinct columns of one row in increasing vertex order, written to out: the six vertex
+// ids of every incident hit, sorted, then the first of each run of equal ids kept.  Returns
+// the count (every lane).  lds: kColCap ints of the wave's LDS; rows with more candidates
+// rank every candidate against all the others in global memory (cand, flag: 6 n entries).
 template <class S>
-__device__ __forceinline__ int32_t row_columns(int32_t* cand, uint8_t* first, int32_t m, bool staged,
-                                               const Incidence* sinc, const Incidence* __restrict__ rinc,
-                                               const AsmRec<S>* __restrict__ recs, int32_t* __restrict__ out,
-                                               int lane) {
-  if (staged) {
-    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[sinc[c / 6].hit].vid[c % 6];
-  } else {
-    for (int32_t c = lane; c < m; c += 64) cand[c] = recs[rinc[c / 6].hit].vid[c % 6];
+__device__ __forceinline__ int32_t row_columns(int32_t* lds, const Incidence* __restrict__ rinc, int32_t n,
+                                               const AsmRec<S>* __restrict__ recs, int32_t* __restrict__ cand,
+                                               uint8_t* __restrict__ flag, int32_t* __restrict__ out, int lane) {
+  const int32_t m = 6 * n;
+  const uint64_t below = (1ull << lane) - 1ull;
+  if (m <= 64) {
+    int32_t v = lane < m ? recs[rinc[lane / 6].hit].vid[lane % 6] : INT32_MAX;
+    v = wave_sort_reg(v, lane);
+    const int32_t prev = __shfl_up(v, 1);
+    const bool keep = v != INT32_MAX && (lane == 0 || prev != v);
+    const uint64_t km = __ballot(keep);
+    if (keep) out[__popcll(km & below)] = v;
+    return (int32_t)__popcll(km);
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (m <= kColCap) {
+    int p = 128;
+    while (p < m) p <<= 1;
+    for (int32_t c = lane; c < p; c += 64) lds[c] = c < m ? recs[rinc[c / 6].hit].vid[c % 6] : INT32_MAX;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    wave_sort_lds(lds, p, lane);
+    int32_t kept = 0;
+    for (int32_t c0 = 0; c0 < m; c0 += 64) {
+      const int32_t c = c0 + lane;
+      const int32_t v = c < m ? lds[c] : INT32_MAX;
+      const bool keep = v != INT32_MAX && (c == 0 || lds[c - 1] != v);
+      const uint64_t km = __ballot(keep);
+      if (keep) out[kept + __popcll(km & below)] = v;
+      kept += (int32_t)__popcll(km);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the LDS is reused by the wave's next row
+    return kept;
+  }
+  // very long rows: quadratic ranking in global memory (each candidate against all others)
+  for (int32_t c = lane; c < m; c += 64) cand[c] = recs[rinc[c / 6].hit].vid[c % 6];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
   for (int32_t c = lane; c < m; c += 64) {
     const int32_t val = cand[c];
-    // no early exit: the loads are independent, so they pipeline instead of each waiting for
-    // the previous compare
     uint32_t dup = 0;
     for (int32_t j = 0; j < c; ++j) dup |= (uint32_t)(cand[j] == val);
-    first[c] = dup ? 0 : 1;
+    flag[c] = dup ? 0 : 1;
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
   int32_t kept = 0;
   for (int32_t c = lane; c < m; c += 64) {
-    if (!first[c]) continue;
+    if (!flag[c]) continue;
     const int32_t val = cand[c];
     int32_t pos = 0;
-    for (int32_t j = 0; j < m; ++j) pos += (int32_t)(first[j] != 0 && cand[j] < val);
+    for (int32_t j = 0; j < m; ++j) pos += (int32_t)(flag[j] != 0 && cand[j] < val);
     out[pos] = val;
     ++kept;
   }
@@ -436,38 +673,37 @@ __device__ __forceinline__ int32_t row_columns(int32_t* cand, uint8_t* first, in
   return kept;
 }
 
+// One row per wave: its incidences ranked by (pair key, slot, position) -- the summation
+// order, deterministic even when a hit holds the vertex twice (a pair sharing one vertex) and
+// a permutation even if a caller repeats a pair -- and, for the BSR, its distinct columns.
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict__ touched, const Counters* ctr,
-                                                      const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_rows_sort(const uint32_t* __restrict__ wp, int64_t nw,
+                                                      const int32_t* __restrict__ roff,
                                                       const Incidence* __restrict__ inc,
                                                       Incidence* __restrict__ inc2, const AsmRec<S>* __restrict__ recs,
                                                       int32_t* __restrict__ colbuf, int32_t* __restrict__ cstage,
                                                       int64_t cstage_len, int32_t* __restrict__ ncol, int want_bsr) {
-  __shared__ int32_t lcand[kWaves][kCandCap];
-  __shared__ uint8_t lflag[kWaves][kCandCap];
-  __shared__ Incidence sinc[kWaves][64];
+  __shared__ int32_t lcol[kWaves][kColCap];
+  __shared__ Incidence sinc[kWaves][kIncCap];
   const int wave = threadIdx.x / 64, lane = __lane_id();
-  const uint32_t U = ctr->n_touched;
-  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t v = touched[u];
-    const int32_t b = off[v], n = off[v + 1] - b;
-    // rank sort of the row's incidences by (pair key, slot, position): deterministic even when
-    // a hit holds the vertex twice (a pair sharing one vertex), and a permutation even if a
-    // caller repeats a pair.  Rows of up to 64 (wave-uniform test) rank from LDS.
-    if (n <= 64) {
-      Incidence me{};
-      if (lane < n) sinc[wave][lane] = me = inc[b + lane];
+  const uint32_t R = wp[nw];
+  for (uint32_t r = blockIdx.x * kWaves + wave; r < R; r += gridDim.x * kWaves) {
+    const int32_t b = roff[r], n = roff[r + 1] - b;
+    if (n <= kIncCap) {
+      for (int32_t i = lane; i < n; i += 64) sinc[wave][i] = inc[b + i];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (lane < n) {
+      for (int32_t i = lane; i < n; i += 64) {
+        const Incidence me = sinc[wave][i];
         int32_t rank = 0;
         for (int32_t j = 0; j < n; ++j) {
           const Incidence o = sinc[wave][j];
-          rank += (o.key < me.key) |
-                  ((o.key == me.key) & ((o.slot < me.slot) | ((o.slot == me.slot) & (j < lane))));
+          rank += (o.key < me.key) | ((o.key == me.key) & ((o.slot < me.slot) | ((o.slot == me.slot) & (j < i))));
         }
         inc2[b + rank] = me;
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     } else {
       for (int32_t i = lane; i < n; i += 64) {
         const Incidence me = inc[b + i];
@@ -480,22 +716,62 @@ __global__ void __launch_bounds__(kBlock) k_rows_sort(const int32_t* __restrict_
       }
     }
     if (want_bsr) {
-      // candidate columns: the six vertices of every incident hit, staged in LDS (or, for very
-      // large rows, in the workspace) with a first-occurrence flag each.  The two cases are
-      // separate calls so that the LDS one reads LDS directly (a pointer that may point to
-      // either memory would compile to slower generic loads).
-      const int32_t m = 6 * n;
-      int32_t kept;
-      if (m <= kCandCap)
-        kept = row_columns(lcand[wave], lflag[wave], m, n <= 64, sinc[wave], inc + b, recs, colbuf + 6 * (int64_t)b,
-                           lane);
-      else
-        kept = row_columns(cstage + 6 * (int64_t)b, reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
-                           m, false, sinc[wave], inc + b, recs, colbuf + 6 * (int64_t)b, lane);
-      if (lane == 0) ncol[v] = kept;
+      // the columns only depend on the set of incident hits, so the unsorted list serves
+      const int32_t kept = row_columns(lcol[wave], inc + b, n, recs, cstage + 6 * (int64_t)b,
+                                       reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
+                                       colbuf + 6 * (int64_t)b, lane);
+      if (lane == 0) ncol[r] = kept;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();  // the LDS staging is reused by the wave's next row
+  }
+}
+
+// Per block of kRankBlockWords rows: its BSR columns (R = wp[nw] rows in all).
+__global__ void __launch_bounds__(kRankThreads) k_col_part(const uint32_t* __restrict__ wp, int64_t nw,
+                                                           const int32_t* __restrict__ ncol, uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[64];
+  const uint32_t R = wp[nw];
+  const int64_t r0 = (int64_t)blockIdx.x * kRankBlockWords;
+  if (r0 > R) return;
+  uint32_t a[4], z[4];
+  load4x2(reinterpret_cast<const uint32_t*>(ncol), reinterpret_cast<const uint32_t*>(ncol), r0 + 4 * threadIdx.x, R, a,
+          z);
+  uint32_t t, unused;
+  block_sum2(a[0] + a[1] + a[2] + a[3], 0u, sh, t, unused);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Exclusive scan of ncol[0, R) into coff[0, R] (R = wp[nw]): block b takes rows
+// [b kRankBlockWords, (b + 1) kRankBlockWords), four per thread, from the totals of the blocks
+// below it.  The total coff[R] also goes to *n_blocks, and past cap latches TTIE_ERR_CAPACITY.
+__global__ void __launch_bounds__(kRankThreads) k_col_scan(const uint32_t* __restrict__ wp, int64_t nw,
+                                                           const int32_t* __restrict__ ncol,
+                                                           const uint32_t* __restrict__ part, int32_t* __restrict__ coff,
+                                                           int64_t cap, int64_t* n_blocks, Counters* ctr) {
+  __shared__ uint32_t sh[64];
+  const uint32_t R = wp[nw];
+  const int64_t r0 = (int64_t)blockIdx.x * kRankBlockWords;
+  if (r0 > R) return;
+  uint32_t pr = 0;
+  for (uint32_t q = threadIdx.x; q < blockIdx.x; q += kRankThreads) pr += part[q];
+  uint32_t base, unused;
+  block_sum2(pr, 0u, sh, base, unused);
+  __syncthreads();  // sh is reused
+  const int64_t i0 = r0 + 4 * threadIdx.x;
+  uint32_t v[4], z[4];
+  load4x2(reinterpret_cast<const uint32_t*>(ncol), reinterpret_cast<const uint32_t*>(ncol), i0, R, v, z);
+  uint32_t e, e2, t, t2;
+  block_scan2(v[0] + v[1] + v[2] + v[3], 0u, sh, e, e2, t, t2);
+  uint32_t p = base + e;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < R) coff[i0 + k] = (int32_t)p;
+    p += v[k];
+  }
+  if (r0 + kRankBlockWords > R && threadIdx.x == 0) {  // the block holding row R: the total
+    const uint32_t total = base + t;
+    coff[R] = (int32_t)total;
+    if (n_blocks) *n_blocks = total;
+    if ((int64_t)total > cap) latch(&ctr->status, STATUS_CAPACITY);
   }
 }
 
@@ -511,26 +787,28 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
     }
 }
 
-// One touched row per wave: the gradient row and the energy of the hits this vertex owns
-// (each hit counted at its first vertex), summed in pair-key order, then the row's BSR blocks,
-// one lane per column.  The row's incidences and hit records pass through LDS in chunks of
-// kRowStage (one memory round trip per chunk instead of a chain of dependent loads per
-// incidence); the sums run over the incidences in order, chunk after chunk.
+// One row per wave: the gradient row and the energy of the hits this vertex owns (each hit
+// counted at its first vertex), summed in pair-key order, then the row's BSR blocks, one lane
+// per column.  The row's incidences and hit records pass through LDS in chunks of kRowStage
+// (one memory round trip per chunk instead of a chain of dependent loads per incidence); the
+// sums run over the incidences in order, chunk after chunk.
+constexpr int kRowStage = 16;
+
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__ touched, const Counters* ctr,
-                                                     const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_rows_asm(const uint32_t* __restrict__ wp, int64_t nw,
+                                                     const int32_t* __restrict__ rowv, const int32_t* __restrict__ roff,
                                                      const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs,
-                                                     const int32_t* __restrict__ colbuf,
-                                                     const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
-                                                     S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
-                                                     double* __restrict__ epart, int32_t* status_word) {
+                                                     const int32_t* __restrict__ colbuf, const int32_t* __restrict__ coff,
+                                                     int32_t* __restrict__ col_idx, S* __restrict__ vals,
+                                                     int64_t block_cap, S* __restrict__ grad, double* __restrict__ erow,
+                                                     int32_t* status_word) {
   __shared__ AsmRec<S> srec[kWaves][kRowStage];
   __shared__ Incidence sinc[kWaves][kRowStage];
   constexpr int kWords = (int)(sizeof(AsmRec<S>) / 8);
   static_assert(sizeof(AsmRec<S>) % 8 == 0, "records are copied as 8-byte words");
   const int wave = threadIdx.x / 64, lane = __lane_id();
-  AsmRec<S>* R = srec[wave];
+  AsmRec<S>* Rr = srec[wave];
   Incidence* I = sinc[wave];
   // stages incidences [k0, k0 + cnt) of the row starting at b (every lane of the wave calls it)
   auto stage = [&](int32_t b, int32_t k0, int32_t cnt) {
@@ -540,34 +818,34 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int j = lane; j < cnt * kWords; j += 64) {
-      const int r = j / kWords, w = j % kWords;
-      reinterpret_cast<uint2*>(&R[r])[w] = reinterpret_cast<const uint2*>(&recs[I[r].hit])[w];
+      const int q = j / kWords, w = j % kWords;
+      reinterpret_cast<uint2*>(&Rr[q])[w] = reinterpret_cast<const uint2*>(&recs[I[q].hit])[w];
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  const uint32_t U = ctr->n_touched;
+  const uint32_t R = wp[nw];
   int status = 0;
-  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t v = touched[u];
-    const int32_t b = off[v], n = off[v + 1] - b;
+  for (uint32_t r = blockIdx.x * kWaves + wave; r < R; r += gridDim.x * kWaves) {
+    const int32_t v = rowv[r];
+    const int32_t b = roff[r], n = roff[r + 1] - b;
     // gradient row (lanes 0-2) and energy (lane 3)
     S acc = Sc<S>::c(0.0);
-    double erow = 0.0;
+    double e = 0.0;
     for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
       const int32_t cnt = min(n - k0, kRowStage);
       stage(b, k0, cnt);
       if (lane < 4)
         for (int32_t k = 0; k < cnt; ++k) {
-          if (lane < 3) acc = acc + R[k].g[3 * I[k].slot + lane];
-          else if (I[k].slot == 0) erow += R[k].T;
+          if (lane < 3) acc = acc + Rr[k].g[3 * I[k].slot + lane];
+          else if (I[k].slot == 0) e += Rr[k].T;
         }
     }
     if (lane < 3) grad[3 * (int64_t)v + lane] = acc;
-    else if (lane == 3) epart[v] = erow;
-    if (!row_ptr) continue;
+    else if (lane == 3) erow[r] = e;
+    if (!coff) continue;
     // BSR blocks: lane q owns column q (rows with more than 64 columns take several rounds)
-    const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
+    const int32_t rp = coff[r], nc = coff[r + 1] - rp;
     for (int32_t q0 = 0; q0 < nc; q0 += 64) {
       const int32_t q = q0 + lane;
       const int32_t col = q < nc ? colbuf[6 * (int64_t)b + q] : -1;
@@ -580,12 +858,11 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
         for (int32_t k = 0; k < cnt; ++k) {
           // the hit's slots holding this lane's column, in slot order: the lanes hold distinct
           // columns, so one pass of block_jmj serves every lane that matches a slot of the hit
-          // (instead of one pass per slot, most with a single lane active)
           uint32_t match = 0;
 #pragma unroll
-          for (int l = 0; l < 6; ++l) match |= (uint32_t)(R[k].vid[l] == col) << l;
+          for (int l = 0; l < 6; ++l) match |= (uint32_t)(Rr[k].vid[l] == col) << l;
           while (match) {
-            block_jmj(R[k], I[k].slot, __builtin_ctz(match), B);
+            block_jmj(Rr[k], I[k].slot, __builtin_ctz(match), B);
             match &= match - 1;
           }
         }
@@ -605,10 +882,12 @@ __global__ void __launch_bounds__(kBlock) k_rows_asm(const int32_t* __restrict__
   if (status) latch(status_word, status);
 }
 
-// Energy of each problem of a batch: block p sums the per-vertex energies of its vertex range
-// in a fixed order (thread-strided, then a tree).  Runs before k_rows_final clears them.
+// Energy of each problem of a batch: block p sums the energies of the rows of its vertex range
+// in a fixed order (thread-strided, then a tree).
 __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_prob, const int64_t* __restrict__ vert_off,
-                                                           const double* __restrict__ epart, double* __restrict__ energies,
+                                                           const uint32_t* __restrict__ bm,
+                                                           const uint32_t* __restrict__ wp,
+                                                           const double* __restrict__ erow, double* __restrict__ energies,
                                                            Counters* ctr) {
   __shared__ double red[kBlock];
   const int p = blockIdx.x;
@@ -617,8 +896,9 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
     latch(&ctr->status, STATUS_INVALID);
   b = max((int64_t)0, min(b, nv));
   e = max(b, min(e, nv));
+  const uint32_t r0 = vrank(bm, wp, b), r1 = vrank(bm, wp, e);
   double acc = 0.0;
-  for (int64_t v = b + threadIdx.x; v < e; v += kBlock) acc += epart[v];
+  for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBlock) acc += erow[r];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -628,78 +908,69 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
   if (threadIdx.x == 0) energies[p] = red[0];
 }
 
+// The dense outputs (blocks 1..): incidence offsets off[v] and BSR row pointers
+// row_ptr[v] = coff[row of v] for v in [0, nv], one thread per vertex; zero gradient entries
+// of untouched vertices, one thread per entry (so the stores coalesce).  The per-vertex and
+// per-word counts are cleared for the next evaluation.  A wave holds 64 consecutive
+// vertices, i.e. two whole bitmap words, so a vertex's offset inside its word is a 32-lane
+// prefix sum.  Block 0 sums the row energies in row order (thread-strided, then a tree), writes
+// the scalar outputs and resets the counters.
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_final(int64_t nv, const double* __restrict__ x,
-                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ cur,
-                                                       int32_t* __restrict__ ncol, double* __restrict__ epart,
-                                                       S* __restrict__ grad, double* __restrict__ blockpart,
-                                                       Counters* ctr) {
-  __shared__ double red[kBlock];
-  double esum = 0.0;
-  int code = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-    if (cnt[v] > 0) {
-      esum += epart[v];
-      cnt[v] = 0;
-      cur[v] = 0;
-      ncol[v] = 0;
-      epart[v] = 0.0;
-    } else {
-      grad[3 * v] = Sc<S>::c(0.0);
-      grad[3 * v + 1] = Sc<S>::c(0.0);
-      grad[3 * v + 2] = Sc<S>::c(0.0);
-    }
-    // every coordinate: finite, and 0 or of magnitude in [2^-200, 2^200] (the domain on which
-    // the exact predicates are exact)
-    for (int c = 0; c < 3; ++c) {
-      const double q = fabs(x[3 * v + c]);
-      if (!(q <= 1.7976931348623157e308)) code = STATUS_NONFINITE;
-      else if (q != 0.0 && (q < 6.223015277861142e-61 || q > 1.6069380442589903e60) && !code)
-        code = STATUS_UNSUPPORTED;
-    }
-  }
-  if (code) latch(&ctr->status, code);
-  red[threadIdx.x] = esum;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+__global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const uint32_t* __restrict__ bm,
+                                                  const uint32_t* __restrict__ wp, const uint32_t* __restrict__ wi,
+                                                  int32_t* __restrict__ cnt, uint32_t* __restrict__ wcnt,
+                                                  int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ coff, int32_t* __restrict__ row_ptr,
+                                                  S* __restrict__ grad, const double* __restrict__ erow, Counters* ctr,
+                                                  uint32_t max_hits, double* energy, int64_t* n_hits) {
+  if (blockIdx.x == 0) {
+    __shared__ double red[kBlock];
+    const uint32_t R = wp[nw];
+    double acc = 0.0;
+    for (uint32_t r = threadIdx.x; r < R; r += kBlock) acc += erow[r];
+    red[threadIdx.x] = acc;
     __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    *energy = red[0];
+    const uint32_t H = ctr->n_hits;
+    if (n_hits) *n_hits = (int64_t)H;
+    if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
+    ctr->last_hits = min(H, max_hits);
+    ctr->last_touched = R;
+    ctr->n_hits = 0;
+    ctr->n_defer = 0;
+    return;
   }
-  if (threadIdx.x == 0) blockpart[blockIdx.x] = red[0];
-}
-
-// Sums the block partials in block order, writes the scalar outputs, hands the hit list to
-// hvp / get_hits and resets the counters for the next evaluation (one wave).
-__global__ void __launch_bounds__(kBlock) k_eval_finish(int nblocks, const double* __restrict__ blockpart, Counters* ctr,
-                                                        uint32_t max_hits, const int32_t* __restrict__ row_ptr,
-                                                        int64_t nv, int64_t block_cap, double* energy,
-                                                        int64_t* n_blocks, int64_t* n_hits) {
-  // fixed-order sum: thread t adds partials t, t + 256, ..., then a tree
-  __shared__ double red[kBlock];
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < nblocks; k += kBlock) acc += blockpart[k];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  const int lane = __lane_id();
+  const int64_t t0 = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
+  for (int64_t v = t0; v - lane <= nv; v += stride) {
+    const bool in = v <= nv;
+    const int64_t w = v >> 5;
+    const uint32_t word = in ? bm[w] : 0u;
+    const uint32_t j = (uint32_t)v & 31u;
+    const int32_t c = in ? cnt[v] : 0;
+    // exclusive prefix of c over the vertices of the same word (lanes 0-31 and 32-63)
+    int32_t incl = c;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const int32_t y = __shfl_up(incl, d, 32);
+      if ((int)j >= d) incl += y;
+    }
+    if (!in) continue;
+    off[v] = (int32_t)wi[w] + incl - c;
+    if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
+    if (c) cnt[v] = 0;
+    if (j == 0 && w < nw) wcnt[w] = 0u;
   }
-  if (threadIdx.x != 0) return;
-  const double E = red[0];
-  *energy = E;
-  const uint32_t H = ctr->n_hits;
-  if (n_hits) *n_hits = (int64_t)H;
-  if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
-  if (row_ptr) {
-    const int64_t nb = row_ptr[nv];
-    if (n_blocks) *n_blocks = nb;
-    if (nb > block_cap) latch(&ctr->status, STATUS_CAPACITY);
+  for (int64_t i = t0; i < 3 * nv; i += stride) {
+    const int64_t v = i / 3;
+    if (!((bm[v >> 5] >> (v & 31)) & 1u)) grad[i] = Sc<S>::c(0.0);
   }
-  ctr->last_hits = min(H, max_hits);
-  ctr->last_touched = ctr->n_touched;
-  ctr->n_hits = 0;
-  ctr->n_defer = 0;
-  ctr->n_touched = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -710,60 +981,43 @@ __global__ void __launch_bounds__(kBlock) k_eval_finish(int nblocks, const doubl
 // Symbolic, first pass: the distinct columns of every touched row (as in k_rows_sort) and
 // their count.
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_sym_cols(const int32_t* __restrict__ touched, const Counters* ctr,
-                                                     const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_sym_cols(const Counters* ctr, const int32_t* __restrict__ roff,
                                                      const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs, int32_t* __restrict__ colbuf,
                                                      int32_t* __restrict__ cstage, int64_t cstage_len,
                                                      int32_t* __restrict__ ncol) {
-  __shared__ int32_t lcand[kWaves][kCandCap];
-  __shared__ uint8_t lflag[kWaves][kCandCap];
-  __shared__ Incidence sinc[kWaves][64];
+  __shared__ int32_t lcol[kWaves][kColCap];
   const int wave = threadIdx.x / 64, lane = __lane_id();
   const uint32_t U = ctr->last_touched;
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t v = touched[u];
-    const int32_t b = off[v], n = off[v + 1] - b;
-    const int32_t m = 6 * n;
-    int32_t kept;
-    if (m <= kCandCap)
-      kept = row_columns(lcand[wave], lflag[wave], m, false, sinc[wave], inc2 + b, recs, colbuf + 6 * (int64_t)b,
-                         lane);
-    else
-      kept = row_columns(cstage + 6 * (int64_t)b, reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
-                         m, false, sinc[wave], inc2 + b, recs, colbuf + 6 * (int64_t)b, lane);
-    if (lane == 0) ncol[v] = kept;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    const int32_t b = roff[u], n = roff[u + 1] - b;
+    const int32_t kept = row_columns(lcol[wave], inc2 + b, n, recs, cstage + 6 * (int64_t)b,
+                                     reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
+                                     colbuf + 6 * (int64_t)b, lane);
+    if (lane == 0) ncol[u] = kept;
   }
 }
 
-// Symbolic, second pass (after the row pointers): column indices of every touched row, the
-// column counts cleared for the next call, the block count.
-__global__ void __launch_bounds__(kBlock) k_sym_write(const int32_t* __restrict__ touched, Counters* ctr,
-                                                      const int32_t* __restrict__ off,
+// Symbolic, second pass (after the column offsets): column indices of every touched row.
+__global__ void __launch_bounds__(kBlock) k_sym_write(const Counters* ctr, const int32_t* __restrict__ roff,
                                                       const int32_t* __restrict__ colbuf,
-                                                      const int32_t* __restrict__ row_ptr, int64_t nv,
-                                                      int32_t* __restrict__ col_idx, int64_t cap,
-                                                      int32_t* __restrict__ ncol, int64_t* n_blocks) {
+                                                      const int32_t* __restrict__ coff, int32_t* __restrict__ col_idx,
+                                                      int64_t cap) {
   const int wave = threadIdx.x / 64, lane = __lane_id();
   const uint32_t U = ctr->last_touched;
-  int status = 0;
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t v = touched[u];
-    const int32_t b = off[v], rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
-    for (int32_t q = lane; q < nc; q += 64) {
+    const int32_t b = roff[u], rp = coff[u], nc = coff[u + 1] - rp;
+    for (int32_t q = lane; q < nc; q += 64)
       if ((int64_t)rp + q < cap) col_idx[rp + q] = colbuf[6 * (int64_t)b + q];
-      else status = STATUS_CAPACITY;
-    }
-    if (lane == 0) ncol[v] = 0;
   }
-  if (status) latch(&ctr->status, status);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int64_t nb = row_ptr[nv];
-    *n_blocks = nb;
-    if (nb > cap) latch(&ctr->status, STATUS_CAPACITY);
-  }
+}
+
+// Symbolic, last pass: the dense row pointers row_ptr[v] = coff[row of v], v in [0, nv].
+__global__ void __launch_bounds__(kBlock) k_rowptr_fill(int64_t nv, const uint32_t* __restrict__ bm,
+                                                        const uint32_t* __restrict__ wp,
+                                                        const int32_t* __restrict__ coff, int32_t* __restrict__ row_ptr) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= nv; v += (int64_t)gridDim.x * blockDim.x)
+    row_ptr[v] = coff[vrank(bm, wp, v)];
 }
 
 template <class S>
@@ -777,8 +1031,8 @@ __global__ void k_zero_blocks(const int32_t* __restrict__ row_ptr, int64_t nv, S
 // the one-call assembly, so the values are the same bit for bit) into the caller's columns.  A
 // hit vertex missing from its row's columns latches TTIE_ERR_INVALID_ARGUMENT.
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_num_rows(const int32_t* __restrict__ touched, Counters* ctr,
-                                                     const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_num_rows(const int32_t* __restrict__ rowv, Counters* ctr,
+                                                     const int32_t* __restrict__ roff,
                                                      const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs,
                                                      const int32_t* __restrict__ row_ptr,
@@ -787,8 +1041,8 @@ __global__ void __launch_bounds__(kBlock) k_num_rows(const int32_t* __restrict__
   const uint32_t U = ctr->last_touched;
   int status = 0;
   for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t v = touched[u];
-    const int32_t b = off[v], n = off[v + 1] - b;
+    const int32_t v = rowv[u];
+    const int32_t b = roff[u], n = roff[u + 1] - b;
     const int32_t rp = row_ptr[v], nc = row_ptr[v + 1] - rp;
     // coverage: every vertex of every incident hit is a column of the row (binary search)
     for (int32_t t = lane; t < 6 * n; t += 64) {
@@ -944,6 +1198,13 @@ static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, h
   return launch_scan_i32(c, in, out, n, s);
 }
 
+// rows of the touched vertices: the bitmap words (one more than needed, so that the row of v
+// is defined for every v in [0, nv])
+static int64_t bitmap_words(int64_t nv) { return nv / 32 + 1; }
+static unsigned col_scan_blocks(const Ctx* c) {
+  return (unsigned)((6 * c->lim.max_hits + 1 + kRankBlockWords - 1) / kRankBlockWords);
+}
+
 template <class S>
 static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                             int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags,
@@ -955,26 +1216,34 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   HitGeom* hits = wsp<HitGeom>(c, L.hits);
   AsmRec<S>* recs = wsp<AsmRec<S>>(c, L.recs);
   int32_t* cnt = wsp<int32_t>(c, L.cnt);
-  int32_t* cur = wsp<int32_t>(c, L.cur);
+  uint32_t* wcnt = wsp<uint32_t>(c, L.wcnt);
+  uint32_t* bm = wsp<uint32_t>(c, L.bm);
+  uint32_t* wp = wsp<uint32_t>(c, L.wp);
+  uint32_t* wi = wsp<uint32_t>(c, L.wi);
+  int32_t* incpos = wsp<int32_t>(c, L.incpos);
+  int32_t* rowv = wsp<int32_t>(c, L.touched);
+  int32_t* roff = wsp<int32_t>(c, L.roff);
+  int32_t* coff = wsp<int32_t>(c, L.coff);
   int32_t* off = wsp<int32_t>(c, L.off);
   int32_t* ncol = wsp<int32_t>(c, L.ncol);
   Incidence* inc = wsp<Incidence>(c, L.inc);
   Incidence* inc2 = wsp<Incidence>(c, L.inc2);
   int32_t* colbuf = wsp<int32_t>(c, L.colbuf);
   int32_t* cstage = wsp<int32_t>(c, L.cstage);
-  int32_t* touched = wsp<int32_t>(c, L.touched);
-  double* epart = wsp<double>(c, L.epart_v);
-  double* blockpart = wsp<double>(c, L.epart);
+  double* erow = wsp<double>(c, L.erow);
+  uint32_t* part = wsp<uint32_t>(c, L.part);
   int32_t* defer = wsp<int32_t>(c, L.defer);
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
   const int va = (o->flags & TTIE_EVAL_VERTEX_ADJACENT) ? 1 : 0;
   const int64_t nv = m->n_verts;
+  const int64_t nw = bitmap_words(nv);
   const bool bsr = row_ptr != nullptr;
 
   stage_begin(c, TTIE_STAGE_SCREEN, s);
-  k_screen<<<grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS)), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half,
-                                                       va, hits, max_hits, defer, ctr, flags, pair_T);
+  k_screen<<<grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS)), kBlock, 0, s>>>(
+      m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half, va, hits, max_hits, defer, ctr, flags, pair_T, bm,
+      nw);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,
@@ -982,26 +1251,28 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   stage_end(c, TTIE_STAGE_SCREEN_EXACT, s);
   stage_begin(c, TTIE_STAGE_DERIVS, s);
   k_derivs<S><<<grid_for(c->lim.max_hits, 1024), kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode,
-                                                                 half, recs, cnt, touched);
+                                                                 half, recs, cnt, wcnt, bm, incpos);
   stage_end(c, TTIE_STAGE_DERIVS, s);
   stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
-  hipError_t err = scan_i32(c, cnt, off, nv + 1, s);
-  if (err != hipSuccess) return err;
-  k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, off, cur, inc);
+  const unsigned rank_blocks = (unsigned)((nw + kRankBlockWords - 1) / kRankBlockWords);
+  k_rank_part<<<rank_blocks, kRankThreads, 0, s>>>(bm, wcnt, nw, part);
+  k_rank<<<rank_blocks, kRankThreads, 0, s>>>(bm, wcnt, nw, part, wp, wi);
+  k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, incpos, cnt, bm, wp, wi, nw,
+                                                                   inc, rowv, roff);
   const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
                                                      (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
-  k_rows_sort<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc, inc2, recs, colbuf, cstage, 36 * c->lim.max_hits,
-                                          ncol, bsr ? 1 : 0);
+  k_rows_sort<S><<<grows, kBlock, 0, s>>>(wp, nw, roff, inc, inc2, recs, colbuf, cstage, 36 * c->lim.max_hits, ncol,
+                                          bsr ? 1 : 0);
   if (bsr) {
-    err = scan_i32(c, ncol, row_ptr, nv + 1, s);
-    if (err != hipSuccess) return err;
+    k_col_part<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part);
+    k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part, coff, block_cap, n_blocks, ctr);
   }
-  k_rows_asm<S><<<grows, kBlock, 0, s>>>(touched, ctr, off, inc2, recs, colbuf, bsr ? row_ptr : nullptr, col_idx,
-                                         vals, block_cap, grad, epart, &ctr->status);
-  if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, epart, energies, ctr);
-  k_rows_final<S><<<kRowBlocks, kBlock, 0, s>>>(nv, m->x, cnt, cur, ncol, epart, grad, blockpart, ctr);
-  k_eval_finish<<<1, kBlock, 0, s>>>(kRowBlocks, blockpart, ctr, max_hits, bsr ? row_ptr : nullptr, nv, block_cap, energy,
-                                 n_blocks, n_hits);
+  k_rows_asm<S><<<grows, kBlock, 0, s>>>(wp, nw, rowv, roff, inc2, recs, colbuf, bsr ? coff : nullptr, col_idx, vals,
+                                         block_cap, grad, erow, &ctr->status);
+  if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
+  k_dense<S><<<1 + grid_for(3 * nv + 1, 2048), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
+                                                                bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
+                                                                energy, n_hits);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
   return hipGetLastError();
 }
@@ -1023,18 +1294,21 @@ static hipError_t bsr_symbolic_impl(Ctx* c, int32_t* row_ptr, int32_t* col_idx, 
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   const int64_t nv = c->last_nverts;
+  const int64_t nw = bitmap_words(nv);
   const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
                                                      (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
+  int32_t* coff = wsp<int32_t>(c, L.coff);
   stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
-  k_sym_cols<S><<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
-                                         wsp<Incidence>(c, L.inc2), wsp<AsmRec<S>>(c, L.recs),
-                                         wsp<int32_t>(c, L.colbuf), wsp<int32_t>(c, L.cstage),
-                                         36 * c->lim.max_hits, wsp<int32_t>(c, L.ncol));
-  hipError_t err = scan_i32(c, wsp<int32_t>(c, L.ncol), row_ptr, nv + 1, s);
-  if (err != hipSuccess) return err;
-  k_sym_write<<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
-                                       wsp<int32_t>(c, L.colbuf), row_ptr, nv, col_idx, cap, wsp<int32_t>(c, L.ncol),
-                                       n_blocks);
+  k_sym_cols<S><<<grows, kBlock, 0, s>>>(ctr, wsp<int32_t>(c, L.roff), wsp<Incidence>(c, L.inc2),
+                                         wsp<AsmRec<S>>(c, L.recs), wsp<int32_t>(c, L.colbuf),
+                                         wsp<int32_t>(c, L.cstage), 36 * c->lim.max_hits, wsp<int32_t>(c, L.ncol));
+  k_col_part<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wsp<uint32_t>(c, L.wp), nw, wsp<int32_t>(c, L.ncol),
+                                                         wsp<uint32_t>(c, L.part));
+  k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wsp<uint32_t>(c, L.wp), nw, wsp<int32_t>(c, L.ncol),
+                                                         wsp<uint32_t>(c, L.part), coff, cap, n_blocks, ctr);
+  k_sym_write<<<grows, kBlock, 0, s>>>(ctr, wsp<int32_t>(c, L.roff), wsp<int32_t>(c, L.colbuf), coff, col_idx, cap);
+  k_rowptr_fill<<<grid_for(nv + 1, 2048), kBlock, 0, s>>>(nv, wsp<uint32_t>(c, L.bm), wsp<uint32_t>(c, L.wp), coff,
+                                                          row_ptr);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
   return hipGetLastError();
 }
@@ -1048,7 +1322,7 @@ static hipError_t bsr_numeric_impl(Ctx* c, const int32_t* row_ptr, const int32_t
                                                      (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
   stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
   k_zero_blocks<S><<<grid_for(9 * c->lim.max_blocks, 2048), kBlock, 0, s>>>(row_ptr, nv, vals);
-  k_num_rows<S><<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.off),
+  k_num_rows<S><<<grows, kBlock, 0, s>>>(wsp<int32_t>(c, L.touched), ctr, wsp<int32_t>(c, L.roff),
                                          wsp<Incidence>(c, L.inc2), wsp<AsmRec<S>>(c, L.recs), row_ptr, col_idx,
                                          vals);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);

@@ -12,8 +12,6 @@
 
 namespace ttie {
 
-// blocks of the row-assembly kernel (fixed, so the energy partial sums have a fixed order)
-constexpr int kRowBlocks = 512;
 constexpr int kMortonBucketBits = 22;  // at most 2^22 buckets in the broad-phase counting sort
 constexpr int kMaxProblems = TTIE_MAX_PROBLEMS;
 constexpr int kHashEntriesPerTri = 8;  // spatial-hash entries reserved per triangle
@@ -41,9 +39,9 @@ struct Incidence {
 struct Counters {
   int32_t status;          // latched TTIE status (first error wins)
   uint32_t n_hits;         // intersecting pairs found by the last screening
-  uint32_t last_touched;   // vertices touched by the hits of the last completed evaluation
+  uint32_t last_touched;   // vertices touched by the hits of the last completed evaluation (its rows)
   uint32_t n_defer;        // candidates whose signs need the exact fallback
-  uint32_t n_touched;      // vertices touched by the hits of the current evaluation
+  uint32_t n_touched;      // (unused)
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
   uint64_t n_entries;      // (cell, triangle) entries of the spatial-hash broad phase
   uint32_t n_heavy;        // broad-phase work items handed to a wave-cooperative kernel
@@ -104,8 +102,11 @@ __device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {
 }
 
 struct Layout {
-  size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart, epart_v, scan_tmp,
+  size_t counters, hits, defer, recs, cnt, cur, off, ncol, inc, colbuf, cstage, hvbuf, epart_v, scan_tmp,
       scan_tmp_bytes;
+  // rows of the touched vertices: bitmap, per-word counts and prefixes, incidence places,
+  // row offsets (incidences, BSR blocks) and row energies
+  size_t bm, wcnt, wp, wi, incpos, roff, coff, erow, part;
   size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state, pcg_flag, pcg_pos, pcg_act;
   size_t total;
