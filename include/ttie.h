@@ -186,6 +186,33 @@ ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs
                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
                       int64_t* n_hits, void* stream);
 
+/* ---- evaluation without a workspace --------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  The same evaluation as ttie_eval (same
+ * kernels, same results bit for bit), run in a file-scope device array of
+ * TTIE_STATIC_SCRATCH_BYTES that every GPU the library runs on holds until the process ends,
+ * in place of the caller's workspace: it needs a context (ttie_create looks the array's
+ * address up on the context's device) but no ttie_set_workspace, and calls no allocating
+ * routine (no hipMalloc, no events).
+ *  max_hits   the intersecting-pair capacity the array is laid out for (as limits.max_hits)
+ *  status     optional device int32: 0, or the TTIE_ERR_* code the kernels of this call
+ *             detected (index out of range, non-finite coordinate, capacity) -- the status
+ *             word that ttie_get_status reads for ttie_eval, which this call does not touch
+ *  the other arguments as ttie_eval; pair_capacity and block_capacity also size the layout.
+ * Returns TTIE_ERR_CAPACITY, before anything runs, when n_verts, pair_capacity, max_hits and
+ * block_capacity need more than TTIE_STATIC_SCRATCH_BYTES (about 13 B per vertex, 4 B per
+ * listed pair and 1.3 KB per hit).  Every call on one GPU uses that GPU's one array and finds
+ * the last call's contents in it (the counts that must start at zero are cleared by fill
+ * kernels at the start of each call): calls that overlap on one GPU -- two streams, two
+ * threads, two contexts -- race, and the caller must order them.  ttie_get_hits, ttie_hvp and
+ * the ttie_bsr_* calls refer to the context's last ttie_eval, never to this call. */
+#define TTIE_STATIC_SCRATCH_BYTES (64ll << 20)
+ttie_status ttie_eval_static(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                             int64_t pair_capacity, int64_t max_hits, const ttie_options* opts, double* energy,
+                             void* grad, uint8_t* flags, double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals,
+                             int64_t block_capacity, int64_t* n_blocks, int64_t* n_hits, int32_t* status,
+                             void* stream);
+
 /* ---- batches of independent problems --------------------------------------------------
  * Many independent problems (each a mesh, or the union of several meshes, whose pairs are
  * evaluated among themselves only) in one call: the hot path of Sec. 1 applied problem by

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -12,12 +13,40 @@ namespace ttie {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspace of ttie_eval_static, for callers that cannot allocate: a file-scope device array
+// that every GPU the library runs on holds (its own copy) until the process ends.  In host code
+// its name is not a device address: ttie_create looks the address up once per device, and the
+// calls use only that.
+static __device__ __align__(256) unsigned char scratch[TTIE_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices];
+
+// With `device` current: its copy's address, looked up on the first call for the device.
+static hipError_t scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = p;
+  return hipSuccess;
+}
+
+static void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
+
 constexpr int64_t kMaxBuckets = (int64_t)1 << kMortonBucketBits;  // buckets of the broad-phase sort
 
 // one scan scratch serves every scan: the vertex-sized ones and the bucket counts
 static int64_t scan_len(const ttie_limits& lim) { return std::max<int64_t>(lim.max_verts, kMaxBuckets) + 1; }
 
-static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
+// eval_only: only the regions the evaluation uses get space (the others are empty)
+static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_only = false) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -25,6 +54,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
     o += align256(bytes);
     return at;
   };
+  auto take_other = [&](size_t bytes) { return take(eval_only ? 0 : bytes); };
   const size_t H = (size_t)lim.max_hits, V = (size_t)lim.max_verts + 1, T = (size_t)std::max<int64_t>(lim.max_tris, 1);
   // bitmap words over the vertices [0, max_verts] (one bit each), plus one
   const size_t W = (size_t)lim.max_verts / 32 + 2;
@@ -33,14 +63,14 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   L.defer = take((size_t)lim.max_pairs * 4);
   L.recs = take(H * sizeof(AsmRec<double>));
   L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time
-  L.cur = take(V * 4);
+  L.cur = take_other(V * 4);
   L.off = take(V * 4);
   L.ncol = take(V * 4);
   L.inc = take(6 * H * sizeof(Incidence));
   L.colbuf = take(36 * H * 4);
   L.cstage = take(36 * H * 4 + 36 * H);  // candidate values, then one flag byte each
-  L.hvbuf = take(18 * H * 8);
-  L.epart_v = take(V * 8);
+  L.hvbuf = take_other(18 * H * 8);
+  L.epart_v = take_other(V * 8);
   L.bm = take(W * 4);
   L.wcnt = take(W * 4);
   L.wp = take(W * 4);
@@ -52,37 +82,37 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes) {
   // block totals of the word scan (two per 1024 words) and of the column scan (one per 1024 rows)
   L.part = take(std::max<size_t>(2 * (W / 1024 + 2), 6 * H / 1024 + 2) * 4);
   L.scan_tmp_bytes = scan_bytes;
-  L.scan_tmp = take(scan_bytes);
-  L.bvh_keys = take(T * 4);
-  L.bvh_qend = take(T * 4);
-  L.bvh_vals = take(T * 4);
-  L.bvh_vals2 = take(T * 4);
-  L.bvh_hist = take((size_t)kMaxBuckets * 4);
-  L.bvh_offset = take(((size_t)kMaxBuckets + 1) * 4);
-  L.bvh_boxes = take((2 * T + 64) * 32);  // implicit tree: at most 2T nodes of 32 B
-  L.bvh_leaves = take((T + 4) * 64);      // sorted leaf records, padded to a multiple of 4
-  L.bvh_tbox = take(T * 6 * 8);
-  L.bvh_centroid = take(T * 3 * 4);
-  L.bvh_part = take(512 * 6 * 4);
-  L.bvh_ext = take(512 * 8);
+  L.scan_tmp = take_other(scan_bytes);
+  L.bvh_keys = take_other(T * 4);
+  L.bvh_qend = take_other(T * 4);
+  L.bvh_vals = take_other(T * 4);
+  L.bvh_vals2 = take_other(T * 4);
+  L.bvh_hist = take_other((size_t)kMaxBuckets * 4);
+  L.bvh_offset = take_other(((size_t)kMaxBuckets + 1) * 4);
+  L.bvh_boxes = take_other((2 * T + 64) * 32);  // implicit tree: at most 2T nodes of 32 B
+  L.bvh_leaves = take_other((T + 4) * 64);      // sorted leaf records, padded to a multiple of 4
+  L.bvh_tbox = take_other(T * 6 * 8);
+  L.bvh_centroid = take_other(T * 3 * 4);
+  L.bvh_part = take_other(512 * 6 * 4);
+  L.bvh_ext = take_other(512 * 8);
   // saved traversal states (32 B each) of the queries handed to the wave-cooperative kernel
   L.bvh_heavy_bytes = (size_t)std::min<int64_t>(2 * T, (int64_t)1 << 20) * 32;
-  L.bvh_heavy = take(L.bvh_heavy_bytes);
-  L.hash_grid = take(64);
+  L.bvh_heavy = take_other(L.bvh_heavy_bytes);
+  L.hash_grid = take_other(64);
   const size_t E = (size_t)kHashEntriesPerTri * T;
-  L.hash_key = take(E * 8);
-  L.hash_tri = take(E * 4);
-  L.hash_rank = take(E * 4);
-  L.hash_skey = take(E * 8);
-  L.hash_stri = take(E * 4);
+  L.hash_key = take_other(E * 8);
+  L.hash_tri = take_other(E * 4);
+  L.hash_rank = take_other(E * 4);
+  L.hash_skey = take_other(E * 8);
+  L.hash_stri = take_other(E * 4);
   L.touched = take(6 * H * 4);  // the vertex of each row
   L.inc2 = take(6 * H * sizeof(Incidence));
-  L.pcg_vec = take(5 * 3 * (size_t)lim.max_verts * 8);
-  L.pcg_flag = take(V * 4);  // active-row flags, their scan and the active-row list
-  L.pcg_pos = take(V * 4);
-  L.pcg_act = take(V * 4);
-  L.pcg_part = take(5 * 256 * 4 * 8);
-  L.pcg_state = take(64);
+  L.pcg_vec = take_other(5 * 3 * (size_t)lim.max_verts * 8);
+  L.pcg_flag = take_other(V * 4);  // active-row flags, their scan and the active-row list
+  L.pcg_pos = take_other(V * 4);
+  L.pcg_act = take_other(V * 4);
+  L.pcg_part = take_other(5 * 256 * 4 * 8);
+  L.pcg_state = take_other(64);
   L.total = o;
   return L;
 }
@@ -209,6 +239,12 @@ ttie_status ttie_create(int device, ttie_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(TTIE_ERR_NO_DEVICE, "no HIP device");
   if (device < 0 || device >= n) return fail(TTIE_ERR_INVALID_ARGUMENT, "device index out of range");
+  {
+    DeviceGuard g(device);
+    if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
+    const hipError_t e = scratch_lookup(device);
+    if (e != hipSuccess) return hip_fail(e, "ttie_create: address of the static scratch");
+  }
   auto* c = new ttie_ctx();
   std::memset(static_cast<Ctx*>(c), 0, sizeof(Ctx));
   c->device = device;
@@ -323,13 +359,9 @@ ttie_status ttie_batch_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int n_pr
                          "ttie_batch_broadphase");
 }
 
-static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
-                              int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags,
-                              double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity,
-                              int64_t* n_blocks, int64_t* n_hits, int n_prob, const int64_t* vert_off,
-                              double* energies, void* stream, const char* who) {
-  if (ttie_status st = need_ws(ctx)) return st;
-  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+static ttie_status check_eval_args(const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                                   int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad,
+                                   int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity) {
   if (!opts) return fail(TTIE_ERR_INVALID_ARGUMENT, "options are NULL");
   if (opts->precision != TTIE_FP64 && opts->precision != TTIE_MIXED) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad precision");
   if (opts->psd_mode < 0 || opts->psd_mode > 3) return fail(TTIE_ERR_INVALID_ARGUMENT, "bad psd_mode");
@@ -338,16 +370,30 @@ static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_
   if (opts->flags & ~TTIE_EVAL_VERTEX_ADJACENT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown option flags");
   if ((!pairs && pair_capacity > 0) || !n_pairs || !energy || (!grad && mesh->n_verts > 0))
     return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL required argument");
-  if (pair_capacity < 0 || pair_capacity > ctx->lim.max_pairs)
-    return fail(TTIE_ERR_CAPACITY, "pair_capacity outside [0, limits.max_pairs]");
+  if (pair_capacity < 0) return fail(TTIE_ERR_CAPACITY, "negative pair_capacity");
   const bool bsr = row_ptr || col_idx || vals;
   if (bsr && (!row_ptr || !col_idx || !vals)) return fail(TTIE_ERR_INVALID_ARGUMENT, "partial BSR output");
-  if (bsr && (block_capacity < 0 || block_capacity > ctx->lim.max_blocks))
+  if (bsr && block_capacity < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "negative block_capacity");
+  return TTIE_OK;
+}
+
+static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                              int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags,
+                              double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity,
+                              int64_t* n_blocks, int64_t* n_hits, int n_prob, const int64_t* vert_off,
+                              double* energies, void* stream, const char* who) {
+  if (ttie_status st = need_ws(ctx)) return st;
+  if (ttie_status st = check_mesh(ctx, mesh)) return st;
+  if (ttie_status st = check_eval_args(mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, row_ptr, col_idx, vals,
+                                       block_capacity))
+    return st;
+  if (pair_capacity > ctx->lim.max_pairs) return fail(TTIE_ERR_CAPACITY, "pair_capacity outside [0, limits.max_pairs]");
+  if (row_ptr && block_capacity > ctx->lim.max_blocks)
     return fail(TTIE_ERR_CAPACITY, "block_capacity exceeds limits.max_blocks");
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_eval(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, bsr ? row_ptr : nullptr,
-                             col_idx, vals, bsr ? block_capacity : 0, n_blocks, n_hits, n_prob, vert_off, energies,
-                             (hipStream_t)stream);
+  hipError_t e = launch_eval(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, row_ptr,
+                             col_idx, vals, row_ptr ? block_capacity : 0, n_blocks, n_hits, n_prob, vert_off, energies,
+                             nullptr, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, who);
   ctx->last_precision = opts->precision;
   ctx->last_psd = opts->psd_mode;
@@ -357,12 +403,64 @@ static ttie_status eval_entry(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_
   return TTIE_OK;
 }
 
+
+
 ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
                       int64_t pair_capacity, const ttie_options* opts, double* energy, void* grad, uint8_t* flags, double* pair_T,
                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
                       int64_t* n_hits, void* stream) {
   return eval_entry(ctx, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, row_ptr, col_idx, vals,
                     block_capacity, n_blocks, n_hits, 0, nullptr, nullptr, stream, "ttie_eval");
+}
+
+ttie_status ttie_eval_static(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs, const int64_t* n_pairs,
+                             int64_t pair_capacity, int64_t max_hits, const ttie_options* opts, double* energy,
+                             void* grad, uint8_t* flags, double* pair_T, int32_t* row_ptr, int32_t* col_idx, void* vals,
+                             int64_t block_capacity, int64_t* n_blocks, int64_t* n_hits, int32_t* status,
+                             void* stream) {
+  if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
+  if (!mesh) return fail(TTIE_ERR_INVALID_ARGUMENT, "mesh is NULL");
+  if (mesh->n_verts < 0 || mesh->n_tris < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "negative mesh size");
+  if ((mesh->n_verts > 0 && !mesh->x) || (mesh->n_tris > 0 && !mesh->tris))
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "mesh array is NULL");
+  if (ttie_status st = check_eval_args(mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, row_ptr, col_idx, vals,
+                                       block_capacity))
+    return st;
+  if (max_hits < 0) return fail(TTIE_ERR_INVALID_ARGUMENT, "negative max_hits");
+  // the evaluation's regions only, laid out for this call's sizes
+  ttie_limits lim{mesh->n_verts, 0, pair_capacity, max_hits, row_ptr ? block_capacity : 0};
+  if (!limits_ok(&lim)) return fail(TTIE_ERR_INVALID_ARGUMENT, "sizes out of range");
+  const Layout L = layout_with(lim, 0, true);
+  if (L.total > (size_t)TTIE_STATIC_SCRATCH_BYTES)
+    return fail(TTIE_ERR_CAPACITY, "the sizes need more than the TTIE_STATIC_SCRATCH_BYTES of static scratch");
+  void* base = scratch_of(ctx->device);
+  if (!base) return fail(TTIE_ERR_HIP, "static scratch not available on this device");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(TTIE_ERR_HIP, "cannot select device");
+  // a private view of the context on the static array: no stage timers (they create events)
+  Ctx t = *static_cast<Ctx*>(ctx);
+  t.timing_mask = 0;
+  t.timers = nullptr;
+  t.n_timers = t.cap_timers = 0;
+  t.event_pool = nullptr;
+  t.n_pool = t.cap_pool = 0;
+  t.lim = lim;
+  t.ws = static_cast<char*>(base);
+  t.ws_bytes = (size_t)TTIE_STATIC_SCRATCH_BYTES;
+  t.L = L;
+  t.have_ws = 1;
+  hipStream_t s = (hipStream_t)stream;
+  // the array keeps the last call's contents, laid out for that call's sizes: the counters and
+  // the counts the evaluation expects at zero are cleared (fill kernels, so a capture holds no
+  // memset nodes)
+  hipError_t e = launch_fill_zero_i32(wsp<int32_t>(&t, L.counters), sizeof(Counters) / 4, s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(&t, L.cnt), 32 * (lim.max_verts / 32 + 2), s);
+  if (e == hipSuccess) e = launch_fill_zero_i32(wsp<int32_t>(&t, L.wcnt), lim.max_verts / 32 + 2, s);
+  if (e == hipSuccess)
+    e = launch_eval(&t, mesh, pairs, n_pairs, pair_capacity, opts, energy, grad, flags, pair_T, row_ptr, col_idx, vals,
+                    row_ptr ? block_capacity : 0, n_blocks, n_hits, 0, nullptr, nullptr, status, s);
+  if (e != hipSuccess) return hip_fail(e, "ttie_eval_static");
+  return TTIE_OK;
 }
 
 ttie_status ttie_batch_eval(ttie_ctx* ctx, const ttie_mesh* mesh, int n_problems, const int64_t* vert_off,

@@ -922,7 +922,8 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
                                                   int32_t* __restrict__ off,
                                                   const int32_t* __restrict__ coff, int32_t* __restrict__ row_ptr,
                                                   S* __restrict__ grad, const double* __restrict__ erow, Counters* ctr,
-                                                  uint32_t max_hits, double* energy, int64_t* n_hits) {
+                                                  uint32_t max_hits, double* energy, int64_t* n_hits,
+                                                  int32_t* status_out) {
   if (blockIdx.x == 0) {
     __shared__ double red[kBlock];
     const uint32_t R = wp[nw];
@@ -943,6 +944,8 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
     ctr->last_touched = R;
     ctr->n_hits = 0;
     ctr->n_defer = 0;
+    // every other kernel of the evaluation has finished, so the latched status is final
+    if (status_out) *status_out = __hip_atomic_load(&ctr->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
   const int lane = __lane_id();
@@ -1210,7 +1213,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
                             int64_t pair_cap, const ttie_options* o, double* energy, S* grad, uint8_t* flags,
                             double* pair_T, int32_t* row_ptr, int32_t* col_idx, S* vals, int64_t block_cap,
                             int64_t* n_blocks, int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies,
-                            hipStream_t s) {
+                            int32_t* status_out, hipStream_t s) {
   const Layout& L = c->L;
   Counters* ctr = wsp<Counters>(c, L.counters);
   HitGeom* hits = wsp<HitGeom>(c, L.hits);
@@ -1272,7 +1275,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
   k_dense<S><<<1 + grid_for(3 * nv + 1, 2048), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
                                                                 bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
-                                                                energy, n_hits);
+                                                                energy, n_hits, status_out);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
   return hipGetLastError();
 }
@@ -1280,12 +1283,13 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
 hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                        int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
-                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, hipStream_t s) {
+                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, int32_t* status_out,
+                       hipStream_t s) {
   if (o->precision == TTIE_FP64)
     return eval_impl<double>(c, m, pairs, n_pairs, pair_capacity, o, energy, (double*)grad, flags, pair_T, row_ptr, col_idx,
-                             (double*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
+                             (double*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, status_out, s);
   return eval_impl<float>(c, m, pairs, n_pairs, pair_capacity, o, energy, (float*)grad, flags, pair_T, row_ptr, col_idx,
-                          (float*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, s);
+                          (float*)vals, block_capacity, n_blocks, n_hits, n_prob, vert_off, energies, status_out, s);
 }
 
 template <class S>

@@ -178,7 +178,8 @@ hipError_t launch_axpy(int64_t n_verts, double alpha, const double* x, const voi
 hipError_t launch_eval(Ctx* c, const ttie_mesh* m, const int32_t* pairs, const int64_t* n_pairs,
                        int64_t pair_capacity, const ttie_options* o, double* energy, void* grad, uint8_t* flags, double* pair_T,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t block_capacity, int64_t* n_blocks,
-                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, hipStream_t s);
+                       int64_t* n_hits, int n_prob, const int64_t* vert_off, double* energies, int32_t* status_out,
+                       hipStream_t s);
 hipError_t launch_hvp(Ctx* c, const ttie_mesh* m, const void* v, void* Hv, int mode, hipStream_t s);
 // BSR pattern and values of the last evaluation's PSD Hessian, as two calls
 hipError_t launch_bsr_symbolic(Ctx* c, int32_t* row_ptr, int32_t* col_idx, int64_t capacity, int64_t* n_blocks,

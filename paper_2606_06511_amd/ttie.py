@@ -62,6 +62,8 @@ SIGNATURES = {
     "ttie_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _i64, _vp, _vp]),
     "ttie_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, ctypes.POINTER(Options), _vp, _vp, _vp,
                          _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ttie_eval_static": (_i32, [_vp, ctypes.POINTER(Mesh), _vp, _vp, _i64, _i64, ctypes.POINTER(Options), _vp, _vp,
+                                _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "ttie_batch_broadphase": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, _vp, _vp]),
     "ttie_batch_eval": (_i32, [_vp, ctypes.POINTER(Mesh), _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(Options), _vp,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -282,6 +284,46 @@ class Context:
                                _ptr(out.get("col_idx")) if hessian else None,
                                _ptr(out.get("vals")) if hessian else None, cap,
                                _ptr(out.get("n_blocks")) if hessian else None, _ptr(out["n_hits"]), _stream()))
+        return out
+
+    def evaluate_static(self, x, tris, pairs, n_pairs=None, max_hits=1 << 14, precision=FP64, psd=PSD_PER_PART,
+                        interval=INTERVAL_EQ1, hessian=True, flags=False, pair_T=False, out=None, vertex_adjacent=False,
+                        block_capacity=None):
+        """``evaluate`` through ttie_eval_static: the library's static device array serves as the
+        workspace, so the call itself allocates nothing (the output tensors here are the
+        caller's; pass ``out`` to reuse them).  Needs no ``reserve``.  The kernels' status (0 or a
+        TTIE_ERR_* code) comes back in ``out["status"]`` (1,) int32."""
+        m = self._mesh(x, tris)
+        dev = self.device
+        if n_pairs is None:
+            n_pairs = torch.tensor([pairs.shape[0]], dtype=torch.int64, device=dev)
+        if out is None:
+            dt = torch.float64 if precision == FP64 else torch.float32
+            nv = x.shape[0]
+            cap = 36 * max_hits if block_capacity is None else block_capacity
+            out = {"energy": torch.zeros(1, dtype=torch.float64, device=dev),
+                   "grad": torch.empty((nv, 3), dtype=dt, device=dev),
+                   "n_hits": torch.zeros(1, dtype=torch.int64, device=dev),
+                   "status": torch.zeros(1, dtype=torch.int32, device=dev)}
+            if hessian:
+                out.update(row_ptr=torch.empty(nv + 1, dtype=torch.int32, device=dev),
+                           col_idx=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                           vals=torch.empty((max(cap, 1), 3, 3), dtype=dt, device=dev),
+                           n_blocks=torch.zeros(1, dtype=torch.int64, device=dev))
+            if flags:
+                out["flags"] = torch.empty(pairs.shape[0], dtype=torch.uint8, device=dev)
+            if pair_T:
+                out["pair_T"] = torch.empty(pairs.shape[0], dtype=torch.float64, device=dev)
+        opts = Options(precision, psd, interval, EVAL_VERTEX_ADJACENT if vertex_adjacent else 0)
+        cap = out["col_idx"].shape[0] if hessian else 0
+        _check(lib().ttie_eval_static(self.handle, ctypes.byref(m), _ptr(pairs), _ptr(n_pairs), pairs.shape[0], max_hits,
+                                      ctypes.byref(opts), _ptr(out["energy"]), _ptr(out["grad"]),
+                                      _ptr(out.get("flags")), _ptr(out.get("pair_T")),
+                                      _ptr(out.get("row_ptr")) if hessian else None,
+                                      _ptr(out.get("col_idx")) if hessian else None,
+                                      _ptr(out.get("vals")) if hessian else None, cap,
+                                      _ptr(out.get("n_blocks")) if hessian else None, _ptr(out["n_hits"]),
+                                      _ptr(out["status"]), _stream()))
         return out
 
     def bsr_symbolic(self, n_verts, capacity=None):

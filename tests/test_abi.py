@@ -29,8 +29,13 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for fn in ["ttie_create", "ttie_broadphase", "ttie_eval", "ttie_hvp", "ttie_get_hits", "ttie_bsr_mv"]:
-        assert fn in names
+    # the calls of the boundary: version and errors, context, workspace, broad phase,
+    # evaluation, the two-call Hessian, matrix-free products, batches
+    for fn in ["ttie_version", "ttie_last_error", "ttie_create", "ttie_destroy", "ttie_workspace_size",
+               "ttie_set_workspace", "ttie_get_status", "ttie_broadphase", "ttie_eval", "ttie_bsr_symbolic",
+               "ttie_bsr_numeric", "ttie_hvp", "ttie_bsr_mv", "ttie_get_hits", "ttie_batch_broadphase",
+               "ttie_batch_eval", "ttie_eval_static"]:
+        assert fn in names, fn
 
 
 def test_library_exports_every_declared_symbol(lib):
