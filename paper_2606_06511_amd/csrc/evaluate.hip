@@ -122,14 +122,14 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
 // ---- the fast pass: FP64 filters only, uncertain pairs deferred --------------------------
 // The screening of Sec. 1 is a cascade whose stages let fewer and fewer pairs through: on the
 // noisy spheres about 35% of the candidates have a vertex of T_a on each side of T_b's plane,
-// about 19% also the converse, and 0.2% intersect.  One lane per candidate all the way down
-// would make every wave execute every stage (some lane nearly always goes on).  Instead each
-// wave runs a stage on 64 candidates at once and queues the survivors in LDS; the next stage
-// runs when 64 are queued.  The last stage is the full screening of screen_one, so every
-// decision and value is exactly the one-pass result.
-constexpr int kQueue = 128;  // queue slots per wave and stage (at most 63 waiting + 64 arriving)
+// about 19% also the converse, and 0.2% intersect.  The first stage decides both plane tests
+// on the six vertices it loads; the survivors (both triangles straddle the other's plane, or
+// T_a lies in T_b's plane) go to a per-wave LDS queue, and the full screening of screen_one
+// runs on 64 of them at once, so its long tail of work is not paid by every wave for one or
+// two lanes.  Every decision and value is exactly the one-pass result.
+constexpr int kQueue = 128;  // queue slots per wave (at most 63 waiting + 64 arriving)
 
-enum { STEP_SETTLED = 0, STEP_DEFER = 1, STEP_NEXT = 2, STEP_FULL = 3 };
+enum { STEP_SETTLED = 0, STEP_DEFER = 1, STEP_FULL = 3 };
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -165,25 +165,17 @@ __device__ __forceinline__ bool load_pair(int64_t p, const double* x, int64_t nv
   return load_tri(x, nv, tris, i, vi, A) && load_tri(x, nv, tris, j, vj, B);
 }
 
-// Coordinates must be finite, and 0 or of magnitude in [2^-200, 2^200]: the domain on which
-// the exact predicates are exact and overflow-free.  Decided on the bit patterns.
-__device__ __forceinline__ int coord_status(const Tri64& A, const Tri64& B) {
+// Status of one coordinate: finite, and 0 or of magnitude in [2^-200, 2^200] (the domain on
+// which the exact predicates are exact and overflow-free), decided on the bit pattern.
+__device__ __forceinline__ int coord_status(double q) {
   constexpr uint64_t kInf = 0x7ff0000000000000ull, kLo = 823ull << 52, kHi = 1223ull << 52;  // 2^-200, 2^200
-  bool nonfinite = false, outside = false;
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const uint64_t qa = (uint64_t)__double_as_longlong(A.p[k][c]) & 0x7fffffffffffffffull;
-      const uint64_t qb = (uint64_t)__double_as_longlong(B.p[k][c]) & 0x7fffffffffffffffull;
-      nonfinite |= (qa >= kInf) | (qb >= kInf);
-      outside |= (qa != 0 && (qa < kLo || qa > kHi)) | (qb != 0 && (qb < kLo || qb > kHi));
-    }
-  return nonfinite ? STATUS_NONFINITE : outside ? STATUS_UNSUPPORTED : 0;
+  const uint64_t a = (uint64_t)__double_as_longlong(q) & 0x7fffffffffffffffull;
+  if (a >= kInf) return STATUS_NONFINITE;
+  return (a != 0 && (a < kLo || a > kHi)) ? STATUS_UNSUPPORTED : 0;
 }
 
-// Stage 1 (every candidate): indices, coordinate domain, adjacency, T_a's sides against T_b's
-// plane.
+// Stage 1 (every candidate): indices, adjacency, T_a's sides against T_b's plane, then T_b's
+// sides against T_a's plane.
 __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
                                              const int32_t* pairs, bool va, uint8_t* flags, double* pair_T,
                                              int& status) {
@@ -194,40 +186,24 @@ __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t
     settle(p, PAIR_NONE, flags, pair_T);
     return STEP_SETTLED;
   }
-  if (const int cs = coord_status(A, B)) {
-    status = cs;
-    settle(p, PAIR_NONE, flags, pair_T);
-    return STEP_SETTLED;
-  }
   if (is_adjacent(vi, vj, va)) {
     settle(p, PAIR_ADJACENT, flags, pair_T);
     return STEP_SETTLED;
   }
-  int sa[3];
-  double da[3];
-  if (!plane_sides<false>(B, A, sa, da, status)) return STEP_DEFER;
+  int sa[3], sb[3];
+  double d[3];
+  if (!plane_sides<false>(B, A, sa, d, status)) return STEP_DEFER;
   if ((sa[0] | sa[1] | sa[2]) == 0) return STEP_FULL;  // T_a in T_b's plane: the coplanar test
   if (!make_cut(sa[0], sa[1], sa[2]).straddle) {
     settle(p, PAIR_NONE, flags, pair_T);
     return STEP_SETTLED;
   }
-  return STEP_NEXT;
-}
-
-// Stage 2 (T_a straddles T_b's plane): T_b's sides against T_a's plane.
-__device__ __forceinline__ int screen_stage2(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
-                                             const int32_t* pairs, uint8_t* flags, double* pair_T, int& status) {
-  int32_t vi[3], vj[3];
-  Tri64 A, B;
-  load_pair(p, x, nv, tris, nt, pairs, vi, vj, A, B);  // checked in stage 1
-  int sb[3];
-  double db[3];
-  if (!plane_sides<false>(A, B, sb, db, status)) return STEP_DEFER;
+  if (!plane_sides<false>(A, B, sb, d, status)) return STEP_DEFER;
   if (!make_cut(sb[0], sb[1], sb[2]).straddle) {
     settle(p, PAIR_NONE, flags, pair_T);
     return STEP_SETTLED;
   }
-  return STEP_NEXT;
+  return STEP_FULL;
 }
 
 __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
@@ -237,14 +213,18 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
                                                    uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
                                                    uint8_t* __restrict__ flags, double* __restrict__ pair_T,
                                                    uint32_t* __restrict__ bm, int64_t nbm) {
-  __shared__ uint32_t q1s[kWaves][kQueue], q2s[kWaves][kQueue];
+  __shared__ uint32_t qs[kWaves][kQueue];
+  int status = 0;
   // the touched-vertex bitmap of the previous evaluation (read by the calls after it) is
-  // cleared here, before k_derivs marks this one's
+  // cleared here, before k_derivs marks this one's; every coordinate is checked against the
+  // exact predicates' domain (a violation is reported, never acted on: out of it the exact
+  // arithmetic only loses exactness, it stays within its arrays)
   for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nbm; w += (int64_t)gridDim.x * blockDim.x)
     bm[w] = 0u;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < 3 * nv; c += (int64_t)gridDim.x * blockDim.x)
+    if (const int cs = coord_status(x[c])) status = status == STATUS_NONFINITE ? status : cs;
   const int wave = threadIdx.x / 64, lane = __lane_id();
-  uint32_t* q1 = q1s[wave];
-  uint32_t* q2 = q2s[wave];
+  uint32_t* q = qs[wave];
   const int64_t np = min(*n_pairs_dev, max_pairs);
   // each wave screens one contiguous chunk of the list; blocks are renumbered so that each XCD
   // runs a contiguous range of chunks (its L2 then sees one region of the mesh)
@@ -253,43 +233,29 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
   const int64_t nw = G * kWaves;
   const int64_t chunk = ((np + nw - 1) / nw + 63) / 64 * 64;
   const int64_t beg = (lb * kWaves + wave) * chunk, end = min(np, beg + chunk);
-  int n1 = 0, n2 = 0, status = 0;
+  int n = 0;
   int64_t base = beg;
-  // One stage per round, chosen wave-uniformly: the last stage as soon as 64 candidates wait for
-  // it, then the middle one, then a new batch; at the end of the chunk the queues drain.  Each
-  // stage runs from one place in the code, so only one of them is live in registers at a time.
-  // Stage 1 runs only with both queues below 64 and stage 2 only with the last one below 64, so
-  // no queue ever holds more than 127.
+  // One stage per round, chosen wave-uniformly: the full screening as soon as 64 candidates wait
+  // for it, else a new batch through stage 1; at the end of the chunk the queue drains.  Stage 1
+  // runs only with the queue below 64, so it never holds more than 127.
   while (true) {
     const bool more = base < end;
-    int st = STEP_SETTLED;
-    int64_t p = -1;
-    if (n2 >= 64 || (!more && n1 == 0 && n2 > 0)) {
-      const int take = min(n2, 64);
-      p = lane < take ? (int64_t)q2[n2 - take + lane] : -1;
+    if (n >= 64 || (!more && n > 0)) {
+      const int take = min(n, 64);
+      const int64_t p = lane < take ? (int64_t)q[n - take + lane] : -1;
       wave_sync_lds();
-      n2 -= take;
+      n -= take;
       screen_one<false>(p, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags,
                         pair_T, status);
       continue;
     }
-    if (n1 >= 64 || (!more && n1 > 0)) {
-      const int take = min(n1, 64);
-      p = lane < take ? (int64_t)q1[n1 - take + lane] : -1;
-      wave_sync_lds();
-      n1 -= take;
-      if (p >= 0) st = screen_stage2(p, x, nv, tris, nt, pairs, flags, pair_T, status);
-      defer_append(st == STEP_DEFER, p, defer, max_pairs, ctr, status);
-      queue_push(q2, n2, st == STEP_NEXT, p);
-      continue;
-    }
     if (!more) break;
-    p = base + lane < end ? base + lane : -1;
+    const int64_t p = base + lane < end ? base + lane : -1;
     base += 64;
+    int st = STEP_SETTLED;
     if (p >= 0) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, status);
     defer_append(st == STEP_DEFER, p, defer, max_pairs, ctr, status);
-    queue_push(q2, n2, st == STEP_FULL, p);
-    queue_push(q1, n1, st == STEP_NEXT, p);
+    queue_push(q, n, st == STEP_FULL, p);
   }
   if (status) latch(&ctr->status, status);
 }
