@@ -164,7 +164,7 @@ ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, co
 
 /* ---- evaluation -----------------------------------------------------------------------
  * Evaluates the candidate pairs and assembles the energy, gradient and Hessian.
- *  pairs      pair_capacity x 2 int32 candidate list; the number of pairs evaluated is
+ *  pairs      pair_capacity x 2 int32 candidate list (8-byte aligned); the number of pairs evaluated is
  *             n = min(*n_pairs, pair_capacity), *n_pairs being a device int64 (so the output of
  *             ttie_broadphase can be passed directly); pair_capacity <= limits.max_pairs
  *  energy     device float64 scalar: E = sum of T over the pairs (accumulated in float64)

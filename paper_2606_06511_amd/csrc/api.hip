@@ -61,6 +61,8 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.counters = take(sizeof(Counters));
   L.hits = take(H * sizeof(HitGeom));
   L.defer = take((size_t)lim.max_pairs * 4);
+  L.full = take((size_t)lim.max_pairs * 4);  // candidates for the full screening
+  L.nfull = take((size_t)65536 * 4 * 4);     // their number per screening wave (grid <= 65536 blocks)
   L.recs = take(H * sizeof(AsmRec<double>));
   L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time
   L.cur = take_other(V * 4);
@@ -370,6 +372,7 @@ static ttie_status check_eval_args(const ttie_mesh* mesh, const int32_t* pairs, 
   if (opts->flags & ~TTIE_EVAL_VERTEX_ADJACENT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown option flags");
   if ((!pairs && pair_capacity > 0) || !n_pairs || !energy || (!grad && mesh->n_verts > 0))
     return fail(TTIE_ERR_INVALID_ARGUMENT, "NULL required argument");
+  if (((uintptr_t)pairs) & 7) return fail(TTIE_ERR_INVALID_ARGUMENT, "pairs must be 8-byte aligned");
   if (pair_capacity < 0) return fail(TTIE_ERR_CAPACITY, "negative pair_capacity");
   const bool bsr = row_ptr || col_idx || vals;
   if (bsr && (!row_ptr || !col_idx || !vals)) return fail(TTIE_ERR_INVALID_ARGUMENT, "partial BSR output");

@@ -2,10 +2,12 @@
 // deterministic (no floating-point atomics) assembly of energy, gradient and BSR Hessian.
 //
 // Pipeline on one stream, no host synchronization:
-//   k_screen         one lane per candidate: adjacency, coordinate domain, FP64-filtered plane
-//                    sides and flag, FP64 interval ends; hits and filter-uncertain candidates
-//                    are appended with one atomic per wave (ballot + mbcnt); clears the bitmap
-//                    of touched vertices
+//   k_screen         one lane per candidate: adjacency and the FP64-filtered plane sides of both
+//                    triangles; candidates that straddle both ways, and filter-uncertain ones, are
+//                    appended to lists with one atomic per wave (ballot + mbcnt); checks the
+//                    coordinate domain and clears the bitmap of touched vertices
+//   k_screen_full    the full screening of the straddling candidates: segment ends, line frame,
+//                    exact flag, FP64 interval ends; hits appended
 //   k_screen_exact   the uncertain candidates again, with the exact fallback
 //   k_derivs<S>      one lane per hit: a = dt_c^0, b = dt_c^1, T, g (Eq. 3), 2x2 Hessian core;
 //                    counts the hit's six incidences and marks its vertices in the bitmap
@@ -122,33 +124,19 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
 // ---- the fast pass: FP64 filters only, uncertain pairs deferred --------------------------
 // The screening of Sec. 1 is a cascade whose stages let fewer and fewer pairs through: on the
 // noisy spheres about 35% of the candidates have a vertex of T_a on each side of T_b's plane,
-// about 19% also the converse, and 0.2% intersect.  The first stage decides both plane tests
-// on the six vertices it loads; the survivors (both triangles straddle the other's plane, or
-// T_a lies in T_b's plane) go to a per-wave LDS queue, and the full screening of screen_one
-// runs on 64 of them at once, so its long tail of work is not paid by every wave for one or
-// two lanes.  Every decision and value is exactly the one-pass result.
-constexpr int kQueue = 128;  // queue slots per wave (at most 63 waiting + 64 arriving)
-
+// about 19% also the converse, and 0.2% intersect.  k_screen decides both plane tests for every
+// candidate, one lane each, on the six vertices it loads; it is small, so many waves fit on a
+// SIMD to hide the latency of those gathers.  The survivors (both triangles straddle the other's
+// plane, or T_a lies in T_b's plane) are written to a list, and k_screen_full runs the full
+// screening of screen_one on them, so its long tail of work is not paid by every wave for one
+// or two lanes.  Every decision and value is exactly the one-pass result.
 enum { STEP_SETTLED = 0, STEP_DEFER = 1, STEP_FULL = 3 };
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Appends the lanes that want it to a wave's LDS queue; n is wave-uniform.
-__device__ __forceinline__ void queue_push(uint32_t* q, int& n, bool want, int64_t p) {
-  const uint64_t mask = __ballot(want);
-  if (want) q[n + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = (uint32_t)p;
-  n += __popcll(mask);
-  wave_sync_lds();
-}
-
-__device__ __forceinline__ void defer_append(bool want, int64_t p, int32_t* defer, int64_t max_defer, Counters* ctr,
-                                             int& status) {
-  const uint32_t ds = wave_slot(want, &ctr->n_defer);
+__device__ __forceinline__ void append(bool want, int64_t p, int32_t* list, int64_t cap, uint32_t* counter,
+                                       int& status) {
+  const uint32_t ds = wave_slot(want, counter);
   if (want) {
-    if ((int64_t)ds < max_defer) defer[ds] = (int32_t)p;
+    if ((int64_t)ds < cap) list[ds] = (int32_t)p;
     else status = STATUS_CAPACITY;
   }
 }
@@ -160,9 +148,9 @@ __device__ __forceinline__ void settle(int64_t p, int kind, uint8_t* flags, doub
 
 __device__ __forceinline__ bool load_pair(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
                                           const int32_t* pairs, int32_t vi[3], int32_t vj[3], Tri64& A, Tri64& B) {
-  const int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
-  if (i < 0 || j < 0 || i >= nt || j >= nt || i == j) return false;
-  return load_tri(x, nv, tris, i, vi, A) && load_tri(x, nv, tris, j, vj, B);
+  const int2 ij = reinterpret_cast<const int2*>(pairs)[p];
+  if (ij.x < 0 || ij.y < 0 || ij.x >= nt || ij.y >= nt || ij.x == ij.y) return false;
+  return load_tri(x, nv, tris, ij.x, vi, A) && load_tri(x, nv, tris, ij.y, vj, B);
 }
 
 // Status of one coordinate: finite, and 0 or of magnitude in [2^-200, 2^200] (the domain on
@@ -206,56 +194,76 @@ __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t
   return STEP_FULL;
 }
 
-__global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
-                                                   const int32_t* __restrict__ tris, int64_t nt,
-                                                   const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
-                                                   int64_t max_pairs, double half, int va, HitGeom* __restrict__ hits,
-                                                   uint32_t max_hits, int32_t* __restrict__ defer, Counters* ctr,
-                                                   uint8_t* __restrict__ flags, double* __restrict__ pair_T,
-                                                   uint32_t* __restrict__ bm, int64_t nbm) {
-  __shared__ uint32_t qs[kWaves][kQueue];
-  int status = 0;
-  // the touched-vertex bitmap of the previous evaluation (read by the calls after it) is
-  // cleared here, before k_derivs marks this one's; every coordinate is checked against the
-  // exact predicates' domain (a violation is reported, never acted on: out of it the exact
-  // arithmetic only loses exactness, it stays within its arrays)
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nbm; w += (int64_t)gridDim.x * blockDim.x)
-    bm[w] = 0u;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < 3 * nv; c += (int64_t)gridDim.x * blockDim.x)
-    if (const int cs = coord_status(x[c])) status = status == STATUS_NONFINITE ? status : cs;
-  const int wave = threadIdx.x / 64, lane = __lane_id();
-  uint32_t* q = qs[wave];
-  const int64_t np = min(*n_pairs_dev, max_pairs);
-  // each wave screens one contiguous chunk of the list; blocks are renumbered so that each XCD
-  // runs a contiguous range of chunks (its L2 then sees one region of the mesh)
+// The candidate list is split into one contiguous chunk per wave (a multiple of 64 long, the
+// same split in both screening kernels).  Blocks are renumbered so that each XCD screens a
+// contiguous range of the list (its L2 then sees one region of the mesh).
+__device__ __forceinline__ void wave_chunk(int64_t np, int64_t& beg, int64_t& end, int64_t& wid) {
   const int64_t G = gridDim.x;
   const int64_t lb = (G % 8 == 0) ? xcd_block(blockIdx.x, G) : (int64_t)blockIdx.x;
   const int64_t nw = G * kWaves;
   const int64_t chunk = ((np + nw - 1) / nw + 63) / 64 * 64;
-  const int64_t beg = (lb * kWaves + wave) * chunk, end = min(np, beg + chunk);
-  int n = 0;
-  int64_t base = beg;
-  // One stage per round, chosen wave-uniformly: the full screening as soon as 64 candidates wait
-  // for it, else a new batch through stage 1; at the end of the chunk the queue drains.  Stage 1
-  // runs only with the queue below 64, so it never holds more than 127.
-  while (true) {
-    const bool more = base < end;
-    if (n >= 64 || (!more && n > 0)) {
-      const int take = min(n, 64);
-      const int64_t p = lane < take ? (int64_t)q[n - take + lane] : -1;
-      wave_sync_lds();
-      n -= take;
-      screen_one<false>(p, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags,
-                        pair_T, status);
-      continue;
-    }
-    if (!more) break;
-    const int64_t p = base + lane < end ? base + lane : -1;
-    base += 64;
+  wid = lb * kWaves + threadIdx.x / 64;
+  beg = min(np, wid * chunk);
+  end = min(np, beg + chunk);
+}
+
+// First stage over the candidate list, one lane per candidate.  A wave writes the candidates it
+// passes to the full screening into its own chunk's index range of `full` (no atomics) and
+// their number to nfull[wave].  Also clears the touched-vertex bitmap of the previous
+// evaluation (read by the calls after it) before k_derivs marks this one's, and checks every
+// coordinate against the exact predicates' domain (a violation is reported, never acted on: out
+// of it the exact arithmetic only loses exactness, it stays within its arrays).
+__global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x, int64_t nv,
+                                                   const int32_t* __restrict__ tris, int64_t nt,
+                                                   const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
+                                                   int64_t max_pairs, int va, int32_t* __restrict__ defer,
+                                                   int32_t* __restrict__ full, int32_t* __restrict__ nfull,
+                                                   Counters* ctr, uint8_t* __restrict__ flags,
+                                                   double* __restrict__ pair_T, uint32_t* __restrict__ bm, int64_t nbm) {
+  int status = 0;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = gt; w < nbm; w += gs) bm[w] = 0u;
+  for (int64_t c = gt; c < 3 * nv; c += gs)
+    if (const int cs = coord_status(x[c])) status = status == STATUS_NONFINITE ? status : cs;
+  const int64_t np = min(*n_pairs_dev, max_pairs);
+  int64_t beg, end, wid;
+  wave_chunk(np, beg, end, wid);
+  const int lane = __lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t nf = 0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int64_t p = base + lane;
     int st = STEP_SETTLED;
-    if (p >= 0) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, status);
-    defer_append(st == STEP_DEFER, p, defer, max_pairs, ctr, status);
-    queue_push(q, n, st == STEP_FULL, p);
+    if (p < end) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, status);
+    append(st == STEP_DEFER, p, defer, max_pairs, &ctr->n_defer, status);
+    const uint64_t fm = __ballot(st == STEP_FULL);
+    if (st == STEP_FULL) full[beg + nf + __popcll(fm & below)] = (int32_t)p;
+    nf += __popcll(fm);
+  }
+  if (lane == 0) nfull[wid] = nf;
+  if (status) latch(&ctr->status, status);
+}
+
+// The full screening (screen_one) of the candidates the first stage passed on, each wave the
+// ones of the same chunk (same grid size as k_screen).
+__global__ void __launch_bounds__(kBlock) k_screen_full(const double* __restrict__ x, int64_t nv,
+                                                        const int32_t* __restrict__ tris, int64_t nt,
+                                                        const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
+                                                        int64_t max_pairs, double half, int va,
+                                                        HitGeom* __restrict__ hits, uint32_t max_hits,
+                                                        int32_t* __restrict__ defer, const int32_t* __restrict__ full,
+                                                        const int32_t* __restrict__ nfull, Counters* ctr,
+                                                        uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
+  const int64_t np = min(*n_pairs_dev, max_pairs);
+  int64_t beg, end, wid;
+  wave_chunk(np, beg, end, wid);
+  const int32_t nf = nfull[wid];
+  const int lane = __lane_id();
+  int status = 0;
+  for (int32_t k0 = 0; k0 < nf; k0 += 64) {
+    const int32_t k = k0 + lane;
+    screen_one<false>(k < nf ? (int64_t)full[beg + k] : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits,
+                      defer, max_pairs, ctr, flags, pair_T, status);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -1202,6 +1210,8 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   double* erow = wsp<double>(c, L.erow);
   uint32_t* part = wsp<uint32_t>(c, L.part);
   int32_t* defer = wsp<int32_t>(c, L.defer);
+  int32_t* full = wsp<int32_t>(c, L.full);
+  int32_t* nfull = wsp<int32_t>(c, L.nfull);
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
   const int va = (o->flags & TTIE_EVAL_VERTEX_ADJACENT) ? 1 : 0;
@@ -1210,9 +1220,12 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   const bool bsr = row_ptr != nullptr;
 
   stage_begin(c, TTIE_STAGE_SCREEN, s);
-  k_screen<<<grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS)), kBlock, 0, s>>>(
-      m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half, va, hits, max_hits, defer, ctr, flags, pair_T, bm,
-      nw);
+  // both screening kernels split the list the same way: the same grid
+  const unsigned gscreen = grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS));
+  k_screen<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, va, defer, full, nfull,
+                                      ctr, flags, pair_T, bm, nw);
+  k_screen_full<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half, va, hits,
+                                           max_hits, defer, full, nfull, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,

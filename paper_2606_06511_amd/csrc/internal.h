@@ -41,7 +41,7 @@ struct Counters {
   uint32_t n_hits;         // intersecting pairs found by the last screening
   uint32_t last_touched;   // vertices touched by the hits of the last completed evaluation (its rows)
   uint32_t n_defer;        // candidates whose signs need the exact fallback
-  uint32_t n_touched;      // (unused)
+  uint32_t pad0_;
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
   uint64_t n_entries;      // (cell, triangle) entries of the spatial-hash broad phase
   uint32_t n_heavy;        // broad-phase work items handed to a wave-cooperative kernel
@@ -106,7 +106,7 @@ struct Layout {
       scan_tmp_bytes;
   // rows of the touched vertices: bitmap, per-word counts and prefixes, incidence places,
   // row offsets (incidences, BSR blocks) and row energies
-  size_t bm, wcnt, wp, wi, incpos, roff, coff, erow, part;
+  size_t bm, wcnt, wp, wi, incpos, roff, coff, erow, part, full, nfull;
   size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state, pcg_flag, pcg_pos, pcg_act;
   size_t total;
