@@ -15,13 +15,13 @@
 //   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists; name the rows
 //   k_rows_sort<S>   one wave per touched vertex (row): rank-sort its incidences by pair key
 //                    (the summation order) and list its distinct neighbour vertices (BSR columns)
-//   k_col_scan       one block: BSR offsets of the rows from their column counts
-//   k_rows_asm<S>    one wave per row, a lane per column: blocks J_k^T M J_l summed in
-//                    pair-key order; the gradient row and the row's energy share
+//   k_col_part, k_col_scan  BSR offsets of the rows from their column counts; column indices
+//   k_assemble<S>    one thread per gradient entry (with the row's energy) and per BSR block
+//                    J_k^T M J_l, each summed over its row's incidences in pair-key order
 //   k_dense<S>       every vertex: incidence offsets, BSR row pointers, zero gradient rows of
 //                    untouched vertices, counts cleared; block 0: energy summed in row order,
 //                    scalar outputs, counters reset
-// Everything from k_derivs to k_rows_asm scales with the hits, not with the mesh.
+// Everything from k_derivs to k_assemble scales with the hits, not with the mesh.
 #include <algorithm>
 
 
@@ -716,10 +716,14 @@ __global__ void __launch_bounds__(kRankThreads) k_col_part(const uint32_t* __res
 
 // Exclusive scan of ncol[0, R) into coff[0, R] (R = wp[nw]): block b takes rows
 // [b kRankBlockWords, (b + 1) kRankBlockWords), four per thread, from the totals of the blocks
-// below it.  The total coff[R] also goes to *n_blocks, and past cap latches TTIE_ERR_CAPACITY.
+// below it.  With brow, each block's row goes to brow; with col_idx, each row's column indices
+// to col_idx.  The total coff[R] also goes to *n_blocks, and past cap latches TTIE_ERR_CAPACITY.
 __global__ void __launch_bounds__(kRankThreads) k_col_scan(const uint32_t* __restrict__ wp, int64_t nw,
                                                            const int32_t* __restrict__ ncol,
                                                            const uint32_t* __restrict__ part, int32_t* __restrict__ coff,
+                                                           const int32_t* __restrict__ roff,
+                                                           const int32_t* __restrict__ colbuf,
+                                                           int32_t* __restrict__ col_idx, int32_t* __restrict__ brow,
                                                            int64_t cap, int64_t* n_blocks, Counters* ctr) {
   __shared__ uint32_t sh[64];
   const uint32_t R = wp[nw];
@@ -738,7 +742,16 @@ __global__ void __launch_bounds__(kRankThreads) k_col_scan(const uint32_t* __res
   uint32_t p = base + e;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (i0 + k < R) coff[i0 + k] = (int32_t)p;
+    if (i0 + k < R) {
+      coff[i0 + k] = (int32_t)p;
+      // the row of each of its blocks (stores only), or the row's column indices
+      if (brow)
+        for (uint32_t q = 0; q < v[k] && (int64_t)(p + q) < cap; ++q) brow[p + q] = (int32_t)(i0 + k);
+      if (col_idx) {
+        const int32_t* cb = colbuf + 6 * (int64_t)roff[i0 + k];
+        for (uint32_t q = 0; q < v[k] && (int64_t)(p + q) < cap; ++q) col_idx[p + q] = cb[q];
+      }
+    }
     p += v[k];
   }
   if (r0 + kRankBlockWords > R && threadIdx.x == 0) {  // the block holding row R: the total
@@ -761,99 +774,93 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
     }
 }
 
-// One row per wave: the gradient row and the energy of the hits this vertex owns (each hit
-// counted at its first vertex), summed in pair-key order, then the row's BSR blocks, one lane
-// per column.  The row's incidences and hit records pass through LDS in chunks of kRowStage
-// (one memory round trip per chunk instead of a chain of dependent loads per incidence); the
-// sums run over the incidences in order, chunk after chunk.
-constexpr int kRowStage = 16;
+// The sums of the assembly, one thread per output: the 3 R gradient entries (with each row's
+// energy: the hits the vertex owns, each counted at its first vertex), then -- when the BSR is
+// wanted -- one per block.  Every sum runs over the row's incidences in pair-key order
+// (inc2), kChunk at a time with the chunk's loads issued together.  Nothing depends on another
+// thread, so all of them are in flight at once and the kernel costs about one chain of
+// dependent loads.
+constexpr int kChunk = 4;
 
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_asm(const uint32_t* __restrict__ wp, int64_t nw,
+__global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict__ wp, int64_t nw,
                                                      const int32_t* __restrict__ rowv, const int32_t* __restrict__ roff,
                                                      const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs,
-                                                     const int32_t* __restrict__ colbuf, const int32_t* __restrict__ coff,
-                                                     int32_t* __restrict__ col_idx, S* __restrict__ vals,
-                                                     int64_t block_cap, S* __restrict__ grad, double* __restrict__ erow,
-                                                     int32_t* status_word) {
-  __shared__ AsmRec<S> srec[kWaves][kRowStage];
-  __shared__ Incidence sinc[kWaves][kRowStage];
-  constexpr int kWords = (int)(sizeof(AsmRec<S>) / 8);
-  static_assert(sizeof(AsmRec<S>) % 8 == 0, "records are copied as 8-byte words");
-  const int wave = threadIdx.x / 64, lane = __lane_id();
-  AsmRec<S>* Rr = srec[wave];
-  Incidence* I = sinc[wave];
-  // stages incidences [k0, k0 + cnt) of the row starting at b (every lane of the wave calls it)
-  auto stage = [&](int32_t b, int32_t k0, int32_t cnt) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();  // the previous chunk is no longer read
-    if (lane < cnt) I[lane] = inc2[b + k0 + lane];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int j = lane; j < cnt * kWords; j += 64) {
-      const int q = j / kWords, w = j % kWords;
-      reinterpret_cast<uint2*>(&Rr[q])[w] = reinterpret_cast<const uint2*>(&recs[I[q].hit])[w];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  };
+                                                     const int32_t* __restrict__ coff, const int32_t* __restrict__ brow,
+                                                     const int32_t* __restrict__ colbuf, int32_t* __restrict__ col_idx,
+                                                     S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
+                                                     double* __restrict__ erow) {
   const uint32_t R = wp[nw];
-  int status = 0;
-  for (uint32_t r = blockIdx.x * kWaves + wave; r < R; r += gridDim.x * kWaves) {
-    const int32_t v = rowv[r];
-    const int32_t b = roff[r], n = roff[r + 1] - b;
-    // gradient row (lanes 0-2) and energy (lane 3)
-    S acc = Sc<S>::c(0.0);
-    double e = 0.0;
-    for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
-      const int32_t cnt = min(n - k0, kRowStage);
-      stage(b, k0, cnt);
-      if (lane < 4)
-        for (int32_t k = 0; k < cnt; ++k) {
-          if (lane < 3) acc = acc + Rr[k].g[3 * I[k].slot + lane];
-          else if (I[k].slot == 0) e += Rr[k].T;
-        }
-    }
-    if (lane < 3) grad[3 * (int64_t)v + lane] = acc;
-    else if (lane == 3) erow[r] = e;
-    if (!coff) continue;
-    // BSR blocks: lane q owns column q (rows with more than 64 columns take several rounds)
-    const int32_t rp = coff[r], nc = coff[r + 1] - rp;
-    for (int32_t q0 = 0; q0 < nc; q0 += 64) {
-      const int32_t q = q0 + lane;
-      const int32_t col = q < nc ? colbuf[6 * (int64_t)b + q] : -1;
+  const int64_t nb = coff ? min((int64_t)coff[R], block_cap) : 0;
+  const int64_t ng = 3 * (int64_t)R;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ng + nb; t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < ng) {
+      const int64_t r = t / 3;
+      const int c = (int)(t % 3);
+      const int32_t b = roff[r], n = roff[r + 1] - b;
+      S acc = Sc<S>::c(0.0);
+      double e = 0.0;
+      for (int32_t k0 = 0; k0 < n; k0 += kChunk) {
+        Incidence I[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+          if (k0 + k < n) I[k] = inc2[b + k0 + k];
+        S gv[kChunk];
+        double Tv[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+          if (k0 + k < n) {
+            gv[k] = recs[I[k].hit].g[3 * I[k].slot + c];
+            Tv[k] = recs[I[k].hit].T;
+          }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+          if (k0 + k < n) {
+            acc = acc + gv[k];
+            if (I[k].slot == 0) e += Tv[k];
+          }
+      }
+      grad[3 * (int64_t)rowv[r] + c] = acc;
+      if (c == 0) erow[r] = e;
+    } else {
+      const int64_t q = t - ng;
+      const int32_t r = brow[q];
+      const int32_t b = roff[r], n = roff[r + 1] - b;
+      const int32_t col = colbuf[6 * (int64_t)b + (q - coff[r])];
+      col_idx[q] = col;
       S B[9];
 #pragma unroll
       for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
-      for (int32_t k0 = 0; k0 < n; k0 += kRowStage) {
-        const int32_t cnt = min(n - k0, kRowStage);
-        if (n > kRowStage || q0 > 0) stage(b, k0, cnt);  // a one-chunk row is still in LDS
-        for (int32_t k = 0; k < cnt; ++k) {
-          // the hit's slots holding this lane's column, in slot order: the lanes hold distinct
-          // columns, so one pass of block_jmj serves every lane that matches a slot of the hit
-          uint32_t match = 0;
+      for (int32_t k0 = 0; k0 < n; k0 += kChunk) {
+        Incidence I[kChunk];
 #pragma unroll
-          for (int l = 0; l < 6; ++l) match |= (uint32_t)(Rr[k].vid[l] == col) << l;
-          while (match) {
-            block_jmj(Rr[k], I[k].slot, __builtin_ctz(match), B);
-            match &= match - 1;
+        for (int k = 0; k < kChunk; ++k)
+          if (k0 + k < n) I[k] = inc2[b + k0 + k];
+        uint32_t match[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+          match[k] = 0;
+          if (k0 + k < n) {
+            const int32_t* vid = recs[I[k].hit].vid;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) match[k] |= (uint32_t)(vid[l] == col) << l;
+          }
+        }
+        // the hit's slots holding the column, in slot order, hit after hit
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+          uint32_t mk = match[k];
+          while (mk) {
+            block_jmj(recs[I[k].hit], I[k].slot, __builtin_ctz(mk), B);
+            mk &= mk - 1;
           }
         }
       }
-      if (q < nc) {
-        const int64_t pos = (int64_t)rp + q;
-        if (pos < block_cap) {
-          col_idx[pos] = col;
 #pragma unroll
-          for (int z = 0; z < 9; ++z) vals[9 * pos + z] = B[z];
-        } else {
-          status = STATUS_CAPACITY;
-        }
-      }
+      for (int z = 0; z < 9; ++z) vals[9 * q + z] = B[z];
     }
   }
-  if (status) latch(status_word, status);
 }
 
 // Energy of each problem of a batch: block p sums the energies of the rows of its vertex range
@@ -972,20 +979,6 @@ __global__ void __launch_bounds__(kBlock) k_sym_cols(const Counters* ctr, const 
                                      reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
                                      colbuf + 6 * (int64_t)b, lane);
     if (lane == 0) ncol[u] = kept;
-  }
-}
-
-// Symbolic, second pass (after the column offsets): column indices of every touched row.
-__global__ void __launch_bounds__(kBlock) k_sym_write(const Counters* ctr, const int32_t* __restrict__ roff,
-                                                      const int32_t* __restrict__ colbuf,
-                                                      const int32_t* __restrict__ coff, int32_t* __restrict__ col_idx,
-                                                      int64_t cap) {
-  const int wave = threadIdx.x / 64, lane = __lane_id();
-  const uint32_t U = ctr->last_touched;
-  for (uint32_t u = blockIdx.x * kWaves + wave; u < U; u += gridDim.x * kWaves) {
-    const int32_t b = roff[u], rp = coff[u], nc = coff[u + 1] - rp;
-    for (int32_t q = lane; q < nc; q += 64)
-      if ((int64_t)rp + q < cap) col_idx[rp + q] = colbuf[6 * (int64_t)b + q];
   }
 }
 
@@ -1212,6 +1205,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   int32_t* defer = wsp<int32_t>(c, L.defer);
   int32_t* full = wsp<int32_t>(c, L.full);
   int32_t* nfull = wsp<int32_t>(c, L.nfull);
+  int32_t* brow = wsp<int32_t>(c, L.brow);
   const uint32_t max_hits = (uint32_t)c->lim.max_hits;
   const double half = o->interval == TTIE_INTERVAL_APPENDIX_HALF ? 0.5 : 1.0;
   const int va = (o->flags & TTIE_EVAL_VERTEX_ADJACENT) ? 1 : 0;
@@ -1247,10 +1241,11 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
                                           bsr ? 1 : 0);
   if (bsr) {
     k_col_part<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part);
-    k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part, coff, block_cap, n_blocks, ctr);
+    k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part, coff, roff, colbuf, nullptr, brow,
+                                                           block_cap, n_blocks, ctr);
   }
-  k_rows_asm<S><<<grows, kBlock, 0, s>>>(wp, nw, rowv, roff, inc2, recs, colbuf, bsr ? coff : nullptr, col_idx, vals,
-                                         block_cap, grad, erow, &ctr->status);
+  k_assemble<S><<<grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096), kBlock, 0, s>>>(
+      wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, col_idx, vals, block_cap, grad, erow);
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
   k_dense<S><<<1 + grid_for(3 * nv + 1, 2048), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
                                                                 bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
@@ -1288,8 +1283,9 @@ static hipError_t bsr_symbolic_impl(Ctx* c, int32_t* row_ptr, int32_t* col_idx, 
   k_col_part<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wsp<uint32_t>(c, L.wp), nw, wsp<int32_t>(c, L.ncol),
                                                          wsp<uint32_t>(c, L.part));
   k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wsp<uint32_t>(c, L.wp), nw, wsp<int32_t>(c, L.ncol),
-                                                         wsp<uint32_t>(c, L.part), coff, cap, n_blocks, ctr);
-  k_sym_write<<<grows, kBlock, 0, s>>>(ctr, wsp<int32_t>(c, L.roff), wsp<int32_t>(c, L.colbuf), coff, col_idx, cap);
+                                                         wsp<uint32_t>(c, L.part), coff, wsp<int32_t>(c, L.roff),
+                                                         wsp<int32_t>(c, L.colbuf), col_idx, nullptr, cap, n_blocks,
+                                                         ctr);
   k_rowptr_fill<<<grid_for(nv + 1, 2048), kBlock, 0, s>>>(nv, wsp<uint32_t>(c, L.bm), wsp<uint32_t>(c, L.wp), coff,
                                                           row_ptr);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);

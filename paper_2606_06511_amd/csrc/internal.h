@@ -106,7 +106,7 @@ struct Layout {
       scan_tmp_bytes;
   // rows of the touched vertices: bitmap, per-word counts and prefixes, incidence places,
   // row offsets (incidences, BSR blocks) and row energies
-  size_t bm, wcnt, wp, wi, incpos, roff, coff, erow, part, full, nfull;
+  size_t bm, wcnt, wp, wi, incpos, roff, coff, erow, part, full, nfull, brow;
   size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state, pcg_flag, pcg_pos, pcg_act;
   size_t total;
