@@ -51,7 +51,17 @@ FLUSH_BYTES = 1 << 30
 #               write_scale (the factors that make a 256 MiB elementwise copy read and write
 #               256 MiB)
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
-MEASURED = {}
+MEASURED = {
+    # both screening kernels (k_screen + k_screen_full), 4,194,304-triangle sphere
+    "screen": [
+        {"bytes": 526518735, "valu_wave": 104992810, "params": {"screen_blocks": 4096},
+         "sources": {
+             "paper_2606_06511_amd/csrc/evaluate.hip": "f8755aa0994204ba132f6b5c24d417942a92d79ce84774390300009c284fec9f",
+             "paper_2606_06511_amd/csrc/pair.h": "7187ad6b1b50c86a2742ceb770e71a472d77253b643a09af1589e3dc0462fb37",
+             "paper_2606_06511_amd/csrc/predicates.h":
+                 "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},
+    ],
+}
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
 
