@@ -794,7 +794,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
   const uint32_t R = wp[nw];
   const int64_t nb = coff ? min((int64_t)coff[R], block_cap) : 0;
   const int64_t ng = 3 * (int64_t)R;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ng + nb; t += (int64_t)gridDim.x * blockDim.x) {
+  const XcdItems it = xcd_items(ng + nb);
+  for (int64_t t = it.first; t < it.end; t += it.step) {
     if (t < ng) {
       const int64_t r = t / 3;
       const int c = (int)(t % 3);
@@ -863,6 +864,24 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
   }
 }
 
+// Sum of a[r] over r = r0 + threadIdx.x + k * kBlock < r1, added in increasing r; sixteen loads
+// are in flight at a time (the adds of zero past the end leave the sum unchanged, the terms
+// being non-negative).
+__device__ __forceinline__ double strided_sum(const double* __restrict__ a, uint32_t r0, uint32_t r1) {
+  double acc = 0.0;
+  for (uint32_t base = r0 + threadIdx.x; base < r1; base += 16 * kBlock) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t r = base + k * kBlock;
+      v[k] = r < r1 ? a[r] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += v[k];
+  }
+  return acc;
+}
+
 // Energy of each problem of a batch: block p sums the energies of the rows of its vertex range
 // in a fixed order (thread-strided, then a tree).
 __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_prob, const int64_t* __restrict__ vert_off,
@@ -878,8 +897,7 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
   b = max((int64_t)0, min(b, nv));
   e = max(b, min(e, nv));
   const uint32_t r0 = vrank(bm, wp, b), r1 = vrank(bm, wp, e);
-  double acc = 0.0;
-  for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBlock) acc += erow[r];
+  const double acc = strided_sum(erow, r0, r1);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -890,8 +908,8 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
 }
 
 // The dense outputs (blocks 1..): incidence offsets off[v] and BSR row pointers
-// row_ptr[v] = coff[row of v] for v in [0, nv], one thread per vertex; zero gradient entries
-// of untouched vertices, one thread per entry (so the stores coalesce).  The per-vertex and
+// row_ptr[v] = coff[row of v] for v in [0, nv], and the zero gradient row of an untouched
+// vertex, one thread per vertex (a wave's stores are contiguous).  The per-vertex and
 // per-word counts are cleared for the next evaluation.  A wave holds 64 consecutive
 // vertices, i.e. two whole bitmap words, so a vertex's offset inside its word is a 32-lane
 // prefix sum.  Block 0 sums the row energies in row order (thread-strided, then a tree), writes
@@ -908,9 +926,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
   if (blockIdx.x == 0) {
     __shared__ double red[kBlock];
     const uint32_t R = wp[nw];
-    double acc = 0.0;
-    for (uint32_t r = threadIdx.x; r < R; r += kBlock) acc += erow[r];
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = strided_sum(erow, 0, R);
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
       if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -929,31 +945,29 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
     if (status_out) *status_out = __hip_atomic_load(&ctr->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
-  const int lane = __lane_id();
-  const int64_t t0 = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
-  for (int64_t v = t0; v - lane <= nv; v += stride) {
-    const bool in = v <= nv;
-    const int64_t w = v >> 5;
-    const uint32_t word = in ? bm[w] : 0u;
-    const uint32_t j = (uint32_t)v & 31u;
-    const int32_t c = in ? cnt[v] : 0;
-    // exclusive prefix of c over the vertices of the same word (lanes 0-31 and 32-63)
-    int32_t incl = c;
+  // one thread per vertex (0..nv: entry nv is the end of the offset and row-pointer arrays),
+  // so every load of the chain below is in flight for all vertices at once
+  const int64_t v = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const bool in = v <= nv;
+  const int64_t w = v >> 5;
+  const uint32_t word = in ? bm[w] : 0u;
+  const uint32_t j = (uint32_t)v & 31u;
+  const int32_t c = in ? cnt[v] : 0;
+  // exclusive prefix of c over the vertices of the same word (lanes 0-31 and 32-63)
+  int32_t incl = c;
 #pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-      const int32_t y = __shfl_up(incl, d, 32);
-      if ((int)j >= d) incl += y;
-    }
-    if (!in) continue;
-    off[v] = (int32_t)wi[w] + incl - c;
-    if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
-    if (c) cnt[v] = 0;
-    if (j == 0 && w < nw) wcnt[w] = 0u;
+  for (int d = 1; d < 32; d <<= 1) {
+    const int32_t y = __shfl_up(incl, d, 32);
+    if ((int)j >= d) incl += y;
   }
-  for (int64_t i = t0; i < 3 * nv; i += stride) {
-    const int64_t v = i / 3;
-    if (!((bm[v >> 5] >> (v & 31)) & 1u)) grad[i] = Sc<S>::c(0.0);
+  if (!in) return;
+  off[v] = (int32_t)wi[w] + incl - c;
+  if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
+  if (c) cnt[v] = 0;
+  if (j == 0 && w < nw) wcnt[w] = 0u;
+  if (v < nv && !((word >> j) & 1u)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad[3 * v + k] = Sc<S>::c(0.0);
   }
 }
 
@@ -1247,7 +1261,7 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   k_assemble<S><<<grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096), kBlock, 0, s>>>(
       wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, col_idx, vals, block_cap, grad, erow);
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
-  k_dense<S><<<1 + grid_for(3 * nv + 1, 2048), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
+  k_dense<S><<<1 + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
                                                                 bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
                                                                 energy, n_hits, status_out);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);

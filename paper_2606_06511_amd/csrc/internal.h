@@ -88,6 +88,20 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
   return (b % 8) * per + b / 8;
 }
 
+// A thread-strided loop over n items that keeps each XCD on one contiguous eighth of them
+// (blocks are dealt to the XCDs round-robin, so block b runs on XCD b mod 8): the thread's
+// first item, the end of its XCD's range and the stride.  With a grid that is not a multiple of
+// 8 it is the plain grid-strided loop.
+struct XcdItems {
+  int64_t first, end, step;
+};
+__device__ __forceinline__ XcdItems xcd_items(int64_t n) {
+  const int64_t G = gridDim.x, B = blockDim.x;
+  if (G % 8 != 0) return {(int64_t)blockIdx.x * B + threadIdx.x, n, G * B};
+  const int64_t per = (n + 7) / 8, beg = min(n, (int64_t)(blockIdx.x % 8) * per);
+  return {beg + (int64_t)(blockIdx.x / 8) * B + threadIdx.x, min(n, beg + per), (G / 8) * B};
+}
+
 // wave-aggregated append to a counter-indexed list: one atomic per wave; every lane of the wave
 // must call it
 __device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* counter) {
