@@ -82,6 +82,10 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.coff = take((6 * H + 1) * 4);
   L.erow = take(6 * H * 8);
   L.brow = take((size_t)lim.max_blocks * 4);  // the row of every BSR block
+  L.irow = take(6 * H * 4);
+  L.csort = take(36 * H * 4);
+  L.cval = take(36 * H * 4);
+  L.colrun = take(36 * H * 4);
   // block totals of the word scan (two per 1024 words) and of the column scan (one per 1024 rows)
   L.part = take(std::max<size_t>(2 * (W / 1024 + 2), 6 * H / 1024 + 2) * 4);
   L.scan_tmp_bytes = scan_bytes;

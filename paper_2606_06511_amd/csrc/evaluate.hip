@@ -13,8 +13,10 @@
 //                    counts the hit's six incidences and marks its vertices in the bitmap
 //   k_rank           one block: per bitmap word, the touched vertices and the incidences below it
 //   k_fill           scatter (pair key, hit, slot) incidences into per-vertex lists; name the rows
-//   k_rows_sort<S>   one wave per touched vertex (row): rank-sort its incidences by pair key
-//                    (the summation order) and list its distinct neighbour vertices (BSR columns)
+//   k_rank_inc<S>    one thread per incidence: its place in its row in pair-key order (the
+//                    summation order); its hit's vertices as the row's column candidates
+//   k_rank_cand, k_row_cols  one thread per candidate: ranked by vertex, then the distinct
+//                    vertices numbered (the row's BSR columns) with their candidate runs
 //   k_col_part, k_col_scan  BSR offsets of the rows from their column counts; column indices
 //   k_assemble<S>    one thread per gradient entry (with the row's energy) and per BSR block
 //                    J_k^T M J_l, each summed over its row's incidences in pair-key order
@@ -529,7 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ r
                                                  const int32_t* __restrict__ cnt, const uint32_t* __restrict__ bm,
                                                  const uint32_t* __restrict__ wp, const uint32_t* __restrict__ wi,
                                                  int64_t nw, Incidence* __restrict__ inc, int32_t* __restrict__ rowv,
-                                                 int32_t* __restrict__ roff) {
+                                                 int32_t* __restrict__ roff, int32_t* __restrict__ irow) {
   const uint32_t H = min(ctr->n_hits, max_hits);
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gt == 0) roff[wp[nw]] = (int32_t)wi[nw];
@@ -540,15 +542,15 @@ __global__ void __launch_bounds__(kBlock) k_fill(const AsmRec<S>* __restrict__ r
     const int32_t pos = incpos[t];
     const uint32_t start = list_start(cnt, wi, v);
     inc[start + pos] = Incidence{recs[h].key, (int32_t)h, k};
+    const uint32_t r = vrank(bm, wp, v);
+    irow[start + pos] = (int32_t)r;
     if (pos == 0) {
-      const uint32_t r = vrank(bm, wp, v);
       rowv[r] = v;
       roff[r] = (int32_t)start;
     }
   }
 }
 
-constexpr int kIncCap = 256;   // incidences of a row ranked from LDS
 constexpr int kColCap = 1024;  // column candidates of a row sorted in LDS
 
 // Bitonic sort of s[0, p) (p a power of two, 64 <= p <= kColCap) by one wave in LDS.
@@ -647,55 +649,98 @@ __device__ __forceinline__ int32_t row_columns(int32_t* lds, const Incidence* __
   return kept;
 }
 
-// One row per wave: its incidences ranked by (pair key, slot, position) -- the summation
-// order, deterministic even when a hit holds the vertex twice (a pair sharing one vertex) and
-// a permutation even if a caller repeats a pair -- and, for the BSR, its distinct columns.
+// The rows of the assembly, one thread per output, in three passes (a wave per row would run
+// the row's chain of dependent loads once per row in turn):
+//   k_rank_inc   one thread per incidence: its rank among the row's incidences by (pair key,
+//                slot, position) -- the summation order, deterministic even when a hit holds the
+//                vertex twice (a pair sharing one vertex) and a permutation even if a caller
+//                repeats a pair -- and its place there, with its hit's six vertex ids as the
+//                row's column candidates (in that order)
+//   k_rank_cand  one thread per candidate: its rank among the row's candidates by (vertex,
+//                candidate index), and whether it is the first of its vertex
+//   k_row_cols   one thread per ranked first candidate: its number among the row's distinct
+//                vertices -- the BSR columns in increasing order -- with the start of its run
+//                of candidates (the incidences whose hit holds that column, in summation
+//                order); the row's last candidate writes the row's column count
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_rows_sort(const uint32_t* __restrict__ wp, int64_t nw,
-                                                      const int32_t* __restrict__ roff,
-                                                      const Incidence* __restrict__ inc,
-                                                      Incidence* __restrict__ inc2, const AsmRec<S>* __restrict__ recs,
-                                                      int32_t* __restrict__ colbuf, int32_t* __restrict__ cstage,
-                                                      int64_t cstage_len, int32_t* __restrict__ ncol, int want_bsr) {
-  __shared__ int32_t lcol[kWaves][kColCap];
-  __shared__ Incidence sinc[kWaves][kIncCap];
-  const int wave = threadIdx.x / 64, lane = __lane_id();
-  const uint32_t R = wp[nw];
-  for (uint32_t r = blockIdx.x * kWaves + wave; r < R; r += gridDim.x * kWaves) {
+__global__ void __launch_bounds__(kBlock) k_rank_inc(const Counters* ctr, uint32_t max_hits,
+                                                     const int32_t* __restrict__ irow,
+                                                     const int32_t* __restrict__ roff,
+                                                     const Incidence* __restrict__ inc,
+                                                     const AsmRec<S>* __restrict__ recs,
+                                                     Incidence* __restrict__ inc2, int32_t* __restrict__ cand) {
+  const XcdItems it = xcd_items(6 * (int64_t)min(ctr->n_hits, max_hits));
+  for (int64_t i = it.first; i < it.end; i += it.step) {
+    const int32_t r = irow[i];
     const int32_t b = roff[r], n = roff[r + 1] - b;
-    if (n <= kIncCap) {
-      for (int32_t i = lane; i < n; i += 64) sinc[wave][i] = inc[b + i];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int32_t i = lane; i < n; i += 64) {
-        const Incidence me = sinc[wave][i];
-        int32_t rank = 0;
-        for (int32_t j = 0; j < n; ++j) {
-          const Incidence o = sinc[wave][j];
-          rank += (o.key < me.key) | ((o.key == me.key) & ((o.slot < me.slot) | ((o.slot == me.slot) & (j < i))));
-        }
-        inc2[b + rank] = me;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    } else {
-      for (int32_t i = lane; i < n; i += 64) {
-        const Incidence me = inc[b + i];
-        int32_t rank = 0;
-        for (int32_t j = 0; j < n; ++j) {
-          const Incidence o = inc[b + j];
-          rank += o.key < me.key || (o.key == me.key && (o.slot < me.slot || (o.slot == me.slot && j < i)));
-        }
-        inc2[b + rank] = me;
-      }
+    const Incidence me = inc[i];
+    const int32_t self = (int32_t)(i - b);
+    int32_t rank = 0;
+#pragma unroll 4
+    for (int32_t j = 0; j < n; ++j) {
+      const Incidence o = inc[b + j];
+      rank += (o.key < me.key) | ((o.key == me.key) & ((o.slot < me.slot) | ((o.slot == me.slot) & (j < self))));
     }
-    if (want_bsr) {
-      // the columns only depend on the set of incident hits, so the unsorted list serves
-      const int32_t kept = row_columns(lcol[wave], inc + b, n, recs, cstage + 6 * (int64_t)b,
-                                       reinterpret_cast<uint8_t*>(cstage + cstage_len) + 6 * (int64_t)b,
-                                       colbuf + 6 * (int64_t)b, lane);
-      if (lane == 0) ncol[r] = kept;
+    inc2[b + rank] = me;
+    const int32_t* vid = recs[me.hit].vid;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) cand[6 * (int64_t)(b + rank) + l] = vid[l];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_rank_cand(const Counters* ctr, uint32_t max_hits,
+                                                      const int32_t* __restrict__ irow,
+                                                      const int32_t* __restrict__ roff,
+                                                      const Incidence* __restrict__ inc2,
+                                                      const int32_t* __restrict__ cand, uint32_t* __restrict__ csort,
+                                                      int32_t* __restrict__ cval, uint8_t* __restrict__ cflag) {
+  const XcdItems it = xcd_items(36 * (int64_t)min(ctr->n_hits, max_hits));
+  for (int64_t c = it.first; c < it.end; c += it.step) {
+    const int64_t i = c / 6;
+    const int32_t r = irow[i];
+    const int32_t b = roff[r], m = 6 * (roff[r + 1] - b);
+    const int64_t base = 6 * (int64_t)b;
+    const int32_t self = (int32_t)(c - base);
+    const int32_t v = cand[c];
+    int32_t pos = 0;
+    bool first = true;
+#pragma unroll 4
+    for (int32_t j = 0; j < m; ++j) {
+      const int32_t w = cand[base + j];
+      const bool dup = (w == v) & (j < self);
+      pos += (int32_t)((w < v) | dup);
+      first &= !dup;
     }
+    const Incidence I = inc2[i];
+    csort[base + pos] = ((uint32_t)I.hit << 6) | ((uint32_t)I.slot << 3) | (uint32_t)(c % 6);
+    cval[base + pos] = v;
+    cflag[base + pos] = first ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_row_cols(const Counters* ctr, uint32_t max_hits,
+                                                     const int32_t* __restrict__ irow,
+                                                     const int32_t* __restrict__ roff,
+                                                     const int32_t* __restrict__ cval,
+                                                     const uint8_t* __restrict__ cflag, int32_t* __restrict__ colbuf,
+                                                     int32_t* __restrict__ colrun, int32_t* __restrict__ ncol) {
+  const XcdItems it = xcd_items(36 * (int64_t)min(ctr->n_hits, max_hits));
+  for (int64_t e = it.first; e < it.end; e += it.step) {
+    const int32_t r = irow[e / 6];
+    const int32_t b = roff[r], m = 6 * (roff[r + 1] - b);
+    const int64_t base = 6 * (int64_t)b;
+    const int32_t pos = (int32_t)(e - base);
+    const int32_t f = cflag[e];
+    const bool last = pos == m - 1;
+    if (!f && !last) continue;
+    int32_t d = 0;
+#pragma unroll 8
+    for (int32_t j = 0; j < pos; ++j) d += cflag[base + j];
+    if (f) {
+      colbuf[base + d] = cval[e];
+      colrun[base + d] = pos;
+    }
+    if (last) ncol[r] = d + f;
   }
 }
 
@@ -776,10 +821,10 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
 
 // The sums of the assembly, one thread per output: the 3 R gradient entries (with each row's
 // energy: the hits the vertex owns, each counted at its first vertex), then -- when the BSR is
-// wanted -- one per block.  Every sum runs over the row's incidences in pair-key order
-// (inc2), kChunk at a time with the chunk's loads issued together.  Nothing depends on another
-// thread, so all of them are in flight at once and the kernel costs about one chain of
-// dependent loads.
+// wanted -- one per block.  A gradient sum runs over the row's incidences in pair-key order
+// (inc2), a block's over its column's run of ranked candidates (the same order), kChunk at a
+// time with the chunk's loads issued together.  Nothing depends on another thread, so all of
+// them are in flight at once and the kernel costs about one chain of dependent loads.
 constexpr int kChunk = 4;
 
 template <class S>
@@ -788,7 +833,9 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
                                                      const Incidence* __restrict__ inc2,
                                                      const AsmRec<S>* __restrict__ recs,
                                                      const int32_t* __restrict__ coff, const int32_t* __restrict__ brow,
-                                                     const int32_t* __restrict__ colbuf, int32_t* __restrict__ col_idx,
+                                                     const int32_t* __restrict__ colbuf,
+                                                     const int32_t* __restrict__ colrun,
+                                                     const uint32_t* __restrict__ csort, int32_t* __restrict__ col_idx,
                                                      S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
                                                      double* __restrict__ erow) {
   const uint32_t R = wp[nw];
@@ -828,35 +875,21 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
       const int64_t q = t - ng;
       const int32_t r = brow[q];
       const int32_t b = roff[r], n = roff[r + 1] - b;
-      const int32_t col = colbuf[6 * (int64_t)b + (q - coff[r])];
-      col_idx[q] = col;
+      const int32_t c0 = coff[r], d = (int32_t)(q - c0), nc = coff[r + 1] - c0;
+      const int64_t base = 6 * (int64_t)b;
+      col_idx[q] = colbuf[base + d];
+      // the column's run of ranked candidates: (hit, row slot, column slot) in summation order
+      const int32_t e0 = colrun[base + d], e1 = d + 1 < nc ? colrun[base + d + 1] : 6 * n;
       S B[9];
 #pragma unroll
       for (int z = 0; z < 9; ++z) B[z] = Sc<S>::c(0.0);
-      for (int32_t k0 = 0; k0 < n; k0 += kChunk) {
-        Incidence I[kChunk];
+      for (int32_t e = e0; e < e1; e += kChunk) {
+        uint32_t pk[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) pk[k] = e + k < e1 ? csort[base + e + k] : 0u;
 #pragma unroll
         for (int k = 0; k < kChunk; ++k)
-          if (k0 + k < n) I[k] = inc2[b + k0 + k];
-        uint32_t match[kChunk];
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-          match[k] = 0;
-          if (k0 + k < n) {
-            const int32_t* vid = recs[I[k].hit].vid;
-#pragma unroll
-            for (int l = 0; l < 6; ++l) match[k] |= (uint32_t)(vid[l] == col) << l;
-          }
-        }
-        // the hit's slots holding the column, in slot order, hit after hit
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-          uint32_t mk = match[k];
-          while (mk) {
-            block_jmj(recs[I[k].hit], I[k].slot, __builtin_ctz(mk), B);
-            mk &= mk - 1;
-          }
-        }
+          if (e + k < e1) block_jmj(recs[pk[k] >> 6], (int)((pk[k] >> 3) & 7u), (int)(pk[k] & 7u), B);
       }
 #pragma unroll
       for (int z = 0; z < 9; ++z) vals[9 * q + z] = B[z];
@@ -976,7 +1009,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
 // on a caller's pattern (numeric), from the hit records and the sorted incidence lists the
 // evaluation leaves in the workspace.
 // ------------------------------------------------------------------------------------------
-// Symbolic, first pass: the distinct columns of every touched row (as in k_rows_sort) and
+// Symbolic, first pass: the distinct columns of every touched row (by a wave per row) and
 // their count.
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_sym_cols(const Counters* ctr, const int32_t* __restrict__ roff,
@@ -1247,19 +1280,27 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   const unsigned rank_blocks = (unsigned)((nw + kRankBlockWords - 1) / kRankBlockWords);
   k_rank_part<<<rank_blocks, kRankThreads, 0, s>>>(bm, wcnt, nw, part);
   k_rank<<<rank_blocks, kRankThreads, 0, s>>>(bm, wcnt, nw, part, wp, wi);
+  int32_t* irow = wsp<int32_t>(c, L.irow);
+  uint32_t* csort = wsp<uint32_t>(c, L.csort);
+  int32_t* cval = wsp<int32_t>(c, L.cval);
+  int32_t* colrun = wsp<int32_t>(c, L.colrun);
+  uint8_t* cflag = reinterpret_cast<uint8_t*>(cstage + 36 * c->lim.max_hits);
   k_fill<S><<<grid_for(6 * c->lim.max_hits, 1024), kBlock, 0, s>>>(recs, ctr, max_hits, incpos, cnt, bm, wp, wi, nw,
-                                                                   inc, rowv, roff);
-  const unsigned grows = (unsigned)std::min<int64_t>(ctx_param(c, TTIE_PARAM_ROW_BLOCKS),
-                                                     (6 * c->lim.max_hits + kWaves - 1) / kWaves + 1);
-  k_rows_sort<S><<<grows, kBlock, 0, s>>>(wp, nw, roff, inc, inc2, recs, colbuf, cstage, 36 * c->lim.max_hits, ncol,
-                                          bsr ? 1 : 0);
+                                                                   inc, rowv, roff, irow);
+  k_rank_inc<S><<<grid_for(6 * c->lim.max_hits, 4096), kBlock, 0, s>>>(ctr, max_hits, irow, roff, inc, recs, inc2,
+                                                                       cstage);
   if (bsr) {
+    k_rank_cand<<<grid_for(36 * c->lim.max_hits, 4096), kBlock, 0, s>>>(ctr, max_hits, irow, roff, inc2, cstage, csort,
+                                                                        cval, cflag);
+    k_row_cols<<<grid_for(36 * c->lim.max_hits, 4096), kBlock, 0, s>>>(ctr, max_hits, irow, roff, cval, cflag, colbuf,
+                                                                       colrun, ncol);
     k_col_part<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part);
     k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part, coff, roff, colbuf, nullptr, brow,
                                                            block_cap, n_blocks, ctr);
   }
   k_assemble<S><<<grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096), kBlock, 0, s>>>(
-      wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, col_idx, vals, block_cap, grad, erow);
+      wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, colrun, csort, col_idx, vals, block_cap, grad,
+      erow);
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
   k_dense<S><<<1 + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
                                                                 bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
