@@ -62,6 +62,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.hits = take(H * sizeof(HitGeom));
   L.defer = take((size_t)lim.max_pairs * 4);
   L.full = take((size_t)lim.max_pairs * 4);  // candidates for the full screening
+  L.fsig = take((size_t)lim.max_pairs * 2);  // and their plane sides
   L.nfull = take((size_t)65536 * 4 * 4);     // their number per screening wave (grid <= 65536 blocks)
   L.recs = take(H * sizeof(AsmRec<double>));
   L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time

@@ -58,8 +58,17 @@ __device__ __forceinline__ bool load_tri(const double* x, int64_t nv, const int3
 
 
 // Screens candidate p (p < 0: inactive lane).  Every lane of the wave must call it.
+// code: 0, or the exact plane sides of a pair that straddles both ways as the first stage found
+// them (bit 12 set; bits 2k..2k+1 hold sa[k] + 1 and bits 6+2k..7+2k sb[k] + 1).
+__device__ __forceinline__ uint32_t side_code(const int (&sa)[3], const int (&sb)[3]) {
+  uint32_t c = 1u << 12;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c |= (uint32_t)(sa[k] + 1) << (2 * k) | (uint32_t)(sb[k] + 1) << (6 + 2 * k);
+  return c;
+}
+
 template <bool kExact>
-__device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__ x, int64_t nv,
+__device__ __forceinline__ void screen_one(int64_t p, uint32_t code, const double* __restrict__ x, int64_t nv,
                                            const int32_t* __restrict__ tris, int64_t nt,
                                            const int32_t* __restrict__ pairs, double half, bool va,
                                            HitGeom* __restrict__ hits, uint32_t max_hits, int32_t* __restrict__ defer,
@@ -82,7 +91,17 @@ __device__ __forceinline__ void screen_one(int64_t p, const double* __restrict__
       if (is_adjacent(vi, vj, va)) {
         kind = PAIR_ADJACENT;
       } else {
-        sc = screen_pair<kExact>(A, B, half, status);
+        if (code) {
+          int sa[3], sb[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            sa[k] = (int)((code >> (2 * k)) & 3u) - 1;
+            sb[k] = (int)((code >> (6 + 2 * k)) & 3u) - 1;
+          }
+          sc = screen_pair_sides<kExact>(A, B, sa, sb, half, status);
+        } else {
+          sc = screen_pair<kExact>(A, B, half, status);
+        }
         kind = sc.kind;
       }
     }
@@ -168,7 +187,7 @@ __device__ __forceinline__ int coord_status(double q) {
 // sides against T_a's plane.
 __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t nv, const int32_t* tris, int64_t nt,
                                              const int32_t* pairs, bool va, uint8_t* flags, double* pair_T,
-                                             int& status) {
+                                             uint32_t& code, int& status) {
   int32_t vi[3], vj[3];
   Tri64 A, B;
   if (!load_pair(p, x, nv, tris, nt, pairs, vi, vj, A, B)) {
@@ -193,6 +212,7 @@ __device__ __forceinline__ int screen_stage1(int64_t p, const double* x, int64_t
     settle(p, PAIR_NONE, flags, pair_T);
     return STEP_SETTLED;
   }
+  code = side_code(sa, sb);
   return STEP_FULL;
 }
 
@@ -210,8 +230,8 @@ __device__ __forceinline__ void wave_chunk(int64_t np, int64_t& beg, int64_t& en
 }
 
 // First stage over the candidate list, one lane per candidate.  A wave writes the candidates it
-// passes to the full screening into its own chunk's index range of `full` (no atomics) and
-// their number to nfull[wave].  Also clears the touched-vertex bitmap of the previous
+// passes to the full screening, with their plane sides, into its own chunk's index range of
+// `full` and `fsig` (no atomics) and their number to nfull[wave].  Also clears the touched-vertex bitmap of the previous
 // evaluation (read by the calls after it) before k_derivs marks this one's, and checks every
 // coordinate against the exact predicates' domain (a violation is reported, never acted on: out
 // of it the exact arithmetic only loses exactness, it stays within its arrays).
@@ -219,8 +239,9 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
                                                    const int32_t* __restrict__ tris, int64_t nt,
                                                    const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
                                                    int64_t max_pairs, int va, int32_t* __restrict__ defer,
-                                                   int32_t* __restrict__ full, int32_t* __restrict__ nfull,
-                                                   Counters* ctr, uint8_t* __restrict__ flags,
+                                                   int32_t* __restrict__ full, uint16_t* __restrict__ fsig,
+                                                   int32_t* __restrict__ nfull, Counters* ctr,
+                                                   uint8_t* __restrict__ flags,
                                                    double* __restrict__ pair_T, uint32_t* __restrict__ bm, int64_t nbm) {
   int status = 0;
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
@@ -236,10 +257,15 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
   for (int64_t base = beg; base < end; base += 64) {
     const int64_t p = base + lane;
     int st = STEP_SETTLED;
-    if (p < end) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, status);
+    uint32_t code = 0;
+    if (p < end) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, code, status);
     append(st == STEP_DEFER, p, defer, max_pairs, &ctr->n_defer, status);
     const uint64_t fm = __ballot(st == STEP_FULL);
-    if (st == STEP_FULL) full[beg + nf + __popcll(fm & below)] = (int32_t)p;
+    if (st == STEP_FULL) {
+      const int64_t at = beg + nf + __popcll(fm & below);
+      full[at] = (int32_t)p;
+      fsig[at] = (uint16_t)code;
+    }
     nf += __popcll(fm);
   }
   if (lane == 0) nfull[wid] = nf;
@@ -247,13 +273,16 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
 }
 
 // The full screening (screen_one) of the candidates the first stage passed on, each wave the
-// ones of the same chunk (same grid size as k_screen).
+// ones of the same chunk (same grid size as k_screen).  A pair that straddles both ways comes
+// with its exact plane sides, so only the four orientations of the flag are new work, and the
+// plane distances are computed again for a hit only.
 __global__ void __launch_bounds__(kBlock) k_screen_full(const double* __restrict__ x, int64_t nv,
                                                         const int32_t* __restrict__ tris, int64_t nt,
                                                         const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
                                                         int64_t max_pairs, double half, int va,
                                                         HitGeom* __restrict__ hits, uint32_t max_hits,
                                                         int32_t* __restrict__ defer, const int32_t* __restrict__ full,
+                                                        const uint16_t* __restrict__ fsig,
                                                         const int32_t* __restrict__ nfull, Counters* ctr,
                                                         uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
   const int64_t np = min(*n_pairs_dev, max_pairs);
@@ -264,8 +293,8 @@ __global__ void __launch_bounds__(kBlock) k_screen_full(const double* __restrict
   int status = 0;
   for (int32_t k0 = 0; k0 < nf; k0 += 64) {
     const int32_t k = k0 + lane;
-    screen_one<false>(k < nf ? (int64_t)full[beg + k] : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits,
-                      defer, max_pairs, ctr, flags, pair_T, status);
+    screen_one<false>(k < nf ? (int64_t)full[beg + k] : -1, k < nf ? (uint32_t)fsig[beg + k] : 0u, x, nv, tris, nt,
+                      pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags, pair_T, status);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -282,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_screen_exact(const double* __restric
   int status = 0;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nd; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = base + threadIdx.x;
-    screen_one<true>(q < nd ? (int64_t)defer[q] : -1, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, nullptr,
+    screen_one<true>(q < nd ? (int64_t)defer[q] : -1, 0u, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, nullptr,
                      0, ctr, flags, pair_T, status);
   }
   if (status) latch(&ctr->status, status);
@@ -1263,10 +1292,11 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   stage_begin(c, TTIE_STAGE_SCREEN, s);
   // both screening kernels split the list the same way: the same grid
   const unsigned gscreen = grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS));
-  k_screen<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, va, defer, full, nfull,
-                                      ctr, flags, pair_T, bm, nw);
+  uint16_t* fsig = wsp<uint16_t>(c, L.fsig);
+  k_screen<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, va, defer, full, fsig,
+                                      nfull, ctr, flags, pair_T, bm, nw);
   k_screen_full<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half, va, hits,
-                                           max_hits, defer, full, nfull, ctr, flags, pair_T);
+                                           max_hits, defer, full, fsig, nfull, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,

@@ -124,6 +124,8 @@ struct Layout {
   // per incidence place: its row; per column candidate place (ranked): the packed (hit, row
   // slot, column slot), the vertex; per distinct column: the start of its candidate run
   size_t irow, csort, cval, colrun;
+  // the first stage's exact plane sides of each candidate passed to the full screening
+  size_t fsig;
   size_t bvh_heavy, bvh_heavy_bytes, bvh_ext, hash_grid, hash_key, hash_tri, hash_rank, hash_skey, hash_stri, bvh_keys, bvh_qend, bvh_vals, bvh_vals2, bvh_hist, bvh_offset, bvh_boxes, bvh_leaves,
       bvh_tbox, bvh_centroid, bvh_part, touched, inc2, pcg_vec, pcg_part, pcg_state, pcg_flag, pcg_pos, pcg_act;
   size_t total;

@@ -261,34 +261,12 @@ struct Screen {
   double da[3], db[3];
 };
 
-// Full screening of one non-adjacent pair in FP64 with exact decisions.  Without kExact,
-// a pair needing the exact fallback for any sign comes back as PAIR_DEFER.
+// The exact flag of two straddling cuts (sign(t(Q) - t(P)) for every pair of ends from four
+// orientation signs, see the header): 1 when the open interval of Eq. 1 contains 0, 0 when it
+// does not, 2 when a sign needs the exact path and kExact is off.
 template <bool kExact>
-__device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, double half, int& status) {
-  Screen out;
-  out.kind = PAIR_NONE;
-  out.desc = 0;
-  out.t0 = out.t1 = 0.0;
-  int sa[3], sb[3];
-  // T_a cut by the plane of T_b first, as the appendix does
-  if (!plane_sides<kExact>(B, A, sa, out.da, status)) {
-    out.kind = PAIR_DEFER;
-    return out;
-  }
-  if ((sa[0] | sa[1] | sa[2]) == 0) {  // A lies in B's plane (or B has no area)
-    out.kind = coplanar_kind<kExact>(A, B, status);
-    return out;
-  }
-  const Cut ca = make_cut(sa[0], sa[1], sa[2]);
-  if (!ca.straddle) return out;
-  if (!plane_sides<kExact>(A, B, sb, out.db, status)) {
-    out.kind = PAIR_DEFER;
-    return out;
-  }
-  const Cut cb = make_cut(sb[0], sb[1], sb[2]);
-  if (!cb.straddle) return out;
-
-  // exact flag from four orientation signs
+__device__ __forceinline__ int cuts_intersect(const Tri64& A, const Tri64& B, const Cut& ca, const Cut& cb,
+                                              int& status) {
   bool after = false, before = false;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -299,18 +277,20 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
       const int r = cb.p[j], s = partner(cb, j);
       // sign(t(Q) - t(P)) = sign(orient(p,q,r,s)) * sign(d_q - d_p) * sign(e_s - e_r)
       const int o = orient_sign<kExact>(P, Q, selv(B, r), selv(B, s), status);
-      if (o == 2) {
-        out.kind = PAIR_DEFER;
-        return out;
-      }
+      if (o == 2) return 2;
       const int tau = o * seli(ca.s, q) * seli(cb.s, s);
       after |= tau < 0;   // t(P) > t(Q)
       before |= tau > 0;  // t(P) < t(Q)
     }
   }
-  if (!(after && before)) return out;
+  return (after && before) ? 1 : 0;
+}
 
-  // FP64 interval ends on pair-local coordinates (origin u0)
+// FP64 interval ends of a hit on pair-local coordinates (origin u0), from its cuts and the
+// plane sides out.da, out.db; fills out's descriptor and t0, t1 and its kind (PAIR_HIT, or
+// PAIR_BAD_FRAME when the rounded line direction is 0).
+__device__ __forceinline__ void interval_ends(const Tri64& A, const Tri64& B, const Cut& ca, const Cut& cb,
+                                              double half, Screen& out) {
   const V3<double> o = selv(A, 0);
   V3<double> D;
   const bool frame = line_direction(A, B, D);
@@ -345,12 +325,67 @@ __device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, do
   out.desc = desc;
   if (!frame) {
     out.kind = PAIR_BAD_FRAME;
-    return out;
+    return;
   }
   const double inv = half / len;
   out.t0 = ((amin ? ta[1] : ta[0]) - (bmax ? tb[1] : tb[0])) * inv;
   out.t1 = ((amax ? ta[1] : ta[0]) - (bmin ? tb[1] : tb[0])) * inv;
   out.kind = PAIR_HIT;
+}
+
+// Full screening of one non-adjacent pair in FP64 with exact decisions.  Without kExact,
+// a pair needing the exact fallback for any sign comes back as PAIR_DEFER.
+template <bool kExact>
+__device__ __forceinline__ Screen screen_pair(const Tri64& A, const Tri64& B, double half, int& status) {
+  Screen out;
+  out.kind = PAIR_NONE;
+  out.desc = 0;
+  out.t0 = out.t1 = 0.0;
+  int sa[3], sb[3];
+  // T_a cut by the plane of T_b first, as the appendix does
+  if (!plane_sides<kExact>(B, A, sa, out.da, status)) {
+    out.kind = PAIR_DEFER;
+    return out;
+  }
+  if ((sa[0] | sa[1] | sa[2]) == 0) {  // A lies in B's plane (or B has no area)
+    out.kind = coplanar_kind<kExact>(A, B, status);
+    return out;
+  }
+  const Cut ca = make_cut(sa[0], sa[1], sa[2]);
+  if (!ca.straddle) return out;
+  if (!plane_sides<kExact>(A, B, sb, out.db, status)) {
+    out.kind = PAIR_DEFER;
+    return out;
+  }
+  const Cut cb = make_cut(sb[0], sb[1], sb[2]);
+  if (!cb.straddle) return out;
+  const int x = cuts_intersect<kExact>(A, B, ca, cb, status);
+  if (x == 2) out.kind = PAIR_DEFER;
+  if (x == 1) interval_ends(A, B, ca, cb, half, out);
+  return out;
+}
+
+// screen_pair for a pair whose exact plane sides are known to straddle both ways (sa: T_a's
+// against T_b's plane, sb: the converse, as the FP64 pass of the first stage found them): the
+// plane distances are computed only for a hit, by the same FP64 arithmetic that gave the
+// signs, so every result is the one screen_pair gives.
+template <bool kExact>
+__device__ __forceinline__ Screen screen_pair_sides(const Tri64& A, const Tri64& B, const int (&sa)[3],
+                                                    const int (&sb)[3], double half, int& status) {
+  Screen out;
+  out.kind = PAIR_NONE;
+  out.desc = 0;
+  out.t0 = out.t1 = 0.0;
+  const Cut ca = make_cut(sa[0], sa[1], sa[2]), cb = make_cut(sb[0], sb[1], sb[2]);
+  const int x = cuts_intersect<kExact>(A, B, ca, cb, status);
+  if (x == 2) out.kind = PAIR_DEFER;
+  if (x != 1) return out;
+  int s2[3];
+  if (!plane_sides<kExact>(B, A, s2, out.da, status) || !plane_sides<kExact>(A, B, s2, out.db, status)) {
+    out.kind = PAIR_DEFER;
+    return out;
+  }
+  interval_ends(A, B, ca, cb, half, out);
   return out;
 }
 
