@@ -6,8 +6,10 @@
 //                    triangles; candidates that straddle both ways, and filter-uncertain ones, are
 //                    appended to lists with one atomic per wave (ballot + mbcnt); checks the
 //                    coordinate domain and clears the bitmap of touched vertices
-//   k_screen_full    the full screening of the straddling candidates: segment ends, line frame,
-//                    exact flag, FP64 interval ends; hits appended
+//   k_screen_flag    the exact flag of the straddling candidates from their plane sides and four
+//                    orientations; non-hits settled, the rest compacted in the wave's list
+//   k_screen_full    the full screening of what is left (hits, in-plane pairs): segment ends,
+//                    line frame, exact flag, FP64 interval ends; hits appended
 //   k_screen_exact   the uncertain candidates again, with the exact fallback
 //   k_derivs<S>      one lane per hit: a = dt_c^0, b = dt_c^1, T, g (Eq. 3), 2x2 Hessian core;
 //                    counts the hit's six incidences and marks its vertices in the bitmap
@@ -272,29 +274,123 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
   if (status) latch(&ctr->status, status);
 }
 
-// The full screening (screen_one) of the candidates the first stage passed on, each wave the
-// ones of the same chunk (same grid size as k_screen).  A pair that straddles both ways comes
-// with its exact plane sides, so only the four orientations of the flag are new work, and the
-// plane distances are computed again for a hit only.
+// The exact flag of the candidates the first stage passed on with their plane sides, one lane
+// each, on the four orientations only (a small kernel: more waves hide the gathers).  Pairs that
+// do not intersect are settled, the ones whose signs need the exact path go to the deferred
+// list, and the rest -- hits, and the pairs with a triangle in the other's plane -- stay in
+// the wave's list (compacted in place: a batch's writes land below the entries still to be
+// read) for k_screen_full.
+__global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict__ x, int64_t nv,
+                                                        const int32_t* __restrict__ tris,
+                                                        const int32_t* __restrict__ pairs,
+                                                        const int64_t* n_pairs_dev, int64_t max_pairs,
+                                                        int32_t* __restrict__ defer, int32_t* __restrict__ full,
+                                                        uint16_t* __restrict__ fsig, int32_t* __restrict__ nfull,
+                                                        Counters* ctr, uint8_t* __restrict__ flags,
+                                                        double* __restrict__ pair_T) {
+  const int64_t np = min(*n_pairs_dev, max_pairs);
+  int64_t beg, end, wid;
+  wave_chunk(np, beg, end, wid);
+  const int32_t nf = nfull[wid];
+  const int lane = __lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  int status = 0;
+  int32_t kept = 0;
+  for (int32_t k0 = 0; k0 < nf; k0 += 64) {
+    const int32_t k = k0 + lane;
+    int32_t p = -1;
+    uint32_t code = 0;
+    int verdict = 1;  // 0 settled, 1 kept, 2 deferred
+    if (k < nf) {
+      p = full[beg + k];
+      code = fsig[beg + k];
+      if (code) {
+        const int2 ij = reinterpret_cast<const int2*>(pairs)[p];
+        int32_t vi[3], vj[3];
+        Tri64 A, B;
+        load_tri(x, nv, tris, ij.x, vi, A);
+        load_tri(x, nv, tris, ij.y, vj, B);
+        int sa[3], sb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sa[c] = (int)((code >> (2 * c)) & 3u) - 1;
+          sb[c] = (int)((code >> (6 + 2 * c)) & 3u) - 1;
+        }
+        const int xr = cuts_intersect<false>(A, B, make_cut(sa[0], sa[1], sa[2]), make_cut(sb[0], sb[1], sb[2]),
+                                             status);
+        verdict = xr == 0 ? 0 : (xr == 2 ? 2 : 1);
+        if (verdict == 0) settle(p, PAIR_NONE, flags, pair_T);
+      }
+    }
+    append(verdict == 2, p, defer, max_pairs, &ctr->n_defer, status);
+    const bool keep = k < nf && verdict == 1;
+    const uint64_t km = __ballot(keep);
+    if (keep) {
+      const int64_t at = beg + kept + __popcll(km & below);
+      full[at] = p;
+      fsig[at] = (uint16_t)code;
+    }
+    kept += (int32_t)__popcll(km);
+  }
+  if (lane == 0) nfull[wid] = kept;
+  if (status) latch(&ctr->status, status);
+}
+
+// The full screening (screen_one) of the candidates k_screen_flag kept: few per chunk (the hits,
+// and pairs with a triangle in the other's plane), so each wave takes the lists of kMergeChunks
+// consecutive chunks and screens them 64 at a time (a wave per chunk would pay its chain of
+// dependent loads for one or two pairs).  A pair that straddles both ways comes with its exact
+// plane sides, so the plane distances are computed again for a hit only.
+constexpr int kMergeChunks = 16;
+
 __global__ void __launch_bounds__(kBlock) k_screen_full(const double* __restrict__ x, int64_t nv,
                                                         const int32_t* __restrict__ tris, int64_t nt,
                                                         const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
-                                                        int64_t max_pairs, double half, int va,
+                                                        int64_t max_pairs, int64_t n_chunks, double half, int va,
                                                         HitGeom* __restrict__ hits, uint32_t max_hits,
                                                         int32_t* __restrict__ defer, const int32_t* __restrict__ full,
                                                         const uint16_t* __restrict__ fsig,
                                                         const int32_t* __restrict__ nfull, Counters* ctr,
                                                         uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
   const int64_t np = min(*n_pairs_dev, max_pairs);
-  int64_t beg, end, wid;
-  wave_chunk(np, beg, end, wid);
-  const int32_t nf = nfull[wid];
+  // the chunk length of the screening grid (as wave_chunk computes it there)
+  const int64_t chunk = ((np + n_chunks - 1) / n_chunks + 63) / 64 * 64;
   const int lane = __lane_id();
+  const int64_t c0 = ((int64_t)blockIdx.x * kWaves + threadIdx.x / 64) * kMergeChunks;
+  int32_t cnt = 0;
+  if (lane < kMergeChunks && c0 + lane < n_chunks) cnt = nfull[c0 + lane];
+  // inclusive prefix of the chunk counts, then every lane holds all of them
+  int32_t incl = cnt;
+#pragma unroll
+  for (int d = 1; d < kMergeChunks; d <<= 1) {
+    const int32_t y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  int32_t pre[kMergeChunks];
+#pragma unroll
+  for (int j = 0; j < kMergeChunks; ++j) pre[j] = __shfl(incl, j);
+  const int32_t total = pre[kMergeChunks - 1];
   int status = 0;
-  for (int32_t k0 = 0; k0 < nf; k0 += 64) {
-    const int32_t k = k0 + lane;
-    screen_one<false>(k < nf ? (int64_t)full[beg + k] : -1, k < nf ? (uint32_t)fsig[beg + k] : 0u, x, nv, tris, nt,
-                      pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags, pair_T, status);
+  for (int32_t e0 = 0; e0 < total; e0 += 64) {
+    const int32_t e = e0 + lane;
+    int64_t p = -1;
+    uint32_t code = 0;
+    if (e < total) {
+      // the chunk holding entry e, and e's place in its list
+      int j = 0;
+      int32_t below = 0;
+#pragma unroll
+      for (int k = 0; k < kMergeChunks - 1; ++k)
+        if (e >= pre[k]) {
+          j = k + 1;
+          below = pre[k];
+        }
+      const int64_t at = min(np, (c0 + j) * chunk) + (e - below);
+      p = full[at];
+      code = fsig[at];
+    }
+    screen_one<false>(p, code, x, nv, tris, nt, pairs, half, va != 0, hits, max_hits, defer, max_pairs, ctr, flags,
+                      pair_T, status);
   }
   if (status) latch(&ctr->status, status);
 }
@@ -1295,8 +1391,12 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   uint16_t* fsig = wsp<uint16_t>(c, L.fsig);
   k_screen<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, va, defer, full, fsig,
                                       nfull, ctr, flags, pair_T, bm, nw);
-  k_screen_full<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, half, va, hits,
-                                           max_hits, defer, full, fsig, nfull, ctr, flags, pair_T);
+  k_screen_flag<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, pairs, n_pairs, pair_cap, defer, full, fsig, nfull, ctr,
+                                           flags, pair_T);
+  const int64_t n_chunks = (int64_t)gscreen * kWaves;
+  k_screen_full<<<(unsigned)((n_chunks + kWaves * kMergeChunks - 1) / (kWaves * kMergeChunks)), kBlock, 0, s>>>(
+      m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, n_chunks, half, va, hits, max_hits, defer, full, fsig,
+      nfull, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,
