@@ -69,5 +69,8 @@ def test_path_bytes_count_the_arrays(prec):
     want = sum(a.nbytes for a in arrays_in) + 2 * records.nbytes + sum(a.nbytes for a in arrays_out)
     assert b.path_bytes(nv, nt, P, H, nnzb, s) == want
     assert b.path_bytes(nv, nt, P, H, nnzb, s, flags=True) == want + np.zeros(P, np.uint8).nbytes
-    # the screening stage reads the same inputs and writes the 80-byte hit geometry
-    assert b.stage_bytes("screen", nv, nt, P, H, nnzb, s) == sum(a.nbytes for a in arrays_in) + 80 * H
+    # the screening stage reads the same inputs and writes each hit's geometry: pair key, pair
+    # index, endpoint descriptor, the two interval ends and the six plane sides
+    geom = np.dtype([("key", np.int64), ("pair", np.int32), ("desc", np.uint32), ("t", np.float64, 2),
+                     ("da", np.float64, 3), ("db", np.float64, 3)])
+    assert b.stage_bytes("screen", nv, nt, P, H, nnzb, s) == sum(a.nbytes for a in arrays_in) + H * geom.itemsize
