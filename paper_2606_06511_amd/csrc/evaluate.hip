@@ -1403,8 +1403,9 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
                                                             hits, max_hits, defer, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN_EXACT, s);
   stage_begin(c, TTIE_STAGE_DERIVS, s);
-  k_derivs<S><<<grid_for(c->lim.max_hits, 1024), kBlock, 0, s>>>(m->x, m->tris, hits, ctr, max_hits, o->psd_mode,
-                                                                 half, recs, cnt, wcnt, bm, incpos);
+  // one wave per block, so the few waves of a small hit count spread over every CU
+  k_derivs<S><<<(unsigned)std::min<int64_t>((c->lim.max_hits + 63) / 64, 4096), 64, 0, s>>>(
+      m->x, m->tris, hits, ctr, max_hits, o->psd_mode, half, recs, cnt, wcnt, bm, incpos);
   stage_end(c, TTIE_STAGE_DERIVS, s);
   stage_begin(c, TTIE_STAGE_ASSEMBLY, s);
   const unsigned rank_blocks = (unsigned)((nw + kRankBlockWords - 1) / kRankBlockWords);
