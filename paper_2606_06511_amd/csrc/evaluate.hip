@@ -277,9 +277,9 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
 // The exact flag of the candidates the first stage passed on with their plane sides, one lane
 // each, on the four orientations only (a small kernel: more waves hide the gathers).  Pairs that
 // do not intersect are settled, the ones whose signs need the exact path go to the deferred
-// list, and the rest -- hits, and the pairs with a triangle in the other's plane -- stay in
-// the wave's list (compacted in place: a batch's writes land below the entries still to be
-// read) for k_screen_full.
+// list, and the rest -- hits, pairs with a triangle in the other's plane and pairs with a
+// vertex exactly on the other plane -- stay in the wave's list (compacted in place: a batch's
+// writes land below the entries still to be read) for k_screen_full.
 __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict__ x, int64_t nv,
                                                         const int32_t* __restrict__ tris,
                                                         const int32_t* __restrict__ pairs,
@@ -304,20 +304,27 @@ __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict
     if (k < nf) {
       p = full[beg + k];
       code = fsig[beg + k];
-      if (code) {
-        const int2 ij = reinterpret_cast<const int2*>(pairs)[p];
-        int32_t vi[3], vj[3];
-        Tri64 A, B;
-        load_tri(x, nv, tris, ij.x, vi, A);
-        load_tri(x, nv, tris, ij.y, vj, B);
-        int sa[3], sb[3];
+      int sa[3], sb[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          sa[c] = (int)((code >> (2 * c)) & 3u) - 1;
-          sb[c] = (int)((code >> (6 + 2 * c)) & 3u) - 1;
-        }
-        const int xr = cuts_intersect<false>(A, B, make_cut(sa[0], sa[1], sa[2]), make_cut(sb[0], sb[1], sb[2]),
-                                             status);
+      for (int c = 0; c < 3; ++c) {
+        sa[c] = (int)((code >> (2 * c)) & 3u) - 1;
+        sb[c] = (int)((code >> (6 + 2 * c)) & 3u) - 1;
+      }
+      // a vertex exactly on the other plane (rare), or a pair without sides (a triangle in
+      // the other's plane), is left to k_screen_full's general path
+      if (code && sa[0] && sa[1] && sa[2] && sb[0] && sb[1] && sb[2]) {
+        const LoneCut la = lone_cut(sa[0], sa[1], sa[2]), lb = lone_cut(sb[0], sb[1], sb[2]);
+        const int2 ij = reinterpret_cast<const int2*>(pairs)[p];
+        const int64_t ta = 3 * (int64_t)ij.x, tb = 3 * (int64_t)ij.y;
+        // the six vertices in cut order, loaded straight from their ids
+        const int64_t vp = tris[ta + la.k], vq0 = tris[ta + la.q0], vq1 = tris[ta + la.q1];
+        const int64_t vr = tris[tb + lb.k], vs0 = tris[tb + lb.q0], vs1 = tris[tb + lb.q1];
+        const auto ld = [x](int64_t v) { return V3<double>{x[3 * v], x[3 * v + 1], x[3 * v + 2]}; };
+        const V3<double> P = ld(vp), R = ld(vr);
+        const V3<double> Q[2] = {ld(vq0), ld(vq1)}, S[2] = {ld(vs0), ld(vs1)};
+        const int sq[2] = {pick(sa[0], sa[1], sa[2], la.q0), pick(sa[0], sa[1], sa[2], la.q1)};
+        const int ss[2] = {pick(sb[0], sb[1], sb[2], lb.q0), pick(sb[0], sb[1], sb[2], lb.q1)};
+        const int xr = cuts_intersect_lone(P, Q, sq, R, S, ss);
         verdict = xr == 0 ? 0 : (xr == 2 ? 2 : 1);
         if (verdict == 0) settle(p, PAIR_NONE, flags, pair_T);
       }

@@ -286,6 +286,56 @@ __device__ __forceinline__ int cuts_intersect(const Tri64& A, const Tri64& B, co
   return (after && before) ? 1 : 0;
 }
 
+// cuts_intersect for two cuts with no vertex on the other plane.  Each cut then has a lone
+// vertex whose two edges carry the segment's ends (make_cut's table), so all four orientations
+// share P (T_a's lone vertex) and R (T_b's): det[Q - P, R - P, S - P] is taken as
+// (Q - P) x (R - P) dotted with S - P, two cross products for four determinants.  The caller
+// passes the vertices in cut order -- P, T_a's two other vertices Q[0], Q[1] in the table's
+// order with their sides sq; R, S[0], S[1] likewise -- so nothing is selected at run time.
+// Each determinant's value, filter bound and verdict are orient_sign's, taken in the same
+// order, so the result is cuts_intersect's.
+struct LoneCut {
+  int k, q0, q1;  // the lone vertex and the other two, in make_cut's order
+};
+__device__ __forceinline__ LoneCut lone_cut(int s0, int s1, int s2) {
+  const int pos = (s0 > 0) + (s1 > 0) + (s2 > 0);
+  const int lone = pos == 2 ? -1 : 1;
+  LoneCut c;
+  c.k = s0 == lone ? 0 : (s1 == lone ? 1 : 2);
+  c.q0 = c.k == 0 ? 1 : 0;
+  c.q1 = c.k == 2 ? 1 : 2;
+  return c;
+}
+
+__device__ __forceinline__ int cuts_intersect_lone(const V3<double>& P, const V3<double> (&Q)[2], const int (&sq)[2],
+                                                   const V3<double>& R, const V3<double> (&S)[2],
+                                                   const int (&ss)[2]) {
+  const V3<double> e2 = R - P;
+  const V3<double> w[2] = {S[0] - P, S[1] - P};
+  bool after = false, before = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const V3<double> e1 = Q[i] - P;
+    const V3<double> n = cross(e1, e2);
+    const double nx = fabs(e1.y * e2.z) + fabs(e1.z * e2.y);
+    const double ny = fabs(e1.z * e2.x) + fabs(e1.x * e2.z);
+    const double nz = fabs(e1.x * e2.y) + fabs(e1.y * e2.x);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double det = dot(n, w[j]);
+      const double bound = kOrientErr * (nx * fabs(w[j].x) + ny * fabs(w[j].y) + nz * fabs(w[j].z));
+      int o;
+      if (fabs(det) > bound) o = det > 0 ? 1 : -1;
+      else if (bound == 0.0) o = 0;  // every monomial has a zero factor: exactly 0
+      else return 2;
+      const int tau = o * sq[i] * ss[j];
+      after |= tau < 0;
+      before |= tau > 0;
+    }
+  }
+  return (after && before) ? 1 : 0;
+}
+
 // FP64 interval ends of a hit on pair-local coordinates (origin u0), from its cuts and the
 // plane sides out.da, out.db; fills out's descriptor and t0, t1 and its kind (PAIR_HIT, or
 // PAIR_BAD_FRAME when the rounded line direction is 0).
