@@ -22,6 +22,9 @@ Prints one JSON line.  Besides the contract fields it carries:
   stages_ms_per_step   per-stage kernel time from the library's stage timers
   roofline      the dominant kernel: its algorithmic bytes / its measured launch duration
   roofline_path the whole step: the path's algorithmic bytes / the step's median time
+  roofline_gather  the dominant stage's vector-L1 tag accesses (counter figure) per second of
+                its launch, against one lookup per CU per clock: what bounds the screening
+  roofline_issue   its VALU instructions (counter figure) against the VALU issue peak
   err           element-wise errors of both paths against the FP64 CPU oracle on the full list
   cpu_baseline  the CPU oracle timed on this host on the same candidate list
   extra         the other workloads (folded cloth step, brute-force icospheres, 1M-triangle
@@ -51,19 +54,29 @@ FLUSH_BYTES = 1 << 30
 #               write_scale (the factors that make a 256 MiB elementwise copy read and write
 #               256 MiB)
 #   valu_wave   SQ_INSTS_VALU, wave-level VALU instructions
+#   tcp_accesses  TCP_TOTAL_CACHE_ACCESSES_sum, the vector L1's tag accesses
 MEASURED = {
-    # both screening kernels (k_screen + k_screen_full), 4,194,304-triangle sphere
+    # the screening kernels (k_screen, k_screen_flag, k_screen_full), 4,194,304-triangle sphere
     "screen": [
-        {"bytes": 526518735, "valu_wave": 104992810, "params": {"screen_blocks": 4096},
+        {"bytes": 573747468, "valu_wave": 79234200, "tcp_accesses": 164497647, "params": {"screen_blocks": 4096},
          "sources": {
-             "paper_2606_06511_amd/csrc/evaluate.hip": "f8755aa0994204ba132f6b5c24d417942a92d79ce84774390300009c284fec9f",
-             "paper_2606_06511_amd/csrc/pair.h": "7187ad6b1b50c86a2742ceb770e71a472d77253b643a09af1589e3dc0462fb37",
+             "paper_2606_06511_amd/csrc/evaluate.hip": "8ea096c58fb297ec2679c377dff025e3b3b1bb48270c43eddf53b1e605d588a3",
+             "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
+             "paper_2606_06511_amd/csrc/predicates.h":
+                 "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},
+        {"bytes": 534210353, "valu_wave": 83307342, "tcp_accesses": 164607182, "params": {"screen_blocks": 8192},
+         "sources": {
+             "paper_2606_06511_amd/csrc/evaluate.hip": "8ea096c58fb297ec2679c377dff025e3b3b1bb48270c43eddf53b1e605d588a3",
+             "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
              "paper_2606_06511_amd/csrc/predicates.h":
                  "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},
     ],
 }
 # VALU issue peak: 256 CUs x 4 SIMD16 units x 2.4 GHz (a wave64 instruction takes a SIMD 4 cycles)
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+# L1 tag-access rate if each CU's vector L1 takes one tag lookup per clock (the gather kernels
+# measure 0.76-0.88 of it; a streaming fill 0.18)
+TCP_ACCESS_PEAK = 256 * 2.4e9
 
 
 def measured(stage, what, params=None):
@@ -452,7 +465,9 @@ def main():
     # (they change the speed only, never a result)
     from paper_2606_06511_amd import autotune
 
-    space = {k: v for k, v in autotune.SPACE.items() if k != "trav_budget"}
+    # (the traversal budget is a broad-phase parameter; the row blocks serve only the two-call
+    # symbolic BSR)
+    space = {k: v for k, v in autotune.SPACE.items() if k not in ("trav_budget", "row_blocks")}
     if args.params:
         tuned = {}
         for item in args.params.split(","):
@@ -538,6 +553,13 @@ def main():
                           "mixed": {"alg_bytes_per_step": b_path_mixed,
                                     "frac": b_path_mixed / (ms_mixed * 1e-3) / 1e9 / HBM_PEAK_GBS}},
     }
+    tcp = measured(dominant, "tcp_accesses", tuned)
+    if tcp and dom_avg_ms > 0:
+        rate = tcp / (dom_avg_ms * 1e-3)
+        rec["roofline_gather"] = {"kernel_stage": dominant, "bound": "l1_gather", "achieved": rate,
+                                  "peak": TCP_ACCESS_PEAK, "unit": "L1 tag accesses/s", "frac": rate / TCP_ACCESS_PEAK,
+                                  "peak_basis": "one vector-L1 tag lookup per CU per clock (256 CUs x 2.4 GHz)",
+                                  "tcp_accesses_per_launch": tcp}
     vw = measured(dominant, "valu_wave", tuned)
     if vw and dom_avg_ms > 0:
         rate = vw * 64 / (dom_avg_ms * 1e-3)

@@ -366,8 +366,8 @@ ttie_status ttie_pcg_coupled(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_p
  * bit for bit (the evaluation sums in pair-key order and a candidate set does not depend on
  * the order of emission); only the speed changes.  A value of 0 restores the default. */
 enum {
-  TTIE_PARAM_SCREEN_BLOCKS = 0, /* blocks of the screening kernel: 64 .. 65536 (default 2048) */
-  TTIE_PARAM_ROW_BLOCKS = 1,    /* blocks of the row (assembly) kernels: 64 .. 65536 (default 2048) */
+  TTIE_PARAM_SCREEN_BLOCKS = 0, /* blocks of the screening kernels: 64 .. 65536 (default 4096) */
+  TTIE_PARAM_ROW_BLOCKS = 1,    /* blocks of ttie_bsr_symbolic's row kernel: 64 .. 65536 (default 2048) */
   TTIE_PARAM_TRAV_BUDGET = 2,   /* nodes a traversal lane visits before a whole wave takes over its
                                    query: 16 .. 2^20 (default 128) */
   TTIE_PARAM_HASH_BUDGET = 3,   /* later bucket entries a hash thread tests before a whole wave takes

@@ -159,7 +159,7 @@ struct Ctx {
 
 // a launch parameter of the context (its default when unset)
 inline int64_t ctx_param(const Ctx* c, int k) {
-  static const int64_t kDefault[TTIE_PARAM_COUNT] = {2048, 2048, 128, 64};
+  static const int64_t kDefault[TTIE_PARAM_COUNT] = {4096, 2048, 128, 64};
   return c->param[k] ? c->param[k] : kDefault[k];
 }
 

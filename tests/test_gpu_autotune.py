@@ -23,7 +23,7 @@ def test_param_range_and_defaults():
     from paper_2606_06511_amd import ttie
 
     c = _ctx(100, 100)
-    assert [c.get_param(p) for p in range(4)] == [2048, 2048, 128, 64]
+    assert [c.get_param(p) for p in range(4)] == [4096, 2048, 128, 64]
     c.set_param(ttie.PARAM_TRAV_BUDGET, 32)
     assert c.get_param(ttie.PARAM_TRAV_BUDGET) == 32
     c.set_param(ttie.PARAM_TRAV_BUDGET, 0)
