@@ -197,6 +197,36 @@ def test_eval_degenerate_integer_triangles(ctx, seed):
     pc.check_hits(ctx.hits(), ref, pairs, 0)
 
 
+def _fan_with_blades(F=400, seed=0):
+    """A fan of F triangles around one hub vertex in z = 0, crossed near the hub by two
+    vertical blade triangles: the hub's row holds 387 incidences (2,322 column candidates), each
+    blade vertex's about 194 -- rows far longer than a wave."""
+    rng = np.random.default_rng(seed)
+    th = 2 * np.pi * (np.arange(F) + 0.37) / F
+    x = [np.zeros((1, 3)), np.stack([np.cos(th), np.sin(th), np.zeros(F)], 1)]
+    tris = [[0, 1 + k, 1 + (k + 1) % F] for k in range(F)]
+    base = 1 + F
+    for d, ang in [(0.05, 0.0), (-0.07, 0.9)]:
+        c, s_ = np.cos(ang), np.sin(ang)
+        rot = np.array([[c, -s_, 0], [s_, c, 0], [0, 0, 1]])
+        x.append(np.array([[-2, d, -1], [2, d, -1], [0, d, 2]]) @ rot.T)
+        tris.append([base, base + 1, base + 2])
+        base += 3
+    return np.concatenate(x) + 1e-3 * rng.standard_normal((base, 3)), np.array(tris, np.int32)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_long_rows(ctx, precision):
+    """Rows far longer than a wave: incidence ranks, column candidates and BSR blocks summed over
+    hundreds of incidences, against the oracle element by element."""
+    x, tris = _fan_with_blades()
+    pairs = oracle.pairs(x, tris)
+    ref, out, _ = _compare_eval(ctx, x, tris, pairs, precision)
+    hp = pairs[ref["hit_pair"]]
+    assert sum(1 for i, j in hp if 0 in tris[i] or 0 in tris[j]) >= 380
+    assert np.diff(ref["row_ptr"]).max() >= 300
+
+
 def test_eval_empty_and_ragged(ctx):
     from paper_2606_06511_amd import ttie
 
