@@ -65,6 +65,29 @@ def test_symbolic_then_numeric(ctx, precision):
     assert torch.equal(ci, one["col_idx"][:nb1])
 
 
+def test_symbolic_then_numeric_on_long_rows(ctx):
+    """The two-call BSR on rows longer than the symbolic kernel's LDS staging (the hub row of a
+    fan crossed by two blades has 2,322 column candidates): the same pattern and values as the
+    one-call assembly, and the oracle's pattern."""
+    from paper_2606_06511_amd import ttie
+    from test_gpu_parity import _fan_with_blades
+
+    x, tris = _fan_with_blades()
+    pairs = oracle.pairs(x, tris)
+    ref = oracle.evaluate(x, tris, pairs)
+    xd, td, pd = _dev(x, torch.float64), _dev(tris, torch.int32), _dev(pairs, torch.int32)
+    one = ctx.evaluate(xd, td, pd, precision=ttie.FP64, hessian=True)
+    nb1 = int(one["n_blocks"].item())
+    assert nb1 == len(ref["col_idx"])
+    rp, ci, nb = ctx.bsr_symbolic(len(x), capacity=nb1)
+    assert ctx.status() == ttie.TTIE_OK and int(nb.item()) == nb1
+    np.testing.assert_array_equal(rp.cpu().numpy(), ref["row_ptr"])
+    np.testing.assert_array_equal(ci[:nb1].cpu().numpy(), ref["col_idx"])
+    vals = ctx.bsr_numeric(rp, ci[:nb1], torch.float64)
+    assert ctx.status() == ttie.TTIE_OK
+    assert torch.equal(vals, one["vals"][:nb1])
+
+
 def test_numeric_refresh_on_a_kept_pattern(ctx):
     """Values refreshed on a fixed pattern after the positions move: the pattern of the first
     evaluation holds the second's blocks (a superset from swept candidates); the refreshed values
