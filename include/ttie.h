@@ -372,7 +372,13 @@ enum {
                                    query: 16 .. 2^20 (default 128) */
   TTIE_PARAM_HASH_BUDGET = 3,   /* later bucket entries a hash thread tests before a whole wave takes
                                    over the rest: 16 .. 2^20 (default 64) */
-  TTIE_PARAM_COUNT = 4
+  TTIE_PARAM_SCREEN_TILE = 4,   /* candidates per tile of the screening's tile queue: a multiple of
+                                   64 in 64 .. 2^20, raised if needed so that a list has at most
+                                   2^18 tiles; the screening grid (TTIE_PARAM_SCREEN_BLOCKS) then
+                                   stays resident and each wave takes the next tile from a
+                                   device counter until the list is done.  Default 0: no queue,
+                                   one contiguous chunk of the list per wave. */
+  TTIE_PARAM_COUNT = 5
 };
 ttie_status ttie_set_param(ttie_ctx* ctx, int param, int64_t value);
 ttie_status ttie_get_param(ttie_ctx* ctx, int param, int64_t* value_host);

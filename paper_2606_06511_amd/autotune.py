@@ -14,11 +14,13 @@ import torch
 
 from . import ttie
 
-# candidate values per parameter (the library's defaults are 2048, 2048, 128 and 64)
+# candidate values per parameter (the library's defaults are 4096, 2048, 128, 64 and 0)
 SPACE = {
     "screen_blocks": (ttie.PARAM_SCREEN_BLOCKS, (512, 1024, 2048, 4096, 8192)),
     "row_blocks": (ttie.PARAM_ROW_BLOCKS, (256, 512, 1024, 2048, 4096)),
     "trav_budget": (ttie.PARAM_TRAV_BUDGET, (16, 24, 32, 64, 128, 256, 1024)),
+    # 0: one contiguous chunk of the candidate list per wave; otherwise tiles from a queue
+    "screen_tile": (ttie.PARAM_SCREEN_TILE, (0, 1024, 4096, 16384)),
 }
 
 

@@ -63,7 +63,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.defer = take((size_t)lim.max_pairs * 4);
   L.full = take((size_t)lim.max_pairs * 4);  // candidates for the full screening
   L.fsig = take((size_t)lim.max_pairs * 2);  // and their plane sides
-  L.nfull = take((size_t)65536 * 4 * 4);     // their number per screening wave (grid <= 65536 blocks)
+  L.nfull = take((size_t)65536 * 4 * 4);     // their number per screening unit (a wave of <= 65536 blocks, or a tile)
   L.recs = take(H * sizeof(AsmRec<double>));
   L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time
   L.cur = take_other(V * 4);
@@ -687,9 +687,11 @@ ttie_status ttie_axpy(ttie_ctx* ctx, int64_t n_verts, double alpha, const double
 ttie_status ttie_set_param(ttie_ctx* ctx, int param, int64_t value) {
   if (!ctx) return fail(TTIE_ERR_INVALID_ARGUMENT, "context is NULL");
   if (param < 0 || param >= TTIE_PARAM_COUNT) return fail(TTIE_ERR_INVALID_ARGUMENT, "unknown parameter");
-  static const int64_t lo[TTIE_PARAM_COUNT] = {64, 64, 16, 16};
-  static const int64_t hi[TTIE_PARAM_COUNT] = {65536, 65536, 1 << 20, 1 << 20};
+  static const int64_t lo[TTIE_PARAM_COUNT] = {64, 64, 16, 16, 64};
+  static const int64_t hi[TTIE_PARAM_COUNT] = {65536, 65536, 1 << 20, 1 << 20, 1 << 20};
   if (value != 0 && (value < lo[param] || value > hi[param])) return fail(TTIE_ERR_INVALID_ARGUMENT, "value out of range");
+  if (param == TTIE_PARAM_SCREEN_TILE && value % 64 != 0)
+    return fail(TTIE_ERR_INVALID_ARGUMENT, "screening tile not a multiple of 64");
   ctx->param[param] = value;
   return TTIE_OK;
 }

@@ -244,33 +244,50 @@ __global__ void __launch_bounds__(kBlock) k_screen(const double* __restrict__ x,
                                                    int32_t* __restrict__ full, uint16_t* __restrict__ fsig,
                                                    int32_t* __restrict__ nfull, Counters* ctr,
                                                    uint8_t* __restrict__ flags,
-                                                   double* __restrict__ pair_T, uint32_t* __restrict__ bm, int64_t nbm) {
+                                                   double* __restrict__ pair_T, uint32_t* __restrict__ bm, int64_t nbm,
+                                                   int64_t tile) {
   int status = 0;
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
   for (int64_t w = gt; w < nbm; w += gs) bm[w] = 0u;
   for (int64_t c = gt; c < 3 * nv; c += gs)
     if (const int cs = coord_status(x[c])) status = status == STATUS_NONFINITE ? status : cs;
   const int64_t np = min(*n_pairs_dev, max_pairs);
-  int64_t beg, end, wid;
-  wave_chunk(np, beg, end, wid);
   const int lane = __lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
-  int32_t nf = 0;
-  for (int64_t base = beg; base < end; base += 64) {
-    const int64_t p = base + lane;
-    int st = STEP_SETTLED;
-    uint32_t code = 0;
-    if (p < end) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, code, status);
-    append(st == STEP_DEFER, p, defer, max_pairs, &ctr->n_defer, status);
-    const uint64_t fm = __ballot(st == STEP_FULL);
-    if (st == STEP_FULL) {
-      const int64_t at = beg + nf + __popcll(fm & below);
-      full[at] = (int32_t)p;
-      fsig[at] = (uint16_t)code;
+  // one unit of the list: its candidates in batches of 64, the passed ones to its range of full
+  const auto unit = [&](int64_t beg, int64_t end, int64_t u) {
+    int32_t nf = 0;
+    for (int64_t base = beg; base < end; base += 64) {
+      const int64_t p = base + lane;
+      int st = STEP_SETTLED;
+      uint32_t code = 0;
+      if (p < end) st = screen_stage1(p, x, nv, tris, nt, pairs, va != 0, flags, pair_T, code, status);
+      append(st == STEP_DEFER, p, defer, max_pairs, &ctr->n_defer, status);
+      const uint64_t fm = __ballot(st == STEP_FULL);
+      if (st == STEP_FULL) {
+        const int64_t at = beg + nf + __popcll(fm & below);
+        full[at] = (int32_t)p;
+        fsig[at] = (uint16_t)code;
+      }
+      nf += __popcll(fm);
     }
-    nf += __popcll(fm);
+    if (lane == 0) nfull[u] = nf;
+  };
+  if (tile == 0) {
+    int64_t beg, end, wid;
+    wave_chunk(np, beg, end, wid);
+    unit(beg, end, wid);
+  } else {
+    // the tile queue: the next tile from the device counter until the list is done
+    for (;;) {
+      uint32_t t = 0;
+      if (lane == 0) t = atomicAdd(&ctr->tile_next, 1u);
+      t = __shfl(t, 0);
+      const int64_t beg = (int64_t)t * tile;
+      if (beg >= np) break;
+      unit(beg, min(np, beg + tile), (int64_t)t);
+    }
   }
-  if (lane == 0) nfull[wid] = nf;
   if (status) latch(&ctr->status, status);
 }
 
@@ -287,14 +304,19 @@ __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict
                                                         int32_t* __restrict__ defer, int32_t* __restrict__ full,
                                                         uint16_t* __restrict__ fsig, int32_t* __restrict__ nfull,
                                                         Counters* ctr, uint8_t* __restrict__ flags,
-                                                        double* __restrict__ pair_T) {
+                                                        double* __restrict__ pair_T, int64_t tile) {
   const int64_t np = min(*n_pairs_dev, max_pairs);
   int64_t beg, end, wid;
   wave_chunk(np, beg, end, wid);
-  const int32_t nf = nfull[wid];
   const int lane = __lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   int status = 0;
+  // the wave's units: its chunk, or with the tile queue every nw-th tile from its own id
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  const int64_t units = tile ? (np + tile - 1) / tile : wid + 1;
+  for (int64_t u = wid; u < units; u += nw) {
+  if (tile) beg = u * tile;
+  const int32_t nf = nfull[u];
   int32_t kept = 0;
   for (int32_t k0 = 0; k0 < nf; k0 += 64) {
     const int32_t k = k0 + lane;
@@ -339,7 +361,8 @@ __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict
     }
     kept += (int32_t)__popcll(km);
   }
-  if (lane == 0) nfull[wid] = kept;
+  if (lane == 0) nfull[u] = kept;
+  }
   if (status) latch(&ctr->status, status);
 }
 
@@ -349,19 +372,23 @@ __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict
 // dependent loads for one or two pairs).  A pair that straddles both ways comes with its exact
 // plane sides, so the plane distances are computed again for a hit only.
 constexpr int kMergeChunks = 16;
+constexpr int64_t kMaxUnits = 65536 * kWaves;  // entries of nfull: chunks of a 65536-block grid, or tiles
 
 __global__ void __launch_bounds__(kBlock) k_screen_full(const double* __restrict__ x, int64_t nv,
                                                         const int32_t* __restrict__ tris, int64_t nt,
                                                         const int32_t* __restrict__ pairs, const int64_t* n_pairs_dev,
-                                                        int64_t max_pairs, int64_t n_chunks, double half, int va,
+                                                        int64_t max_pairs, int64_t n_chunks, int64_t tile, double half,
+                                                        int va,
                                                         HitGeom* __restrict__ hits, uint32_t max_hits,
                                                         int32_t* __restrict__ defer, const int32_t* __restrict__ full,
                                                         const uint16_t* __restrict__ fsig,
                                                         const int32_t* __restrict__ nfull, Counters* ctr,
                                                         uint8_t* __restrict__ flags, double* __restrict__ pair_T) {
   const int64_t np = min(*n_pairs_dev, max_pairs);
-  // the chunk length of the screening grid (as wave_chunk computes it there)
-  const int64_t chunk = ((np + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+  // the units' length and count: the tiles, or the chunks of the screening grid's n_chunks
+  // waves (as wave_chunk computes them there)
+  const int64_t chunk = tile ? tile : ((np + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+  if (tile) n_chunks = (np + tile - 1) / tile;
   const int lane = __lane_id();
   const int64_t c0 = ((int64_t)blockIdx.x * kWaves + threadIdx.x / 64) * kMergeChunks;
   int32_t cnt = 0;
@@ -1106,6 +1133,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
     ctr->last_touched = R;
     ctr->n_hits = 0;
     ctr->n_defer = 0;
+    ctr->tile_next = 0;
     // every other kernel of the evaluation has finished, so the latched status is final
     if (status_out) *status_out = __hip_atomic_load(&ctr->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -1396,14 +1424,19 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   // both screening kernels split the list the same way: the same grid
   const unsigned gscreen = grid_for(pair_cap, (unsigned)ctx_param(c, TTIE_PARAM_SCREEN_BLOCKS));
   uint16_t* fsig = wsp<uint16_t>(c, L.fsig);
+  // the screening's units: one chunk per wave, or tiles from a queue (at most kMaxUnits of
+  // them, the length of nfull)
+  int64_t tile = ctx_param(c, TTIE_PARAM_SCREEN_TILE);
+  if (tile) tile = std::max<int64_t>(tile, ((pair_cap + kMaxUnits - 1) / kMaxUnits + 63) / 64 * 64);
   k_screen<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, va, defer, full, fsig,
-                                      nfull, ctr, flags, pair_T, bm, nw);
+                                      nfull, ctr, flags, pair_T, bm, nw, tile);
   k_screen_flag<<<gscreen, kBlock, 0, s>>>(m->x, nv, m->tris, pairs, n_pairs, pair_cap, defer, full, fsig, nfull, ctr,
-                                           flags, pair_T);
+                                           flags, pair_T, tile);
   const int64_t n_chunks = (int64_t)gscreen * kWaves;
-  k_screen_full<<<(unsigned)((n_chunks + kWaves * kMergeChunks - 1) / (kWaves * kMergeChunks)), kBlock, 0, s>>>(
-      m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, n_chunks, half, va, hits, max_hits, defer, full, fsig,
-      nfull, ctr, flags, pair_T);
+  const int64_t max_units = tile ? (pair_cap + tile - 1) / tile : n_chunks;
+  k_screen_full<<<(unsigned)std::max<int64_t>(1, (max_units + kWaves * kMergeChunks - 1) / (kWaves * kMergeChunks)),
+                  kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, n_pairs, pair_cap, n_chunks, tile, half, va,
+                                  hits, max_hits, defer, full, fsig, nfull, ctr, flags, pair_T);
   stage_end(c, TTIE_STAGE_SCREEN, s);
   stage_begin(c, TTIE_STAGE_SCREEN_EXACT, s);
   k_screen_exact<<<grid_for(pair_cap, 256), kBlock, 0, s>>>(m->x, nv, m->tris, m->n_tris, pairs, pair_cap, half, va,

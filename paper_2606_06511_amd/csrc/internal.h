@@ -41,7 +41,7 @@ struct Counters {
   uint32_t n_hits;         // intersecting pairs found by the last screening
   uint32_t last_touched;   // vertices touched by the hits of the last completed evaluation (its rows)
   uint32_t n_defer;        // candidates whose signs need the exact fallback
-  uint32_t pad0_;
+  uint32_t tile_next;      // next tile of the screening's tile queue (0 between calls)
   uint32_t last_hits;      // hits of the last completed evaluation (for hvp / get_hits)
   uint64_t n_entries;      // (cell, triangle) entries of the spatial-hash broad phase
   uint32_t n_heavy;        // broad-phase work items handed to a wave-cooperative kernel
@@ -159,7 +159,7 @@ struct Ctx {
 
 // a launch parameter of the context (its default when unset)
 inline int64_t ctx_param(const Ctx* c, int k) {
-  static const int64_t kDefault[TTIE_PARAM_COUNT] = {4096, 2048, 128, 64};
+  static const int64_t kDefault[TTIE_PARAM_COUNT] = {4096, 2048, 128, 64, 0};
   return c->param[k] ? c->param[k] : kDefault[k];
 }
 

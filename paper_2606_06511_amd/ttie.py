@@ -31,7 +31,7 @@ EVAL_VERTEX_ADJACENT = 1       # Options.flags bit: evaluate pairs sharing one v
 HVP_EXACT, HVP_PSD = 0, 1
 PAIR_NONE, PAIR_HIT, PAIR_ADJACENT, PAIR_DEGENERATE_FRAME, PAIR_COPLANAR = 0, 1, 2, 3, 4
 MAX_PROBLEMS = 4096
-PARAM_SCREEN_BLOCKS, PARAM_ROW_BLOCKS, PARAM_TRAV_BUDGET, PARAM_HASH_BUDGET = 0, 1, 2, 3
+PARAM_SCREEN_BLOCKS, PARAM_ROW_BLOCKS, PARAM_TRAV_BUDGET, PARAM_HASH_BUDGET, PARAM_SCREEN_TILE = 0, 1, 2, 3, 4
 
 # every function the header declares, with (restype, argtypes)
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t

@@ -23,12 +23,13 @@ def test_param_range_and_defaults():
     from paper_2606_06511_amd import ttie
 
     c = _ctx(100, 100)
-    assert [c.get_param(p) for p in range(4)] == [4096, 2048, 128, 64]
+    assert [c.get_param(p) for p in range(5)] == [4096, 2048, 128, 64, 0]
     c.set_param(ttie.PARAM_TRAV_BUDGET, 32)
     assert c.get_param(ttie.PARAM_TRAV_BUDGET) == 32
     c.set_param(ttie.PARAM_TRAV_BUDGET, 0)
     assert c.get_param(ttie.PARAM_TRAV_BUDGET) == 128
-    for p, bad in ((ttie.PARAM_SCREEN_BLOCKS, 1), (ttie.PARAM_ROW_BLOCKS, 1 << 20), (ttie.PARAM_TRAV_BUDGET, 8)):
+    for p, bad in ((ttie.PARAM_SCREEN_BLOCKS, 1), (ttie.PARAM_ROW_BLOCKS, 1 << 20), (ttie.PARAM_TRAV_BUDGET, 8),
+                   (ttie.PARAM_SCREEN_TILE, 32), (ttie.PARAM_SCREEN_TILE, 100), (ttie.PARAM_SCREEN_TILE, 1 << 21)):
         with pytest.raises(ttie.TTIEError):
             c.set_param(p, bad)
     with pytest.raises(ttie.TTIEError):
@@ -48,10 +49,14 @@ def test_results_do_not_depend_on_params(which):
     settings = [{}, {ttie.PARAM_SCREEN_BLOCKS: 64, ttie.PARAM_ROW_BLOCKS: 64, ttie.PARAM_TRAV_BUDGET: 16,
                      ttie.PARAM_HASH_BUDGET: 16},
                 {ttie.PARAM_SCREEN_BLOCKS: 65536, ttie.PARAM_ROW_BLOCKS: 65536, ttie.PARAM_TRAV_BUDGET: 1 << 20,
-                 ttie.PARAM_HASH_BUDGET: 1 << 20}]
+                 ttie.PARAM_HASH_BUDGET: 1 << 20},
+                # the screening's tile queue: tiles of one batch, of many, and one tile for all
+                {ttie.PARAM_SCREEN_TILE: 64, ttie.PARAM_SCREEN_BLOCKS: 64},
+                {ttie.PARAM_SCREEN_TILE: 1024},
+                {ttie.PARAM_SCREEN_TILE: 1 << 20, ttie.PARAM_SCREEN_BLOCKS: 65536}]
     ref = None
     for st in settings:
-        for p in range(4):
+        for p in range(5):
             c.set_param(p, st.get(p, 0))
         res = []
         for method in (ttie.BROAD_LBVH, ttie.BROAD_HASH):
