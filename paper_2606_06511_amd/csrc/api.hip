@@ -87,8 +87,8 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.csort = take(36 * H * 4);
   L.cval = take(36 * H * 4);
   L.colrun = take(36 * H * 4);
-  // block totals of the word scan (two per 1024 words) and of the column scan (one per 1024 rows)
-  L.part = take(std::max<size_t>(2 * (W / 1024 + 2), 6 * H / 1024 + 2) * 4);
+  // block totals of the word scan (two per 1024 words) and of the column scan (one per 256 rows)
+  L.part = take(std::max<size_t>(2 * (W / 1024 + 2), 6 * H / 256 + 2) * 4);
   L.scan_tmp_bytes = scan_bytes;
   L.scan_tmp = take_other(scan_bytes);
   L.bvh_keys = take_other(T * 4);

@@ -338,9 +338,13 @@ __global__ void __launch_bounds__(kBlock) k_screen_flag(const double* __restrict
         const LoneCut la = lone_cut(sa[0], sa[1], sa[2]), lb = lone_cut(sb[0], sb[1], sb[2]);
         const int2 ij = reinterpret_cast<const int2*>(pairs)[p];
         const int64_t ta = 3 * (int64_t)ij.x, tb = 3 * (int64_t)ij.y;
+        const int32_t ia[3] = {tris[ta], tris[ta + 1], tris[ta + 2]};  // one load per row
+        const int32_t ib[3] = {tris[tb], tris[tb + 1], tris[tb + 2]};
         // the six vertices in cut order, loaded straight from their ids
-        const int64_t vp = tris[ta + la.k], vq0 = tris[ta + la.q0], vq1 = tris[ta + la.q1];
-        const int64_t vr = tris[tb + lb.k], vs0 = tris[tb + lb.q0], vs1 = tris[tb + lb.q1];
+        const int64_t vp = pick(ia[0], ia[1], ia[2], la.k), vq0 = pick(ia[0], ia[1], ia[2], la.q0),
+                      vq1 = pick(ia[0], ia[1], ia[2], la.q1);
+        const int64_t vr = pick(ib[0], ib[1], ib[2], lb.k), vs0 = pick(ib[0], ib[1], ib[2], lb.q0),
+                      vs1 = pick(ib[0], ib[1], ib[2], lb.q1);
         const auto ld = [x](int64_t v) { return V3<double>{x[3 * v], x[3 * v + 1], x[3 * v + 2]}; };
         const V3<double> P = ld(vp), R = ld(vr);
         const V3<double> Q[2] = {ld(vq0), ld(vq1)}, S[2] = {ld(vs0), ld(vs1)};
@@ -489,9 +493,9 @@ __device__ __forceinline__ void hit_vids(const int32_t* tris, int64_t key, int32
 //   first incidence of vertex v's list  = wi[v/32] + sum of cnt over the vertices below v in its word
 // Everything after the screening scales with the hits, not with N_v, except the final pass
 // that writes the dense outputs (gradient rows, BSR row pointers, incidence offsets).
-// The word scan and the column scan run in blocks of kRankBlockWords entries: a first launch
-// writes each block's totals, the second adds the totals of the blocks below its own and scans
-// inside the block.  (Counting into a few shared totals with atomics instead serialises on the
+// The word scan (blocks of kRankBlockWords words) and the column scan (blocks of kColBlockRows
+// rows) run in two launches each: the first writes each block's totals, the second adds the
+// totals of the blocks below its own and scans inside the block.  (Counting into a few shared totals with atomics instead serialises on the
 // contended addresses: measured 55 us for the 4M-triangle sphere's 27 K hits.)
 constexpr int kRankThreads = 256;
 constexpr int kRankWordsPerThread = 4;
@@ -903,25 +907,28 @@ __global__ void __launch_bounds__(kBlock) k_row_cols(const Counters* ctr, uint32
   }
 }
 
-// Per block of kRankBlockWords rows: its BSR columns (R = wp[nw] rows in all).
+// The column scan runs in blocks of kColBlockRows rows, one row per thread (a row's block
+// indices or column indices are written by its thread, so more blocks write them side by side).
+constexpr int kColBlockRows = kRankThreads;
+
+// Per block of kColBlockRows rows: its BSR columns (R = wp[nw] rows in all).
 __global__ void __launch_bounds__(kRankThreads) k_col_part(const uint32_t* __restrict__ wp, int64_t nw,
                                                            const int32_t* __restrict__ ncol, uint32_t* __restrict__ part) {
   __shared__ uint32_t sh[64];
   const uint32_t R = wp[nw];
-  const int64_t r0 = (int64_t)blockIdx.x * kRankBlockWords;
+  const int64_t r0 = (int64_t)blockIdx.x * kColBlockRows;
   if (r0 > R) return;
-  uint32_t a[4], z[4];
-  load4x2(reinterpret_cast<const uint32_t*>(ncol), reinterpret_cast<const uint32_t*>(ncol), r0 + 4 * threadIdx.x, R, a,
-          z);
+  const int64_t i = r0 + threadIdx.x;
+  const uint32_t a = i < R ? (uint32_t)ncol[i] : 0u;
   uint32_t t, unused;
-  block_sum2(a[0] + a[1] + a[2] + a[3], 0u, sh, t, unused);
+  block_sum2(a, 0u, sh, t, unused);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // Exclusive scan of ncol[0, R) into coff[0, R] (R = wp[nw]): block b takes rows
-// [b kRankBlockWords, (b + 1) kRankBlockWords), four per thread, from the totals of the blocks
-// below it.  With brow, each block's row goes to brow; with col_idx, each row's column indices
-// to col_idx.  The total coff[R] also goes to *n_blocks, and past cap latches TTIE_ERR_CAPACITY.
+// [b kColBlockRows, (b + 1) kColBlockRows), one per thread, from the totals of the blocks below
+// it.  With brow, each block's row goes to brow; with col_idx, each row's column indices to
+// col_idx.  The total coff[R] also goes to *n_blocks, and past cap latches TTIE_ERR_CAPACITY.
 __global__ void __launch_bounds__(kRankThreads) k_col_scan(const uint32_t* __restrict__ wp, int64_t nw,
                                                            const int32_t* __restrict__ ncol,
                                                            const uint32_t* __restrict__ part, int32_t* __restrict__ coff,
@@ -931,34 +938,29 @@ __global__ void __launch_bounds__(kRankThreads) k_col_scan(const uint32_t* __res
                                                            int64_t cap, int64_t* n_blocks, Counters* ctr) {
   __shared__ uint32_t sh[64];
   const uint32_t R = wp[nw];
-  const int64_t r0 = (int64_t)blockIdx.x * kRankBlockWords;
+  const int64_t r0 = (int64_t)blockIdx.x * kColBlockRows;
   if (r0 > R) return;
   uint32_t pr = 0;
   for (uint32_t q = threadIdx.x; q < blockIdx.x; q += kRankThreads) pr += part[q];
   uint32_t base, unused;
   block_sum2(pr, 0u, sh, base, unused);
   __syncthreads();  // sh is reused
-  const int64_t i0 = r0 + 4 * threadIdx.x;
-  uint32_t v[4], z[4];
-  load4x2(reinterpret_cast<const uint32_t*>(ncol), reinterpret_cast<const uint32_t*>(ncol), i0, R, v, z);
+  const int64_t i = r0 + threadIdx.x;
+  const uint32_t v = i < R ? (uint32_t)ncol[i] : 0u;
   uint32_t e, e2, t, t2;
-  block_scan2(v[0] + v[1] + v[2] + v[3], 0u, sh, e, e2, t, t2);
-  uint32_t p = base + e;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (i0 + k < R) {
-      coff[i0 + k] = (int32_t)p;
-      // the row of each of its blocks (stores only), or the row's column indices
-      if (brow)
-        for (uint32_t q = 0; q < v[k] && (int64_t)(p + q) < cap; ++q) brow[p + q] = (int32_t)(i0 + k);
-      if (col_idx) {
-        const int32_t* cb = colbuf + 6 * (int64_t)roff[i0 + k];
-        for (uint32_t q = 0; q < v[k] && (int64_t)(p + q) < cap; ++q) col_idx[p + q] = cb[q];
-      }
+  block_scan2(v, 0u, sh, e, e2, t, t2);
+  const uint32_t p = base + e;
+  if (i < R) {
+    coff[i] = (int32_t)p;
+    // the row of each of its blocks (stores only), or the row's column indices
+    if (brow)
+      for (uint32_t q = 0; q < v && (int64_t)(p + q) < cap; ++q) brow[p + q] = (int32_t)i;
+    if (col_idx) {
+      const int32_t* cb = colbuf + 6 * (int64_t)roff[i];
+      for (uint32_t q = 0; q < v && (int64_t)(p + q) < cap; ++q) col_idx[p + q] = cb[q];
     }
-    p += v[k];
   }
-  if (r0 + kRankBlockWords > R && threadIdx.x == 0) {  // the block holding row R: the total
+  if (r0 + kColBlockRows > R && threadIdx.x == 0) {  // the block holding row R: the total
     const uint32_t total = base + t;
     coff[R] = (int32_t)total;
     if (n_blocks) *n_blocks = total;
@@ -1379,7 +1381,7 @@ static hipError_t scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, h
 // is defined for every v in [0, nv])
 static int64_t bitmap_words(int64_t nv) { return nv / 32 + 1; }
 static unsigned col_scan_blocks(const Ctx* c) {
-  return (unsigned)((6 * c->lim.max_hits + 1 + kRankBlockWords - 1) / kRankBlockWords);
+  return (unsigned)((6 * c->lim.max_hits + 1 + kColBlockRows - 1) / kColBlockRows);
 }
 
 template <class S>
