@@ -896,9 +896,17 @@ __global__ void __launch_bounds__(kBlock) k_row_cols(const Counters* ctr, uint32
     const int32_t f = cflag[e];
     const bool last = pos == m - 1;
     if (!f && !last) continue;
+    // the first-flags below pos (each byte 0 or 1): bytes up to a 4-byte boundary, then whole
+    // words (the popcount of a word is its number of 1-bytes), then the last bytes
     int32_t d = 0;
-#pragma unroll 8
-    for (int32_t j = 0; j < pos; ++j) d += cflag[base + j];
+    int64_t j = base;
+    const int64_t stop = base + pos;
+    for (; j < stop && (j & 3); ++j) d += cflag[j];
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(cflag + j);
+    const int64_t nwd = (stop - j) >> 2;
+#pragma unroll 4
+    for (int64_t q = 0; q < nwd; ++q) d += __popc(w[q]);
+    for (j += 4 * nwd; j < stop; ++j) d += cflag[j];
     if (f) {
       colbuf[base + d] = cval[e];
       colrun[base + d] = pos;
