@@ -130,11 +130,95 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_i32(const int32_t* __rest
   }
 }
 
+// Long scans in three launches (tile sums, one block scanning them, each tile's scan from its
+// prefix): the look-back above hands each tile's prefix on through device-scope words that
+// travel between the XCDs' L2s, which set its pace on long inputs (0.17 ms for 2^22 entries);
+// the three passes stream the input twice at full width instead.
+__global__ void __launch_bounds__(kScanThreads) k_scan_tile_sums(const int32_t* __restrict__ in, int64_t n,
+                                                                 int32_t* __restrict__ tsum) {
+  __shared__ int32_t s_wave[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) run += base + j < n ? in[base + j] : 0;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) run += __shfl_xor(run, d);
+  if (__lane_id() == 0) s_wave[threadIdx.x / 64] = run;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) t += s_wave[w];
+    tsum[blockIdx.x] = t;
+  }
+}
+
+// one block: exclusive scan of the tile sums in place (each thread a contiguous run of them)
+__global__ void __launch_bounds__(1024) k_scan_tile_prefix(int32_t* __restrict__ tsum, int64_t tiles) {
+  __shared__ int32_t s_wave[16];
+  const int64_t per = (tiles + 1023) / 1024;
+  const int64_t b = (int64_t)threadIdx.x * per, e = std::min<int64_t>(tiles, b + per);
+  int32_t run = 0;
+  for (int64_t i = b; i < e; ++i) run += tsum[i];
+  const int lane = __lane_id(), wave = threadIdx.x / 64;
+  int32_t inc = run;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  int32_t excl = inc - run;
+  for (int w = 0; w < wave; ++w) excl += s_wave[w];
+  for (int64_t i = b; i < e; ++i) {
+    const int32_t t = tsum[i];
+    tsum[i] = excl;
+    excl += t;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tile_apply(const int32_t* __restrict__ in,
+                                                                  int32_t* __restrict__ out, int64_t n,
+                                                                  const int32_t* __restrict__ tsum) {
+  __shared__ int32_t s_wave[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) v[j] = base + j < n ? in[base + j] : 0;
+  int32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int32_t t = v[j];
+    v[j] = run;
+    run += t;
+  }
+  const int lane = __lane_id(), wave = threadIdx.x / 64;
+  int32_t inc = run;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  int32_t pre = tsum[blockIdx.x] + inc - run;
+  for (int w = 0; w < wave; ++w) pre += s_wave[w];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j < n) out[base + j] = pre + v[j];
+}
+
+// tiles from which the three-launch form is used
+constexpr int64_t kLongScanTiles = 256;
+
 }  // namespace
 
+// counters, then a look-back word and a tile sum per tile (separate arrays: the words must stay
+// zero between one-launch scans)
 size_t scan_temp_bytes(int64_t n) {
   const int64_t tiles = (std::max<int64_t>(n, 1) + kScanTile - 1) / kScanTile;
-  return 256 + (size_t)tiles * sizeof(uint64_t);
+  return 256 + (size_t)tiles * (sizeof(uint64_t) + sizeof(int32_t));
 }
 
 hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
@@ -142,6 +226,15 @@ hipError_t launch_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n, h
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   if (scan_temp_bytes(n) > c->L.scan_tmp_bytes) return hipErrorInvalidValue;
   char* base = c->ws + c->L.scan_tmp;
+  if (tiles >= kLongScanTiles) {
+    // the tile sums after the words of the most tiles the region holds
+    const int64_t tiles_cap = (int64_t)(c->L.scan_tmp_bytes - 256) / (int64_t)(sizeof(uint64_t) + sizeof(int32_t));
+    int32_t* tsum = reinterpret_cast<int32_t*>(base + 256 + tiles_cap * sizeof(uint64_t));
+    k_scan_tile_sums<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, n, tsum);
+    k_scan_tile_prefix<<<1, 1024, 0, s>>>(tsum, tiles);
+    k_scan_tile_apply<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, out, n, tsum);
+    return hipGetLastError();
+  }
   k_scan_i32<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, out, n, reinterpret_cast<ScanState*>(base),
                                                       reinterpret_cast<uint64_t*>(base + 256),
                                                       &reinterpret_cast<Counters*>(c->ws + c->L.counters)->status);

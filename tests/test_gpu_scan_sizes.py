@@ -1,8 +1,12 @@
-"""Counts at the tile edges of the one-launch scan (2048 entries per tile).  The evaluation
-scans N_v + 1 incidence counts and N_v + 1 column counts (the second is the BSR row pointer
-itself), so a small folded cloth is spread over N_v vertex slots, the rest unused, with N_v + 1
-just below, at and just above tile edges and past 64 tiles (the look-back window).  Candidates,
-flags, energy, gradient and the BSR matrix against the oracle; the row pointers bit-exact."""
+"""Sizes at the tile edges of the library's scans.  The exclusive scan of int32 counts works in
+tiles of 2048 entries: in one launch with a look-back below 256 tiles, in three launches (tile
+sums, their scan, each tile from its prefix) from 256 tiles on.  The springs pattern scans
+N_v + 1 vertex degrees and N_v + 1 row counts, so it is checked at N_v + 1 just below, at and
+above tile edges, past 64 tiles (the look-back window) and on both sides of 256 tiles.  The
+evaluation's own row ranks scan the touched-vertex bitmap in blocks of 1024 words (32,768
+vertices): a small folded cloth spread over N_v vertex slots, the rest unused, is evaluated at
+the same sizes.  Candidates, flags, energy, gradient and the BSR matrix against the oracle; the
+row pointers bit-exact."""
 
 import numpy as np
 import pytest
@@ -24,7 +28,7 @@ def ctx():
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a GPU")
     c = ttie.Context(0)
-    c.reserve(70 * TILE, 4096, 1 << 18, max_hits=1 << 14, max_blocks=1 << 19)
+    c.reserve(300 * TILE, 4096, 1 << 18, max_hits=1 << 14, max_blocks=1 << 19)
     return c
 
 
@@ -56,3 +60,19 @@ def test_scan_tile_edges(ctx, nv):
     out = ctx.evaluate(xd, td, torch.from_numpy(ref_pairs).cuda(), precision=ttie.FP64, flags=True)
     ctx.check()
     pc.check_eval_outputs(out, ref, ref_pairs, tris, ttie.FP64, what=f"n_v = {nv}")
+
+
+@pytest.mark.parametrize("nv", [TILE - 1, 64 * TILE, 255 * TILE - 1, 255 * TILE, 256 * TILE - 1, 256 * TILE,
+                                299 * TILE + 5])
+def test_scan_forms_through_the_springs_pattern(ctx, nv):
+    """Both scan forms and the switch between them (255 and 256 tiles of N_v + 1 counts): the
+    springs pattern of the spread cloth against the oracle's, bit for bit."""
+    from oracle import quasistatic as qs
+
+    x, tris = spread_cloth(nv, seed=nv % 5)
+    rp, ci = ctx.springs_pattern(torch.from_numpy(tris).cuda(), nv)
+    ctx.check()
+    edges = qs.spring_edges(tris)
+    rp_ref, ci_ref, _ = qs.stiffness_bsr(nv, edges, np.zeros((len(edges), 3, 3)), 0.0)
+    np.testing.assert_array_equal(rp.cpu().numpy(), rp_ref)
+    np.testing.assert_array_equal(ci.cpu().numpy(), ci_ref)
