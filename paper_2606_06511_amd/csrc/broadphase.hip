@@ -65,25 +65,35 @@ __global__ void __launch_bounds__(kBpBlock) k_tri_boxes(const double* __restrict
   bool bad = false;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    bool ok = true;
-    for (int k = 0; k < 3; ++k) {
-      const int32_t v = tris[3 * t + k];
-      if (v < 0 || v >= nv) {
-        ok = false;
-        break;
-      }
+    // the row, then all nine coordinates at once (a triangle with an index out of range is
+    // reported and gets the empty box at the origin)
+    const int32_t vr[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    const bool ok = vr[0] >= 0 && vr[0] < nv && vr[1] >= 0 && vr[1] < nv && vr[2] >= 0 && vr[2] < nv;
+    if (ok) {
+      double q[3][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[k][c] = x[3 * (int64_t)vr[k] + c];
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double q = x[3 * (int64_t)v + c];
-        lo[c] = k == 0 ? q : fmin(lo[c], q);
-        hi[c] = k == 0 ? q : fmax(hi[c], q);
-        if (x_end) {  // swept box: the triangle at both ends of the straight path
-          const double e = x_end[3 * (int64_t)v + c];
-          lo[c] = fmin(lo[c], e);
-          hi[c] = fmax(hi[c], e);
+        lo[c] = fmin(q[0][c], fmin(q[1][c], q[2][c]));
+        hi[c] = fmax(q[0][c], fmax(q[1][c], q[2][c]));
+      }
+      if (x_end) {  // swept box: the triangle at both ends of the straight path
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q[k][c] = x_end[3 * (int64_t)vr[k] + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lo[c] = fmin(lo[c], fmin(q[0][c], fmin(q[1][c], q[2][c])));
+          hi[c] = fmax(hi[c], fmax(q[0][c], fmax(q[1][c], q[2][c])));
         }
       }
+    } else {
+      bad = true;
     }
-    if (!ok) bad = true;
     ext += fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
     for (int c = 0; c < 3; ++c) {
       tbox[6 * t + c] = lo[c];
