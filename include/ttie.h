@@ -163,7 +163,10 @@ ttie_status ttie_broadphase(ttie_ctx* ctx, const ttie_mesh* mesh, int method, co
                             int64_t capacity, int64_t* n_pairs, void* stream);
 
 /* ---- evaluation -----------------------------------------------------------------------
- * Evaluates the candidate pairs and assembles the energy, gradient and Hessian.
+ * Evaluates the candidate pairs and assembles the energy, gradient and Hessian: per pair the
+ * screening and intervals of Sec. 1 and Eq. 1, T of Eq. 2, its gradient (Eq. 3) and the Eq. 4
+ * Hessian made PSD as in Sec. 1.1; then the sums over the pairs into one energy, one gradient
+ * and one block-sparse matrix (Sec. 1.2).
  *  pairs      pair_capacity x 2 int32 candidate list (8-byte aligned); the number of pairs evaluated is
  *             n = min(*n_pairs, pair_capacity), *n_pairs being a device int64 (so the output of
  *             ttie_broadphase can be passed directly); pair_capacity <= limits.max_pairs
@@ -282,14 +285,15 @@ ttie_status ttie_bsr_numeric(ttie_ctx* ctx, const int32_t* row_ptr, const int32_
                              void* stream);
 
 /* Hessian-vector product of the energy at the positions of the last ttie_eval (same mesh
- * and x): Hv = H v, v and Hv n_verts x 3 in the evaluation's precision.  mode
+ * and x): Hv = H v, v and Hv n_verts x 3 in the evaluation's precision (the second derivative
+ * of the summed Eq. 2 energy, or the Eq. 4 / Sec. 1.1 PSD form).  mode
  * TTIE_HVP_EXACT: the exact Hessian of the summed energy (forward-mode differentiation of
  * the gradient along v, through the line direction and the lerp weights); TTIE_HVP_PSD:
  * the assembled Hessian of the evaluation's PSD mode applied matrix-free. */
 ttie_status ttie_hvp(ttie_ctx* ctx, const ttie_mesh* mesh, const void* v, void* Hv, int mode, void* stream);
 
-/* y = H x with a BSR matrix from ttie_eval (precision as in opts->precision); n_rows =
- * n_verts.  Used by the Newton consumer. */
+/* y = H x with a BSR matrix from ttie_eval (the summed Eq. 4 blocks of Sec. 1.2; precision as
+ * in opts->precision); n_rows = n_verts.  Used by the Newton consumer. */
 ttie_status ttie_bsr_mv(ttie_ctx* ctx, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                         const void* vals, const void* x, void* y, int precision, void* stream);
 
