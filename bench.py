@@ -391,6 +391,7 @@ def main():
     if args.extra_only:
         only = set(args.extra_only.split(","))
         print(json.dumps({"extra": extra_configs(args, np, torch, ttie, workloads, only=only)}), flush=True)
+        copy_probe(torch, args.copy_probe)
         return
 
     x, tris = workloads.noisy_sphere(seed=0, n_lon=2048, n_bands=1025)
@@ -614,12 +615,19 @@ def main():
     if not args.no_extra:
         rec["extra"] = extra_configs(args, np, torch, ttie, workloads)
     print(json.dumps(rec), flush=True)
-    if args.copy_probe > 0:
-        n = args.copy_probe * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)  # one elementwise kernel: reads and writes exactly MB each
-        torch.cuda.synchronize()
+    copy_probe(torch, args.copy_probe)
+
+
+def copy_probe(torch, mb):
+    """One elementwise kernel that reads and writes exactly `mb` MiB each (nothing when 0): the
+    known-size dispatch that calibrates a profiler run's HBM byte counters."""
+    if mb <= 0:
+        return
+    n = mb * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
