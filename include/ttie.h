@@ -203,7 +203,7 @@ ttie_status ttie_eval(ttie_ctx* ctx, const ttie_mesh* mesh, const int32_t* pairs
  *             word that ttie_get_status reads for ttie_eval, which this call does not touch
  *  the other arguments as ttie_eval; pair_capacity and block_capacity also size the layout.
  * Returns TTIE_ERR_CAPACITY, before anything runs, when n_verts, pair_capacity, max_hits and
- * block_capacity need more than TTIE_STATIC_SCRATCH_BYTES (about 13 B per vertex, 10 B per
+ * block_capacity need more than TTIE_STATIC_SCRATCH_BYTES (about 9 B per vertex, 10 B per
  * listed pair and 2 KB per hit).  Every call on one GPU uses that GPU's one array and finds
  * the last call's contents in it (the counts that must start at zero are cleared by fill
  * kernels at the start of each call): calls that overlap on one GPU -- two streams, two

@@ -67,7 +67,7 @@ static Layout layout_with(const ttie_limits& lim, size_t scan_bytes, bool eval_o
   L.recs = take(H * sizeof(AsmRec<double>));
   L.cnt = take(32 * W * 4);  // read a whole bitmap word's 32 counts at a time
   L.cur = take_other(V * 4);
-  L.off = take(V * 4);
+  L.off = take_other(V * 4);  // incidence ranges per vertex (the solvers fill them)
   L.ncol = take(V * 4);
   L.inc = take(6 * H * sizeof(Incidence));
   L.colbuf = take(36 * H * 4);

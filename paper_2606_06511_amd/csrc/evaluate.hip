@@ -20,11 +20,12 @@
 //   k_rank_cand, k_row_cols  one thread per candidate: ranked by vertex, then the distinct
 //                    vertices numbered (the row's BSR columns) with their candidate runs
 //   k_col_part, k_col_scan  BSR offsets of the rows from their column counts; column indices
-//   k_assemble<S>    one thread per gradient entry (with the row's energy) and per BSR block
-//                    J_k^T M J_l, each summed over its row's incidences in pair-key order
-//   k_dense<S>       every vertex: incidence offsets, BSR row pointers, zero gradient rows of
-//                    untouched vertices, counts cleared; block 0: energy summed in row order,
-//                    scalar outputs, counters reset
+//   k_assemble<S>    one thread per gradient entry (with the row's energy; the row's count
+//                    cleared) and per BSR block J_k^T M J_l, each summed over its row's
+//                    incidences in pair-key order
+//   k_dense<S>       every vertex: BSR row pointers, zero gradient rows of untouched vertices,
+//                    word counts cleared; block 0: energy summed in row order, scalar outputs,
+//                    counters reset
 // Everything from k_derivs to k_assemble scales with the hits, not with the mesh.
 #include <algorithm>
 
@@ -1006,7 +1007,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
                                                      const int32_t* __restrict__ colrun,
                                                      const uint32_t* __restrict__ csort, int32_t* __restrict__ col_idx,
                                                      S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
-                                                     double* __restrict__ erow) {
+                                                     double* __restrict__ erow, int32_t* __restrict__ cnt) {
   const uint32_t R = wp[nw];
   const int64_t nb = coff ? min((int64_t)coff[R], block_cap) : 0;
   const int64_t ng = 3 * (int64_t)R;
@@ -1038,8 +1039,12 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
             if (I[k].slot == 0) e += Tv[k];
           }
       }
-      grad[3 * (int64_t)rowv[r] + c] = acc;
-      if (c == 0) erow[r] = e;
+      const int32_t v = rowv[r];
+      grad[3 * (int64_t)v + c] = acc;
+      if (c == 0) {
+        erow[r] = e;
+        cnt[v] = 0;  // the row's incidence count, zero again for the next evaluation
+      }
     } else {
       const int64_t q = t - ng;
       const int32_t r = brow[q];
@@ -1109,18 +1114,14 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
   if (threadIdx.x == 0) energies[p] = red[0];
 }
 
-// The dense outputs (blocks 1..): incidence offsets off[v] and BSR row pointers
-// row_ptr[v] = coff[row of v] for v in [0, nv], and the zero gradient row of an untouched
-// vertex, one thread per vertex (a wave's stores are contiguous).  The per-vertex and
-// per-word counts are cleared for the next evaluation.  A wave holds 64 consecutive
-// vertices, i.e. two whole bitmap words, so a vertex's offset inside its word is a 32-lane
-// prefix sum.  Block 0 sums the row energies in row order (thread-strided, then a tree), writes
-// the scalar outputs and resets the counters.
+// The dense outputs (blocks 1..): BSR row pointers row_ptr[v] = coff[row of v] for v in
+// [0, nv], and the zero gradient row of an untouched vertex, one thread per vertex (a wave's
+// stores are contiguous).  The per-word counts are cleared for the next evaluation (k_assemble
+// clears the per-vertex ones, which only rows hold).  Block 0 sums the row energies in row
+// order (thread-strided, then a tree), writes the scalar outputs and resets the counters.
 template <class S>
 __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const uint32_t* __restrict__ bm,
-                                                  const uint32_t* __restrict__ wp, const uint32_t* __restrict__ wi,
-                                                  int32_t* __restrict__ cnt, uint32_t* __restrict__ wcnt,
-                                                  int32_t* __restrict__ off,
+                                                  const uint32_t* __restrict__ wp, uint32_t* __restrict__ wcnt,
                                                   const int32_t* __restrict__ coff, int32_t* __restrict__ row_ptr,
                                                   S* __restrict__ grad, const double* __restrict__ erow, Counters* ctr,
                                                   uint32_t max_hits, double* energy, int64_t* n_hits,
@@ -1153,20 +1154,10 @@ __global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const 
   const int64_t v = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
   const bool in = v <= nv;
   const int64_t w = v >> 5;
-  const uint32_t word = in ? bm[w] : 0u;
-  const uint32_t j = (uint32_t)v & 31u;
-  const int32_t c = in ? cnt[v] : 0;
-  // exclusive prefix of c over the vertices of the same word (lanes 0-31 and 32-63)
-  int32_t incl = c;
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const int32_t y = __shfl_up(incl, d, 32);
-    if ((int)j >= d) incl += y;
-  }
   if (!in) return;
-  off[v] = (int32_t)wi[w] + incl - c;
+  const uint32_t word = bm[w];
+  const uint32_t j = (uint32_t)v & 31u;
   if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
-  if (c) cnt[v] = 0;
   if (j == 0 && w < nw) wcnt[w] = 0u;
   if (v < nv && !((word >> j) & 1u)) {
 #pragma unroll
@@ -1333,12 +1324,23 @@ __global__ void __launch_bounds__(kBlock) k_hvp_psd(const S* __restrict__ v, con
 }
 
 template <class S>
-__global__ void __launch_bounds__(kBlock) k_hvp_rows(int64_t nv, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_hvp_rows(int64_t nv, const uint32_t* __restrict__ bm,
+                                                     const uint32_t* __restrict__ wp, const int32_t* __restrict__ roff,
                                                      const Incidence* __restrict__ inc, const S* __restrict__ hv,
                                                      S* __restrict__ out) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
     S acc[3] = {S(0), S(0), S(0)};
-    for (int32_t k = off[v]; k < off[v + 1]; ++k) {
+    // the vertex's incidences: its row's range of the summation-ordered list (none when the
+    // last evaluation's hits do not touch it)
+    const uint64_t w = (uint64_t)v >> 5;
+    const uint32_t word = bm[w];
+    int32_t k0 = 0, k1 = 0;
+    if ((word >> (v & 31)) & 1u) {
+      const uint32_t r = wp[w] + (uint32_t)__popc(word & ((1u << (v & 31)) - 1u));
+      k0 = roff[r];
+      k1 = roff[r + 1];
+    }
+    for (int32_t k = k0; k < k1; ++k) {
       const Incidence in = inc[k];
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[c] = acc[c] + hv[18 * (int64_t)in.hit + 3 * in.slot + c];
@@ -1411,7 +1413,6 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   int32_t* rowv = wsp<int32_t>(c, L.touched);
   int32_t* roff = wsp<int32_t>(c, L.roff);
   int32_t* coff = wsp<int32_t>(c, L.coff);
-  int32_t* off = wsp<int32_t>(c, L.off);
   int32_t* ncol = wsp<int32_t>(c, L.ncol);
   Incidence* inc = wsp<Incidence>(c, L.inc);
   Incidence* inc2 = wsp<Incidence>(c, L.inc2);
@@ -1481,9 +1482,9 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
   }
   k_assemble<S><<<grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096), kBlock, 0, s>>>(
       wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, colrun, csort, col_idx, vals, block_cap, grad,
-      erow);
+      erow, cnt);
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
-  k_dense<S><<<1 + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(nv, nw, bm, wp, wi, cnt, wcnt, off, coff,
+  k_dense<S><<<1 + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(nv, nw, bm, wp, wcnt, coff,
                                                                 bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
                                                                 energy, n_hits, status_out);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
@@ -1569,7 +1570,8 @@ static hipError_t hvp_impl(Ctx* c, const ttie_mesh* m, const S* v, S* Hv, int mo
                                          half, hvbuf);
   else
     k_hvp_psd<S><<<gh, kBlock, 0, s>>>(v, wsp<AsmRec<S>>(c, L.recs), ctr, max_hits, hvbuf);
-  k_hvp_rows<S><<<grid_for(m->n_verts, 2048), kBlock, 0, s>>>(m->n_verts, wsp<int32_t>(c, L.off),
+  k_hvp_rows<S><<<grid_for(m->n_verts, 2048), kBlock, 0, s>>>(m->n_verts, wsp<uint32_t>(c, L.bm),
+                                                               wsp<uint32_t>(c, L.wp), wsp<int32_t>(c, L.roff),
                                                                wsp<Incidence>(c, L.inc2), hvbuf, Hv);
   stage_end(c, TTIE_STAGE_HVP, s);
   return hipGetLastError();

@@ -71,19 +71,31 @@ __device__ __forceinline__ int64_t diag_block(const int32_t* row_ptr, const int3
 
 
 // ---- the active rows ------------------------------------------------------------------------
-// flag[v] = row v holds blocks (row_ptr) or incidences (off); x, p = 0 on every row; a non-zero
-// b on an inactive row latches STATUS_INVALID.  Row n's flag is 0 (the scan's total).
+// flag[v] = row v holds blocks (row_ptr) or incidences of the last evaluation's hits; x, p = 0
+// on every row; a non-zero b on an inactive row latches STATUS_INVALID.  Row n's flag is 0 (the
+// scan's total).  With off, each vertex's range in the evaluation's incidence lists is written
+// there too: off[v] = roff[number of touched vertices below v] for v in [0, n] (the touched
+// vertices are the rows, in vertex order, and roff their list starts), so that the range of v
+// is [off[v], off[v + 1]), empty when no hit touches v.
 template <class S>
 __global__ void __launch_bounds__(kPB) k_pcg_flags(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                   const int32_t* __restrict__ off, const S* __restrict__ b,
-                                                   S* __restrict__ x, S* __restrict__ p, int32_t* __restrict__ flag,
-                                                   Counters* ctr) {
+                                                   const uint32_t* __restrict__ bm, const uint32_t* __restrict__ wp,
+                                                   const int32_t* __restrict__ roff, int32_t* __restrict__ off,
+                                                   const S* __restrict__ b, S* __restrict__ x, S* __restrict__ p,
+                                                   int32_t* __restrict__ flag, Counters* ctr) {
   for (int64_t v = (int64_t)blockIdx.x * kPB + threadIdx.x; v <= n; v += (int64_t)gridDim.x * kPB) {
+    bool touched = false;
+    if (off) {
+      const int64_t w = v >> 5;
+      const uint32_t word = bm[w], j = (uint32_t)v & 31u;
+      off[v] = roff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
+      touched = (word >> j) & 1u;
+    }
     if (v == n) {
       flag[n] = 0;
       continue;
     }
-    const bool act = (row_ptr && row_ptr[v + 1] > row_ptr[v]) || (off && off[v + 1] > off[v]);
+    const bool act = (row_ptr && row_ptr[v + 1] > row_ptr[v]) || touched;
     flag[v] = act ? 1 : 0;
     bool nz = false;
 #pragma unroll
@@ -109,7 +121,7 @@ struct Active {
 };
 
 template <class S>
-static hipError_t pcg_active(Ctx* c, int64_t n, const int32_t* row_ptr, const int32_t* off, const S* b, S* x, S* p,
+static hipError_t pcg_active(Ctx* c, int64_t n, const int32_t* row_ptr, int32_t* off, const S* b, S* x, S* p,
                              Active& a, hipStream_t s) {
   const Layout& L = c->L;
   int32_t* flag = wsp<int32_t>(c, L.pcg_flag);
@@ -117,7 +129,8 @@ static hipError_t pcg_active(Ctx* c, int64_t n, const int32_t* row_ptr, const in
   int32_t* act = wsp<int32_t>(c, L.pcg_act);
   Counters* ctr = wsp<Counters>(c, L.counters);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 1 + kPB - 1) / kPB));
-  k_pcg_flags<S><<<g, kPB, 0, s>>>(n, row_ptr, off, b, x, p, flag, ctr);
+  k_pcg_flags<S><<<g, kPB, 0, s>>>(n, row_ptr, wsp<uint32_t>(c, L.bm), wsp<uint32_t>(c, L.wp), wsp<int32_t>(c, L.roff),
+                                   off, b, x, p, flag, ctr);
   hipError_t e = launch_scan_i32(c, flag, pos, n + 1, s);
   if (e != hipSuccess) return e;
   k_pcg_compact<<<g, kPB, 0, s>>>(n, flag, pos, act);
@@ -574,7 +587,7 @@ static hipError_t pcg_mf_impl(Ctx* c, int64_t n, const S* b, double scale, S* x,
   const Layout& L = c->L;
   PcgBufs<S> B(c);
   const AsmRec<S>* recs = wsp<AsmRec<S>>(c, L.recs);
-  const int32_t* off = wsp<int32_t>(c, L.off);
+  int32_t* off = wsp<int32_t>(c, L.off);
   const Incidence* inc = wsp<Incidence>(c, L.inc2);
   S* hv = wsp<S>(c, L.hvbuf);
   const Counters* ctr = wsp<Counters>(c, L.counters);
@@ -606,7 +619,7 @@ hipError_t launch_pcg_coupled(Ctx* c, int64_t n, const int32_t* row_ptr, const i
   const Layout& L = c->L;
   PcgBufs<double> B(c);
   const AsmRec<double>* recs = wsp<AsmRec<double>>(c, L.recs);
-  const int32_t* off = wsp<int32_t>(c, L.off);
+  int32_t* off = wsp<int32_t>(c, L.off);
   const Incidence* inc = wsp<Incidence>(c, L.inc2);
   double* hv = wsp<double>(c, L.hvbuf);
   const Counters* ctr = wsp<Counters>(c, L.counters);
