@@ -13,7 +13,8 @@
 //                  leaves [k 4^l, (k+1) 4^l); boxes are reduced level by level in LDS, four
 //                  levels per launch from the leaves, five per launch above, so building needs
 //                  no atomics and no fences.  The first launch also writes the sorted leaf
-//                  records (FP64 box, vertex ids).
+//                  records (FP64 box, vertex ids).  Each inner node also records a vertex
+//                  all its triangles hold, if there is one.
 //   k_traverse     two lanes per leaf s (its own 256-leaf subtree, staged in LDS, and the rest
 //                  of the tree), depth first over the subtrees holding leaves after s,
 //                  four child boxes per visit and a 64-bit mask stack, descending where the
@@ -21,6 +22,8 @@
 //                  once; a leaf is confirmed by the exact closed FP64 box test and the
 //                  shared-vertex test; pairs are staged per wave in LDS (ballot + mbcnt) and
 //                  flushed with one atomic per full buffer
+//   k_traverse_heavy  the searches k_traverse deferred, a wave's lanes sharing one stack of
+//                  nodes; a subtree whose triangles all hold a vertex of the query is skipped
 //   k_brute        all i < j without a shared vertex (no box test)
 
 #include "internal.h"
@@ -249,11 +252,32 @@ struct Levels {
   int64_t off[24];
 };
 
-// FP32 node box, padded to two 16-byte halves
+// FP32 node box, padded to two 16-byte halves.  The padding of lo holds, for an inner node, the
+// bits of an int32: a vertex id that every triangle of the node's subtree holds, or kNoCommon
+// (kEmpty for a node with no leaves, the identity of the merge).  A query that holds that
+// vertex shares it with every leaf below, so none of them can be its candidate (Sec. 1: pairs
+// with a shared vertex are adjacent), and k_traverse_heavy skips the subtree: the deferred
+// searches are mostly those of fans of thin triangles around one vertex, whose boxes all
+// overlap.  (k_traverse does not test it: the extra compares cost its every visit more than
+// the few fan queries it meets save.)
 struct Box32 {
   float lo[4];
   float hi[4];
 };
+constexpr int32_t kNoCommon = -1;
+constexpr int32_t kEmpty = -2;
+
+__device__ __forceinline__ int32_t box_common(const Box32& b) { return __float_as_int(b.lo[3]); }
+__device__ __forceinline__ void set_common(Box32& b, int32_t v) { b.lo[3] = __int_as_float(v); }
+__device__ __forceinline__ int32_t merge_common(int32_t a, int32_t b) {
+  return a == kEmpty ? b : (b == kEmpty ? a : (a == b ? a : kNoCommon));
+}
+// Whether a query with vertex ids q skips the subtree of inner node b (never with the
+// vertex-adjacent option, under which one shared vertex does not make a pair adjacent).
+__device__ __forceinline__ bool skip_common(const Box32& b, const int32_t q[3], bool va) {
+  const int32_t v = box_common(b);
+  return !va & (v >= 0) & ((v == q[0]) | (v == q[1]) | (v == q[2]));
+}
 
 // sorted leaf record: the triangle's FP64 box, its vertex ids and its index
 struct LeafRec {
@@ -265,11 +289,26 @@ struct LeafRec {
 __device__ __forceinline__ Box32 box_union(const Box32& a, const Box32& b) {
   Box32 r;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 3; ++c) {
     r.lo[c] = fminf(a.lo[c], b.lo[c]);
     r.hi[c] = fmaxf(a.hi[c], b.hi[c]);
   }
+  set_common(r, merge_common(box_common(a), box_common(b)));
+  r.hi[3] = 0.0f;
   return r;
+}
+
+// The shared vertex of up to four triangles (vertex ids, or kEmpty rows for absent leaves): the
+// first vertex of the first present one that every present one holds.
+__device__ __forceinline__ int32_t common_of_leaves(const int3& t0, const int3& t1, const int3& t2, const int3& t3) {
+  const int3 f = t0.x != kEmpty ? t0 : (t1.x != kEmpty ? t1 : (t2.x != kEmpty ? t2 : t3));
+  if (f.x == kEmpty) return kEmpty;
+  const auto holds = [](const int3& t, int32_t v) { return t.x == kEmpty || t.x == v || t.y == v || t.z == v; };
+  const int32_t cand[3] = {f.x, f.y, f.z};
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (holds(t0, cand[u]) && holds(t1, cand[u]) && holds(t2, cand[u]) && holds(t3, cand[u])) return cand[u];
+  return kNoCommon;
 }
 
 // Reduces levels l0+1 .. l0+4 (256 threads) or l0+1 .. l0+5 (1024 threads) from the boxes of
@@ -285,12 +324,16 @@ __global__ void __launch_bounds__(kThreads) k_levels(int l0, Levels lv, const do
                                                      int n_prob, int mbits, const int32_t* __restrict__ offset,
                                                      int32_t* __restrict__ qend) {
   __shared__ Box32 sh[kThreads];
+  __shared__ int3 sv[kThreads];  // the leaves' vertex ids (leaf pass only)
   const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   Box32 bx;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 3; ++c) {
     bx.lo[c] = 3.0e38f;
     bx.hi[c] = -3.0e38f;
   }
+  set_common(bx, kEmpty);
+  bx.hi[3] = 0.0f;
+  int3 tv = make_int3(kEmpty, kEmpty, kEmpty);
   if (k < lv.m[l0]) {
     if (l0 == 0) {
       const int32_t t = ids[k];
@@ -303,6 +346,10 @@ __global__ void __launch_bounds__(kThreads) k_levels(int l0, Levels lv, const do
         r.v[c] = tris[3 * (int64_t)t + c];
       }
       r.tri = t;
+      // a leaf with a negative id (reported as an index error) shares nothing
+      tv = (r.v[0] < 0 || r.v[1] < 0 || r.v[2] < 0) ? make_int3(kNoCommon, kNoCommon, kNoCommon)
+                                                   : make_int3(r.v[0], r.v[1], r.v[2]);
+      set_common(bx, kNoCommon);  // a leaf box's padding is not read
       leaves[k] = r;
       if (tri_off) {
         const int p = problem_of(tri_off, n_prob, t);
@@ -314,6 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_levels(int l0, Levels lv, const do
     }
   }
   sh[threadIdx.x] = bx;
+  if (l0 == 0) sv[threadIdx.x] = tv;
   __syncthreads();
   constexpr int kLevels = kThreads == 256 ? 4 : 5;
   static_assert(kThreads == 1 << (2 * kLevels), "a block reduces kThreads nodes to one");
@@ -321,8 +369,14 @@ __global__ void __launch_bounds__(kThreads) k_levels(int l0, Levels lv, const do
     const int cnt = kThreads >> (2 * j);
     Box32 r;
     const bool act = threadIdx.x < cnt;
-    if (act) r = box_union(box_union(sh[4 * threadIdx.x], sh[4 * threadIdx.x + 1]),
-                           box_union(sh[4 * threadIdx.x + 2], sh[4 * threadIdx.x + 3]));
+    if (act) {
+      r = box_union(box_union(sh[4 * threadIdx.x], sh[4 * threadIdx.x + 1]),
+                    box_union(sh[4 * threadIdx.x + 2], sh[4 * threadIdx.x + 3]));
+      if (l0 == 0 && j == 1) {  // level 1: the vertex its (up to four) triangles share
+        set_common(r, common_of_leaves(sv[4 * threadIdx.x], sv[4 * threadIdx.x + 1], sv[4 * threadIdx.x + 2],
+                                       sv[4 * threadIdx.x + 3]));
+      }
+    }
     __syncthreads();
     if (act) {
       sh[threadIdx.x] = r;
@@ -648,7 +702,8 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(int64_t n64, Levels l
 }
 
 // One wave per batch of saved queries (one query while the list is no longer than the grid,
-// at most kHeavyQ): the remaining nodes of all of them form
+// at most kHeavyQ), skipping every subtree whose triangles all hold one of the query's
+// vertices: the remaining nodes of all of them form
 // one stack in LDS, each entry tagged with its query's slot; every step each lane takes one
 // node, tests its four children against that query's box, and pushes the overlapping inner
 // children (or tests the leaves).  A query that overlaps hundreds of leaves needs tens of steps
@@ -753,10 +808,14 @@ __global__ void __launch_bounds__(64) k_traverse_heavy(Levels lv, const Box32* _
         Box32 cb[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) cb[i] = g[i];
+        const int32_t* qv = sme[slot].v;
+        const int32_t qv3[3] = {qv[0], qv[1], qv[2]};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t c = c0 + i;
-          if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i])) mask |= 1u << i;
+          if (c < mcount && c >= first && c <= lastc && overlap32(q, cb[i]) &&
+              !(lc > 0 && skip_common(cb[i], qv3, va != 0)))
+            mask |= 1u << i;
         }
       }
       // leaves: exact tests and emission

@@ -157,6 +157,45 @@ def test_lbvh_capacity_overflow_reports_count(ctx):
     assert all(tuple(p) in ref_set for p in got.tolist())
 
 
+def _crossing_fans(F=1024, seed=1):
+    """Two fans of F thin triangles around hubs 0.3 apart, the second tilted against the first.
+    Every box of a fan holds its hub, so each triangle's box overlaps all of its own fan's --
+    pairs that share the hub, never candidates -- and many of the other fan's, which are."""
+    rng = np.random.default_rng(seed)
+    th = 2 * np.pi * (np.arange(F) + 0.5) / F
+    ring = np.stack([np.cos(th), np.sin(th), np.zeros(F)], 1)
+    c, s_ = np.cos(0.3), np.sin(0.3)
+    tilt = np.array([[1, 0, 0], [0, c, -s_], [0, s_, c]])
+    hub2 = np.array([0.3, 0.0, 0.02])
+    x = np.concatenate([np.zeros((1, 3)), ring, hub2[None], hub2 + ring @ tilt.T])
+    x = x + 1e-4 * rng.standard_normal(x.shape)
+    fan = lambda h: [[h, h + 1 + k, h + 1 + (k + 1) % F] for k in range(F)]
+    return x, np.array(fan(0) + fan(F + 1), np.int32)
+
+
+@pytest.mark.parametrize("budget", [0, 16])
+def test_lbvh_pairs_crossing_fans(ctx, budget):
+    """The LBVH skips a subtree whose triangles all hold a vertex of the query (in the deferred
+    searches); the lists must still be the oracle's, pair for pair, with the traversal budget at
+    its default and at 16 (every fan query deferred), and with the vertex-adjacent option (which
+    turns the skip off: one shared vertex no longer excludes a pair)."""
+    from paper_2606_06511_amd import ttie
+
+    x, tris = _crossing_fans()
+    xd, td = _dev(x, torch.float64), _dev(tris, torch.int32)
+    ctx.set_param(ttie.PARAM_TRAV_BUDGET, budget)
+    try:
+        for va in (False, True):
+            ref = oracle.pairs(x, tris, vertex_adjacent=va)
+            pairs, n = ctx.broadphase(xd, td, ttie.BROAD_LBVH, vertex_adjacent=va)
+            ctx.check()
+            np.testing.assert_array_equal(_sorted_pairs(pairs, n), ref)
+            if va:  # every pair of one fan touches: the option lists each fan's pairs too
+                assert len(ref) > 2 * (len(tris) // 2) * (len(tris) // 2 - 1) // 2
+    finally:
+        ctx.set_param(ttie.PARAM_TRAV_BUDGET, 0)
+
+
 # ---------------------------------------------------------------------------------------
 # evaluation
 # ---------------------------------------------------------------------------------------
