@@ -58,15 +58,15 @@ FLUSH_BYTES = 1 << 30
 MEASURED = {
     # the screening kernels (k_screen, k_screen_flag, k_screen_full), 4,194,304-triangle sphere
     "screen": [
-        {"bytes": 573154466, "valu_wave": 78717497, "tcp_accesses": 152847001, "params": {"screen_blocks": 4096, "screen_tile": 0},
+        {"bytes": 572544683, "valu_wave": 78731139, "tcp_accesses": 152781216, "params": {"screen_blocks": 4096, "screen_tile": 0},
          "sources": {
-             "paper_2606_06511_amd/csrc/evaluate.hip": "2630f26dc72c926c39e807c9152f61e23fdc58aa2fe252f6f6f7c33eb23cb163",
+             "paper_2606_06511_amd/csrc/evaluate.hip": "9e7027fad3176ef52052cd152e6a3d38b9491027d4513fb9e842bacd477a9e14",
              "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
              "paper_2606_06511_amd/csrc/predicates.h":
                  "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},
-        {"bytes": 533137318, "valu_wave": 82931139, "tcp_accesses": 152941485, "params": {"screen_blocks": 8192, "screen_tile": 0},
+        {"bytes": 533334670, "valu_wave": 82897012, "tcp_accesses": 153007571, "params": {"screen_blocks": 8192, "screen_tile": 0},
          "sources": {
-             "paper_2606_06511_amd/csrc/evaluate.hip": "2630f26dc72c926c39e807c9152f61e23fdc58aa2fe252f6f6f7c33eb23cb163",
+             "paper_2606_06511_amd/csrc/evaluate.hip": "9e7027fad3176ef52052cd152e6a3d38b9491027d4513fb9e842bacd477a9e14",
              "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
              "paper_2606_06511_amd/csrc/predicates.h":
                  "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},

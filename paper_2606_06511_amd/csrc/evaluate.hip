@@ -22,11 +22,11 @@
 //   k_col_part, k_col_scan  BSR offsets of the rows from their column counts; column indices
 //   k_assemble<S>    one thread per gradient entry (with the row's energy; the row's count
 //                    cleared) and per BSR block J_k^T M J_l, each summed over its row's
-//                    incidences in pair-key order
-//   k_dense<S>       every vertex: BSR row pointers, zero gradient rows of untouched vertices,
-//                    word counts cleared; block 0: energy summed in row order, scalar outputs,
-//                    counters reset
-// Everything from k_derivs to k_assemble scales with the hits, not with the mesh.
+//                    incidences in pair-key order; in the same launch, one thread per vertex
+//                    for the dense outputs (BSR row pointers, zero gradient rows of untouched
+//                    vertices, word counts cleared)
+//   k_finish         energy summed in row order, scalar outputs, counters reset
+// Everything from k_derivs to k_assemble's sums scales with the hits, not with the mesh.
 #include <algorithm>
 
 
@@ -995,6 +995,11 @@ __device__ __forceinline__ void block_jmj(const AsmRec<S>& r, int s, int l, S B[
 // (inc2), a block's over its column's run of ranked candidates (the same order), kChunk at a
 // time with the chunk's loads issued together.  Nothing depends on another thread, so all of
 // them are in flight at once and the kernel costs about one chain of dependent loads.
+// The blocks from `ablocks` on write the dense outputs meanwhile, one thread per vertex v in
+// [0, nv] (a wave's stores are contiguous): the BSR row pointer row_ptr[v] = coff[row of v]
+// and the zero gradient row of an untouched vertex; they also clear the per-word counts for
+// the next evaluation (the row threads clear the per-vertex ones, which only rows hold).  These
+// stores stream at HBM speed while the sums wait on their loads.
 constexpr int kChunk = 4;
 
 template <class S>
@@ -1007,11 +1012,27 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
                                                      const int32_t* __restrict__ colrun,
                                                      const uint32_t* __restrict__ csort, int32_t* __restrict__ col_idx,
                                                      S* __restrict__ vals, int64_t block_cap, S* __restrict__ grad,
-                                                     double* __restrict__ erow, int32_t* __restrict__ cnt) {
+                                                     double* __restrict__ erow, int32_t* __restrict__ cnt,
+                                                     int64_t ablocks, int64_t nv, const uint32_t* __restrict__ bm,
+                                                     uint32_t* __restrict__ wcnt, int32_t* __restrict__ row_ptr) {
+  if ((int64_t)blockIdx.x >= ablocks) {
+    const int64_t v = ((int64_t)blockIdx.x - ablocks) * blockDim.x + threadIdx.x;
+    if (v > nv) return;
+    const int64_t w = v >> 5;
+    const uint32_t word = bm[w];
+    const uint32_t j = (uint32_t)v & 31u;
+    if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
+    if (j == 0 && w < nw) wcnt[w] = 0u;
+    if (v < nv && !((word >> j) & 1u)) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) grad[3 * v + k] = Sc<S>::c(0.0);
+    }
+    return;
+  }
   const uint32_t R = wp[nw];
   const int64_t nb = coff ? min((int64_t)coff[R], block_cap) : 0;
   const int64_t ng = 3 * (int64_t)R;
-  const XcdItems it = xcd_items(ng + nb);
+  const XcdItems it = xcd_items(ng + nb, ablocks);
   for (int64_t t = it.first; t < it.end; t += it.step) {
     if (t < ng) {
       const int64_t r = t / 3;
@@ -1074,13 +1095,14 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
 // Sum of a[r] over r = r0 + threadIdx.x + k * kBlock < r1, added in increasing r; sixteen loads
 // are in flight at a time (the adds of zero past the end leave the sum unchanged, the terms
 // being non-negative).
+template <int kThreads = kBlock>
 __device__ __forceinline__ double strided_sum(const double* __restrict__ a, uint32_t r0, uint32_t r1) {
   double acc = 0.0;
-  for (uint32_t base = r0 + threadIdx.x; base < r1; base += 16 * kBlock) {
+  for (uint32_t base = r0 + threadIdx.x; base < r1; base += 16 * kThreads) {
     double v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const uint32_t r = base + k * kBlock;
+      const uint32_t r = base + k * kThreads;
       v[k] = r < r1 ? a[r] : 0.0;
     }
 #pragma unroll
@@ -1114,55 +1136,33 @@ __global__ void __launch_bounds__(kBlock) k_problem_energy(int64_t nv, int n_pro
   if (threadIdx.x == 0) energies[p] = red[0];
 }
 
-// The dense outputs (blocks 1..): BSR row pointers row_ptr[v] = coff[row of v] for v in
-// [0, nv], and the zero gradient row of an untouched vertex, one thread per vertex (a wave's
-// stores are contiguous).  The per-word counts are cleared for the next evaluation (k_assemble
-// clears the per-vertex ones, which only rows hold).  Block 0 sums the row energies in row
-// order (thread-strided, then a tree), writes the scalar outputs and resets the counters.
-template <class S>
-__global__ void __launch_bounds__(kBlock) k_dense(int64_t nv, int64_t nw, const uint32_t* __restrict__ bm,
-                                                  const uint32_t* __restrict__ wp, uint32_t* __restrict__ wcnt,
-                                                  const int32_t* __restrict__ coff, int32_t* __restrict__ row_ptr,
-                                                  S* __restrict__ grad, const double* __restrict__ erow, Counters* ctr,
-                                                  uint32_t max_hits, double* energy, int64_t* n_hits,
-                                                  int32_t* status_out) {
-  if (blockIdx.x == 0) {
-    __shared__ double red[kBlock];
-    const uint32_t R = wp[nw];
-    red[threadIdx.x] = strided_sum(erow, 0, R);
+// The end of an evaluation, one block of kFinishThreads: the row energies summed in row order
+// (thread-strided, then a tree), the scalar outputs, and the counters reset for the next call.
+constexpr int kFinishThreads = 1024;
+__global__ void __launch_bounds__(kFinishThreads) k_finish(int64_t nw, const uint32_t* __restrict__ wp,
+                                                           const double* __restrict__ erow, Counters* ctr,
+                                                           uint32_t max_hits, double* energy, int64_t* n_hits,
+                                                           int32_t* status_out) {
+  __shared__ double red[kFinishThreads];
+  const uint32_t R = wp[nw];
+  red[threadIdx.x] = strided_sum<kFinishThreads>(erow, 0, R);
+  __syncthreads();
+  for (int w = kFinishThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    *energy = red[0];
-    const uint32_t H = ctr->n_hits;
-    if (n_hits) *n_hits = (int64_t)H;
-    if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
-    ctr->last_hits = min(H, max_hits);
-    ctr->last_touched = R;
-    ctr->n_hits = 0;
-    ctr->n_defer = 0;
-    ctr->tile_next = 0;
-    // every other kernel of the evaluation has finished, so the latched status is final
-    if (status_out) *status_out = __hip_atomic_load(&ctr->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
   }
-  // one thread per vertex (0..nv: entry nv is the end of the offset and row-pointer arrays),
-  // so every load of the chain below is in flight for all vertices at once
-  const int64_t v = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
-  const bool in = v <= nv;
-  const int64_t w = v >> 5;
-  if (!in) return;
-  const uint32_t word = bm[w];
-  const uint32_t j = (uint32_t)v & 31u;
-  if (row_ptr) row_ptr[v] = coff[wp[w] + (uint32_t)__popc(word & ((1u << j) - 1u))];
-  if (j == 0 && w < nw) wcnt[w] = 0u;
-  if (v < nv && !((word >> j) & 1u)) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) grad[3 * v + k] = Sc<S>::c(0.0);
-  }
+  if (threadIdx.x != 0) return;
+  *energy = red[0];
+  const uint32_t H = ctr->n_hits;
+  if (n_hits) *n_hits = (int64_t)H;
+  if (H > max_hits) latch(&ctr->status, STATUS_CAPACITY);
+  ctr->last_hits = min(H, max_hits);
+  ctr->last_touched = R;
+  ctr->n_hits = 0;
+  ctr->n_defer = 0;
+  ctr->tile_next = 0;
+  // every other kernel of the evaluation has finished, so the latched status is final
+  if (status_out) *status_out = __hip_atomic_load(&ctr->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1480,13 +1480,13 @@ static hipError_t eval_impl(Ctx* c, const ttie_mesh* m, const int32_t* pairs, co
     k_col_scan<<<col_scan_blocks(c), kRankThreads, 0, s>>>(wp, nw, ncol, part, coff, roff, colbuf, nullptr, brow,
                                                            block_cap, n_blocks, ctr);
   }
-  k_assemble<S><<<grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096), kBlock, 0, s>>>(
+  // the sums' blocks, then one block per kBlock vertices of the dense outputs
+  const unsigned ablocks = grid_for(3 * 6 * c->lim.max_hits + (bsr ? block_cap : 0), 4096);
+  k_assemble<S><<<ablocks + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(
       wp, nw, rowv, roff, inc2, recs, bsr ? coff : nullptr, brow, colbuf, colrun, csort, col_idx, vals, block_cap, grad,
-      erow, cnt);
+      erow, cnt, ablocks, nv, bm, wcnt, bsr ? row_ptr : nullptr);
   if (energies) k_problem_energy<<<n_prob, kBlock, 0, s>>>(nv, n_prob, vert_off, bm, wp, erow, energies, ctr);
-  k_dense<S><<<1 + (unsigned)((nv + kBlock) / kBlock), kBlock, 0, s>>>(nv, nw, bm, wp, wcnt, coff,
-                                                                bsr ? row_ptr : nullptr, grad, erow, ctr, max_hits,
-                                                                energy, n_hits, status_out);
+  k_finish<<<1, kFinishThreads, 0, s>>>(nw, wp, erow, ctr, max_hits, energy, n_hits, status_out);
   stage_end(c, TTIE_STAGE_ASSEMBLY, s);
   return hipGetLastError();
 }

@@ -95,8 +95,10 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
 struct XcdItems {
   int64_t first, end, step;
 };
-__device__ __forceinline__ XcdItems xcd_items(int64_t n) {
-  const int64_t G = gridDim.x, B = blockDim.x;
+// (blocks [0, G) of the grid take part: G = gridDim.x unless given)
+__device__ __forceinline__ XcdItems xcd_items(int64_t n, int64_t G = -1) {
+  if (G < 0) G = gridDim.x;
+  const int64_t B = blockDim.x;
   if (G % 8 != 0) return {(int64_t)blockIdx.x * B + threadIdx.x, n, G * B};
   const int64_t per = (n + 7) / 8, beg = min(n, (int64_t)(blockIdx.x % 8) * per);
   return {beg + (int64_t)(blockIdx.x / 8) * B + threadIdx.x, min(n, beg + per), (G / 8) * B};
