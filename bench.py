@@ -60,13 +60,13 @@ MEASURED = {
     "screen": [
         {"bytes": 572544683, "valu_wave": 78731139, "tcp_accesses": 152781216, "params": {"screen_blocks": 4096, "screen_tile": 0},
          "sources": {
-             "paper_2606_06511_amd/csrc/evaluate.hip": "9e7027fad3176ef52052cd152e6a3d38b9491027d4513fb9e842bacd477a9e14",
+             "paper_2606_06511_amd/csrc/evaluate.hip": "56f61dd399e314b14b02833e811c690b4b5f79691f3e4dc9f783489f3f79c76d",
              "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
              "paper_2606_06511_amd/csrc/predicates.h":
                  "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},
         {"bytes": 533334670, "valu_wave": 82897012, "tcp_accesses": 153007571, "params": {"screen_blocks": 8192, "screen_tile": 0},
          "sources": {
-             "paper_2606_06511_amd/csrc/evaluate.hip": "9e7027fad3176ef52052cd152e6a3d38b9491027d4513fb9e842bacd477a9e14",
+             "paper_2606_06511_amd/csrc/evaluate.hip": "56f61dd399e314b14b02833e811c690b4b5f79691f3e4dc9f783489f3f79c76d",
              "paper_2606_06511_amd/csrc/pair.h": "3214cbbbfc3adb8bb21bbd5a4ee7d42e551980c8d14782361af7c442d4b87904",
              "paper_2606_06511_amd/csrc/predicates.h":
                  "3dae2f86b3e306a1ff3a8053680aef2da3a8efdcbc81ab88b515de9126bd9a42"}},

@@ -1092,8 +1092,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const uint32_t* __restrict_
   }
 }
 
-// Sum of a[r] over r = r0 + threadIdx.x + k * kBlock < r1, added in increasing r; sixteen loads
-// are in flight at a time (the adds of zero past the end leave the sum unchanged, the terms
+// Sum of a[r] over r = r0 + threadIdx.x + k * kThreads < r1 (kThreads the block size), added in
+// increasing r; sixteen loads are in flight at a time (the adds of zero past the end leave the sum unchanged, the terms
 // being non-negative).
 template <int kThreads = kBlock>
 __device__ __forceinline__ double strided_sum(const double* __restrict__ a, uint32_t r0, uint32_t r1) {
